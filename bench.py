@@ -1,0 +1,230 @@
+"""Benchmark: hierarchical multicontinuum cell solves on one MI355X.
+
+One step = the whole hot path on one batch: every constrained cell problem
+(mch_solve_cells), the effective tensors (mch_effective_coeffs) and their
+adjoint gradient with respect to log kappa (mch_effective_coeffs_backward)
+for the loss sum_p ||A_eff(p) - A_target(p)||_F^2. Inputs are seeded
+synthetic media already resident in HBM. Prints one JSON line.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+from paper_2503_01276_amd import workloads as W  # noqa: E402
+
+FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
+HBM_PEAK_GBS = 8000.0
+# Algorithmic FP64 flops of one projected-PCG iteration per free node:
+# K apply 18 (9-point row), B apply 4, B^T apply 4, two D^-1 scalings 2,
+# three vector updates 6, two dot products 4.
+FLOPS_PER_NODE_ITER = 38
+
+DESCR = {
+    "c2": "hierarchical L=3 eta=2, 2D 512^2 fine grid, 32x32 macropoints, 64^2-element cells "
+          "(levels 64^2/32^2/16^2), N=2, contrast 1e4",
+    "c2flat": "flat L=1, 2D 512^2 fine grid, 32x32 macropoints, 64^2-element cells, N=2, contrast 1e4",
+    "c1": "flat L=1, 2D 128^2 fine grid, 8x8 macropoints, 32^2-element cells, N=2, contrast 1e4",
+    "c5": "hierarchical L=4 eta=2, 2D 2048^2 fine grid, 256x256 macropoints, 64^2-element cells "
+          "(levels 64^2/32^2/16^2/8^2), N=3 with inclusions, contrast 1e8",
+}
+
+
+def cpu_baseline(name: str, workers: int):
+    """Time the oracle (as it stands) on the host cores; runs before any GPU use."""
+    import oracle
+
+    cfg = W.PRESETS[name]
+    k, l = W.medium(name)
+    kt, _ = W.medium(name, channel_factor=W.target_factor(4))
+    T = oracle.stack_A(oracle.forward(cfg, kt, l, workers=workers), cfg)
+    t0 = time.perf_counter()
+    fwd = oracle.forward(cfg, k, l, workers=workers)
+    A = oracle.stack_A(fwd, cfg)
+    t1 = time.perf_counter()
+    gA = {p: 2.0 * (A[p] - T[p]) for p in range(cfg.n_points)}
+    oracle.backward(cfg, k, l, fwd, gA, workers=workers)
+    t2 = time.perf_counter()
+    solves = cfg.n_points * cfg.n_rhs
+    return {
+        "value": solves / (t2 - t0),
+        "unit": "cell-solves/s",
+        "cores": workers,
+        "kind": "oracle",
+        "sample": f"full {name} workload ({solves} solves): SciPy SuperLU forward {t1 - t0:.2f} s + "
+                  f"adjoint {t2 - t1:.2f} s, one process per core",
+    }
+
+
+class Runner:
+    def __init__(self, name: str):
+        import torch
+
+        from paper_2503_01276_amd import mch
+
+        self.torch = torch
+        self.cfg = W.PRESETS[name]
+        self.plan = mch.Plan(self.cfg)
+        dev = torch.device("cuda:0")
+        k, l = W.medium(name)
+        kt, _ = W.medium(name, channel_factor=W.target_factor(4))
+        self.k = torch.from_numpy(k.reshape(-1).copy()).to(dev)
+        self.l = torch.from_numpy(l.reshape(-1).copy()).to(dev)
+        P, M = self.plan.P, self.plan.M
+        self.A = torch.empty(P * M * M, dtype=torch.float64, device=dev)
+        self.gA = torch.empty_like(self.A)
+        self.g = torch.empty_like(self.k)
+        # target tensors: same path on the perturbed medium (an input of the loss, outside timing)
+        kt_d = torch.from_numpy(kt.reshape(-1).copy()).to(dev)
+        self.plan.solve_cells(kt_d, self.l)
+        self.T = torch.empty_like(self.A)
+        self.plan.effective_coeffs(kt_d, self.T)
+        torch.cuda.synchronize()
+
+    def step(self):
+        self.plan.solve_cells(self.k, self.l)
+        self.plan.effective_coeffs(self.k, self.A)
+        self.torch.sub(self.A, self.T, out=self.gA)
+        self.gA.mul_(2.0)
+        self.plan.effective_coeffs_backward(self.k, self.gA, self.g)
+
+    def time_steps(self, steps: int, warmup: int, profile: bool):
+        torch = self.torch
+        for _ in range(warmup):
+            self.step()
+        torch.cuda.synchronize()
+        self.plan.profile(profile)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record()
+        for _ in range(steps):
+            self.step()
+        e1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = e0.elapsed_time(e1) / steps
+        recs = self.plan.profile_records() if profile else []
+        self.plan.profile(False)
+        return ms, wall, recs
+
+
+def kernel_table(recs, steps):
+    tab = {}
+    for name, ms in recs:
+        t = tab.setdefault(name, [0.0, 0])
+        t[0] += ms
+        t[1] += 1
+    return {k: {"avg_ms": v[0] / v[1], "launches_per_step": v[1] / steps} for k, v in tab.items()}
+
+
+def solve_flops(runner, level_idx: int, iters: np.ndarray, levels: np.ndarray, adjoint: bool = False):
+    cfg = runner.cfg
+    r = cfg.eta ** level_idx
+    NC = cfg.n_cell // r
+    nfree = (NC - 1) ** cfg.dim
+    m = runner.plan.m
+    its = iters[levels == level_idx + 1].astype(np.float64)
+    return float(its.sum()) * (FLOPS_PER_NODE_ITER * nfree + 2 * m * m + 2 * m)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c2", choices=sorted(DESCR))
+    ap.add_argument("--flat", default=None, help="flat workload for the speedup (default: c2flat for c2)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-workers", type=int, default=None)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is a design described in DESIGN.md, not a measured path)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        workers = args.cpu_workers or min(16, os.cpu_count() or 1)
+        cpu = cpu_baseline(args.workload, workers)
+        print(f"[bench] cpu baseline: {cpu['value']:.1f} solves/s on {workers} cores", file=sys.stderr, flush=True)
+
+    run = Runner(args.workload)
+    cfg, plan = run.cfg, run.plan
+    ms, wall, recs = run.time_steps(args.steps, args.warmup, profile=True)
+    print(f"[bench] {args.workload}: {ms:.3f} ms/step", file=sys.stderr, flush=True)
+    ktab = kernel_table(recs, args.steps)
+    iters, _ = plan.diagnostics()
+    aiters, _ = plan.diagnostics(adjoint=True)
+    lev, _ = plan.hierarchy()
+    lev_pm = np.repeat(lev[:, None], plan.M, axis=1)
+    # dominant kernel and its algorithmic flops per launch
+    dom = max(ktab, key=lambda k: ktab[k]["avg_ms"] * ktab[k]["launches_per_step"])
+    roof = None
+    if dom.startswith(("solve_L", "adjsolve_L")):
+        li = int(dom.split("_L")[1]) - 1
+        flops = solve_flops(run, li, aiters if dom.startswith("adj") else iters, lev_pm)
+        achieved = flops / (ktab[dom]["avg_ms"] * 1e-3) / 1e12
+        roof = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                "flops_per_launch": flops}
+    solves = plan.P * plan.M
+    fwd_ms = sum(v["avg_ms"] * v["launches_per_step"] for k, v in ktab.items()
+                 if k.startswith(("setup", "solve")))
+    eff_ms = sum(v["avg_ms"] * v["launches_per_step"] for k, v in ktab.items() if k.startswith("eff"))
+    grad_ms = ms - fwd_ms - eff_ms
+    detail = {
+        "solve_ms": fwd_ms, "eff_ms": eff_ms, "grad_ms_incl_loss": grad_ms,
+        "solves_per_s_forward_only": solves / (fwd_ms * 1e-3),
+        "iterations": {f"L{n}": [int(iters[lev == n].min()), float(np.median(iters[lev == n])),
+                                 int(iters[lev == n].max())] for n in range(1, cfg.levels + 1)},
+        "adjoint_iterations": {f"L{n}": [int(aiters[lev == n].min()), float(np.median(aiters[lev == n])),
+                                         int(aiters[lev == n].max())] for n in range(1, cfg.levels + 1)},
+        "kernels": ktab,
+        "wall_s": wall,
+    }
+    flat = args.flat or ("c2flat" if args.workload == "c2" else None)
+    if flat:
+        frun = Runner(flat)
+        fms, _, frecs = frun.time_steps(max(3, args.steps // 4), 1, profile=True)
+        ftab = kernel_table(frecs, max(3, args.steps // 4))
+        ffwd = sum(v["avg_ms"] * v["launches_per_step"] for k, v in ftab.items() if k.startswith(("setup", "solve")))
+        detail["flat"] = {"workload": flat, "ms_per_step": fms, "solve_ms": ffwd,
+                          "speedup_step": fms / ms, "speedup_solve": ffwd / fwd_ms}
+        print(f"[bench] {flat}: {fms:.3f} ms/step", file=sys.stderr, flush=True)
+    out = {
+        "metric": "cell-solves/sec & eff-tensor+grad time, hier L=3 vs flat, 1 GPU, rel err <=1e-8",
+        "value": solves / (ms * 1e-3),
+        "unit": "cell-solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": DESCR[args.workload], "preset": args.workload, "macropoints": plan.P,
+                   "rhs_per_macropoint": plan.M, "solves_per_step": solves, "levels": cfg.levels,
+                   "eta": cfg.eta, "n_fine": cfg.n_fine, "n_cell": cfg.n_cell, "rtol": cfg.rtol},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "detail": detail,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,175 @@
+/*
+ * mch.h -- C ABI of the hierarchical multicontinuum homogenization cell-solve
+ * library (libmch.so) for AMD Instinct MI355X (gfx950).
+ *
+ * The library computes, for every macropoint of a structured macrogrid, the
+ * local solutions of the constrained cell problems of multicontinuum
+ * homogenization (Xie, Hoang, Yang, Huang, arXiv 2503.01276, Sec. 2,
+ * Eqs. phi_avar and phi_grad), either on the fine grid at every macropoint
+ * (flat method, levels = 1) or hierarchically (Sec. 3, Algorithm 1): a
+ * macropoint of level n >= 2 inherits the fine solution of the level-1
+ * macropoint of its group and solves a correction on the coarsened mesh
+ * h*eta^(n-1) (Eqs. phi_avar_corrector and phi_grad_corrector). From the local
+ * solutions it forms the effective coefficient tensors (Eq. Bs_defi) and the
+ * adjoint gradient of a loss on them with respect to log kappa per fine element.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Fine elements: e = i1 + n1*(i2 + n2*i3) (x1 fastest), uniform size h, on the
+ *   unit square / cube; kappa is piecewise constant per element and labels
+ *   (continuum index of each element, 0..n_cont-1) are uint8.
+ * Macropoints: p = j1 + m1*(j2 + m2*j3); macropoint p is the centre of coarse
+ *   block K_p, the H^d block of fine elements starting at H*j (H = n_fine/n_macro).
+ * Cell of p: n_cell^d fine elements centred on the macropoint, local
+ *   coordinates centred there; kappa and labels are sampled with periodic wrap
+ *   of the global grid; homogeneous Dirichlet data on the cell boundary.
+ * Constraint regions: the cell is tiled by n_sub^d equal sub-blocks R_q; one
+ *   constraint row per (R_q, continuum j) holding the average of the unknown
+ *   over R_q intersected with continuum j (rows with an empty intersection are
+ *   inactive).
+ * Right-hand sides: M = N + N*d per macropoint; alpha = i is phi_i (average
+ *   constraints delta_ij), alpha = N + i*d + m is phi_i^m (first-moment
+ *   constraints delta_ij*(xbar_{m,qj} - c_mj), c_mj the continuum-j centroid in K_p).
+ * Hierarchy: T_n keeps macropoints with index = o (mod eta^(L-n)) per axis,
+ *   o = floor(eta^(L-1)/2); S_1 = T_1, S_n = T_n minus T_(n-1) (Sec. 3.1,
+ *   Eq. defi_Sn). Level-n points inherit the level-1 point of their aligned
+ *   eta^(L-1)-per-axis block with weight 1 (the rule of the paper's experiments).
+ * Precision: every floating-point quantity is IEEE binary64.
+ *
+ * Memory and streams
+ * ------------------
+ * Every pointer argument named kappa, label, A_eff, gA, glogk or out is a
+ * device pointer on the plan's device, contiguous, owned by the caller.
+ * The plan owns its scratch (local solutions, multipliers, diagnostics).
+ * hip_stream is a hipStream_t (NULL = default stream). Calls are asynchronous
+ * on that stream unless stated otherwise; a plan must not be used from two
+ * streams concurrently.
+ *
+ * Errors
+ * ------
+ * Every int-returning call returns MCH_OK (0) or a negative code; nothing
+ * throws across the ABI. mch_last_error() returns a thread-local message
+ * describing the most recent failure on the calling thread.
+ */
+#ifndef MCH_H
+#define MCH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MCH_OK 0
+#define MCH_EINVAL (-1)     /* invalid configuration or argument */
+#define MCH_ESINGULAR (-2)  /* over-constrained coarsest level or singular Schur matrix */
+#define MCH_ENOCONV (-3)    /* a Krylov solve hit max_iter before rtol (results still written) */
+#define MCH_EHIP (-4)       /* HIP runtime error */
+#define MCH_ESTALE (-5)     /* backward / effective tensors requested without a completed forward */
+#define MCH_ENOTIMPL (-6)   /* configuration recognised but not implemented */
+
+typedef struct {
+  int32_t dim;          /* 2 or 3 */
+  int32_t n_fine[3];    /* fine elements per axis (equal on used axes; unused axes = 1) */
+  double h;             /* fine element size, must equal 1/n_fine[0] */
+  int32_t n_macro[3];   /* macropoints per axis (equal on used axes); H = n_fine/n_macro, even */
+  int32_t n_cell;       /* oversampled cell width in fine elements; even, divisible by n_sub*eta^(L-1) */
+  int32_t n_sub;        /* constraint sub-blocks per axis (s) */
+  int32_t n_cont;       /* number of continua N (1..3) */
+  int32_t levels;       /* L >= 1; L = 1 is the flat method */
+  int32_t eta;          /* coarsening factor >= 1; n_macro divisible by eta^(L-1) */
+  int32_t interp;       /* 0: inherit the level-1 solution of the group (only mode implemented) */
+  int32_t bc;           /* 0: homogeneous Dirichlet on the cell boundary (only mode implemented) */
+  double rtol;          /* relative tolerance on the projected preconditioned residual norm */
+  int32_t max_iter;     /* Krylov iteration cap per solve */
+} mch_config;
+
+typedef struct mch_plan mch_plan;
+
+/* Build the macrogrid hierarchy (Algorithm 1 steps 1-2; Sec. 3.1-3.2),
+ * validate the configuration, choose kernels per size class, and allocate the
+ * plan's device scratch on the current HIP device. Synchronous.
+ * Returns MCH_EINVAL for inconsistent sizes, MCH_ESINGULAR when the coarsest
+ * level has more constraint rows than free unknowns, MCH_ENOTIMPL for a mode
+ * outside the implemented ones, MCH_EHIP on allocation failure.
+ * On success *out owns the plan; release it with mch_destroy. */
+int mch_build_levels(const mch_config* cfg, mch_plan** out);
+
+/* Host-only form of the hierarchy step (no device needed): level and
+ * inherited level-1 macropoint of every macropoint for the given macrogrid
+ * (only dim, n_macro, levels and eta are read), into host arrays of length
+ * n_macro^dim. Synchronous. MCH_EINVAL for inconsistent sizes. */
+int mch_build_hierarchy(const mch_config* cfg, int32_t* level, int32_t* parent);
+
+/* Static description of a built plan (host memory, synchronous):
+ * info[0] = P (macropoints), info[1] = M (right-hand sides per macropoint),
+ * info[2] = m (constraint rows per cell, including inactive ones),
+ * info[3] = L, info[4..4+L) = number of macropoints of each level,
+ * info[4+L..] unused. info must hold at least 16 entries. */
+int mch_plan_info(const mch_plan* plan, int64_t* info);
+
+/* Level (1..L) and inherited level-1 macropoint (-1 for level 1) of every
+ * macropoint, into host arrays of length P. Synchronous. */
+int mch_hierarchy(const mch_plan* plan, int32_t* level, int32_t* parent);
+
+/* Algorithm 1 steps 3-5 (Sec. 3.3): solve every cell problem, level by level,
+ * in the hierarchical form (inherited solution plus correction in V_n).
+ * kappa: [n_fine^d] f64 > 0, finite; label: [n_fine^d] u8 < n_cont.
+ * Values are not validated on the device. Asynchronous on hip_stream.
+ * Returns MCH_ENOCONV only from mch_diagnostics; here errors are launch errors. */
+int mch_solve_cells(mch_plan* plan, const double* kappa, const uint8_t* label, void* hip_stream);
+
+/* Effective tensors (Eq. Bs_defi with R_p = K_p): A_eff[p][a][b] =
+ * sum over fine elements e of K_p of kappa_e Phi_a|_e^T K_ref Phi_b|_e for the
+ * M local solutions of macropoint p. kappa must be the array passed to the
+ * last mch_solve_cells. A_eff: [P][M][M] f64 device array. Asynchronous.
+ * MCH_ESTALE if no forward solve has been issued on this plan. */
+int mch_effective_coeffs(mch_plan* plan, const double* kappa, double* A_eff, void* hip_stream);
+
+/* Adjoint of mch_effective_coeffs o mch_solve_cells: given gA[p][a][b] =
+ * dLoss/dA_eff[p][a][b], writes glogk[e] = dLoss/dlog(kappa_e) for every
+ * fine element (the gradient flows through the local solutions, through the
+ * inherited solutions of level-1 cells, and through the explicit kappa in the
+ * tensors). Uses the state of the most recent forward on this plan; kappa
+ * must be that forward's array. gA: [P][M][M], glogk: [n_fine^d] f64 device.
+ * Asynchronous. MCH_ESTALE if no forward solve has been issued. */
+int mch_effective_coeffs_backward(mch_plan* plan, const double* kappa, const double* gA,
+                                  double* glogk, void* hip_stream);
+
+/* Test hook: the full fine local solutions Phi of the listed macropoints,
+ * out[k][a][node] with node = b1 + (n_cell+1)*(b2 + (n_cell+1)*b3) over all
+ * (n_cell+1)^d cell nodes (boundary nodes are zero). cells: host array of n
+ * macropoint indices. out: device array. Asynchronous. */
+int mch_local_solutions(mch_plan* plan, const int64_t* cells, int64_t n, double* out, void* hip_stream);
+
+/* Per (macropoint, right-hand side) Krylov iteration count and final relative
+ * projected residual of the most recent forward solve, into host arrays of
+ * length P*M. Synchronous (waits for the plan's last stream). Returns
+ * MCH_ENOCONV when any solve stopped at max_iter. */
+int mch_diagnostics(const mch_plan* plan, int32_t* iters, double* resid);
+
+/* Measurement hook. mode 1 turns profiling on, 0 off; either clears the
+ * records. While on, every kernel launch of the plan is bracketed by HIP
+ * events recorded on the launch's own stream. Host-side, synchronous. */
+int mch_profile(mch_plan* plan, int32_t mode);
+
+/* With idx < 0 returns the number of profile records. Otherwise waits for
+ * record idx and writes its kernel name (NUL-terminated, at most cap bytes)
+ * and its elapsed milliseconds; returns the record count or an error. */
+int mch_profile_read(mch_plan* plan, int32_t idx, char* name, int32_t cap, double* ms);
+
+/* As mch_diagnostics, for the adjoint solves of the most recent
+ * mch_effective_coeffs_backward (zeros before the first backward). */
+int mch_adjoint_diagnostics(const mch_plan* plan, int32_t* iters, double* resid);
+
+/* Release the plan and its device scratch. NULL is allowed. */
+void mch_destroy(mch_plan* plan);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char* mch_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MCH_H */

@@ -1,0 +1,334 @@
+// 2D adjoint of the effective tensors with respect to log kappa.
+//
+// The paper gives no adjoint; it follows from the cell equations
+// (Eqs. phi_avar_corrector / phi_grad_corrector with I = 0 on level 1) and
+// Eq. Bs_defi. For a loss with G_p = dLoss/dA_eff(p), per cell
+//   Phibar_a = sum_b (G_ab + G_ba) K^{K_p} Phi_b  (+ seeds from inheriting cells),
+//   [K_n B_n^T; B_n 0][w_a; mu_a] = [P^T Phibar_a; 0],
+//   dLoss/dkappa_e += -(P w_a)|_e^T K_ref Phi_a|_e           (every element of the cell)
+//                   + sum_ab G_ab Phi_a|_e^T K_ref Phi_b|_e   (elements of K_p),
+//   Ibar_a = Phibar_a - K_h P w_a - B_h^T mu_a                (seed of the inherited cell),
+// processed from the last level down to level 1, then dLoss/dlog kappa = kappa dLoss/dkappa.
+//
+// Determinism: no floating-point atomics. Each cell writes its gradient
+// window to its own buffer, the seeds of a level-1 cell are summed over its
+// inheriting cells in a fixed order, and a gather kernel adds the windows
+// covering each fine element in a fixed order.
+#include <cstdio>
+
+#include "kernels2d.h"
+
+namespace mch {
+
+constexpr int BT = 256;
+
+// Explicit seeds on the K_p nodes and the explicit K_p gradient term.
+template <int MM>
+__global__ __launch_bounds__(BT) void k_seed2d(CellArgs a, const double* gA, double* seed_kp, double* gk) {
+  extern __shared__ double sm[];
+  const int H = a.H, Hp = H + 1;
+  double* ph = sm;                // [MM][Hp*Hp]
+  double* G = ph + MM * Hp * Hp;  // [MM*MM]
+  const int tid = threadIdx.x;
+  const int ci = blockIdx.x;
+  const int p = a.cells[ci];
+  const int k0 = (a.nc - H) / 2;
+  for (int k = tid; k < MM * Hp * Hp; k += BT) {
+    const int al = k / (Hp * Hp), nd = k % (Hp * Hp);
+    ph[k] = phi_at(a, ci, al, k0 + nd % Hp, k0 + nd / Hp);
+  }
+  for (int k = tid; k < MM * MM; k += BT) G[k] = gA[(size_t)p * MM * MM + k];
+  __syncthreads();
+  const int jx = p % a.n_macro, jy = p / a.n_macro;
+  for (int nd = tid; nd < Hp * Hp; nd += BT) {
+    const int X = nd % Hp, Y = nd / Hp;
+    double kphi[MM];
+#pragma unroll
+    for (int b = 0; b < MM; ++b) kphi[b] = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int ex = X - 1 + (q & 1), ey = Y - 1 + (q >> 1);
+      if (ex < 0 || ey < 0 || ex >= H || ey >= H) continue;
+      const double k6 = a.kappa[(size_t)(H * jy + ey) * a.n + (H * jx + ex)] * (1.0 / 6.0);
+      const int corner = (X - ex) + 2 * (Y - ey);
+#pragma unroll
+      for (int b = 0; b < MM; ++b) {
+        double v[4], y[4];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) v[d] = ph[b * Hp * Hp + (ey + (d >> 1)) * Hp + ex + (d & 1)];
+        kref6_apply(v, y);
+        kphi[b] += k6 * y[corner];
+      }
+    }
+#pragma unroll
+    for (int al = 0; al < MM; ++al) {
+      double s = 0.0;
+#pragma unroll
+      for (int b = 0; b < MM; ++b) s += (G[al * MM + b] + G[b * MM + al]) * kphi[b];
+      seed_kp[((size_t)p * MM + al) * Hp * Hp + nd] = s;
+    }
+  }
+  for (int e = tid; e < H * H; e += BT) {
+    const int ex = e % H, ey = e / H;
+    double v[MM][4], y[MM][4];
+#pragma unroll
+    for (int al = 0; al < MM; ++al) {
+#pragma unroll
+      for (int d = 0; d < 4; ++d) v[al][d] = ph[al * Hp * Hp + (ey + (d >> 1)) * Hp + ex + (d & 1)];
+      kref6_apply(v[al], y[al]);
+    }
+    double t = 0.0;
+#pragma unroll
+    for (int al = 0; al < MM; ++al)
+#pragma unroll
+      for (int b = 0; b < MM; ++b)
+        t += G[al * MM + b] * (v[al][0] * y[b][0] + v[al][1] * y[b][1] + v[al][2] * y[b][2] + v[al][3] * y[b][3]);
+    gk[(size_t)(H * jy + ey) * a.n + (H * jx + ex)] = t * (1.0 / 6.0);
+  }
+}
+
+// Per-cell gradient window: gcell[p][e] = -sum_a (P w_a)|_e^T K_ref Phi_a|_e.
+__global__ __launch_bounds__(BT) void k_grad2d(CellArgs a, const double* w, double* gcell) {
+  extern __shared__ double sm[];
+  const int nc = a.nc, nn1 = nc + 1;
+  double* phS = sm;                  // [nn1^2]
+  double* pwS = phS + nn1 * nn1;     // [nn1^2]
+  double* gS = pwS + nn1 * nn1;      // [nc^2]
+  const int tid = threadIdx.x;
+  const int ci = blockIdx.x;
+  const int p = a.cells[ci];
+  const size_t NNl = (size_t)(a.NC + 1) * (a.NC + 1);
+  for (int e = tid; e < nc * nc; e += BT) gS[e] = 0.0;
+  for (int al = 0; al < a.M; ++al) {
+    const double* wv = w + ((size_t)ci * a.M + al) * NNl;
+    for (int nd = tid; nd < nn1 * nn1; nd += BT) {
+      const int X = nd % nn1, Y = nd / nn1;
+      phS[nd] = phi_at(a, ci, al, X, Y);
+      pwS[nd] = prolong_at(wv, a.r, a.NC, X, Y);
+    }
+    __syncthreads();
+    for (int e = tid; e < nc * nc; e += BT) {
+      const int ex = e % nc, ey = e / nc;
+      double v[4], y[4];
+#pragma unroll
+      for (int d = 0; d < 4; ++d) v[d] = phS[(ey + (d >> 1)) * nn1 + ex + (d & 1)];
+      kref6_apply(v, y);
+      double t = 0.0;
+#pragma unroll
+      for (int d = 0; d < 4; ++d) t += pwS[(ey + (d >> 1)) * nn1 + ex + (d & 1)] * y[d];
+      gS[e] -= t * (1.0 / 6.0);
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < nc * nc; e += BT) gcell[(size_t)p * nc * nc + e] = gS[e];
+}
+
+struct LevelTab {
+  int r[MAX_LEVELS];
+  int NC[MAX_LEVELS];
+  const double* w[MAX_LEVELS];
+};
+
+// Seeds of level-1 cell t for right-hand side alpha: sum over its inheriting
+// cells c of Ibar_c = Phibar_c - K_h(c) P w_c - B_h(c)^T mu_c on the fine nodes.
+__global__ __launch_bounds__(BT) void k_ibar2d(CellArgs a, LevelTab lt, const int32_t* level, const int32_t* child_ptr,
+                                               const int32_t* child, const double* mu, double* seed_par) {
+  extern __shared__ double sm[];
+  const int nc = a.nc, nn1 = nc + 1, H = a.H, Hp = H + 1, m = a.m, N = a.N, s = a.s;
+  double* accS = sm;                 // [nn1^2]
+  double* pwS = accS + nn1 * nn1;    // [nn1^2]
+  double* kS = pwS + nn1 * nn1;      // [nc^2] kappa/6
+  double* cmS = kS + nc * nc;        // [m] cw * mu
+  uint8_t* labS = reinterpret_cast<uint8_t*>(cmS + m);  // [nc^2]
+  const int tid = threadIdx.x;
+  const int t = blockIdx.x / a.M, al = blockIdx.x % a.M;
+  const int k0 = (nc - H) / 2, sb = nc / s;
+  for (int nd = tid; nd < nn1 * nn1; nd += BT) accS[nd] = 0.0;
+  for (int ch = child_ptr[t]; ch < child_ptr[t + 1]; ++ch) {
+    const int p = child[ch];
+    const int l = level[p] - 1;
+    const int ci = a.slot[p];
+    const int jx = p % a.n_macro, jy = p / a.n_macro;
+    const int ox = H * jx + H / 2 - nc / 2, oy = H * jy + H / 2 - nc / 2;
+    __syncthreads();  // previous child's data fully consumed
+    for (int e = tid; e < nc * nc; e += BT) {
+      const int ex = e % nc, ey = e / nc;
+      const size_t ge = (size_t)wrapi(oy + ey, a.n) * a.n + wrapi(ox + ex, a.n);
+      kS[e] = a.kappa[ge] * (1.0 / 6.0);
+      labS[e] = a.label[ge];
+    }
+    for (int k = tid; k < m; k += BT) cmS[k] = a.cw[(size_t)p * m + k] * mu[((size_t)p * a.M + al) * m + k];
+    const double* wv = lt.w[l] + ((size_t)ci * a.M + al) * (size_t)(lt.NC[l] + 1) * (lt.NC[l] + 1);
+    for (int nd = tid; nd < nn1 * nn1; nd += BT) pwS[nd] = prolong_at(wv, lt.r[l], lt.NC[l], nd % nn1, nd / nn1);
+    __syncthreads();
+    const double* skp = a.seed_kp + ((size_t)p * a.M + al) * Hp * Hp;
+    for (int nd = tid; nd < nn1 * nn1; nd += BT) {
+      const int X = nd % nn1, Y = nd / nn1;
+      if (X < 1 || Y < 1 || X >= nc || Y >= nc) continue;
+      double kpw = 0.0, btmu = 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int ex = X - 1 + (q & 1), ey = Y - 1 + (q >> 1);
+        const int e = ey * nc + ex;
+        double v[4], y[4];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) v[d] = pwS[(ey + (d >> 1)) * nn1 + ex + (d & 1)];
+        kref6_apply(v, y);
+        kpw += kS[e] * y[(X - ex) + 2 * (Y - ey)];
+        const int lab = labS[e];
+        if (lab < N) btmu += cmS[((ey / sb) * s + ex / sb) * N + lab];
+      }
+      double pb = 0.0;
+      if (X >= k0 && Y >= k0 && X <= k0 + H && Y <= k0 + H) pb = skp[(Y - k0) * Hp + (X - k0)];
+      accS[nd] += pb - kpw - btmu;
+    }
+  }
+  __syncthreads();
+  double* dst = seed_par + ((size_t)t * a.M + al) * nn1 * nn1;
+  for (int nd = tid; nd < nn1 * nn1; nd += BT) dst[nd] = accS[nd];
+}
+
+MCH_DEV int floordiv(int a, int b) {
+  int q = a / b;
+  return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
+}
+
+// glogk[e] = kappa_e * (explicit K_p term + sum of the cell windows covering e).
+__global__ void k_gather_grad2d(CellArgs a, const double* gk, const double* gcell, double* glogk) {
+  const int n = a.n, H = a.H, nc = a.nc, nm = a.n_macro;
+  const size_t total = (size_t)n * n;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int i1 = (int)(e % n), i2 = (int)(e / n);
+    const int t1 = i1 + nc / 2 - H / 2, t2 = i2 + nc / 2 - H / 2;
+    double acc = gk[e];
+    for (int j2 = floordiv(t2 - nc, H) + 1; j2 <= floordiv(t2, H); ++j2) {
+      const int a2 = t2 - H * j2;
+      const int jj2 = wrapi(j2, nm);
+      for (int j1 = floordiv(t1 - nc, H) + 1; j1 <= floordiv(t1, H); ++j1) {
+        const int a1 = t1 - H * j1;
+        const int q = wrapi(j1, nm) + nm * jj2;
+        acc += gcell[(size_t)q * nc * nc + (size_t)a2 * nc + a1];
+      }
+    }
+    glogk[e] = a.kappa[e] * acc;
+  }
+}
+
+template <typename F>
+static int set_lds(F fn, size_t lds) {
+  if (lds > 160 * 1024) return set_error(MCH_EINVAL, "kernel exceeds the LDS budget");
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return hip_check(e, "hipFuncSetAttribute");
+  }
+  return MCH_OK;
+}
+
+int launch_backward_2d(mch_plan* pl, const double* kappa, const double* gA, double* glogk, hipStream_t s) {
+  const int M = pl->M, nc = pl->cfg.n_cell, nn1 = nc + 1;
+  // 1. explicit seeds and K_p gradient term (the K_p blocks tile the domain)
+  for (int l = 0; l < pl->L; ++l) {
+    if (pl->lev[l].count == 0) continue;
+    CellArgs a = base_args(pl, kappa, pl->fwd_label, l);
+    const size_t lds = ((size_t)M * (a.H + 1) * (a.H + 1) + (size_t)M * M) * sizeof(double);
+    void (*fn)(CellArgs, const double*, double*, double*) = nullptr;
+    switch (M) {
+      case 3: fn = k_seed2d<3>; break;
+      case 6: fn = k_seed2d<6>; break;
+      case 9: fn = k_seed2d<9>; break;
+      default: return set_error(MCH_ENOTIMPL, "M");
+    }
+    int rc = set_lds(fn, lds);
+    if (rc) return rc;
+    char name[32];
+    std::snprintf(name, sizeof(name), "seed_L%d", l + 1);
+    {
+      ProfScope ps(pl, name, s);
+      hipLaunchKernelGGL(fn, dim3(a.count), dim3(BT), lds, s, a, gA, pl->d_seed_kp, pl->d_gk);
+    }
+    if ((rc = hip_check(hipGetLastError(), "launch k_seed2d"))) return rc;
+  }
+  const size_t lds_grad = ((size_t)2 * nn1 * nn1 + (size_t)nc * nc) * sizeof(double);
+  {
+    int rc = set_lds(k_grad2d, lds_grad);
+    if (rc) return rc;
+  }
+  // 2. inheriting levels (they only depend on level 1): adjoint solves and gradient windows
+  for (int l = pl->L - 1; l >= 1; --l) {
+    if (pl->lev[l].count == 0) continue;
+    CellArgs a = base_args(pl, kappa, pl->fwd_label, l);
+    a.adjoint = 1;
+    a.out = pl->lev[l].d_w;
+    a.beta = pl->d_mu;
+    a.iters = pl->d_iters_adj;
+    a.resid = pl->d_resid_adj;
+    char name[32];
+    std::snprintf(name, sizeof(name), "adjsolve_L%d", l + 1);
+    int rc;
+    {
+      ProfScope ps(pl, name, s);
+      rc = launch_solve(a, pl->lev[l].shape.rpt, s);
+    }
+    if (rc) return rc;
+    CellArgs g = base_args(pl, kappa, pl->fwd_label, l);
+    std::snprintf(name, sizeof(name), "grad_L%d", l + 1);
+    {
+      ProfScope ps(pl, name, s);
+      hipLaunchKernelGGL(k_grad2d, dim3(g.count), dim3(BT), lds_grad, s, g, pl->lev[l].d_w, pl->d_gcell);
+    }
+    if ((rc = hip_check(hipGetLastError(), "launch k_grad2d"))) return rc;
+  }
+  // 3. seeds of the level-1 cells from their inheriting cells
+  const bool inherit = pl->L > 1 && pl->lev[0].count > 0 && pl->lev[0].count < pl->P;
+  if (inherit) {
+    CellArgs a = base_args(pl, kappa, pl->fwd_label, 0);
+    LevelTab lt{};
+    for (int l = 0; l < pl->L; ++l) {
+      lt.r[l] = pl->lev[l].r;
+      lt.NC[l] = pl->lev[l].NC;
+      lt.w[l] = pl->lev[l].d_w;
+    }
+    const size_t lds = ((size_t)2 * nn1 * nn1 + (size_t)nc * nc + pl->m) * sizeof(double) + (size_t)nc * nc;
+    int rc = set_lds(k_ibar2d, lds);
+    if (rc) return rc;
+    {
+      ProfScope ps(pl, "ibar", s);
+      hipLaunchKernelGGL(k_ibar2d, dim3(pl->lev[0].count * M), dim3(BT), lds, s, a, lt, pl->d_level, pl->d_child_ptr,
+                         pl->d_child, pl->d_mu, pl->d_seed_par);
+    }
+    if ((rc = hip_check(hipGetLastError(), "launch k_ibar2d"))) return rc;
+  }
+  // 4. level 1
+  if (pl->lev[0].count > 0) {
+    CellArgs a = base_args(pl, kappa, pl->fwd_label, 0);
+    a.adjoint = 1;
+    a.out = pl->lev[0].d_w;
+    a.beta = pl->d_mu;
+    a.iters = pl->d_iters_adj;
+    a.resid = pl->d_resid_adj;
+    a.seed_par = inherit ? pl->d_seed_par : nullptr;
+    int rc;
+    {
+      ProfScope ps(pl, "adjsolve_L1", s);
+      rc = launch_solve(a, pl->lev[0].shape.rpt, s);
+    }
+    if (rc) return rc;
+    CellArgs g = base_args(pl, kappa, pl->fwd_label, 0);
+    {
+      ProfScope ps(pl, "grad_L1", s);
+      hipLaunchKernelGGL(k_grad2d, dim3(g.count), dim3(BT), lds_grad, s, g, pl->lev[0].d_w, pl->d_gcell);
+    }
+    if ((rc = hip_check(hipGetLastError(), "launch k_grad2d"))) return rc;
+  }
+  // 5. gather
+  CellArgs a = base_args(pl, kappa, pl->fwd_label, 0);
+  const size_t total = (size_t)pl->n * pl->n;
+  const unsigned blocks = (unsigned)((total + 255) / 256 < 65536 ? (total + 255) / 256 : 65536);
+  {
+    ProfScope ps(pl, "gather", s);
+    hipLaunchKernelGGL(k_gather_grad2d, dim3(blocks), dim3(256), 0, s, a, pl->d_gk, pl->d_gcell, glogk);
+  }
+  return hip_check(hipGetLastError(), "launch k_gather_grad2d");
+}
+
+}  // namespace mch

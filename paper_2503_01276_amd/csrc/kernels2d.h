@@ -1,0 +1,12 @@
+// Internal declarations shared by the 2D kernel translation units.
+#pragma once
+
+#include "device_common.h"
+#include "plan.h"
+
+namespace mch {
+// Kernel arguments for the cells of level l (0-based) of a plan.
+CellArgs base_args(mch_plan* pl, const double* kappa, const uint8_t* label, int l);
+// Launch the constrained Krylov solve of every (cell, right-hand side) of a.
+int launch_solve(const CellArgs& a, int rpt, hipStream_t s);
+}  // namespace mch

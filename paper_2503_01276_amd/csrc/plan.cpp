@@ -1,0 +1,402 @@
+// Plan construction: configuration checks, the macrogrid hierarchy
+// (Sec. 3.1, Eq. defi_Sn), per-level kernel shapes, Galerkin tables for the
+// nested spaces V_n (Sec. 3.2) and device scratch.
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "plan.h"
+
+namespace mch {
+
+static thread_local std::string g_last_error;
+
+int set_error(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int hip_check(hipError_t e, const char* what) {
+  if (e == hipSuccess) return MCH_OK;
+  return set_error(MCH_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+static int ipow(int b, int e) {
+  int r = 1;
+  for (int i = 0; i < e; ++i) r *= b;
+  return r;
+}
+
+// Node rows per thread for a level's cell width. A shape is valid when the
+// band height divides the sub-block width (bands never straddle constraint
+// regions) and the block holds whole waves of at most 1024 threads. An
+// environment override MCH_RPT_<NC> lets the tuner sweep the choice.
+static bool rpt_ok(int NC, int sbw, int rpt) {
+  int t = NC * NC / rpt;
+  return rpt >= 1 && NC % rpt == 0 && sbw % rpt == 0 && t <= 1024 && t >= 64 && t % 64 == 0;
+}
+
+static int default_rpt(int NC, int sbw) {
+  int want = NC >= 64 ? 8 : 4;
+  char name[32];
+  std::snprintf(name, sizeof(name), "MCH_RPT_%d", NC);
+  if (const char* v = std::getenv(name)) want = std::atoi(v);
+  if (rpt_ok(NC, sbw, want)) return want;
+  for (int rpt : {4, 8, 2, 1, 16})
+    if (rpt_ok(NC, sbw, rpt)) return rpt;
+  return 0;
+}
+
+template <typename T>
+static int dev_alloc(mch_plan* p, T** ptr, size_t count) {
+  *ptr = nullptr;
+  if (count == 0) count = 1;
+  void* v = nullptr;
+  hipError_t e = hipMalloc(&v, count * sizeof(T));
+  if (e != hipSuccess) return hip_check(e, "hipMalloc");
+  e = hipMemset(v, 0, count * sizeof(T));
+  if (e != hipSuccess) {
+    (void)hipFree(v);
+    return hip_check(e, "hipMemset");
+  }
+  p->allocations.push_back(v);
+  *ptr = static_cast<T*>(v);
+  return MCH_OK;
+}
+
+template <typename T>
+static int upload(mch_plan* p, T** ptr, const std::vector<T>& host) {
+  int rc = dev_alloc(p, ptr, host.size());
+  if (rc) return rc;
+  if (host.empty()) return MCH_OK;
+  return hip_check(hipMemcpy(*ptr, host.data(), host.size() * sizeof(T), hipMemcpyHostToDevice), "hipMemcpy");
+}
+
+// Level of every macropoint: T_n keeps indices = o (mod eta^(L-n)) per axis,
+// o = floor(eta^(L-1)/2); the level is the smallest n with the point in T_n.
+static void build_hierarchy(mch_plan* p) {
+  const int d = p->dim, nm = p->nm, L = p->L, eta = p->cfg.eta;
+  const int g = ipow(eta, L - 1), o = g / 2;
+  p->level.assign(p->P, 0);
+  p->parent.assign(p->P, -1);
+  p->slot.assign(p->P, 0);
+  for (int q = 0; q < p->P; ++q) {
+    int j[3] = {q % nm, (q / nm) % nm, (q / (nm * nm)) % nm};
+    int lvl = L;
+    for (int n = 1; n <= L; ++n) {
+      int step = ipow(eta, L - n);
+      bool in = true;
+      for (int a = 0; a < d; ++a) in = in && (((j[a] - o) % step + step) % step == 0);
+      if (in) {
+        lvl = n;
+        break;
+      }
+    }
+    p->level[q] = lvl;
+    if (lvl > 1) {
+      int par = 0, stride = 1;
+      for (int a = 0; a < d; ++a) {
+        par += ((j[a] / g) * g + o) * stride;
+        stride *= nm;
+      }
+      p->parent[q] = par;
+    }
+  }
+  for (int n = 0; n < L; ++n) p->lev[n].cells.clear();
+  for (int q = 0; q < p->P; ++q) {
+    mch::Level& lv = p->lev[p->level[q] - 1];
+    p->slot[q] = (int32_t)lv.cells.size();
+    lv.cells.push_back(q);
+  }
+}
+
+// Coarse-element tables of the Galerkin operator for a level with ratio r:
+// fine element at position (u, v) inside a coarse element contributes
+// kappa_s * R^T K_ref R to the coarse element matrix, and rho[a] = sum of
+// R[delta][a] over its corners to the coarse constraint weights.
+static void galerkin_tables(int r, std::vector<double>& tk, std::vector<double>& tr) {
+  static const double kref[4][4] = {{4, -1, -1, -2}, {-1, 4, -2, -1}, {-1, -2, 4, -1}, {-2, -1, -1, 4}};
+  tk.assign((size_t)r * r * 16, 0.0);
+  tr.assign((size_t)r * r * 4, 0.0);
+  for (int v = 0; v < r; ++v)
+    for (int u = 0; u < r; ++u) {
+      double R[4][4];
+      for (int dlt = 0; dlt < 4; ++dlt) {
+        double xi = (u + (dlt & 1)) / (double)r, ze = (v + (dlt >> 1)) / (double)r;
+        for (int a = 0; a < 4; ++a) R[dlt][a] = ((a & 1) ? xi : 1.0 - xi) * ((a >> 1) ? ze : 1.0 - ze);
+      }
+      const int pos = u + r * v;
+      for (int a = 0; a < 4; ++a) {
+        double s = 0;
+        for (int dlt = 0; dlt < 4; ++dlt) s += R[dlt][a];
+        tr[pos * 4 + a] = s;
+        for (int b = 0; b < 4; ++b) {
+          double t = 0;
+          for (int x = 0; x < 4; ++x)
+            for (int y = 0; y < 4; ++y) t += R[x][a] * (kref[x][y] / 6.0) * R[y][b];
+          tk[pos * 16 + a * 4 + b] = t;
+        }
+      }
+    }
+}
+
+ProfScope::ProfScope(mch_plan* plan, const char* name, hipStream_t stream) : p(plan), s(stream), idx(0), on(false) {
+  if (!p || !p->profiling) return;
+  if (p->prof_used == p->prof.size()) {
+    ProfRec r;
+    if (hipEventCreate(&r.start) != hipSuccess || hipEventCreate(&r.stop) != hipSuccess) return;
+    p->prof.push_back(r);
+  }
+  idx = p->prof_used++;
+  p->prof[idx].name = name;
+  on = hipEventRecord(p->prof[idx].start, s) == hipSuccess;
+}
+
+ProfScope::~ProfScope() {
+  if (on) (void)hipEventRecord(p->prof[idx].stop, s);
+}
+
+}  // namespace mch
+
+using namespace mch;
+
+extern "C" const char* mch_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" void mch_destroy(mch_plan* plan) {
+  if (!plan) return;
+  for (auto& r : plan->prof) {
+    if (r.start) (void)hipEventDestroy(r.start);
+    if (r.stop) (void)hipEventDestroy(r.stop);
+  }
+  for (void* v : plan->allocations) (void)hipFree(v);
+  delete plan;
+}
+
+extern "C" int mch_build_levels(const mch_config* cfg, mch_plan** out) {
+  g_last_error.clear();
+  if (!cfg || !out) return set_error(MCH_EINVAL, "null argument");
+  *out = nullptr;
+  const mch_config& c = *cfg;
+  if (c.dim != 2 && c.dim != 3) return set_error(MCH_EINVAL, "dim must be 2 or 3");
+  if (c.dim == 3) return set_error(MCH_ENOTIMPL, "3D cells are not implemented in this build");
+  const int d = c.dim, n = c.n_fine[0], nm = c.n_macro[0];
+  for (int a = 0; a < d; ++a) {
+    if (c.n_fine[a] != n || c.n_macro[a] != nm) return set_error(MCH_EINVAL, "grid must be cubic (equal sizes per axis)");
+  }
+  if (n < 2 || nm < 1 || n % nm != 0) return set_error(MCH_EINVAL, "n_fine must be a positive multiple of n_macro");
+  if (!(std::fabs(c.h * n - 1.0) < 1e-12)) return set_error(MCH_EINVAL, "h must equal 1/n_fine");
+  const int H = n / nm;
+  if (H % 2 != 0) return set_error(MCH_EINVAL, "coarse block size H = n_fine/n_macro must be even");
+  if (c.levels < 1 || c.levels > MAX_LEVELS) return set_error(MCH_EINVAL, "levels out of range");
+  if (c.eta < 1) return set_error(MCH_EINVAL, "eta must be >= 1");
+  if (c.n_cont < 1 || c.n_cont > 3) return set_error(MCH_EINVAL, "n_cont must be 1..3");
+  if (c.n_sub < 1) return set_error(MCH_EINVAL, "n_sub must be >= 1");
+  if (c.interp != 0) return set_error(MCH_ENOTIMPL, "only interp = 0 (inherit the group's level-1 solution) is implemented");
+  if (c.bc != 0) return set_error(MCH_ENOTIMPL, "only bc = 0 (homogeneous Dirichlet) is implemented");
+  if (!(c.rtol > 0.0) || c.max_iter < 1) return set_error(MCH_EINVAL, "rtol must be > 0 and max_iter >= 1");
+  const int nc = c.n_cell;
+  const int gL = ipow(c.eta, c.levels - 1);
+  if (nc < 2 || nc % 2 != 0 || nc > n) return set_error(MCH_EINVAL, "n_cell must be even and at most n_fine");
+  if (nc < H) return set_error(MCH_EINVAL, "n_cell must be at least H (the cell contains K_p)");
+  if (nc % c.n_sub != 0 || (nc / c.n_sub) % gL != 0)
+    return set_error(MCH_EINVAL, "n_cell must be divisible by n_sub * eta^(L-1)");
+  if (nm % gL != 0) return set_error(MCH_EINVAL, "n_macro must be divisible by eta^(L-1)");
+
+  mch_plan* p = new mch_plan();
+  p->cfg = c;
+  p->dim = d;
+  p->n = n;
+  p->nm = nm;
+  p->H = H;
+  p->L = c.levels;
+  p->P = ipow(nm, d);
+  p->M = c.n_cont * (1 + d);
+  p->m = c.n_cont * ipow(c.n_sub, d);
+  p->nn = ipow(nc + 1, d);
+  const int coarsest = nc / gL;
+  const int free_coarsest = ipow(coarsest - 1, d);
+  if (p->m > 64) {
+    delete p;
+    return set_error(MCH_ENOTIMPL, "more than 64 constraint rows per cell");
+  }
+  if (p->m > free_coarsest) {
+    delete p;
+    return set_error(MCH_ESINGULAR, "over-constrained: " + std::to_string(c.n_cont * ipow(c.n_sub, d)) +
+                                        " constraint rows but " + std::to_string(free_coarsest) +
+                                        " free unknowns at the coarsest level");
+  }
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    delete p;
+    return set_error(MCH_EHIP, "no HIP device");
+  }
+  build_hierarchy(p);
+  int rc = MCH_OK;
+  for (int l = 0; l < p->L && rc == MCH_OK; ++l) {
+    Level& lv = p->lev[l];
+    lv.n = l + 1;
+    lv.r = ipow(c.eta, l);
+    lv.NC = nc / lv.r;
+    lv.count = (int)lv.cells.size();
+    const int sbw = nc / c.n_sub / lv.r;
+    lv.shape.NC = lv.NC;
+    lv.shape.rpt = default_rpt(lv.NC, sbw);
+    lv.shape.threads = lv.NC * lv.NC / lv.shape.rpt;
+    if (!shape_supported_2d(lv.NC, lv.shape.rpt, c.n_cont, lv.r > 1)) {
+      rc = set_error(MCH_ENOTIMPL, "no kernel instantiated for level cell width " + std::to_string(lv.NC) +
+                                       " rows/thread " + std::to_string(lv.shape.rpt) + " N=" +
+                                       std::to_string(c.n_cont));
+      break;
+    }
+    if (lv.count == 0) continue;
+    std::vector<int32_t> ps(lv.count, -1);
+    for (int k = 0; k < lv.count; ++k) {
+      int q = lv.cells[k];
+      ps[k] = (p->parent[q] >= 0) ? p->slot[p->parent[q]] : -1;
+    }
+    if ((rc = upload(p, &lv.d_cells, lv.cells))) break;
+    if ((rc = upload(p, &lv.d_pslot, ps))) break;
+    size_t vec = (l == 0) ? (size_t)p->nn : (size_t)ipow(lv.NC + 1, d);
+    if ((rc = dev_alloc(p, &lv.d_out, (size_t)lv.count * p->M * vec))) break;
+    if ((rc = dev_alloc(p, &lv.d_w, (size_t)lv.count * p->M * vec))) break;
+    if (lv.r > 1) {
+      std::vector<double> tk, tr;
+      galerkin_tables(lv.r, tk, tr);
+      if ((rc = upload(p, &lv.d_tabK, tk))) break;
+      if ((rc = upload(p, &lv.d_tabR, tr))) break;
+    }
+  }
+  const size_t P = p->P, M = p->M, m = p->m;
+  const size_t n1 = p->lev[0].count;
+  if (!rc) rc = dev_alloc(p, &p->d_cw, P * m);
+  if (!rc) rc = dev_alloc(p, &p->d_g, P * M * m);
+  if (!rc) rc = dev_alloc(p, &p->d_sinv, P * m * m);
+  if (!rc) rc = dev_alloc(p, &p->d_beta, P * M * m);
+  if (!rc) rc = dev_alloc(p, &p->d_mu, P * M * m);
+  if (!rc) rc = dev_alloc(p, &p->d_iters, P * M);
+  if (!rc) rc = dev_alloc(p, &p->d_resid, P * M);
+  if (!rc) rc = upload(p, &p->d_slot, p->slot);
+  if (!rc) rc = dev_alloc(p, &p->d_seed_kp, P * M * (size_t)ipow(H + 1, d));
+  if (!rc) rc = dev_alloc(p, &p->d_seed_par, n1 * M * (size_t)p->nn);
+  if (!rc) rc = dev_alloc(p, &p->d_gk, (size_t)ipow(n, d));
+  if (!rc) rc = dev_alloc(p, &p->d_gcell, P * (size_t)ipow(nc, d));
+  if (!rc) rc = dev_alloc(p, &p->d_iters_adj, P * M);
+  if (!rc) rc = dev_alloc(p, &p->d_resid_adj, P * M);
+  if (!rc) rc = upload(p, &p->d_level, p->level);
+  if (!rc) {
+    std::vector<int32_t> ptr(n1 + 1, 0), child;
+    for (int q = 0; q < p->P; ++q)
+      if (p->parent[q] >= 0) ptr[p->slot[p->parent[q]] + 1]++;
+    for (size_t t = 0; t < n1; ++t) ptr[t + 1] += ptr[t];
+    child.assign(ptr[n1], 0);
+    std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+    for (int q = 0; q < p->P; ++q)
+      if (p->parent[q] >= 0) child[fill[p->slot[p->parent[q]]]++] = q;
+    rc = upload(p, &p->d_child_ptr, ptr);
+    if (!rc) rc = upload(p, &p->d_child, child);
+  }
+  if (rc) {
+    mch_destroy(p);
+    return rc;
+  }
+  *out = p;
+  return MCH_OK;
+}
+
+extern "C" int mch_build_hierarchy(const mch_config* cfg, int32_t* level, int32_t* parent) {
+  g_last_error.clear();
+  if (!cfg || !level || !parent) return set_error(MCH_EINVAL, "null argument");
+  const mch_config& c = *cfg;
+  if (c.dim != 2 && c.dim != 3) return set_error(MCH_EINVAL, "dim must be 2 or 3");
+  const int nm = c.n_macro[0];
+  for (int a = 0; a < c.dim; ++a)
+    if (c.n_macro[a] != nm) return set_error(MCH_EINVAL, "n_macro must be equal on every axis");
+  if (nm < 1 || c.levels < 1 || c.levels > MAX_LEVELS || c.eta < 1)
+    return set_error(MCH_EINVAL, "bad n_macro, levels or eta");
+  if (nm % ipow(c.eta, c.levels - 1) != 0) return set_error(MCH_EINVAL, "n_macro must be divisible by eta^(L-1)");
+  mch_plan tmp;
+  tmp.cfg = c;
+  tmp.dim = c.dim;
+  tmp.nm = nm;
+  tmp.L = c.levels;
+  tmp.P = ipow(nm, c.dim);
+  build_hierarchy(&tmp);
+  std::memcpy(level, tmp.level.data(), sizeof(int32_t) * tmp.P);
+  std::memcpy(parent, tmp.parent.data(), sizeof(int32_t) * tmp.P);
+  return MCH_OK;
+}
+
+extern "C" int mch_plan_info(const mch_plan* p, int64_t* info) {
+  if (!p || !info) return set_error(MCH_EINVAL, "null argument");
+  for (int k = 0; k < 16; ++k) info[k] = 0;
+  info[0] = p->P;
+  info[1] = p->M;
+  info[2] = p->m;
+  info[3] = p->L;
+  for (int l = 0; l < p->L && 4 + l < 16; ++l) info[4 + l] = p->lev[l].count;
+  return MCH_OK;
+}
+
+extern "C" int mch_hierarchy(const mch_plan* p, int32_t* level, int32_t* parent) {
+  if (!p || !level || !parent) return set_error(MCH_EINVAL, "null argument");
+  std::memcpy(level, p->level.data(), sizeof(int32_t) * p->P);
+  std::memcpy(parent, p->parent.data(), sizeof(int32_t) * p->P);
+  return MCH_OK;
+}
+
+static int diagnostics_impl(const mch_plan* p, int32_t* iters, double* resid, bool adjoint) {
+  if (!p || !iters || !resid) return set_error(MCH_EINVAL, "null argument");
+  if (!p->forward_done) return set_error(MCH_ESTALE, "no forward solve has been issued on this plan");
+  int rc = hip_check(hipSetDevice(p->device), "hipSetDevice");
+  if (rc) return rc;
+  rc = hip_check(hipStreamSynchronize(p->last_stream), "hipStreamSynchronize");
+  if (rc) return rc;
+  size_t cnt = (size_t)p->P * p->M;
+  rc = hip_check(hipMemcpy(iters, adjoint ? p->d_iters_adj : p->d_iters, cnt * sizeof(int32_t), hipMemcpyDeviceToHost),
+                 "hipMemcpy");
+  if (rc) return rc;
+  rc = hip_check(hipMemcpy(resid, adjoint ? p->d_resid_adj : p->d_resid, cnt * sizeof(double), hipMemcpyDeviceToHost),
+                 "hipMemcpy");
+  if (rc) return rc;
+  for (size_t k = 0; k < cnt; ++k) {
+    if (iters[k] < 0) return set_error(MCH_ESINGULAR, "singular constraint Schur matrix in a cell");
+  }
+  for (size_t k = 0; k < cnt; ++k) {
+    if (iters[k] >= p->cfg.max_iter && !(resid[k] <= p->cfg.rtol))
+      return set_error(MCH_ENOCONV, "a cell solve reached max_iter before rtol");
+  }
+  return MCH_OK;
+}
+
+extern "C" int mch_diagnostics(const mch_plan* p, int32_t* iters, double* resid) {
+  return diagnostics_impl(p, iters, resid, false);
+}
+
+extern "C" int mch_adjoint_diagnostics(const mch_plan* p, int32_t* iters, double* resid) {
+  return diagnostics_impl(p, iters, resid, true);
+}
+
+extern "C" int mch_profile(mch_plan* p, int32_t mode) {
+  if (!p) return set_error(MCH_EINVAL, "null plan");
+  if (mode == 0 || mode == 1) p->profiling = mode;
+  p->prof_used = 0;
+  return MCH_OK;
+}
+
+extern "C" int mch_profile_read(mch_plan* p, int32_t idx, char* name, int32_t cap, double* ms) {
+  if (!p) return set_error(MCH_EINVAL, "null plan");
+  const int count = (int)p->prof_used;
+  if (idx < 0) return count;
+  if (idx >= count || !name || cap < 1 || !ms) return set_error(MCH_EINVAL, "bad profile record request");
+  ProfRec& r = p->prof[idx];
+  int rc = hip_check(hipEventSynchronize(r.stop), "hipEventSynchronize");
+  if (rc) return rc;
+  float t = 0.0f;
+  rc = hip_check(hipEventElapsedTime(&t, r.start, r.stop), "hipEventElapsedTime");
+  if (rc) return rc;
+  *ms = t;
+  std::snprintf(name, (size_t)cap, "%s", r.name.c_str());
+  return count;
+}

@@ -1,0 +1,111 @@
+// Host-side plan of the cell-solve library (internal header).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/mch.h"
+
+namespace mch {
+
+constexpr int MAX_LEVELS = 8;
+
+// Kernel shape chosen for one level's cells.
+struct KernelShape {
+  int NC = 0;    // cell width in level elements
+  int rpt = 0;   // node rows per thread
+  int threads = 0;
+};
+
+struct Level {
+  int n = 0;       // 1..L
+  int r = 1;       // eta^(n-1)
+  int NC = 0;      // cell width in level elements
+  int count = 0;   // macropoints on this level
+  std::vector<int32_t> cells;   // host copy
+  int32_t* d_cells = nullptr;
+  int32_t* d_pslot = nullptr;   // level-1 slot of the inherited point
+  double* d_out = nullptr;      // level 1: Phi [count][M][(nc+1)^d]; else xi [count][M][(NC+1)^d]
+  double* d_w = nullptr;        // adjoint solution, same shape as d_out
+  double* d_tabK = nullptr;     // Galerkin tables (levels >= 2)
+  double* d_tabR = nullptr;
+  KernelShape shape;
+};
+
+}  // namespace mch
+
+namespace mch {
+// One profiled launch: HIP events recorded on the launch's stream around it.
+struct ProfRec {
+  std::string name;
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+}  // namespace mch
+
+struct mch_plan {
+  mch_config cfg{};
+  int dim = 2;
+  int n = 0;        // fine elements per axis
+  int nm = 0;       // macropoints per axis
+  int H = 0;        // fine elements per coarse block
+  int P = 0;        // macropoints
+  int M = 0;        // right-hand sides per macropoint
+  int m = 0;        // constraint rows per cell
+  int L = 1;
+  int nn = 0;       // fine nodes per cell, (nc+1)^d
+  int device = 0;
+  std::vector<int32_t> level, parent, slot;  // host, per macropoint
+  mch::Level lev[mch::MAX_LEVELS];
+  // per-point device scratch
+  double* d_cw = nullptr;
+  double* d_g = nullptr;
+  double* d_sinv = nullptr;
+  double* d_beta = nullptr;
+  double* d_mu = nullptr;
+  int32_t* d_iters = nullptr;
+  double* d_resid = nullptr;
+  int32_t* d_slot = nullptr;
+  // adjoint scratch
+  double* d_seed_kp = nullptr;   // [P][M][(H+1)^d]
+  double* d_seed_par = nullptr;  // [n1][M][nn]
+  double* d_gk = nullptr;        // [n^d] explicit part of dLoss/dkappa (K_p terms)
+  double* d_gcell = nullptr;     // [P][nc^d] per-cell part of dLoss/dkappa on the cell window
+  int32_t* d_iters_adj = nullptr;
+  double* d_resid_adj = nullptr;
+  int32_t* d_level = nullptr;    // [P]
+  int32_t* d_child_ptr = nullptr;  // [n1+1] CSR of inheriting points per level-1 slot
+  int32_t* d_child = nullptr;      // [P - n1] macropoint ids
+  hipStream_t last_stream = nullptr;
+  int forward_done = 0;
+  const double* fwd_kappa = nullptr;
+  const uint8_t* fwd_label = nullptr;
+  std::vector<void*> allocations;
+  // profiling (off by default)
+  int profiling = 0;
+  std::vector<mch::ProfRec> prof;
+  size_t prof_used = 0;
+};
+
+namespace mch {
+// Brackets one kernel launch with events when the plan's profiling is on.
+struct ProfScope {
+  mch_plan* p;
+  hipStream_t s;
+  size_t idx;
+  bool on;
+  ProfScope(mch_plan* plan, const char* name, hipStream_t stream);
+  ~ProfScope();
+};
+
+int set_error(int code, const std::string& msg);
+int hip_check(hipError_t e, const char* what);
+
+// Launchers implemented in the .hip translation units.
+int launch_forward_2d(mch_plan* p, const double* kappa, const uint8_t* label, hipStream_t s);
+int launch_eff_2d(mch_plan* p, const double* kappa, double* A, hipStream_t s);
+int launch_backward_2d(mch_plan* p, const double* kappa, const double* gA, double* glogk, hipStream_t s);
+int launch_local_solutions_2d(mch_plan* p, const int64_t* cells, int64_t n, double* out, hipStream_t s);
+bool shape_supported_2d(int NC, int rpt, int N, bool galerkin);
+}  // namespace mch

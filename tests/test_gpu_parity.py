@@ -1,0 +1,101 @@
+"""Parity of the HIP path with the oracle, through the C ABI (needs an MI355X).
+
+Bars: local solutions 1e-8 relative (2-norm per cell and right-hand side),
+effective tensors 1e-9 relative (Frobenius per macropoint), constraints
+B_h Phi = g to 1e-12, integer hierarchy bit-exact.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import cells as ocells
+from paper_2503_01276_amd import workloads as W
+
+from gpu_util import A_rel_err, gpu_forward, phi_rel_err, say
+
+pytestmark = pytest.mark.gpu
+
+PHI_TOL = 1e-8
+A_TOL = 1e-9
+
+
+def _check(name, cfg, k, l, phi_cells, a_points=None, workers=None):
+    say(f"[gpu] {name}: forward on the GPU ({cfg})")
+    plan, A, Phi, it, rs, _ = gpu_forward(cfg, k, l, cells=phi_cells)
+    say(f"[gpu] {name}: iterations min/median/max {it.min()}/{int(np.median(it))}/{it.max()}, "
+        f"max resid {rs.max():.2e}")
+    pts = np.arange(cfg.n_points) if a_points is None else np.asarray(a_points)
+    need = sorted(set(int(p) for p in pts) | set(int(p) for p in phi_cells))
+    say(f"[gpu] {name}: oracle on {len(need)} cells")
+    ref = oracle.forward(cfg, k, l, points=need, workers=workers)
+    Aref = np.stack([ref.A[int(p)] for p in pts])
+    ea = A_rel_err(A[pts], Aref)
+    ep = max(phi_rel_err(Phi[p], ref.Phi[p]) for p in phi_cells) if len(phi_cells) else 0.0
+    say(f"[gpu] {name}: max A rel err {ea.max():.3e}, max Phi rel err {ep:.3e}")
+    # constraints on the GPU solutions, fine rows assembled by the oracle
+    for p in phi_cells[:8]:
+        cs = ocells.assemble_cell(cfg, k, l, int(p), int(ref.level[p]))
+        cres = np.abs(cs.Bf @ Phi[p][cs.free] - cs.g).max()
+        assert cres < 1e-12, (p, cres)
+    assert ep <= PHI_TOL, ep
+    assert ea.max() <= A_TOL, ea.max()
+    sym = np.abs(A - A.transpose(0, 2, 1)).max() / np.abs(A).max()
+    assert sym < 1e-14
+    return plan, A
+
+
+def test_hierarchy_matches_oracle():
+    from paper_2503_01276_amd import mch
+    for name in ("c1", "c2", "t2", "t3", "c5"):
+        cfg = W.PRESETS[name]
+        plan = mch.Plan(cfg) if name != "c5" else None
+        lev, par = (plan.hierarchy() if plan else mch.build_hierarchy(cfg))
+        olev = oracle.hierarchy.levels(cfg.n_macro, cfg.dim, cfg.levels, cfg.eta)
+        opar = oracle.hierarchy.parents(cfg.n_macro, cfg.dim, cfg.levels, cfg.eta)
+        assert np.array_equal(lev, olev) and np.array_equal(par, opar), name
+
+
+def test_small_hierarchical_L2_full():
+    cfg = W.PRESETS["t2"]
+    k, l = W.medium("t2")
+    _check("t2", cfg, k, l, phi_cells=list(range(cfg.n_points)), workers=1)
+
+
+def test_flat_c1_full():
+    cfg = W.PRESETS["c1"]
+    k, l = W.medium("c1")
+    _check("c1", cfg, k, l, phi_cells=list(range(cfg.n_points)), workers=1)
+
+
+def test_hierarchical_L3_small_full():
+    cfg = W.PRESETS["t3"]
+    k, l = W.medium("t3")
+    _check("t3", cfg, k, l, phi_cells=list(range(cfg.n_points)), workers=1)
+
+
+def test_hierarchical_c2_all_tensors_sampled_phi():
+    cfg = W.PRESETS["c2"]
+    k, l = W.medium("c2")
+    lev = oracle.hierarchy.levels(cfg.n_macro, 2, cfg.levels, cfg.eta)
+    par = oracle.hierarchy.parents(cfg.n_macro, 2, cfg.levels, cfg.eta)
+    t = int(np.flatnonzero(lev == 1)[5])
+    group = [t] + [int(p) for p in np.flatnonzero(par == t)]
+    sample = sorted(set(group) | set(range(0, cfg.n_points, 97)))
+    _check("c2", cfg, k, l, phi_cells=sample, workers=1)
+
+
+def test_determinism_bitwise():
+    cfg = W.PRESETS["t3"]
+    k, l = W.medium("t3")
+    _, A1, _, _, _, _ = gpu_forward(cfg, k, l)
+    _, A2, _, _, _, _ = gpu_forward(cfg, k, l)
+    assert np.array_equal(A1, A2)
+
+
+def test_L1_plan_equals_flat_bitwise():
+    # a hierarchical configuration with L = 1 runs the flat path exactly
+    cfg = W.PRESETS["t2"].replace(levels=1)
+    k, l = W.medium("t2")
+    _, A1, _, _, _, _ = gpu_forward(cfg, k, l)
+    _, A2, _, _, _, _ = gpu_forward(cfg.replace(eta=3), k, l)
+    assert np.array_equal(A1, A2)
