@@ -15,28 +15,58 @@ MCH_DEV int wrapi(int i, int n) {
   return r < 0 ? r + n : r;
 }
 
-// Sum over all 64 lanes (butterfly; every lane gets the result).
-MCH_DEV double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+// Cross-lane moves of a binary64 value with DPP (VALU, no LDS round trip).
+// Lanes whose source is outside the wave receive 0.
+template <int CTRL>
+MCH_DEV double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+MCH_DEV double readlane_f64(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+constexpr int DPP_QUAD_XOR1 = 0xB1;    // quad_perm [1,0,3,2]
+constexpr int DPP_QUAD_XOR2 = 0x4E;    // quad_perm [2,3,0,1]
+constexpr int DPP_ROW_MIRROR = 0x140;  // lane i <- 15-i within 16
+constexpr int DPP_HALF_MIRROR = 0x141; // lane i <- 7-i within 8
+constexpr int DPP_WAVE_SHL1 = 0x130;   // lane i <- lane i+1
+constexpr int DPP_WAVE_SHR1 = 0x138;   // lane i <- lane i-1
+
+// Sum over aligned groups of `width` lanes (a power of two, 1..64); every lane
+// of a group receives the group sum. Fixed order, so bitwise reproducible.
+MCH_DEV double seg_sum(double v, int width) {
+  if (width >= 2) v += dpp_f64<DPP_QUAD_XOR1>(v);
+  if (width >= 4) v += dpp_f64<DPP_QUAD_XOR2>(v);
+  if (width >= 8) v += dpp_f64<DPP_HALF_MIRROR>(v);
+  if (width >= 16) v += dpp_f64<DPP_ROW_MIRROR>(v);
+  if (width >= 32) {
+    const double r0 = readlane_f64(v, 0), r1 = readlane_f64(v, 16);
+    const double r2 = readlane_f64(v, 32), r3 = readlane_f64(v, 48);
+    if (width == 32)
+      v = ((int)(threadIdx.x & 63) < 32) ? r0 + r1 : r2 + r3;
+    else
+      v = (r0 + r1) + (r2 + r3);
+  }
   return v;
 }
 
-// Sum over aligned groups of `width` lanes (width a power of two <= 64).
-MCH_DEV double seg_sum(double v, int width) {
-  for (int o = width >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
-  return v;
-}
+// Sum over all 64 lanes; every lane gets the result.
+MCH_DEV double wave_sum(double v) { return seg_sum(v, 64); }
 
 // Value held by lane+1 (0 for the last lane of a group of `width` lanes).
 MCH_DEV double from_right(double v, int c, int width) {
-  double t = __shfl_down(v, 1, WAVE);
+  const double t = dpp_f64<DPP_WAVE_SHL1>(v);
   return (c == width - 1) ? 0.0 : t;
 }
 
 // Value held by lane-1 (0 for the first lane of a group).
 MCH_DEV double from_left(double v, int c) {
-  double t = __shfl_up(v, 1, WAVE);
+  const double t = dpp_f64<DPP_WAVE_SHR1>(v);
   return (c == 0) ? 0.0 : t;
 }
 
@@ -74,6 +104,16 @@ struct CellArgs {
   // Galerkin tables for this level: T[r*r][16] (R^T K_ref R), rho[r*r][4]
   const double* tabK;
   const double* tabR;
+  // Galerkin level data written by the setup kernel, per cell of this level:
+  // 9-point stencil per owned node [count][NC*NC][9] and constraint weights per
+  // node, side (0: element column X-1, 1: column X), part (0: element row Y-1,
+  // 1: row Y) and continuum [count][NC*NC][4][N]; inherited right-hand sides
+  // f [count][M][NC*NC] and g' [count][M][m] from the inherit kernel.
+  double* nodeW;
+  float* nodeB;
+  double* fin;
+  double* gin;
+  int J;                  // lanes per Schur row in the solve kernel
   // adjoint mode inputs
   int adjoint;
   const double* seed_kp;  // [P][M][(H+1)^2] explicit seed on the K_p nodes

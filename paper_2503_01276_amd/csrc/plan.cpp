@@ -266,6 +266,11 @@ extern "C" int mch_build_levels(const mch_config* cfg, mch_plan** out) {
       galerkin_tables(lv.r, tk, tr);
       if ((rc = upload(p, &lv.d_tabK, tk))) break;
       if ((rc = upload(p, &lv.d_tabR, tr))) break;
+      const size_t nodes = (size_t)ipow(lv.NC, d);
+      if ((rc = dev_alloc(p, &lv.d_nodeW, (size_t)lv.count * nodes * 9))) break;
+      if ((rc = dev_alloc(p, &lv.d_nodeB, (size_t)lv.count * nodes * 4 * c.n_cont))) break;
+      if ((rc = dev_alloc(p, &lv.d_fin, (size_t)lv.count * p->M * nodes))) break;
+      if ((rc = dev_alloc(p, &lv.d_gin, (size_t)lv.count * p->M * p->m))) break;
     }
   }
   const size_t P = p->P, M = p->M, m = p->m;

@@ -31,6 +31,10 @@ struct Level {
   double* d_w = nullptr;        // adjoint solution, same shape as d_out
   double* d_tabK = nullptr;     // Galerkin tables (levels >= 2)
   double* d_tabR = nullptr;
+  double* d_nodeW = nullptr;    // Galerkin 9-point stencils [count][NC^d][9]
+  float* d_nodeB = nullptr;     // Galerkin constraint weights [count][NC^d][4][N]
+  double* d_fin = nullptr;      // inherited right-hand sides [count][M][NC^d]
+  double* d_gin = nullptr;      // [count][M][m]
   KernelShape shape;
 };
 

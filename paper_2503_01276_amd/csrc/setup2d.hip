@@ -1,0 +1,437 @@
+// 2D per-cell preparation kernels for gfx950.
+//
+// k_setup2d (one workgroup per cell of a level):
+//   * constraint statistics on the fine grid: for every sub-block R_q and
+//     continuum j the element count n_qj and centroid, and the continuum
+//     centroids c_mj in K_p; row weights cw = 1/(4 n_qj) (0: inactive row) and
+//     right-hand sides g (paper Eqs. phi_avar and phi_grad, constraints
+//     normalised to averages);
+//   * for Galerkin levels (r = eta^(n-1) > 1, Sec. 3.2 with V_n a subspace of
+//     V_h): the coarse element matrices sum_s kappa_s R^T K_ref R assembled into
+//     a 9-point stencil per level node, and the constraint weights of B_n = B_h P
+//     per node, side and part (written to global memory for the solve kernel);
+//   * S = B_n D^-1 B_n^T with D = diag(K_n), and S^-1 by Cholesky.
+// k_inherit2d (levels >= 2, one workgroup per cell): the inherited
+//   right-hand sides f = -P^T K_h I and g' = g - B_h I of Eqs.
+//   phi_avar_corrector / phi_grad_corrector, I = Phi of the inherited level-1 cell.
+//
+// Every reduction runs in a fixed order (no floating-point atomics), so the
+// results are bitwise reproducible.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+
+#include "kernels2d.h"
+
+namespace mch {
+
+constexpr int SETUP_T = 256;
+
+template <int N>
+struct Quad {
+  double K[16];   // coarse element stiffness, corners in tensor order
+  double b[4][N]; // constraint weights per corner and continuum (no 1/(4 n_qj))
+};
+
+// Coarse element (EX, EY) of the level-r cell from its r^2 fine elements.
+template <int N>
+MCH_DEV void coarse_element(const CellArgs& a, int ox, int oy, int EX, int EY, Quad<N>& q) {
+#pragma unroll
+  for (int k = 0; k < 16; ++k) q.K[k] = 0.0;
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int j = 0; j < N; ++j) q.b[c][j] = 0.0;
+  const int r = a.r;
+  for (int v = 0; v < r; ++v) {
+    const int gy = wrapi(oy + EY * r + v, a.n);
+    for (int u = 0; u < r; ++u) {
+      const int gx = wrapi(ox + EX * r + u, a.n);
+      const size_t e = (size_t)gy * a.n + gx;
+      const double kap = a.kappa[e];
+      const int lab = a.label[e];
+      const int pos = u + r * v;
+      const double* tk = a.tabK + pos * 16;
+      const double* tr = a.tabR + pos * 4;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) q.K[k] += kap * tk[k];
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int j = 0; j < N; ++j) q.b[c][j] += (lab == j) ? tr[c] : 0.0;
+    }
+  }
+}
+
+template <int N>
+__global__ __launch_bounds__(SETUP_T) void k_setup2d(CellArgs a) {
+  extern __shared__ double sm[];
+  const int m = a.m, s = a.s, nc = a.nc, NC = a.NC, NCp = NC + 1, sbw = a.sbw;
+  const bool gal = a.r > 1;
+  const int R = sbw + 1;                 // node rows per constraint-pair partial
+  const int npairs = m * (m + 1) / 2;
+  double* S = sm;                        // m*m
+  double* X = S + m * m;                 // m*m
+  double* stat = X + m * m;              // (s*s+1)*N*3
+  double* wred = stat + (s * s + 1) * N * 3;  // 4*N*3
+  double* Dn = wred + (SETUP_T / 64) * N * 3; // NCp*NCp
+  double* partS = Dn + NCp * NCp;        // npairs*R
+  uint8_t* labS = reinterpret_cast<uint8_t*>(partS + npairs * R);  // fine: NC*NC
+  __shared__ int singular;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int ci = blockIdx.x;
+  const int p = a.cells[ci];
+  const int jx = p % a.n_macro, jy = p / a.n_macro;
+  const int ox = a.H * jx + a.H / 2 - nc / 2, oy = a.H * jy + a.H / 2 - nc / 2;
+  if (tid == 0) singular = 0;
+
+  // ---- constraint statistics per region (sub-blocks, then K_p) -------------
+  const int sb = nc / s;
+  for (int reg = 0; reg <= s * s; ++reg) {
+    int x0, y0, w;
+    if (reg < s * s) {
+      x0 = (reg % s) * sb;
+      y0 = (reg / s) * sb;
+      w = sb;
+    } else {
+      x0 = (nc - a.H) / 2;
+      y0 = x0;
+      w = a.H;
+    }
+    double acc[N][3];
+#pragma unroll
+    for (int j = 0; j < N; ++j) acc[j][0] = acc[j][1] = acc[j][2] = 0.0;
+    for (int k = tid; k < w * w; k += SETUP_T) {
+      const int ex = x0 + k % w, ey = y0 + k / w;
+      const int lab = a.label[(size_t)wrapi(oy + ey, a.n) * a.n + wrapi(ox + ex, a.n)];
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        if (lab == j) {
+          acc[j][0] += 1.0;
+          acc[j][1] += ex + 0.5;
+          acc[j][2] += ey + 0.5;
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        double v = wave_sum(acc[j][t]);
+        if (lane == 0) wred[(wave * N + j) * 3 + t] = v;
+      }
+    __syncthreads();
+    if (tid < N * 3) {
+      double v = 0.0;
+      for (int w2 = 0; w2 < SETUP_T / 64; ++w2) v += wred[w2 * N * 3 + tid];
+      stat[reg * N * 3 + tid] = v;
+    }
+    __syncthreads();
+  }
+  const int M = a.M;
+  double* cwp = a.cw + (size_t)p * m;
+  if (tid < m) {
+    const int k = tid, q = k / N, j = k % N;
+    const double cnt = stat[(q * N + j) * 3];
+    cwp[k] = cnt > 0.0 ? 1.0 / (4.0 * cnt) : 0.0;
+    const double ckp = stat[(s * s * N + j) * 3];
+    for (int al = 0; al < M; ++al) {
+      double v = 0.0;
+      if (cnt > 0.0) {
+        if (al < N) {
+          v = (al == j) ? 1.0 : 0.0;
+        } else {
+          const int i = (al - N) / 2, mm = (al - N) % 2;
+          if (i == j) {
+            const double xbar = stat[(q * N + j) * 3 + 1 + mm] / cnt;
+            const double cmj = ckp > 0.0 ? stat[(s * s * N + j) * 3 + 1 + mm] / ckp : nc * 0.5;
+            v = (xbar - cmj) * a.h;
+          }
+        }
+      }
+      a.g[((size_t)p * M + al) * m + k] = v;
+    }
+  }
+
+  // ---- level operator data ------------------------------------------------
+  double* nW = gal ? a.nodeW + (size_t)ci * NC * NC * 9 : nullptr;
+  float* nB = gal ? a.nodeB + (size_t)ci * NC * NC * 4 * N : nullptr;
+  if (gal) {
+    for (int k = tid; k < NC * NC * 9; k += SETUP_T) nW[k] = 0.0;
+    for (int k = tid; k < NC * NC * 4 * N; k += SETUP_T) nB[k] = 0.0f;
+    __syncthreads();
+    // four colour passes: elements of one colour share no node
+    for (int color = 0; color < 4; ++color) {
+      const int cx = color & 1, cy = color >> 1;
+      const int hx = (NC - cx + 1) / 2, hy = (NC - cy + 1) / 2;
+      for (int k = tid; k < hx * hy; k += SETUP_T) {
+        const int EX = cx + 2 * (k % hx), EY = cy + 2 * (k / hx);
+        Quad<N> qd;
+        coarse_element<N>(a, ox, oy, EX, EY, qd);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int Xn = EX + (c & 1), Yn = EY + (c >> 1);
+          if (Xn >= NC || Yn >= NC) continue;
+          const int nd = Yn * NC + Xn;
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const int dx = (b & 1) - (c & 1), dy = (b >> 1) - (c >> 1);
+            nW[nd * 9 + (dy + 1) * 3 + dx + 1] += qd.K[c * 4 + b];
+          }
+          const int side = (c & 1) ? 0 : 1;   // element left of the node -> side 0
+          const int part = (c >> 1) ? 0 : 1;  // element below the node -> part 0
+#pragma unroll
+          for (int j = 0; j < N; ++j) nB[((nd * 4) + side * 2 + part) * N + j] += (float)qd.b[c][j];
+        }
+      }
+      __syncthreads();
+    }
+    for (int k = tid; k < NCp * NCp; k += SETUP_T) {
+      const int Xn = k % NCp, Yn = k / NCp;
+      Dn[k] = (Xn >= 1 && Yn >= 1 && Xn < NC && Yn < NC) ? nW[(Yn * NC + Xn) * 9 + 4] : 1.0;
+    }
+  } else {
+    for (int e = tid; e < NC * NC; e += SETUP_T) {
+      const int EX = e % NC, EY = e / NC;
+      labS[e] = a.label[(size_t)wrapi(oy + EY, a.n) * a.n + wrapi(ox + EX, a.n)];
+    }
+    // D = 4*(((SW + SE) + NW) + NE) of kappa/6, the solve kernel's order
+    for (int k = tid; k < NCp * NCp; k += SETUP_T) {
+      const int Xn = k % NCp, Yn = k / NCp;
+      if (Xn < 1 || Yn < 1 || Xn >= NC || Yn >= NC) {
+        Dn[k] = 1.0;
+        continue;
+      }
+      auto kq = [&](int ex, int ey) {
+        return a.kappa[(size_t)wrapi(oy + ey, a.n) * a.n + wrapi(ox + ex, a.n)] * (1.0 / 6.0);
+      };
+      const double ks = kq(Xn - 1, Yn - 1) + kq(Xn, Yn - 1) + kq(Xn - 1, Yn) + kq(Xn, Yn);
+      Dn[k] = 4.0 * ks;
+    }
+  }
+  __syncthreads();
+
+  // ---- S = B_n D^-1 B_n^T --------------------------------------------------
+  // partial (pair, node row) sums, then a fixed-order sum over the rows
+  for (int item = tid; item < npairs * R; item += SETUP_T) {
+    int pr = item / R;
+    const int yy = item % R;
+    int ra = 0;
+    while (pr >= m - ra) {
+      pr -= m - ra;
+      ++ra;
+    }
+    const int rb = ra + pr;
+    const int qa = ra / N, ja = ra % N, qb = rb / N, jb = rb % N;
+    const int qax = qa % s, qay = qa / s, qbx = qb % s, qby = qb / s;
+    const double cwa = cwp[ra], cwb = cwp[rb];
+    double acc = 0.0;
+    if (abs(qax - qbx) <= 1 && abs(qay - qby) <= 1 && cwa != 0.0 && cwb != 0.0) {
+      const int X0 = max(max(qax, qbx) * sbw, 1), X1 = min((min(qax, qbx) + 1) * sbw, NC - 1);
+      const int Y0 = max(max(qay, qby) * sbw, 1), Y1 = min((min(qay, qby) + 1) * sbw, NC - 1);
+      const int Yn = Y0 + yy;
+      if (Yn <= Y1) {
+        for (int Xn = X0; Xn <= X1; ++Xn) {
+          double ba = 0.0, bb = 0.0;
+#pragma unroll
+          for (int Qd = 0; Qd < 4; ++Qd) {
+            const int EX = Xn - 1 + (Qd & 1), EY = Yn - 1 + (Qd >> 1);
+            const int qE = (EY / sbw) * s + EX / sbw;
+            double wa, wb;
+            if (!gal) {
+              const int lab = labS[EY * NC + EX];
+              wa = (lab == ja) ? 1.0 : 0.0;
+              wb = (lab == jb) ? 1.0 : 0.0;
+            } else {
+              const int side = Qd & 1, part = Qd >> 1;
+              const float* w4 = nB + ((Yn * NC + Xn) * 4 + side * 2 + part) * N;
+              wa = (double)w4[ja];
+              wb = (double)w4[jb];
+            }
+            if (qE == qa) ba += wa;
+            if (qE == qb) bb += wb;
+          }
+          acc += (cwa * ba) * (cwb * bb) * (1.0 / Dn[Yn * NCp + Xn]);
+        }
+      }
+    }
+    partS[item] = acc;
+  }
+  __syncthreads();
+  for (int pr0 = tid; pr0 < npairs; pr0 += SETUP_T) {
+    int pr = pr0, ra = 0;
+    while (pr >= m - ra) {
+      pr -= m - ra;
+      ++ra;
+    }
+    const int rb = ra + pr;
+    double acc = 0.0;
+    for (int yy = 0; yy < R; ++yy) acc += partS[pr0 * R + yy];
+    S[ra * m + rb] = acc;
+    S[rb * m + ra] = acc;
+  }
+  __syncthreads();
+
+  // ---- Cholesky S = L L^T in place, one wave; inactive rows get 1 ---------
+  if (wave == 0) {
+    for (int k = lane; k < m; k += 64)
+      if (cwp[k] == 0.0) S[k * m + k] = 1.0;
+    __builtin_amdgcn_wave_barrier();
+    for (int k = 0; k < m; ++k) {
+      const double piv = S[k * m + k];
+      if (!(piv > 0.0) && lane == 0) singular = 1;
+      const double lkk = sqrt(piv > 0.0 ? piv : 1.0);
+      __builtin_amdgcn_wave_barrier();
+      for (int i = k + 1 + lane; i < m; i += 64) S[i * m + k] /= lkk;
+      if (lane == 0) S[k * m + k] = lkk;
+      __builtin_amdgcn_wave_barrier();
+      for (int i = k + 1 + lane; i < m; i += 64) {
+        const double lik = S[i * m + k];
+        for (int jj = k + 1; jj <= i; ++jj) S[i * m + jj] -= lik * S[jj * m + k];
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+    for (int col = lane; col < m; col += 64) {
+      for (int i = 0; i < m; ++i) {
+        double v = (i == col) ? 1.0 : 0.0;
+        for (int jj = col; jj < i; ++jj) v -= S[i * m + jj] * X[jj * m + col];
+        X[i * m + col] = (i >= col) ? v / S[i * m + i] : 0.0;
+      }
+    }
+  }
+  __syncthreads();
+  const bool bad = singular != 0;
+  for (int k = tid; k < m * m; k += SETUP_T) {
+    const int i = k / m, j = k % m;
+    double v = 0.0;
+    for (int t = (i > j ? i : j); t < m; ++t) v += X[t * m + i] * X[t * m + j];
+    a.sinv[(size_t)p * m * m + k] = bad ? __builtin_nan("") : v;
+  }
+}
+
+// Inherited right-hand sides of a level >= 2 cell for every alpha:
+// f = -P^T K_h I on the owned level nodes, g' = g - B_h I.
+template <int N>
+__global__ __launch_bounds__(SETUP_T) void k_inherit2d(CellArgs a) {
+  extern __shared__ double sm[];
+  const int nc = a.nc, nn1 = nc + 1, NC = a.NC, r = a.r, m = a.m, s = a.s, sbw = a.sbw, M = a.M;
+  double* IS = sm;                    // nn1^2 inherited solution
+  double* kS = IS + nn1 * nn1;        // nc^2 kappa/6
+  double* FE = kS + nc * nc;          // NC^2 * 4 coarse-element load vectors
+  double* accq = FE + NC * NC * 4;    // NC^2 * N element sums of I per continuum
+  uint8_t* labS = reinterpret_cast<uint8_t*>(accq + NC * NC * N);  // nc^2
+  const int tid = threadIdx.x;
+  const int ci = blockIdx.x;
+  const int p = a.cells[ci];
+  const int jx = p % a.n_macro, jy = p / a.n_macro;
+  const int ox = a.H * jx + a.H / 2 - nc / 2, oy = a.H * jy + a.H / 2 - nc / 2;
+  for (int e = tid; e < nc * nc; e += SETUP_T) {
+    const size_t ge = (size_t)wrapi(oy + e / nc, a.n) * a.n + wrapi(ox + e % nc, a.n);
+    kS[e] = a.kappa[ge] * (1.0 / 6.0);
+    labS[e] = a.label[ge];
+  }
+  const double inv_r = 1.0 / r;
+  for (int al = 0; al < M; ++al) {
+    const double* I = a.phi1 + ((size_t)a.pslot[ci] * M + al) * (size_t)nn1 * nn1;
+    for (int k = tid; k < nn1 * nn1; k += SETUP_T) IS[k] = I[k];
+    __syncthreads();
+    for (int E = tid; E < NC * NC; E += SETUP_T) {
+      const int EX = E % NC, EY = E / NC;
+      double F[4] = {0.0, 0.0, 0.0, 0.0};
+      double acc[N];
+#pragma unroll
+      for (int j = 0; j < N; ++j) acc[j] = 0.0;
+      for (int v = 0; v < r; ++v)
+        for (int u = 0; u < r; ++u) {
+          const int fx = EX * r + u, fy = EY * r + v;
+          double Iv[4], y[4];
+#pragma unroll
+          for (int d = 0; d < 4; ++d) Iv[d] = IS[(fy + (d >> 1)) * nn1 + fx + (d & 1)];
+          kref6_apply(Iv, y);
+          const double k6 = kS[fy * nc + fx];
+#pragma unroll
+          for (int d = 0; d < 4; ++d) {
+            const double xi = (u + (d & 1)) * inv_r, ze = (v + (d >> 1)) * inv_r;
+            const double yd = k6 * y[d];
+            F[0] += (1.0 - xi) * (1.0 - ze) * yd;
+            F[1] += xi * (1.0 - ze) * yd;
+            F[2] += (1.0 - xi) * ze * yd;
+            F[3] += xi * ze * yd;
+          }
+          const int lab = labS[fy * nc + fx];
+          const double es = Iv[0] + Iv[1] + Iv[2] + Iv[3];
+#pragma unroll
+          for (int j = 0; j < N; ++j) acc[j] += (lab == j) ? es : 0.0;
+        }
+#pragma unroll
+      for (int d = 0; d < 4; ++d) FE[E * 4 + d] = F[d];
+#pragma unroll
+      for (int j = 0; j < N; ++j) accq[E * N + j] = acc[j];
+    }
+    __syncthreads();
+    double* fo = a.fin + ((size_t)ci * M + al) * NC * NC;
+    for (int nd = tid; nd < NC * NC; nd += SETUP_T) {
+      const int Xn = nd % NC, Yn = nd / NC;
+      double t = 0.0;
+      if (Xn >= 1 && Yn >= 1) {
+        t = FE[(Yn * NC + Xn) * 4 + 0] + FE[(Yn * NC + Xn - 1) * 4 + 1] + FE[((Yn - 1) * NC + Xn) * 4 + 2] +
+            FE[((Yn - 1) * NC + Xn - 1) * 4 + 3];
+      }
+      fo[nd] = -t;
+    }
+    for (int k = tid; k < m; k += SETUP_T) {
+      const int q = k / N, j = k % N, qx = q % s, qy = q / s;
+      double bI = 0.0;
+      for (int ey = qy * sbw; ey < (qy + 1) * sbw; ++ey)
+        for (int ex = qx * sbw; ex < (qx + 1) * sbw; ++ex) bI += accq[(ey * NC + ex) * N + j];
+      a.gin[((size_t)ci * M + al) * m + k] = a.g[((size_t)p * M + al) * m + k] - a.cw[(size_t)p * m + k] * bI;
+    }
+    __syncthreads();
+  }
+}
+
+static size_t setup_lds_bytes(const CellArgs& a) {
+  const size_t NCp = a.NC + 1, R = a.sbw + 1, npairs = (size_t)a.m * (a.m + 1) / 2;
+  size_t d = (size_t)2 * a.m * a.m + (size_t)(a.s * a.s + 1) * a.N * 3 + (SETUP_T / 64) * a.N * 3 + NCp * NCp +
+             npairs * R;
+  return d * sizeof(double) + (a.r > 1 ? 0 : (size_t)a.NC * a.NC);
+}
+
+template <typename F>
+static int lds_attr(F fn, size_t lds) {
+  if (lds > 160 * 1024) return set_error(MCH_EINVAL, "kernel exceeds the LDS budget");
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return hip_check(e, "hipFuncSetAttribute");
+  }
+  return MCH_OK;
+}
+
+int launch_setup(const CellArgs& a, hipStream_t s) {
+  const size_t lds = setup_lds_bytes(a);
+  void (*fn)(CellArgs) = nullptr;
+  if (a.N == 1) fn = k_setup2d<1>;
+  if (a.N == 2) fn = k_setup2d<2>;
+  if (a.N == 3) fn = k_setup2d<3>;
+  if (!fn) return set_error(MCH_ENOTIMPL, "n_cont");
+  int rc = lds_attr(fn, lds);
+  if (rc) return rc;
+  hipLaunchKernelGGL(fn, dim3(a.count), dim3(SETUP_T), lds, s, a);
+  return hip_check(hipGetLastError(), "launch k_setup2d");
+}
+
+int launch_inherit(const CellArgs& a, hipStream_t s) {
+  const size_t nn1 = a.nc + 1, nc = a.nc, NC = a.NC;
+  const size_t lds = (nn1 * nn1 + nc * nc + NC * NC * 4 + NC * NC * a.N) * sizeof(double) + nc * nc;
+  void (*fn)(CellArgs) = nullptr;
+  if (a.N == 1) fn = k_inherit2d<1>;
+  if (a.N == 2) fn = k_inherit2d<2>;
+  if (a.N == 3) fn = k_inherit2d<3>;
+  if (!fn) return set_error(MCH_ENOTIMPL, "n_cont");
+  int rc = lds_attr(fn, lds);
+  if (rc) return rc;
+  hipLaunchKernelGGL(fn, dim3(a.count), dim3(SETUP_T), lds, s, a);
+  return hip_check(hipGetLastError(), "launch k_inherit2d");
+}
+
+}  // namespace mch

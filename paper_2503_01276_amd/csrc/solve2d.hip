@@ -29,297 +29,19 @@
 
 namespace mch {
 
-// ---------------------------------------------------------------------------
-// Setup: per cell (one workgroup of 256 threads), on the fine grid:
-//   n_qj, centroid sums of R_q intersect continuum j and of K_p intersect j,
-//   cw[row] = 1/(4 n_qj) (0 when empty), g[alpha][row];
-// then, for the level operator, S = B_n D^-1 B_n^T and S^-1 (Cholesky).
-// ---------------------------------------------------------------------------
-
-constexpr int SETUP_T = 256;
-
-template <int N>
-struct Quad {
-  // coarse element data: stiffness (4x4) and constraint weights per corner/continuum
-  double K[16];
-  double b[4][N];
-};
-
-// Coarse element (EX, EY) of the level-r cell: Galerkin stiffness and corner
-// weights of the constraint rows (without the 1/(4 n_qj) normalisation).
-template <int N>
-MCH_DEV void coarse_element(const CellArgs& a, int ox, int oy, int EX, int EY, Quad<N>& q) {
-#pragma unroll
-  for (int k = 0; k < 16; ++k) q.K[k] = 0.0;
-#pragma unroll
-  for (int c = 0; c < 4; ++c)
-#pragma unroll
-    for (int j = 0; j < N; ++j) q.b[c][j] = 0.0;
-  const int r = a.r;
-  for (int v = 0; v < r; ++v) {
-    const int gy = wrapi(oy + EY * r + v, a.n);
-    for (int u = 0; u < r; ++u) {
-      const int gx = wrapi(ox + EX * r + u, a.n);
-      const size_t e = (size_t)gy * a.n + gx;
-      const double kap = a.kappa[e];
-      const int lab = a.label[e];
-      const int pos = u + r * v;
-      const double* tk = a.tabK + pos * 16;
-      const double* tr = a.tabR + pos * 4;
-#pragma unroll
-      for (int k = 0; k < 16; ++k) q.K[k] += kap * tk[k];
-#pragma unroll
-      for (int c = 0; c < 4; ++c)
-#pragma unroll
-        for (int j = 0; j < N; ++j) q.b[c][j] += (lab == j) ? tr[c] : 0.0;
-    }
-  }
-}
-
-template <int N>
-__global__ __launch_bounds__(SETUP_T) void k_setup2d(CellArgs a) {
-  extern __shared__ double sm[];
-  const int m = a.m, s = a.s, nc = a.nc;
-  double* S = sm;                  // m*m
-  double* X = S + m * m;           // m*m (inverse of the Cholesky factor)
-  double* stat = X + m * m;        // (s*s + 1) * N * 3 : count, sum x1, sum x2
-  double* wred = stat + (s * s + 1) * N * 3;  // SETUP_T/64 * N * 3
-  __shared__ int singular;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int ci = blockIdx.x;
-  const int p = a.cells[ci];
-  const int jx = p % a.n_macro, jy = p / a.n_macro;
-  const int ox = a.H * jx + a.H / 2 - nc / 2, oy = a.H * jy + a.H / 2 - nc / 2;
-
-  for (int k = tid; k < 2 * m * m; k += SETUP_T) S[k] = 0.0;
-  if (tid == 0) singular = 0;
-
-  // statistics per region: region < s*s is sub-block q, region s*s is K_p
-  const int sb = nc / s;
-  for (int reg = 0; reg <= s * s; ++reg) {
-    int x0, y0, w;
-    if (reg < s * s) {
-      x0 = (reg % s) * sb;
-      y0 = (reg / s) * sb;
-      w = sb;
-    } else {
-      x0 = (nc - a.H) / 2;
-      y0 = x0;
-      w = a.H;
-    }
-    double acc[N][3];
-#pragma unroll
-    for (int j = 0; j < N; ++j) acc[j][0] = acc[j][1] = acc[j][2] = 0.0;
-    for (int k = tid; k < w * w; k += SETUP_T) {
-      const int ex = x0 + k % w, ey = y0 + k / w;
-      const int lab = a.label[(size_t)wrapi(oy + ey, a.n) * a.n + wrapi(ox + ex, a.n)];
-#pragma unroll
-      for (int j = 0; j < N; ++j) {
-        if (lab == j) {
-          acc[j][0] += 1.0;
-          acc[j][1] += ex + 0.5;
-          acc[j][2] += ey + 0.5;
-        }
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < N; ++j)
-#pragma unroll
-      for (int t = 0; t < 3; ++t) {
-        double v = wave_sum(acc[j][t]);
-        if (lane == 0) wred[(wave * N + j) * 3 + t] = v;
-      }
-    __syncthreads();
-    if (tid < N * 3) {
-      double v = 0.0;
-      for (int w2 = 0; w2 < SETUP_T / 64; ++w2) v += wred[w2 * N * 3 + tid];
-      stat[reg * N * 3 + tid] = v;
-    }
-    __syncthreads();
-  }
-
-  // row weights and right-hand sides
-  const int M = a.M;
-  if (tid < m) {
-    const int k = tid, q = k / N, j = k % N;
-    const double cnt = stat[(q * N + j) * 3];
-    const double cw = cnt > 0.0 ? 1.0 / (4.0 * cnt) : 0.0;
-    a.cw[(size_t)p * m + k] = cw;
-    const double ckp = stat[(s * s * N + j) * 3];
-    for (int al = 0; al < M; ++al) {
-      double v = 0.0;
-      if (cnt > 0.0) {
-        if (al < N) {
-          v = (al == j) ? 1.0 : 0.0;
-        } else {
-          const int i = (al - N) / 2, mm = (al - N) % 2;
-          if (i == j) {
-            const double xbar = stat[(q * N + j) * 3 + 1 + mm] / cnt;
-            const double cmj = ckp > 0.0 ? stat[(s * s * N + j) * 3 + 1 + mm] / ckp : nc * 0.5;
-            v = (xbar - cmj) * a.h;
-          }
-        }
-      }
-      a.g[((size_t)p * M + al) * m + k] = v;
-    }
-  }
-  __syncthreads();
-
-  // Level data per element, and the diagonal D of K_n per level node summed
-  // in the solve kernel's order (fine: ((SW+SE)+NW)+NE of kappa/6, times 4;
-  // Galerkin: SW, NW, SE, NE corner entries), so S is formed with exactly the
-  // preconditioner the iteration applies.
-  const int NC = a.NC, sbw = a.sbw, NCp = NC + 1;
-  const bool gal = a.r > 1;
-  double* Dn = wred + (SETUP_T / 64) * N * 3;                  // [NCp*NCp]
-  double* kdS = Dn + NCp * NCp;                                 // fine: kappa/6 [NC*NC]; Galerkin: K_E diagonal [NC*NC][4]
-  float* betaS = reinterpret_cast<float*>(kdS + (gal ? NC * NC * 4 : NC * NC));  // Galerkin: [NC*NC][4][N]
-  uint8_t* labS = reinterpret_cast<uint8_t*>(betaS + (gal ? NC * NC * 4 * N : 0));  // fine: [NC*NC]
-  const double* cwp = a.cw + (size_t)p * m;
-  for (int e = tid; e < NC * NC; e += SETUP_T) {
-    const int EX = e % NC, EY = e / NC;
-    if (!gal) {
-      const size_t ge = (size_t)wrapi(oy + EY, a.n) * a.n + wrapi(ox + EX, a.n);
-      kdS[e] = a.kappa[ge] * (1.0 / 6.0);
-      labS[e] = a.label[ge];
-    } else {
-      Quad<N> qd;
-      coarse_element<N>(a, ox, oy, EX, EY, qd);
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        kdS[e * 4 + c] = qd.K[c * 4 + c];
-#pragma unroll
-        for (int j = 0; j < N; ++j) betaS[(e * 4 + c) * N + j] = (float)qd.b[c][j];
-      }
-    }
-  }
-  __syncthreads();
-  for (int k = tid; k < NCp * NCp; k += SETUP_T) {
-    const int X = k % NCp, Y = k / NCp;
-    if (X < 1 || Y < 1 || X >= NC || Y >= NC) {
-      Dn[k] = 1.0;
-      continue;
-    }
-    const int eSW = (Y - 1) * NC + X - 1, eSE = eSW + 1, eNW = Y * NC + X - 1, eNE = eNW + 1;
-    if (!gal) {
-      const double ks = kdS[eSW] + kdS[eSE] + kdS[eNW] + kdS[eNE];
-      Dn[k] = 4.0 * ks;
-    } else {
-      double d = 0.0;
-      d += kdS[eSW * 4 + 3];
-      d += kdS[eNW * 4 + 1];
-      d += kdS[eSE * 4 + 2];
-      d += kdS[eNE * 4 + 0];
-      Dn[k] = d;
-    }
-  }
-  __syncthreads();
-
-  // S = B_n D^-1 B_n^T: entry (ra, rb) summed by one thread over the free
-  // level nodes shared by the closures of the two sub-blocks, in a fixed order.
-  for (int pr = tid; pr < m * m; pr += SETUP_T) {
-    const int ra = pr / m, rb = pr % m;
-    if (rb < ra) continue;
-    const int qa = ra / N, ja = ra % N, qb = rb / N, jb = rb % N;
-    const int qax = qa % s, qay = qa / s, qbx = qb % s, qby = qb / s;
-    const double cwa = cwp[ra], cwb = cwp[rb];
-    double acc = 0.0;
-    if (abs(qax - qbx) <= 1 && abs(qay - qby) <= 1 && cwa != 0.0 && cwb != 0.0) {
-      const int X0 = max(max(qax, qbx) * sbw, 1), X1 = min((min(qax, qbx) + 1) * sbw, NC - 1);
-      const int Y0 = max(max(qay, qby) * sbw, 1), Y1 = min((min(qay, qby) + 1) * sbw, NC - 1);
-      for (int Y = Y0; Y <= Y1; ++Y)
-        for (int X = X0; X <= X1; ++X) {
-          double ba = 0.0, bb = 0.0;
-#pragma unroll
-          for (int Qd = 0; Qd < 4; ++Qd) {
-            const int EX = X - 1 + (Qd & 1), EY = Y - 1 + (Qd >> 1);
-            const int corner = 3 - Qd;
-            const int e = EY * NC + EX;
-            const int qE = (EY / sbw) * s + EX / sbw;
-            double wa, wb;
-            if (!gal) {
-              const int lab = labS[e];
-              wa = (lab == ja) ? 1.0 : 0.0;
-              wb = (lab == jb) ? 1.0 : 0.0;
-            } else {
-              wa = (double)betaS[(e * 4 + corner) * N + ja];
-              wb = (double)betaS[(e * 4 + corner) * N + jb];
-            }
-            if (qE == qa) ba += wa;
-            if (qE == qb) bb += wb;
-          }
-          acc += (cwa * ba) * (cwb * bb) * (1.0 / Dn[Y * NCp + X]);
-        }
-    }
-    S[ra * m + rb] = acc;
-    S[rb * m + ra] = acc;
-  }
-  __syncthreads();
-
-  // Cholesky S = L L^T in place (lower triangle), one wave; inactive rows get 1.
-  if (wave == 0) {
-    for (int k = lane; k < m; k += 64)
-      if (cwp[k] == 0.0) S[k * m + k] = 1.0;
-    __builtin_amdgcn_wave_barrier();
-    for (int k = 0; k < m; ++k) {
-      const double piv = S[k * m + k];
-      if (!(piv > 0.0)) {
-        if (lane == 0) singular = 1;
-      }
-      const double lkk = sqrt(piv > 0.0 ? piv : 1.0);
-      __builtin_amdgcn_wave_barrier();
-      for (int i = k + 1 + lane; i < m; i += 64) S[i * m + k] /= lkk;
-      if (lane == 0) S[k * m + k] = lkk;
-      __builtin_amdgcn_wave_barrier();
-      for (int i = k + 1 + lane; i < m; i += 64) {
-        const double lik = S[i * m + k];
-        for (int jj = k + 1; jj <= i; ++jj) S[i * m + jj] -= lik * S[jj * m + k];
-      }
-      __builtin_amdgcn_wave_barrier();
-    }
-    // X = L^-1 (lower triangular), lane = column
-    for (int col = lane; col < m; col += 64) {
-      for (int i = 0; i < m; ++i) {
-        double v = (i == col) ? 1.0 : 0.0;
-        for (int jj = col; jj < i; ++jj) v -= S[i * m + jj] * X[jj * m + col];
-        X[i * m + col] = (i >= col) ? v / S[i * m + i] : 0.0;
-      }
-    }
-  }
-  __syncthreads();
-  // S^-1 = X^T X
-  const bool bad = singular != 0;
-  for (int k = tid; k < m * m; k += SETUP_T) {
-    const int i = k / m, j = k % m;
-    double v = 0.0;
-    for (int t = (i > j ? i : j); t < m; ++t) v += X[t * m + i] * X[t * m + j];
-    a.sinv[(size_t)p * m * m + k] = bad ? __builtin_nan("") : v;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// The cell solve.
-// ---------------------------------------------------------------------------
-
 // Fine cells of width >= 64 keep kappa/6 and the iterate x in LDS instead of
-// registers (the register file cannot hold them at 4-8 nodes per lane).
+// registers (the register file cannot hold them at 8 nodes per lane).
 template <int NC, bool GAL>
 constexpr bool kBig = !GAL && NC >= 64;
 
-template <int NC, int RPT, int N, bool GAL>
-struct NodeData {
-  // fine level: kappa/6 of the quadrant elements (columns c-1, c; rows y0-1..y0+RPT-1)
-  double kq[(GAL || kBig<NC, GAL>) ? 1 : 2][(GAL || kBig<NC, GAL>) ? 1 : RPT + 1];
-  // Galerkin level: 9-point stencil per node, index (dy+1)*3 + dx+1
-  double W[GAL ? RPT : 1][GAL ? 9 : 1];
-  double Dinv[RPT];
-  // constraint weights without row normalisation: side (0: element column
-  // c-1, 1: column c), node row, continuum; lower quadrants of node row 0 on
-  // their own when the band starts a new sub-block row. The weights are sums
-  // of multiples of 1/r^2 below 2^24/r^2, hence exact in binary32.
-  float w[2][RPT][N];
-  float wlo[2][N];
-};
+// One iteration of the projected PCG needs two workgroup barriers: after the
+// fused reduction of (p.Ap, r.D^-1 r, r.D^-1 Ap, Ap.D^-1 Ap, B D^-1 r,
+// B D^-1 Ap), and after the new search direction is written to LDS. With
+// r' the projected residual, r_new = r' + alpha Ap, so both B D^-1 r_new and
+// r_new.D^-1 r_new follow from those sums without another reduction. Every
+// wave then solves the small Schur system S v = u on its own (same inputs,
+// same order, identical results), so no wave waits on a serial section.
+constexpr int ZPERIOD = 16;
 
 template <int NC, int RPT, int N, bool GAL>
 __global__ __launch_bounds__(NC* NC / RPT) void k_solve2d(CellArgs a) {
@@ -327,20 +49,19 @@ __global__ __launch_bounds__(NC* NC / RPT) void k_solve2d(CellArgs a) {
   constexpr int NW = NT / 64;
   constexpr int NB = NC / RPT;
   constexpr int PW = NC + 2;
-  extern __shared__ double smem[];
-  const int m = a.m, s = a.s, M = a.M, sbw = a.sbw;
-  double* pS = smem;                       // PW*PW (ring of zeros)
-  double* red = pS + PW * PW;              // 2*NW
-  double* part = red + 2 * NW;             // NB*2*s*N
-  double* sinvS = part + NB * 2 * s * N;   // m*m
-  double* uS = sinvS + m * m;              // m
-  double* vS = uS + m;                     // m  (v * cw)
-  double* cwS = vS + m;                    // m
-  double* scal = cwS + m;                  // 8
-  double* feS = scal + 8;                  // GAL: NC*NC*4 coarse-element load vectors
   constexpr bool BIG = kBig<NC, GAL>;
-  double* kS = scal + 8;                   // BIG: (NC+1)^2 kappa/6, ring of zeros at -1
-  double* xS = kS + (NC + 1) * (NC + 1);   // BIG: NC*NC iterate
+  extern __shared__ double smem[];
+  const int m = a.m, s = a.s, M = a.M, sbw = a.sbw, J = a.J;
+  const int MS = (m + J - 1) / J;
+  double* pS = smem;                        // PW*PW, ring of zeros
+  double* red = pS + PW * PW;               // 4*NW
+  double* part = red + 4 * NW;              // [band][vec][iy][qx][j]: NB*2*2*s*N
+  double* sinvL = part + NB * 4 * s * N;    // MS*64, lane-major S^-1
+  double* cwS = sinvL + MS * 64;            // m
+  double* uW = cwS + m;                     // NW*m per-wave right-hand side
+  double* vW = uW + NW * m;                 // NW*m per-wave v*cw
+  double* kS = vW + NW * m;                 // BIG: (NC+1)^2 kappa/6, ring of zeros at -1
+  double* xS = kS + (NC + 1) * (NC + 1);    // BIG: NC*NC iterate
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int c = tid % NC, band = tid / NC, y0 = band * RPT;
@@ -349,26 +70,32 @@ __global__ __launch_bounds__(NC* NC / RPT) void k_solve2d(CellArgs a) {
   const int jx = p % a.n_macro, jy = p / a.n_macro;
   const int ox = a.H * jx + a.H / 2 - a.nc / 2, oy = a.H * jy + a.H / 2 - a.nc / 2;
   const bool split0 = (y0 > 0) && (y0 % sbw == 0);
+  const bool anysplit = __ballot(split0) != 0;
   const int qxL = (c > 0 ? c - 1 : 0) / sbw, qxR = c / sbw;
   const int qyU = y0 / sbw, qyL = (y0 > 0 ? y0 - 1 : 0) / sbw;
+  const int nn1 = a.nc + 1;
 
   for (int k = tid; k < PW * PW; k += NT) pS[k] = 0.0;
-  for (int k = tid; k < m * m; k += NT) sinvS[k] = a.sinv[(size_t)p * m * m + k];
+  for (int k = tid; k < MS * 64; k += NT) {
+    const int t = k / 64, L = k % 64, row = L / J, col = L % J + J * t;
+    sinvL[k] = (row < m && col < m) ? a.sinv[(size_t)p * m * m + row * m + col] : 0.0;
+  }
   for (int k = tid; k < m; k += NT) cwS[k] = a.cw[(size_t)p * m + k];
 
-  NodeData<NC, RPT, N, GAL> nd;
-  double x[RPT], r[RPT], pv[RPT];
-  double f[RPT];
-
-  // ---- operator data --------------------------------------------------------
+  // ---- per-node operator data in registers --------------------------------
+  double kq[(GAL || BIG) ? 1 : 2][(GAL || BIG) ? 1 : RPT + 1];
+  double W[GAL ? RPT : 1][GAL ? 9 : 1];
+  double Dinv[RPT];
+  // Constraint weights (exact in binary32) per side, node row and continuum.
+  // Every continuum is accumulated explicitly: deriving one from the total
+  // would cancel badly, since D^-1-scaled values differ by the contrast.
+  constexpr int NJ = N;
+  float w[2][RPT][NJ];
+  float wlo[2][NJ];     // lower quadrants of node row 0 when the band starts a sub-block row
 #pragma unroll
   for (int sd = 0; sd < 2; ++sd) {
 #pragma unroll
-    for (int i = 0; i < RPT; ++i)
-#pragma unroll
-      for (int j = 0; j < N; ++j) nd.w[sd][i][j] = 0.0f;
-#pragma unroll
-    for (int j = 0; j < N; ++j) nd.wlo[sd][j] = 0.0f;
+    for (int j = 0; j < NJ; ++j) wlo[sd][j] = 0.0f;
   }
   if constexpr (!GAL) {
     int lab[2][RPT + 1];
@@ -382,7 +109,7 @@ __global__ __launch_bounds__(NC* NC / RPT) void k_solve2d(CellArgs a) {
         const size_t e = (size_t)wrapi(oy + ey, a.n) * a.n + wrapi(ox + ex, a.n);
         kl[sd][i] = ok ? a.kappa[e] * (1.0 / 6.0) : 0.0;
         lab[sd][i] = ok ? (int)a.label[e] : 255;
-        if constexpr (!BIG) nd.kq[sd][i] = kl[sd][i];
+        if constexpr (!BIG) kq[sd][i] = kl[sd][i];
       }
     if constexpr (BIG) {
       for (int k = tid; k < (NC + 1) * (NC + 1); k += NT) {
@@ -395,93 +122,54 @@ __global__ __launch_bounds__(NC* NC / RPT) void k_solve2d(CellArgs a) {
     for (int i = 0; i < RPT; ++i) {
       const bool fr = (c >= 1) && (y0 + i >= 1);
       const double ksum = kl[0][i] + kl[1][i] + kl[0][i + 1] + kl[1][i + 1];
-      nd.Dinv[i] = fr ? 1.0 / (4.0 * ksum) : 0.0;
+      Dinv[i] = fr ? 1.0 / (4.0 * ksum) : 0.0;
 #pragma unroll
       for (int sd = 0; sd < 2; ++sd)
 #pragma unroll
-        for (int j = 0; j < N; ++j) {
+        for (int j = 0; j < NJ; ++j) {
           const float up = (lab[sd][i + 1] == j) ? 1.0f : 0.0f;
           const float lo = (lab[sd][i] == j) ? 1.0f : 0.0f;
           if (i == 0 && split0) {
-            nd.w[sd][i][j] = fr ? up : 0.0f;
-            nd.wlo[sd][j] = fr ? lo : 0.0f;
+            w[sd][i][j] = fr ? up : 0.0f;
+            wlo[sd][j] = fr ? lo : 0.0f;
           } else {
-            nd.w[sd][i][j] = fr ? up + lo : 0.0f;
+            w[sd][i][j] = fr ? up + lo : 0.0f;
           }
         }
     }
   } else {
-#pragma unroll
-    for (int i = 0; i < RPT; ++i)
-#pragma unroll
-      for (int k = 0; k < 9; ++k) nd.W[i][k] = 0.0;
-#pragma unroll
-    for (int sd = 0; sd < 2; ++sd) {
-#pragma unroll
-      for (int ip = 0; ip <= RPT; ++ip) {
-        const int EX = c - 1 + sd, EY = y0 - 1 + ip;
-        if (EX < 0 || EY < 0) continue;
-        Quad<N> qd;
-        coarse_element<N>(a, ox, oy, EX, EY, qd);
-        // lower quadrant of node row ip (SW for sd=0, SE for sd=1)
-        if (ip < RPT) {
-          const int cn = sd == 0 ? 3 : 2;
-          const int ax = cn & 1, ay = cn >> 1;
-#pragma unroll
-          for (int b = 0; b < 4; ++b) {
-            const int dx = (b & 1) - ax, dy = (b >> 1) - ay;
-            nd.W[ip][(dy + 1) * 3 + dx + 1] += qd.K[cn * 4 + b];
-          }
-#pragma unroll
-          for (int j = 0; j < N; ++j) {
-            if (ip == 0 && split0)
-              nd.wlo[sd][j] += (float)qd.b[cn][j];
-            else
-              nd.w[sd][ip][j] += (float)qd.b[cn][j];
-          }
-        }
-        // upper quadrant of node row ip-1 (NW for sd=0, NE for sd=1)
-        if (ip >= 1) {
-          const int cn = sd == 0 ? 1 : 0;
-          const int ax = cn & 1, ay = cn >> 1;
-#pragma unroll
-          for (int b = 0; b < 4; ++b) {
-            const int dx = (b & 1) - ax, dy = (b >> 1) - ay;
-            nd.W[ip - 1][(dy + 1) * 3 + dx + 1] += qd.K[cn * 4 + b];
-          }
-#pragma unroll
-          for (int j = 0; j < N; ++j) nd.w[sd][ip - 1][j] += (float)qd.b[cn][j];
-        }
-      }
-    }
+    const double* nW = a.nodeW + (size_t)ci * NC * NC * 9;
+    const float* nB = a.nodeB + (size_t)ci * NC * NC * 4 * N;
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
+      const int nd = (y0 + i) * NC + c;
       const bool fr = (c >= 1) && (y0 + i >= 1);
-      nd.Dinv[i] = fr ? 1.0 / nd.W[i][4] : 0.0;
-      if (!fr) {
 #pragma unroll
-        for (int k = 0; k < 9; ++k) nd.W[i][k] = 0.0;
+      for (int k = 0; k < 9; ++k) W[i][k] = fr ? nW[nd * 9 + k] : 0.0;
+      Dinv[i] = fr ? 1.0 / W[i][4] : 0.0;
 #pragma unroll
-        for (int sd = 0; sd < 2; ++sd)
+      for (int sd = 0; sd < 2; ++sd)
 #pragma unroll
-          for (int j = 0; j < N; ++j) nd.w[sd][i][j] = 0.0f;
-        if (i == 0) {
-#pragma unroll
-          for (int sd = 0; sd < 2; ++sd)
-#pragma unroll
-            for (int j = 0; j < N; ++j) nd.wlo[sd][j] = 0.0f;
+        for (int j = 0; j < NJ; ++j) {
+          const float lo = fr ? nB[((nd * 4) + sd * 2 + 0) * N + j] : 0.0f;
+          const float up = fr ? nB[((nd * 4) + sd * 2 + 1) * N + j] : 0.0f;
+          if (i == 0 && split0) {
+            w[sd][i][j] = up;
+            wlo[sd][j] = lo;
+          } else {
+            w[sd][i][j] = up + lo;
+          }
         }
-      }
     }
   }
 
-  // ---- helpers over the band ------------------------------------------------
+  // ---- building blocks -------------------------------------------------------
   auto P_at = [&](int xx, int yy) -> double { return pS[(yy + 1) * PW + xx + 1]; };
 
-  // y = K_n v for the thread's nodes; v own values in `vv`, neighbours from pS.
+  // y = K_n v on the thread's nodes (own values in vv, neighbours from pS).
   auto apply_K = [&](const double (&vv)[RPT], double (&yv)[RPT]) {
     double Lc[RPT + 2], Rc[RPT + 2];
-    double Cb = P_at(c, y0 - 1), Ct = P_at(c, y0 + RPT);
+    const double Cb = P_at(c, y0 - 1), Ct = P_at(c, y0 + RPT);
 #pragma unroll
     for (int i = 0; i < RPT + 2; ++i) {
       Lc[i] = P_at(c - 1, y0 - 1 + i);
@@ -490,111 +178,103 @@ __global__ __launch_bounds__(NC* NC / RPT) void k_solve2d(CellArgs a) {
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       const double pC = vv[i];
-      const double pS_ = i == 0 ? Cb : vv[i - 1];
+      const double pSo = i == 0 ? Cb : vv[i - 1];
       const double pN = i == RPT - 1 ? Ct : vv[i + 1];
       if constexpr (!GAL) {
         double kSW, kSE, kNW, kNE;
         if constexpr (BIG) {
-          const double* kr0 = kS + (y0 + i) * (NC + 1) + c;  // element row y0-1+i, column c-1
+          const double* kr0 = kS + (y0 + i) * (NC + 1) + c;
           kSW = kr0[0];
           kSE = kr0[1];
           kNW = kr0[NC + 1];
           kNE = kr0[NC + 2];
         } else {
-          kSW = nd.kq[0][i];
-          kSE = nd.kq[1][i];
-          kNW = nd.kq[0][i + 1];
-          kNE = nd.kq[1][i + 1];
+          kSW = kq[0][i];
+          kSE = kq[1][i];
+          kNW = kq[0][i + 1];
+          kNE = kq[1][i + 1];
         }
         const double aS = kSW + kSE, aN = kNW + kNE, aW = kSW + kNW, aE = kSE + kNE;
         double t = 4.0 * (aS + aN) * pC;
-        t -= aS * pS_ + aN * pN + aW * Lc[i + 1] + aE * Rc[i + 1];
+        t -= aS * pSo + aN * pN + aW * Lc[i + 1] + aE * Rc[i + 1];
         t -= 2.0 * (kSW * Lc[i] + kSE * Rc[i] + kNW * Lc[i + 2] + kNE * Rc[i + 2]);
         yv[i] = t;
       } else {
-        const double* W = nd.W[i];
-        double t = W[4] * pC;
-        t += W[1] * pS_ + W[7] * pN + W[3] * Lc[i + 1] + W[5] * Rc[i + 1];
-        t += W[0] * Lc[i] + W[2] * Rc[i] + W[6] * Lc[i + 2] + W[8] * Rc[i + 2];
+        const double* Wi = W[i];
+        double t = Wi[4] * pC;
+        t += Wi[1] * pSo + Wi[7] * pN + Wi[3] * Lc[i + 1] + Wi[5] * Rc[i + 1];
+        t += Wi[0] * Lc[i] + Wi[2] * Rc[i] + Wi[6] * Lc[i + 2] + Wi[8] * Rc[i + 2];
         yv[i] = t;
       }
     }
   };
 
-  // Block sum of one value per thread into red[slot]; returns the total.
-  auto block_sum = [&](double v, int slot) -> double {
-    v = wave_sum(v);
-    if (lane == 0) red[slot * NW + wave] = v;
-    __syncthreads();
-    double t = 0.0;
+  // Band partials of B_n tv (no row normalisation) into part[band][vec].
+  auto accumulate_B = [&](const double (&tv)[RPT], int vec) {
 #pragma unroll
-    for (int w2 = 0; w2 < NW; ++w2) t += red[slot * NW + w2];
-    return t;
-  };
-
-  // Partial sums of B_n t (without the row normalisation) into `part`.
-  auto accumulate_B = [&](const double (&tv)[RPT]) {
-    double acc[2][2][N];  // side, iy (0: below the band's sub-block row), j
+    for (int j = 0; j < N; ++j) {
+      double up[2];
 #pragma unroll
-    for (int sd = 0; sd < 2; ++sd)
+      for (int sd = 0; sd < 2; ++sd) {
+        double acc = 0.0;
 #pragma unroll
-      for (int j = 0; j < N; ++j) {
-        double up = 0.0;
-#pragma unroll
-        for (int i = 0; i < RPT; ++i) up += (double)nd.w[sd][i][j] * tv[i];
-        acc[sd][1][j] = up;
-        acc[sd][0][j] = (double)nd.wlo[sd][j] * tv[0];
+        for (int i = 0; i < RPT; ++i) acc += (double)w[sd][i][j] * tv[i];
+        up[sd] = acc;
       }
-    // element column c collects side 1 of lane c and side 0 of lane c+1
-#pragma unroll
-    for (int iy = 0; iy < 2; ++iy)
-#pragma unroll
-      for (int j = 0; j < N; ++j) {
-        double v = acc[1][iy][j] + from_right(acc[0][iy][j], c, NC);
-        v = seg_sum(v, sbw);
-        if (c % sbw == 0) part[((band * 2 + iy) * s + c / sbw) * N + j] = v;
-      }
-  };
-
-  // Row k of B_n t from the band partials (called by threads k < m).
-  auto finalize_u = [&](int k) -> double {
-    const int q = k / N, j = k % N, qx = q % s, qy = q / s;
-    double u = 0.0;
-    for (int b = 0; b < NB; ++b) {
-      const int yb = b * RPT;
-      if (yb / sbw == qy) u += part[((b * 2 + 1) * s + qx) * N + j];
-      if (yb > 0 && yb % sbw == 0 && (yb - 1) / sbw == qy) u += part[((b * 2 + 0) * s + qx) * N + j];
+      // element column c collects side 1 of lane c and side 0 of lane c+1
+      const double v = seg_sum(up[1] + from_right(up[0], c, NC), sbw);
+      if (c % sbw == 0) part[(((band * 2 + vec) * 2 + 1) * s + c / sbw) * N + j] = v;
+      double vl = 0.0;
+      if (anysplit) vl = seg_sum((double)wlo[1][j] * tv[0] + from_right((double)wlo[0][j] * tv[0], c, NC), sbw);
+      if (c % sbw == 0) part[(((band * 2 + vec) * 2 + 0) * s + c / sbw) * N + j] = vl;
     }
-    return u * cwS[k];
   };
 
-  // Wave 0: v = S^-1 u (u in uS), vS = v*cw, returns v.u in lane 0 (all lanes).
-  auto schur_solve = [&](double* Vacc) -> double {
-    int J = 1;
-    while (J * 2 * m <= 64) J *= 2;
+  // Row k of B_n (vector vec) summed over the bands (fixed order), without cw.
+  auto zsum = [&](int vec, int k) -> double {
+    const int q = k / N, j = k % N, qx = q % s, qy = q / s;
+    const int b0 = qy * sbw / RPT, b1 = (qy + 1) * sbw / RPT;
+    double z = 0.0;
+#pragma unroll 4
+    for (int b = b0; b < b1; ++b) z += part[(((b * 2 + vec) * 2 + 1) * s + qx) * N + j];
+    if (b1 < NB) z += part[(((b1 * 2 + vec) * 2 + 0) * s + qx) * N + j];
+    return z;
+  };
+
+  // Per wave: v = S^-1 u for u in uW[wave]; vW[wave] = v*cw; returns v.u (all lanes)
+  // and, for the lane holding row k (lane = k*J), v_k in *vk.
+  auto wave_schur = [&](double* vk) -> double {
+    __builtin_amdgcn_wave_barrier();
     const int k = lane / J, jj = lane % J;
+    const double* u = uW + wave * m;
     double sum = 0.0;
-    if (k < m)
-      for (int j = jj; j < m; j += J) sum += sinvS[k * m + j] * uS[j];
+#pragma unroll 8
+    for (int t = 0; t < MS; ++t) {
+      const int j = jj + J * t;
+      if (j < m) sum += sinvL[t * 64 + lane] * u[j];
+    }
     sum = seg_sum(sum, J);
     double vu = 0.0;
+    *vk = 0.0;
     if (k < m && jj == 0) {
-      vS[k] = sum * cwS[k];
-      *Vacc += sum;
-      vu = sum * uS[k];
+      *vk = sum;
+      vW[wave * m + k] = sum * cwS[k];
+      vu = sum * u[k];
     }
+    __builtin_amdgcn_wave_barrier();
     return wave_sum(vu);
   };
 
-  // r -= B_n^T v (or x += D^-1 B_n^T v with sign), node-local with vS.
+  // tv += sign * B_n^T v for v*cw in vW[wave].
   auto scatter_B = [&](double (&tv)[RPT], double sign) {
+    const double* vv = vW + wave * m;
     double vs[2][2][N];
 #pragma unroll
     for (int j = 0; j < N; ++j) {
-      vs[0][1][j] = vS[(qyU * s + qxL) * N + j];
-      vs[1][1][j] = vS[(qyU * s + qxR) * N + j];
-      vs[0][0][j] = vS[(qyL * s + qxL) * N + j];
-      vs[1][0][j] = vS[(qyL * s + qxR) * N + j];
+      vs[0][1][j] = vv[(qyU * s + qxL) * N + j];
+      vs[1][1][j] = vv[(qyU * s + qxR) * N + j];
+      vs[0][0][j] = vv[(qyL * s + qxL) * N + j];
+      vs[1][0][j] = vv[(qyL * s + qxR) * N + j];
     }
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
@@ -602,92 +282,31 @@ __global__ __launch_bounds__(NC* NC / RPT) void k_solve2d(CellArgs a) {
 #pragma unroll
       for (int sd = 0; sd < 2; ++sd)
 #pragma unroll
-        for (int j = 0; j < N; ++j) t += nd.w[sd][i][j] * vs[sd][1][j];
+        for (int j = 0; j < N; ++j) t += (double)w[sd][i][j] * vs[sd][1][j];
       if (i == 0) {
 #pragma unroll
         for (int sd = 0; sd < 2; ++sd)
 #pragma unroll
-          for (int j = 0; j < N; ++j) t += nd.wlo[sd][j] * vs[sd][0][j];
+          for (int j = 0; j < N; ++j) t += (double)wlo[sd][j] * vs[sd][0][j];
       }
       tv[i] += sign * t;
     }
   };
 
-  // ---- right-hand side ------------------------------------------------------
-  double Vacc = 0.0;  // wave 0, lanes holding a row: accumulated projections
+  // ---- right-hand side -------------------------------------------------------
+  double f[RPT];
 #pragma unroll
   for (int i = 0; i < RPT; ++i) f[i] = 0.0;
-  const size_t NNl = (size_t)(NC + 1) * (NC + 1);
-  const int nn1 = (a.nc + 1);
-  const int k0 = (a.nc - a.H) / 2;  // first fine node index of K_p
-  __syncthreads();
+  const int k0 = (a.nc - a.H) / 2;  // first fine node of K_p
+  double* uw = uW + wave * m;
   if (!a.adjoint) {
     if constexpr (GAL) {
-      // inherited solution I = Phi of the level-1 point (same local coordinates)
-      const double* I = a.phi1 + ((size_t)a.pslot[ci] * M + alpha) * (size_t)(nn1 * nn1);
-      const int rr = a.r;
-      double accI[N];
+      const double* fi = a.fin + ((size_t)ci * M + alpha) * NC * NC;
 #pragma unroll
-      for (int j = 0; j < N; ++j) accI[j] = 0.0;
-      for (int i = 0; i < RPT; ++i) {
-        const int EX = c, EY = y0 + i;
-        double FE[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int v = 0; v < rr; ++v)
-          for (int u = 0; u < rr; ++u) {
-            const int fx = EX * rr + u, fy = EY * rr + v;
-            const size_t e = (size_t)wrapi(oy + fy, a.n) * a.n + wrapi(ox + fx, a.n);
-            const double k6 = a.kappa[e] * (1.0 / 6.0);
-            const int lab = a.label[e];
-            double Iv[4];
-#pragma unroll
-            for (int d = 0; d < 4; ++d) Iv[d] = I[(size_t)(fy + (d >> 1)) * nn1 + fx + (d & 1)];
-            const double y00 = k6 * (4 * Iv[0] - Iv[1] - Iv[2] - 2 * Iv[3]);
-            const double y10 = k6 * (-Iv[0] + 4 * Iv[1] - 2 * Iv[2] - Iv[3]);
-            const double y01 = k6 * (-Iv[0] - 2 * Iv[1] + 4 * Iv[2] - Iv[3]);
-            const double y11 = k6 * (-2 * Iv[0] - Iv[1] - Iv[2] + 4 * Iv[3]);
-            const double yv[4] = {y00, y10, y01, y11};
-#pragma unroll
-            for (int d = 0; d < 4; ++d) {
-              const double xi = (u + (d & 1)) / (double)rr, ze = (v + (d >> 1)) / (double)rr;
-              FE[0] += (1.0 - xi) * (1.0 - ze) * yv[d];
-              FE[1] += xi * (1.0 - ze) * yv[d];
-              FE[2] += (1.0 - xi) * ze * yv[d];
-              FE[3] += xi * ze * yv[d];
-            }
-            const double es = Iv[0] + Iv[1] + Iv[2] + Iv[3];
-#pragma unroll
-            for (int j = 0; j < N; ++j) accI[j] += (lab == j) ? es : 0.0;
-          }
-#pragma unroll
-        for (int d = 0; d < 4; ++d) feS[(EY * NC + EX) * 4 + d] = FE[d];
-      }
-      // B_h I partials: all own elements lie in sub-block (c/sbw, y0/sbw)
-#pragma unroll
-      for (int j = 0; j < N; ++j) {
-        double v = seg_sum(accI[j], sbw);
-        if (c % sbw == 0) {
-          part[((band * 2 + 1) * s + c / sbw) * N + j] = v;
-          part[((band * 2 + 0) * s + c / sbw) * N + j] = 0.0;
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int i = 0; i < RPT; ++i) {
-        const int X = c, Y = y0 + i;
-        const bool fr = X >= 1 && Y >= 1;
-        double t = feS[(Y * NC + X) * 4 + 0];
-        if (X >= 1) t += feS[(Y * NC + X - 1) * 4 + 1];
-        if (Y >= 1) t += feS[((Y - 1) * NC + X) * 4 + 2];
-        if (X >= 1 && Y >= 1) t += feS[((Y - 1) * NC + X - 1) * 4 + 3];
-        f[i] = fr ? -t : 0.0;
-      }
-      if (wave == 0) {
-        for (int k = lane; k < m; k += 64)
-          uS[k] = a.g[((size_t)p * M + alpha) * m + k] - finalize_u(k);
-      }
+      for (int i = 0; i < RPT; ++i) f[i] = fi[(y0 + i) * NC + c];
+      for (int k = lane; k < m; k += 64) uw[k] = a.gin[((size_t)ci * M + alpha) * m + k];
     } else {
-      if (wave == 0)
-        for (int k = lane; k < m; k += 64) uS[k] = a.g[((size_t)p * M + alpha) * m + k];
+      for (int k = lane; k < m; k += 64) uw[k] = a.g[((size_t)p * M + alpha) * m + k];
     }
   } else {
     // adjoint: f = P^T Phibar, g' = 0
@@ -712,70 +331,109 @@ __global__ __launch_bounds__(NC* NC / RPT) void k_solve2d(CellArgs a) {
       }
       f[i] = t;
     }
-    if (wave == 0)
-      for (int k = lane; k < m; k += 64) uS[k] = 0.0;
+    for (int k = lane; k < m; k += 64) uw[k] = 0.0;
   }
-  __syncthreads();
+  __syncthreads();  // sinvL, cwS, kS visible
 
-  // ---- feasible start: x0 = D^-1 B^T S^-1 g' --------------------------------
-  if (wave == 0) (void)schur_solve(&Vacc);
-  __syncthreads();
+  // ---- feasible start x0 = D^-1 B^T S^-1 g' ---------------------------------
+  double x[RPT], r[RPT], t[RPT], pv[RPT];
+  double Vacc = 0.0, vk = 0.0;
+  (void)wave_schur(&vk);
 #pragma unroll
   for (int i = 0; i < RPT; ++i) x[i] = 0.0;
   scatter_B(x, 1.0);
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
-    x[i] *= nd.Dinv[i];
+    x[i] *= Dinv[i];
     pS[(y0 + i + 1) * PW + c + 1] = x[i];
     if constexpr (BIG) xS[(y0 + i) * NC + c] = x[i];
   }
-  if (wave == 0 && lane < 64) Vacc = 0.0;  // x0's multiplier part is not a projection of r
   __syncthreads();
   apply_K(x, r);
-#pragma unroll
-  for (int i = 0; i < RPT; ++i) r[i] -= f[i];
-  __syncthreads();
-
-  // ---- project the initial residual -----------------------------------------
-  double t[RPT];
-  double rDr = 0.0;
+  double s_rr = 0.0;
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
-    t[i] = nd.Dinv[i] * r[i];
-    rDr += r[i] * t[i];
+    r[i] -= f[i];
+    t[i] = Dinv[i] * r[i];
+    s_rr += r[i] * t[i];
   }
-  accumulate_B(t);
-  rDr = block_sum(rDr, 0);  // includes __syncthreads (part visible)
-  if (wave == 0) {
-    for (int k = lane; k < m; k += 64) uS[k] = finalize_u(k);
-    __builtin_amdgcn_wave_barrier();
-    const double vu = schur_solve(&Vacc);
-    if (lane == 0) scal[0] = rDr - vu;
-  }
+  accumulate_B(t, 0);
+  s_rr = wave_sum(s_rr);
+  if (lane == 0) red[wave * 4] = s_rr;
   __syncthreads();
-  double rz = scal[0];
+  double rr = 0.0;
+#pragma unroll
+  for (int w2 = 0; w2 < NW; ++w2) rr += red[w2 * 4];
+  for (int k = lane; k < m; k += 64) uw[k] = cwS[k] * zsum(0, k);
+  double vu = wave_schur(&vk);
+  Vacc = vk;
+  double rz = rr - vu;
   const double rz0 = rz;
   scatter_B(r, -1.0);
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
-    pv[i] = -nd.Dinv[i] * r[i];
-    pS[(y0 + i + 1) * PW + c + 1] = pv[i];
+    t[i] = Dinv[i] * r[i];
+    pv[i] = -t[i];
   }
+  __syncthreads();  // everyone done reading pS (x0) and part
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) pS[(y0 + i + 1) * PW + c + 1] = pv[i];
   __syncthreads();
 
   const double tol2 = a.rtol * a.rtol * rz0;
   int it = 0;
-  bool done = !(rz0 > 0.0) || rz0 <= 0.0;
+  bool done = !(rz0 > 0.0);
   while (!done) {
-    // Ap and p.Ap
-    double Ap[RPT];
+    double Ap[RPT], tA[RPT];
     apply_K(pv, Ap);
-    double pAp = 0.0;
+    double s4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int i = 0; i < RPT; ++i) pAp += pv[i] * Ap[i];
-    pAp = block_sum(pAp, 0);
-    const double al = rz / pAp;
-    rDr = 0.0;
+    for (int i = 0; i < RPT; ++i) {
+      tA[i] = Dinv[i] * Ap[i];
+      s4[0] += pv[i] * Ap[i];
+      s4[1] += r[i] * t[i];
+      s4[2] += t[i] * Ap[i];
+      s4[3] += Ap[i] * tA[i];
+    }
+    // B D^-1 r' vanishes up to rounding; it is folded in every ZPERIOD
+    // iterations, which keeps the constraint residual at rounding level.
+    const bool withz0 = (it % ZPERIOD) == 0;
+    if (withz0) accumulate_B(t, 0);
+    accumulate_B(tA, 1);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double v = wave_sum(s4[q]);
+      if (lane == 0) red[wave * 4 + q] = v;
+    }
+    __syncthreads();
+    double pAp = 0.0, rrk = 0.0, rA = 0.0, AA = 0.0;
+#pragma unroll
+    for (int w2 = 0; w2 < NW; ++w2) {
+      pAp += red[w2 * 4 + 0];
+      rrk += red[w2 * 4 + 1];
+      rA += red[w2 * 4 + 2];
+      AA += red[w2 * 4 + 3];
+    }
+    const double al = rrk / pAp;
+    const double rDr = rrk + 2.0 * al * rA + al * al * AA;
+    for (int k = lane; k < m; k += 64) uw[k] = cwS[k] * ((withz0 ? zsum(0, k) : 0.0) + al * zsum(1, k));
+    vu = wave_schur(&vk);
+    Vacc += vk;
+    const double rzn = rDr - vu;
+    ++it;
+    if (rzn <= tol2 || it >= a.max_iter) {
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        if constexpr (BIG)
+          xS[(y0 + i) * NC + c] += al * pv[i];
+        else
+          x[i] += al * pv[i];
+      }
+      rz = rzn;
+      break;
+    }
+    const double be = rzn / rrk;
+    rz = rzn;
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       if constexpr (BIG)
@@ -783,49 +441,23 @@ __global__ __launch_bounds__(NC* NC / RPT) void k_solve2d(CellArgs a) {
       else
         x[i] += al * pv[i];
       r[i] += al * Ap[i];
-      t[i] = nd.Dinv[i] * r[i];
-      rDr += r[i] * t[i];
-    }
-    accumulate_B(t);
-    rDr = block_sum(rDr, 1);
-    if (wave == 0) {
-      for (int k = lane; k < m; k += 64) uS[k] = finalize_u(k);
-      __builtin_amdgcn_wave_barrier();
-      const double vu = schur_solve(&Vacc);
-      if (lane == 0) scal[1] = rDr - vu;
-    }
-    __syncthreads();
-    const double rzn = scal[1];
-    ++it;
-    if (rzn <= tol2 || it >= a.max_iter) {
-      rz = rzn;
-      break;
     }
     scatter_B(r, -1.0);
-    const double be = rzn / rz;
-    rz = rzn;
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
-      pv[i] = -nd.Dinv[i] * r[i] + be * pv[i];
+      t[i] = Dinv[i] * r[i];
+      pv[i] = -t[i] + be * pv[i];
       pS[(y0 + i + 1) * PW + c + 1] = pv[i];
     }
     __syncthreads();
   }
 
   // ---- outputs ---------------------------------------------------------------
-  double* dst;
-  size_t vec;
-  if (a.r == 1) {
-    vec = (size_t)nn1 * nn1;
-  } else {
-    vec = NNl;
-  }
-  dst = a.out + ((size_t)ci * M + alpha) * vec;
+  const size_t vec = (size_t)(NC + 1) * (NC + 1);
+  double* dst = a.out + ((size_t)ci * M + alpha) * vec;
 #pragma unroll
   for (int i = 0; i < RPT; ++i) dst[(size_t)(y0 + i) * (NC + 1) + c] = BIG ? xS[(y0 + i) * NC + c] : x[i];
   if (wave == 0) {
-    int J = 1;
-    while (J * 2 * m <= 64) J *= 2;
     const int k = lane / J, jj = lane % J;
     if (k < m && jj == 0) a.beta[((size_t)p * M + alpha) * m + k] = -Vacc;
   }
@@ -834,7 +466,6 @@ __global__ __launch_bounds__(NC* NC / RPT) void k_solve2d(CellArgs a) {
     a.resid[(size_t)p * M + alpha] = (rz0 > 0.0) ? sqrt(fmax(rz, 0.0) / rz0) : 0.0;
   }
 }
-
 // ---------------------------------------------------------------------------
 // Effective tensors: A[p][a][b] = sum_{e in K_p} kappa_e Phi_a|e^T K_ref Phi_b|e,
 // Phi = I + P xi on the fine nodes of K_p. One workgroup per cell.
@@ -935,6 +566,11 @@ CellArgs base_args(mch_plan* pl, const double* kappa, const uint8_t* label, int 
   a.out = lv.d_out;
   a.tabK = lv.d_tabK;
   a.tabR = lv.d_tabR;
+  a.nodeW = lv.d_nodeW;
+  a.nodeB = lv.d_nodeB;
+  a.fin = lv.d_fin;
+  a.gin = lv.d_gin;
+  a.J = 1;
   a.adjoint = 0;
   a.seed_kp = pl->d_seed_kp;
   a.seed_par = nullptr;
@@ -944,10 +580,16 @@ CellArgs base_args(mch_plan* pl, const double* kappa, const uint8_t* label, int 
   return a;
 }
 
+static int schur_lanes(int m) {
+  int J = 1;
+  while (J * 2 * m <= 64) J *= 2;
+  return J;
+}
+
 static size_t solve_lds_bytes(int NC, int rpt, int s, int N, int m, bool gal) {
   const int NT = NC * NC / rpt, NW = NT / 64, NB = NC / rpt, PW = NC + 2;
-  size_t d = (size_t)PW * PW + 2 * NW + (size_t)NB * 2 * s * N + (size_t)m * m + 3 * (size_t)m + 8;
-  if (gal) d += (size_t)NC * NC * 4;
+  const int J = schur_lanes(m), MS = (m + J - 1) / J;
+  size_t d = (size_t)PW * PW + 4 * NW + (size_t)NB * 4 * s * N + (size_t)MS * 64 + (size_t)m + 2 * (size_t)NW * m;
   if (!gal && NC >= 64) d += (size_t)(NC + 1) * (NC + 1) + (size_t)NC * NC;
   return d * sizeof(double);
 }
@@ -985,7 +627,9 @@ bool shape_supported_2d(int NC, int rpt, int N, bool gal) {
   return false;
 }
 
-int launch_solve(const CellArgs& a, int rpt, hipStream_t s) {
+int launch_solve(const CellArgs& a_in, int rpt, hipStream_t s) {
+  CellArgs a = a_in;
+  a.J = schur_lanes(a.m);
   const bool gal = a.r > 1;
   const size_t lds = solve_lds_bytes(a.NC, rpt, a.s, a.N, a.m, gal);
   if (lds > 160 * 1024) return set_error(MCH_EINVAL, "cell solve exceeds the LDS budget");
@@ -994,33 +638,6 @@ int launch_solve(const CellArgs& a, int rpt, hipStream_t s) {
   MCH_SHAPES(X)
 #undef X
   return set_error(MCH_ENOTIMPL, "no kernel for this cell shape");
-}
-
-static size_t setup_lds_bytes(const CellArgs& a) {
-  const size_t NC = a.NC, NCp = NC + 1;
-  size_t d = (size_t)2 * a.m * a.m + (size_t)(a.s * a.s + 1) * a.N * 3 + (SETUP_T / 64) * a.N * 3 + NCp * NCp;
-  size_t bytes;
-  if (a.r > 1)
-    bytes = (d + NC * NC * 4) * sizeof(double) + NC * NC * 4 * a.N * sizeof(float);
-  else
-    bytes = (d + NC * NC) * sizeof(double) + NC * NC;
-  return bytes;
-}
-
-static int launch_setup(const CellArgs& a, hipStream_t s) {
-  const size_t lds = setup_lds_bytes(a);
-  if (lds > 160 * 1024) return set_error(MCH_EINVAL, "setup exceeds the LDS budget");
-  void (*fn)(CellArgs) = nullptr;
-  if (a.N == 1) fn = k_setup2d<1>;
-  if (a.N == 2) fn = k_setup2d<2>;
-  if (a.N == 3) fn = k_setup2d<3>;
-  if (!fn) return set_error(MCH_ENOTIMPL, "n_cont");
-  if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return hip_check(e, "hipFuncSetAttribute");
-  }
-  hipLaunchKernelGGL(fn, dim3(a.count), dim3(SETUP_T), lds, s, a);
-  return hip_check(hipGetLastError(), "launch k_setup2d");
 }
 
 int launch_forward_2d(mch_plan* pl, const double* kappa, const uint8_t* label, hipStream_t s) {
@@ -1033,6 +650,12 @@ int launch_forward_2d(mch_plan* pl, const double* kappa, const uint8_t* label, h
       std::snprintf(name, sizeof(name), "setup_L%d", l + 1);
       ProfScope ps(pl, name, s);
       rc = launch_setup(a, s);
+    }
+    if (rc) return rc;
+    if (a.r > 1) {
+      std::snprintf(name, sizeof(name), "inherit_L%d", l + 1);
+      ProfScope ps(pl, name, s);
+      rc = launch_inherit(a, s);
     }
     if (rc) return rc;
     {
