@@ -46,6 +46,20 @@ def cpu_baseline(name: str, workers: int):
 
     cfg = W.PRESETS[name]
     k, l = W.medium(name)
+    if cfg.n_points > 4096:
+        # bounded sample: every cell of two level-1 groups, forward only
+        lev = oracle.hierarchy.levels(cfg.n_macro, cfg.dim, cfg.levels, cfg.eta)
+        par = oracle.hierarchy.parents(cfg.n_macro, cfg.dim, cfg.levels, cfg.eta)
+        l1 = np.flatnonzero(lev == 1)
+        groups = [int(l1[0]), int(l1[len(l1) // 2])]
+        pts = sorted(set(groups) | set(int(p) for p in np.flatnonzero(np.isin(par, groups))))
+        t0 = time.perf_counter()
+        oracle.forward(cfg, k, l, points=pts, workers=workers)
+        t1 = time.perf_counter()
+        solves = len(pts) * cfg.n_rhs
+        return {"value": solves / (t1 - t0), "unit": "cell-solves/s", "cores": workers, "kind": "oracle",
+                "sample": f"{len(pts)} cells of two whole level-1 groups of {name} ({solves} solves), "
+                          f"SciPy SuperLU forward only, {t1 - t0:.2f} s, one process per core"}
     kt, _ = W.medium(name, channel_factor=W.target_factor(4))
     T = oracle.stack_A(oracle.forward(cfg, kt, l, workers=workers), cfg)
     t0 = time.perf_counter()
@@ -73,6 +87,7 @@ class Runner:
         from paper_2503_01276_amd import mch
 
         self.torch = torch
+        self.stream = torch.cuda.Stream()  # non-default stream: launch sequences are captured as hipGraphs
         self.cfg = W.PRESETS[name]
         self.plan = mch.Plan(self.cfg)
         dev = torch.device("cuda:0")
@@ -100,6 +115,12 @@ class Runner:
 
     def time_steps(self, steps: int, warmup: int, profile: bool):
         torch = self.torch
+        with torch.cuda.stream(self.stream):
+            return self._time_steps(steps, warmup, profile)
+
+    def _time_steps(self, steps: int, warmup: int, profile: bool):
+        torch = self.torch
+        self.plan.profile(profile)
         for _ in range(warmup):
             self.step()
         torch.cuda.synchronize()
@@ -163,7 +184,9 @@ def main():
     run = Runner(args.workload)
     cfg, plan = run.cfg, run.plan
     ms, wall, recs = run.time_steps(args.steps, args.warmup, profile=True)
-    print(f"[bench] {args.workload}: {ms:.3f} ms/step", file=sys.stderr, flush=True)
+    print(f"[bench] {args.workload}: {ms:.3f} ms/step (eager, per-kernel events)", file=sys.stderr, flush=True)
+    ms_graph, _, _ = run.time_steps(args.steps, 1, profile=False)
+    print(f"[bench] {args.workload}: {ms_graph:.3f} ms/step (hipGraph replay)", file=sys.stderr, flush=True)
     ktab = kernel_table(recs, args.steps)
     iters, _ = plan.diagnostics()
     aiters, _ = plan.diagnostics(adjoint=True)
@@ -193,8 +216,11 @@ def main():
                                          int(aiters[lev == n].max())] for n in range(1, cfg.levels + 1)},
         "kernels": ktab,
         "wall_s": wall,
+        "ms_per_step_graph_replay": ms_graph,
     }
     flat = args.flat or ("c2flat" if args.workload == "c2" else None)
+    if flat == "none":
+        flat = None
     if flat:
         frun = Runner(flat)
         fms, _, frecs = frun.time_steps(max(3, args.steps // 4), 1, profile=True)

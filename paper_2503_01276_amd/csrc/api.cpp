@@ -6,6 +6,42 @@
 
 using namespace mch;
 
+// Replays the captured launch sequence of `g` when the arguments and stream
+// match the captured ones; otherwise captures `issue` afresh. The legacy
+// default stream cannot be captured, so calls on it (and profiled calls)
+// run eagerly.
+template <typename F>
+static int run_graph(mch_plan* p, mch_plan::Graph& g, const void* k0, const void* k1, const void* k2, hipStream_t s,
+                     F issue) {
+  if (!p->use_graphs || p->profiling || s == nullptr) return issue();
+  if (g.exec && g.stream == s && g.key[0] == k0 && g.key[1] == k1 && g.key[2] == k2)
+    return hip_check(hipGraphLaunch(g.exec, s), "hipGraphLaunch");
+  if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (g.graph) (void)hipGraphDestroy(g.graph);
+  g.exec = nullptr;
+  g.graph = nullptr;
+  int rc = hip_check(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed), "hipStreamBeginCapture");
+  if (rc) return rc;
+  const int rc_issue = issue();
+  hipGraph_t graph = nullptr;
+  rc = hip_check(hipStreamEndCapture(s, &graph), "hipStreamEndCapture");
+  if (rc_issue || rc) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc_issue ? rc_issue : rc;
+  }
+  rc = hip_check(hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+  if (rc) {
+    (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  g.graph = graph;
+  g.stream = s;
+  g.key[0] = k0;
+  g.key[1] = k1;
+  g.key[2] = k2;
+  return hip_check(hipGraphLaunch(g.exec, s), "hipGraphLaunch");
+}
+
 static int enter(mch_plan* p, void* stream, hipStream_t* s) {
   if (!p) return set_error(MCH_EINVAL, "null plan");
   int rc = hip_check(hipSetDevice(p->device), "hipSetDevice");
@@ -19,7 +55,7 @@ extern "C" int mch_solve_cells(mch_plan* p, const double* kappa, const uint8_t* 
   int rc = enter(p, stream, &s);
   if (rc) return rc;
   if (!kappa || !label) return set_error(MCH_EINVAL, "null kappa or label");
-  rc = launch_forward_2d(p, kappa, label, s);
+  rc = run_graph(p, p->g_fwd, kappa, label, nullptr, s, [&] { return launch_forward_2d(p, kappa, label, s); });
   if (rc) return rc;
   p->forward_done = 1;
   p->fwd_kappa = kappa;
@@ -34,7 +70,7 @@ extern "C" int mch_effective_coeffs(mch_plan* p, const double* kappa, double* A,
   if (rc) return rc;
   if (!kappa || !A) return set_error(MCH_EINVAL, "null kappa or A_eff");
   if (!p->forward_done) return set_error(MCH_ESTALE, "no forward solve has been issued on this plan");
-  rc = launch_eff_2d(p, kappa, A, s);
+  rc = run_graph(p, p->g_eff, kappa, A, p->fwd_label, s, [&] { return launch_eff_2d(p, kappa, A, s); });
   if (!rc) p->last_stream = s;
   return rc;
 }
@@ -46,7 +82,7 @@ extern "C" int mch_effective_coeffs_backward(mch_plan* p, const double* kappa, c
   if (rc) return rc;
   if (!kappa || !gA || !glogk) return set_error(MCH_EINVAL, "null argument");
   if (!p->forward_done) return set_error(MCH_ESTALE, "no forward solve has been issued on this plan");
-  rc = launch_backward_2d(p, kappa, gA, glogk, s);
+  rc = run_graph(p, p->g_bwd, kappa, gA, glogk, s, [&] { return launch_backward_2d(p, kappa, gA, glogk, s); });
   if (!rc) p->last_stream = s;
   return rc;
 }

@@ -224,11 +224,21 @@ static int set_lds(F fn, size_t lds) {
   return MCH_OK;
 }
 
+// Backward DAG: seeds of every level in parallel; the inheriting levels'
+// adjoint solves and gradient windows on their side streams; the level-1
+// seeds from the inheriting cells, the level-1 adjoint and the gather on s.
 int launch_backward_2d(mch_plan* pl, const double* kappa, const double* gA, double* glogk, hipStream_t s) {
   const int M = pl->M, nc = pl->cfg.n_cell, nn1 = nc + 1;
-  // 1. explicit seeds and K_p gradient term (the K_p blocks tile the domain)
-  for (int l = 0; l < pl->L; ++l) {
+  char name[32];
+  int rc = ensure_streams(pl);
+  if (!rc) rc = fork_levels(pl, s);
+  if (rc) return rc;
+  const size_t lds_grad = ((size_t)2 * nn1 * nn1 + (size_t)nc * nc) * sizeof(double);
+  rc = set_lds(k_grad2d, lds_grad);
+  if (rc) return rc;
+  for (int l = pl->L - 1; l >= 0; --l) {
     if (pl->lev[l].count == 0) continue;
+    hipStream_t t = l == 0 ? s : pl->side[l];
     CellArgs a = base_args(pl, kappa, pl->fwd_label, l);
     const size_t lds = ((size_t)M * (a.H + 1) * (a.H + 1) + (size_t)M * M) * sizeof(double);
     void (*fn)(CellArgs, const double*, double*, double*) = nullptr;
@@ -238,47 +248,37 @@ int launch_backward_2d(mch_plan* pl, const double* kappa, const double* gA, doub
       case 9: fn = k_seed2d<9>; break;
       default: return set_error(MCH_ENOTIMPL, "M");
     }
-    int rc = set_lds(fn, lds);
+    rc = set_lds(fn, lds);
     if (rc) return rc;
-    char name[32];
     std::snprintf(name, sizeof(name), "seed_L%d", l + 1);
     {
-      ProfScope ps(pl, name, s);
-      hipLaunchKernelGGL(fn, dim3(a.count), dim3(BT), lds, s, a, gA, pl->d_seed_kp, pl->d_gk);
+      ProfScope ps(pl, name, t);
+      hipLaunchKernelGGL(fn, dim3(a.count), dim3(BT), lds, t, a, gA, pl->d_seed_kp, pl->d_gk);
     }
     if ((rc = hip_check(hipGetLastError(), "launch k_seed2d"))) return rc;
-  }
-  const size_t lds_grad = ((size_t)2 * nn1 * nn1 + (size_t)nc * nc) * sizeof(double);
-  {
-    int rc = set_lds(k_grad2d, lds_grad);
-    if (rc) return rc;
-  }
-  // 2. inheriting levels (they only depend on level 1): adjoint solves and gradient windows
-  for (int l = pl->L - 1; l >= 1; --l) {
-    if (pl->lev[l].count == 0) continue;
-    CellArgs a = base_args(pl, kappa, pl->fwd_label, l);
+    if (l == 0) continue;
     a.adjoint = 1;
     a.out = pl->lev[l].d_w;
     a.beta = pl->d_mu;
     a.iters = pl->d_iters_adj;
     a.resid = pl->d_resid_adj;
-    char name[32];
     std::snprintf(name, sizeof(name), "adjsolve_L%d", l + 1);
-    int rc;
     {
-      ProfScope ps(pl, name, s);
-      rc = launch_solve(a, pl->lev[l].shape.rpt, s);
+      ProfScope ps(pl, name, t);
+      rc = launch_solve(a, pl->lev[l].shape.rpt, t);
     }
     if (rc) return rc;
     CellArgs g = base_args(pl, kappa, pl->fwd_label, l);
     std::snprintf(name, sizeof(name), "grad_L%d", l + 1);
     {
-      ProfScope ps(pl, name, s);
-      hipLaunchKernelGGL(k_grad2d, dim3(g.count), dim3(BT), lds_grad, s, g, pl->lev[l].d_w, pl->d_gcell);
+      ProfScope ps(pl, name, t);
+      hipLaunchKernelGGL(k_grad2d, dim3(g.count), dim3(BT), lds_grad, t, g, pl->lev[l].d_w, pl->d_gcell);
     }
     if ((rc = hip_check(hipGetLastError(), "launch k_grad2d"))) return rc;
   }
-  // 3. seeds of the level-1 cells from their inheriting cells
+  rc = join_levels(pl, s);
+  if (rc) return rc;
+  // seeds of the level-1 cells from their inheriting cells
   const bool inherit = pl->L > 1 && pl->lev[0].count > 0 && pl->lev[0].count < pl->P;
   if (inherit) {
     CellArgs a = base_args(pl, kappa, pl->fwd_label, 0);
@@ -289,7 +289,7 @@ int launch_backward_2d(mch_plan* pl, const double* kappa, const double* gA, doub
       lt.w[l] = pl->lev[l].d_w;
     }
     const size_t lds = ((size_t)2 * nn1 * nn1 + (size_t)nc * nc + pl->m) * sizeof(double) + (size_t)nc * nc;
-    int rc = set_lds(k_ibar2d, lds);
+    rc = set_lds(k_ibar2d, lds);
     if (rc) return rc;
     {
       ProfScope ps(pl, "ibar", s);
@@ -298,7 +298,6 @@ int launch_backward_2d(mch_plan* pl, const double* kappa, const double* gA, doub
     }
     if ((rc = hip_check(hipGetLastError(), "launch k_ibar2d"))) return rc;
   }
-  // 4. level 1
   if (pl->lev[0].count > 0) {
     CellArgs a = base_args(pl, kappa, pl->fwd_label, 0);
     a.adjoint = 1;
@@ -307,7 +306,6 @@ int launch_backward_2d(mch_plan* pl, const double* kappa, const double* gA, doub
     a.iters = pl->d_iters_adj;
     a.resid = pl->d_resid_adj;
     a.seed_par = inherit ? pl->d_seed_par : nullptr;
-    int rc;
     {
       ProfScope ps(pl, "adjsolve_L1", s);
       rc = launch_solve(a, pl->lev[0].shape.rpt, s);
@@ -320,7 +318,6 @@ int launch_backward_2d(mch_plan* pl, const double* kappa, const double* gA, doub
     }
     if ((rc = hip_check(hipGetLastError(), "launch k_grad2d"))) return rc;
   }
-  // 5. gather
   CellArgs a = base_args(pl, kappa, pl->fwd_label, 0);
   const size_t total = (size_t)pl->n * pl->n;
   const unsigned blocks = (unsigned)((total + 255) / 256 < 65536 ? (total + 255) / 256 : 65536);

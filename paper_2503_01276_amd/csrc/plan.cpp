@@ -159,6 +159,34 @@ ProfScope::~ProfScope() {
   if (on) (void)hipEventRecord(p->prof[idx].stop, s);
 }
 
+int ensure_streams(mch_plan* p) {
+  if (p->ev_fork) return MCH_OK;
+  int rc = hip_check(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming), "hipEventCreate");
+  if (!rc) rc = hip_check(hipEventCreateWithFlags(&p->ev_l1, hipEventDisableTiming), "hipEventCreate");
+  for (int l = 1; l < p->L && !rc; ++l) {
+    rc = hip_check(hipStreamCreateWithFlags(&p->side[l], hipStreamNonBlocking), "hipStreamCreate");
+    if (!rc) rc = hip_check(hipEventCreateWithFlags(&p->ev_join[l], hipEventDisableTiming), "hipEventCreate");
+  }
+  return rc;
+}
+
+int fork_levels(mch_plan* p, hipStream_t s) {
+  int rc = hip_check(hipEventRecord(p->ev_fork, s), "hipEventRecord");
+  for (int l = 1; l < p->L && !rc; ++l)
+    if (p->lev[l].count) rc = hip_check(hipStreamWaitEvent(p->side[l], p->ev_fork, 0), "hipStreamWaitEvent");
+  return rc;
+}
+
+int join_levels(mch_plan* p, hipStream_t s) {
+  int rc = MCH_OK;
+  for (int l = 1; l < p->L && !rc; ++l) {
+    if (!p->lev[l].count) continue;
+    rc = hip_check(hipEventRecord(p->ev_join[l], p->side[l]), "hipEventRecord");
+    if (!rc) rc = hip_check(hipStreamWaitEvent(s, p->ev_join[l], 0), "hipStreamWaitEvent");
+  }
+  return rc;
+}
+
 }  // namespace mch
 
 using namespace mch;
@@ -167,6 +195,17 @@ extern "C" const char* mch_last_error(void) { return g_last_error.c_str(); }
 
 extern "C" void mch_destroy(mch_plan* plan) {
   if (!plan) return;
+  (void)hipDeviceSynchronize();
+  for (auto* g : {&plan->g_fwd, &plan->g_eff, &plan->g_bwd}) {
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+  }
+  for (int l = 0; l < MAX_LEVELS; ++l) {
+    if (plan->side[l]) (void)hipStreamDestroy(plan->side[l]);
+    if (plan->ev_join[l]) (void)hipEventDestroy(plan->ev_join[l]);
+  }
+  if (plan->ev_fork) (void)hipEventDestroy(plan->ev_fork);
+  if (plan->ev_l1) (void)hipEventDestroy(plan->ev_l1);
   for (auto& r : plan->prof) {
     if (r.start) (void)hipEventDestroy(r.start);
     if (r.stop) (void)hipEventDestroy(r.stop);
@@ -228,6 +267,7 @@ extern "C" int mch_build_levels(const mch_config* cfg, mch_plan** out) {
                                         " constraint rows but " + std::to_string(free_coarsest) +
                                         " free unknowns at the coarsest level");
   }
+  if (const char* v = std::getenv("MCH_GRAPHS")) p->use_graphs = std::atoi(v) != 0;
   if (hipGetDevice(&p->device) != hipSuccess) {
     delete p;
     return set_error(MCH_EHIP, "no HIP device");

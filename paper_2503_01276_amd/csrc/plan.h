@@ -86,6 +86,19 @@ struct mch_plan {
   const double* fwd_kappa = nullptr;
   const uint8_t* fwd_label = nullptr;
   std::vector<void*> allocations;
+  // per-level side streams (default priority) and events for the level DAG:
+  // levels >= 2 depend only on level 1, so they run as parallel branches
+  hipStream_t side[mch::MAX_LEVELS] = {};
+  hipEvent_t ev_fork = nullptr, ev_l1 = nullptr;
+  hipEvent_t ev_join[mch::MAX_LEVELS] = {};
+  // captured launch sequences, replayed while the arguments are unchanged
+  struct Graph {
+    const void* key[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipStream_t stream = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+  } g_fwd, g_eff, g_bwd;
+  int use_graphs = 1;
   // profiling (off by default)
   int profiling = 0;
   std::vector<mch::ProfRec> prof;
@@ -104,6 +117,12 @@ struct ProfScope {
 };
 
 int set_error(int code, const std::string& msg);
+// Side streams/events of the level DAG (created on first use).
+int ensure_streams(mch_plan* p);
+// Fork: every side stream of levels 2..L waits for the work issued so far on s.
+int fork_levels(mch_plan* p, hipStream_t s);
+// Join: s waits for every side stream of levels 2..L.
+int join_levels(mch_plan* p, hipStream_t s);
 int hip_check(hipError_t e, const char* what);
 
 // Launchers implemented in the .hip translation units.

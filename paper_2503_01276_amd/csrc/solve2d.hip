@@ -640,37 +640,59 @@ int launch_solve(const CellArgs& a_in, int rpt, hipStream_t s) {
   return set_error(MCH_ENOTIMPL, "no kernel for this cell shape");
 }
 
+// Forward DAG: the setups of levels >= 2 need only kappa and labels and run
+// on their side streams from the start (they fill the CUs left idle by the
+// level-1 solve); each level >= 2 then waits for level 1 and runs its
+// inherit and solve kernels on its own stream, in parallel with the others.
 int launch_forward_2d(mch_plan* pl, const double* kappa, const uint8_t* label, hipStream_t s) {
   char name[32];
-  for (int l = 0; l < pl->L; ++l) {
+  int rc = ensure_streams(pl);
+  if (!rc) rc = fork_levels(pl, s);
+  for (int l = 1; l < pl->L && !rc; ++l) {
     if (pl->lev[l].count == 0) continue;
     CellArgs a = base_args(pl, kappa, label, l);
-    int rc;
+    std::snprintf(name, sizeof(name), "setup_L%d", l + 1);
+    ProfScope ps(pl, name, pl->side[l]);
+    rc = launch_setup(a, pl->side[l]);
+  }
+  if (!rc && pl->lev[0].count) {
+    CellArgs a = base_args(pl, kappa, label, 0);
     {
-      std::snprintf(name, sizeof(name), "setup_L%d", l + 1);
-      ProfScope ps(pl, name, s);
+      ProfScope ps(pl, "setup_L1", s);
       rc = launch_setup(a, s);
     }
-    if (rc) return rc;
-    if (a.r > 1) {
-      std::snprintf(name, sizeof(name), "inherit_L%d", l + 1);
-      ProfScope ps(pl, name, s);
-      rc = launch_inherit(a, s);
+    if (!rc) {
+      ProfScope ps(pl, "solve_L1", s);
+      rc = launch_solve(a, pl->lev[0].shape.rpt, s);
     }
-    if (rc) return rc;
-    {
-      std::snprintf(name, sizeof(name), "solve_L%d", l + 1);
-      ProfScope ps(pl, name, s);
-      rc = launch_solve(a, pl->lev[l].shape.rpt, s);
-    }
-    if (rc) return rc;
   }
-  return MCH_OK;
+  if (!rc) rc = hip_check(hipEventRecord(pl->ev_l1, s), "hipEventRecord");
+  for (int l = 1; l < pl->L && !rc; ++l) {
+    if (pl->lev[l].count == 0) continue;
+    hipStream_t t = pl->side[l];
+    rc = hip_check(hipStreamWaitEvent(t, pl->ev_l1, 0), "hipStreamWaitEvent");
+    CellArgs a = base_args(pl, kappa, label, l);
+    if (!rc) {
+      std::snprintf(name, sizeof(name), "inherit_L%d", l + 1);
+      ProfScope ps(pl, name, t);
+      rc = launch_inherit(a, t);
+    }
+    if (!rc) {
+      std::snprintf(name, sizeof(name), "solve_L%d", l + 1);
+      ProfScope ps(pl, name, t);
+      rc = launch_solve(a, pl->lev[l].shape.rpt, t);
+    }
+  }
+  if (!rc) rc = join_levels(pl, s);
+  return rc;
 }
 
 int launch_eff_2d(mch_plan* pl, const double* kappa, double* A, hipStream_t s) {
-  for (int l = 0; l < pl->L; ++l) {
+  int rc = ensure_streams(pl);
+  if (!rc) rc = fork_levels(pl, s);
+  for (int l = 0; l < pl->L && !rc; ++l) {
     if (pl->lev[l].count == 0) continue;
+    hipStream_t t = l == 0 ? s : pl->side[l];
     CellArgs a = base_args(pl, kappa, pl->fwd_label, l);
     const size_t lds = ((size_t)a.M * (a.H + 1) * (a.H + 1) + (EFF_T / 64) * (size_t)a.M * a.M) * sizeof(double);
     if (lds > 160 * 1024) return set_error(MCH_EINVAL, "effective-tensor kernel exceeds the LDS budget");
@@ -688,13 +710,13 @@ int launch_eff_2d(mch_plan* pl, const double* kappa, double* A, hipStream_t s) {
     char name[32];
     std::snprintf(name, sizeof(name), "eff_L%d", l + 1);
     {
-      ProfScope ps(pl, name, s);
-      hipLaunchKernelGGL(fn, dim3(a.count), dim3(EFF_T), lds, s, a, A);
+      ProfScope ps(pl, name, t);
+      hipLaunchKernelGGL(fn, dim3(a.count), dim3(EFF_T), lds, t, a, A);
     }
-    int rc = hip_check(hipGetLastError(), "launch k_eff2d");
-    if (rc) return rc;
+    rc = hip_check(hipGetLastError(), "launch k_eff2d");
   }
-  return MCH_OK;
+  if (!rc) rc = join_levels(pl, s);
+  return rc;
 }
 
 // Fine local solutions of selected cells: out[k][alpha][node] over (nc+1)^2 nodes.

@@ -136,6 +136,7 @@ class Plan:
         check(LIB.mch_plan_info(self._h, info))
         self.P, self.M, self.m, self.levels = int(info[0]), int(info[1]), int(info[2]), int(info[3])
         self.level_counts = [int(info[4 + k]) for k in range(self.levels)]
+        self.generation = 0  # bumped by every forward solve
 
     def close(self):
         if getattr(self, "_h", None):
@@ -159,6 +160,7 @@ class Plan:
         _require(kappa, "float64", self.cfg.n_fine ** self.cfg.dim)
         _require(label, "uint8", self.cfg.n_fine ** self.cfg.dim)
         check(LIB.mch_solve_cells(self._h, _ptr(kappa), _ptr(label), _stream(stream)))
+        self.generation += 1
 
     def effective_coeffs(self, kappa, A_eff, stream=None):
         _require(kappa, "float64", self.cfg.n_fine ** self.cfg.dim)
