@@ -30,6 +30,52 @@ HBM_PEAK_GBS = 8000.0
 # three vector updates 6, two dot products 4.
 FLOPS_PER_NODE_ITER = 38
 
+# HBM traffic per launch of the dominant kernel, from two rocprofv3 --pmc runs of
+# this script (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch), each scaled by what
+# the same counter reads for a plain device copy of known size (--copy-probe).
+# An entry holds only while the kernel sources hash to the recorded value.
+KERNEL_SOURCES = ("paper_2503_01276_amd/csrc/solve2d.hip", "paper_2503_01276_amd/csrc/device_common.h")
+_SHA_C2 = "aa4616ad7babc3e64b3a4761eec9f4dae41a725bb22d212c3d5098481f17d15b"
+_COPY_SCALE = {"fetch": 1048576.0 / 524304.8, "write": 1048576.0 / 1048576.0}  # 1 GiB copy
+TRAFFIC = {
+    ("c2", "solve_L1"): {"sha256": _SHA_C2, "fetch_kib": 16074.0, "write_kib": 31571.0,
+                         "fetch_scale": _COPY_SCALE["fetch"], "write_scale": _COPY_SCALE["write"]},
+    ("c2", "adjsolve_L1"): {"sha256": _SHA_C2, "fetch_kib": 22796.0, "write_kib": 31880.0,
+                            "fetch_scale": _COPY_SCALE["fetch"], "write_scale": _COPY_SCALE["write"]},
+}
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(HERE, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str, kernel: str):
+    t = TRAFFIC.get((workload, kernel))
+    if t is None or t["sha256"] != kernel_sources_sha256():
+        return None
+    return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0
+
+
+def copy_probe(mib: int, reps: int = 3):
+    """A plain device-to-device copy of a known size, for scaling the traffic counters."""
+    import torch
+
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "reps": reps}))
+
+
 DESCR = {
     "c2": "hierarchical L=3 eta=2, 2D 512^2 fine grid, 32x32 macropoints, 64^2-element cells "
           "(levels 64^2/32^2/16^2), N=2, contrast 1e4",
@@ -106,12 +152,21 @@ class Runner:
         self.plan.effective_coeffs(kt_d, self.T)
         torch.cuda.synchronize()
 
-    def step(self):
+    def step(self, ev=None):
+        """One pass of the hot path; ev = four events recorded between the phases (or None)."""
+        if ev:
+            ev[0].record()
         self.plan.solve_cells(self.k, self.l)
+        if ev:
+            ev[1].record()
         self.plan.effective_coeffs(self.k, self.A)
+        if ev:
+            ev[2].record()
         self.torch.sub(self.A, self.T, out=self.gA)
         self.gA.mul_(2.0)
         self.plan.effective_coeffs_backward(self.k, self.gA, self.g)
+        if ev:
+            ev[3].record()
 
     def time_steps(self, steps: int, warmup: int, profile: bool):
         torch = self.torch
@@ -126,18 +181,26 @@ class Runner:
         torch.cuda.synchronize()
         self.plan.profile(profile)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        # per-phase events on the launch stream (the library forks and joins its level
+        # streams inside each call, so these bracket each call's whole span)
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)] if profile else None
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         e0.record()
-        for _ in range(steps):
-            self.step()
+        for i in range(steps):
+            self.step(evs[i] if evs else None)
         e1.record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         ms = e0.elapsed_time(e1) / steps
+        phases = None
+        if evs:
+            ph = np.array([[e[j].elapsed_time(e[j + 1]) for j in range(3)] for e in evs])
+            phases = {"solve_ms": float(ph[:, 0].mean()), "eff_ms": float(ph[:, 1].mean()),
+                      "grad_ms_incl_loss": float(ph[:, 2].mean())}
         recs = self.plan.profile_records() if profile else []
         self.plan.profile(False)
-        return ms, wall, recs
+        return ms, wall, recs, phases
 
 
 def kernel_table(recs, steps):
@@ -168,12 +231,17 @@ def main():
     ap.add_argument("--flat", default=None, help="flat workload for the speedup (default: c2flat for c2)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-workers", type=int, default=None)
+    ap.add_argument("--copy-probe", type=int, default=None, metavar="MIB",
+                    help="only run a plain copy of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU sharding is a design described in DESIGN.md, not a measured path)",
               file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -183,9 +251,9 @@ def main():
 
     run = Runner(args.workload)
     cfg, plan = run.cfg, run.plan
-    ms, wall, recs = run.time_steps(args.steps, args.warmup, profile=True)
+    ms, wall, recs, phases = run.time_steps(args.steps, args.warmup, profile=True)
     print(f"[bench] {args.workload}: {ms:.3f} ms/step (eager, per-kernel events)", file=sys.stderr, flush=True)
-    ms_graph, _, _ = run.time_steps(args.steps, 1, profile=False)
+    ms_graph, _, _, _ = run.time_steps(args.steps, 1, profile=False)
     print(f"[bench] {args.workload}: {ms_graph:.3f} ms/step (hipGraph replay)", file=sys.stderr, flush=True)
     ktab = kernel_table(recs, args.steps)
     iters, _ = plan.diagnostics()
@@ -200,15 +268,13 @@ def main():
         flops = solve_flops(run, li, aiters if dom.startswith("adj") else iters, lev_pm)
         achieved = flops / (ktab[dom]["avg_ms"] * 1e-3) / 1e12
         roof = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
-                "flops_per_launch": flops}
+                "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
+                "traffic": measured_traffic(args.workload, dom), "flops_per_launch": flops}
     solves = plan.P * plan.M
-    fwd_ms = sum(v["avg_ms"] * v["launches_per_step"] for k, v in ktab.items()
-                 if k.startswith(("setup", "solve")))
-    eff_ms = sum(v["avg_ms"] * v["launches_per_step"] for k, v in ktab.items() if k.startswith("eff"))
-    grad_ms = ms - fwd_ms - eff_ms
+    fwd_ms = phases["solve_ms"]
     detail = {
-        "solve_ms": fwd_ms, "eff_ms": eff_ms, "grad_ms_incl_loss": grad_ms,
+        **phases,
+        "eff_tensor_time_ms": phases["solve_ms"] + phases["eff_ms"],
         "solves_per_s_forward_only": solves / (fwd_ms * 1e-3),
         "iterations": {f"L{n}": [int(iters[lev == n].min()), float(np.median(iters[lev == n])),
                                  int(iters[lev == n].max())] for n in range(1, cfg.levels + 1)},
@@ -223,11 +289,11 @@ def main():
         flat = None
     if flat:
         frun = Runner(flat)
-        fms, _, frecs = frun.time_steps(max(3, args.steps // 4), 1, profile=True)
-        ftab = kernel_table(frecs, max(3, args.steps // 4))
-        ffwd = sum(v["avg_ms"] * v["launches_per_step"] for k, v in ftab.items() if k.startswith(("setup", "solve")))
-        detail["flat"] = {"workload": flat, "ms_per_step": fms, "solve_ms": ffwd,
-                          "speedup_step": fms / ms, "speedup_solve": ffwd / fwd_ms}
+        fms, _, _, fph = frun.time_steps(max(3, args.steps // 4), 1, profile=True)
+        detail["flat"] = {"workload": flat, "ms_per_step": fms, **fph,
+                          "speedup_step": fms / ms, "speedup_solve": fph["solve_ms"] / fwd_ms,
+                          "speedup_eff_tensor_time": (fph["solve_ms"] + fph["eff_ms"]) /
+                                                     (phases["solve_ms"] + phases["eff_ms"])}
         print(f"[bench] {flat}: {fms:.3f} ms/step", file=sys.stderr, flush=True)
     out = {
         "metric": "cell-solves/sec & eff-tensor+grad time, hier L=3 vs flat, 1 GPU, rel err <=1e-8",
