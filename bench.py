@@ -29,6 +29,11 @@ HBM_PEAK_GBS = 8000.0
 # K apply 18 (9-point row), B apply 4, B^T apply 4, two D^-1 scalings 2,
 # three vector updates 6, two dot products 4.
 FLOPS_PER_NODE_ITER = 38
+# 3D, same accounting: the fine operator row has 21 points (self, 12 face
+# diagonals, 8 body diagonals; edge neighbours do not couple) -> 42, a Galerkin
+# level row 27 -> 54; the other terms as in 2D (20).
+FLOPS_PER_NODE_ITER_3D_FINE = 62
+FLOPS_PER_NODE_ITER_3D_GAL = 74
 
 # HBM traffic per launch of the dominant kernel, from two rocprofv3 --pmc runs of
 # this script (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch), each scaled by what
@@ -83,6 +88,9 @@ DESCR = {
     "c1": "flat L=1, 2D 128^2 fine grid, 8x8 macropoints, 32^2-element cells, N=2, contrast 1e4",
     "c5": "hierarchical L=4 eta=2, 2D 2048^2 fine grid, 256x256 macropoints, 64^2-element cells "
           "(levels 64^2/32^2/16^2/8^2), N=3 with inclusions, contrast 1e8",
+    "c3": "hierarchical L=2 eta=2, 3D 128^3 fine grid, 8^3 macropoints, 32^3-element cells "
+          "(levels 32^3/16^3), N=2, contrast 1e4",
+    "c3flat": "flat L=1, 3D 128^3 fine grid, 8^3 macropoints, 32^3-element cells, N=2, contrast 1e4",
 }
 
 
@@ -92,19 +100,19 @@ def cpu_baseline(name: str, workers: int):
 
     cfg = W.PRESETS[name]
     k, l = W.medium(name)
-    if cfg.n_points > 4096:
+    if cfg.n_points > 4096 or cfg.dim == 3:
         # bounded sample: every cell of two level-1 groups, forward only
         lev = oracle.hierarchy.levels(cfg.n_macro, cfg.dim, cfg.levels, cfg.eta)
         par = oracle.hierarchy.parents(cfg.n_macro, cfg.dim, cfg.levels, cfg.eta)
         l1 = np.flatnonzero(lev == 1)
-        groups = [int(l1[0]), int(l1[len(l1) // 2])]
+        groups = [int(l1[0])] if cfg.dim == 3 else [int(l1[0]), int(l1[len(l1) // 2])]
         pts = sorted(set(groups) | set(int(p) for p in np.flatnonzero(np.isin(par, groups))))
         t0 = time.perf_counter()
         oracle.forward(cfg, k, l, points=pts, workers=workers)
         t1 = time.perf_counter()
         solves = len(pts) * cfg.n_rhs
         return {"value": solves / (t1 - t0), "unit": "cell-solves/s", "cores": workers, "kind": "oracle",
-                "sample": f"{len(pts)} cells of two whole level-1 groups of {name} ({solves} solves), "
+                "sample": f"{len(pts)} cells of {len(groups)} whole level-1 group(s) of {name} ({solves} solves), "
                           f"SciPy SuperLU forward only, {t1 - t0:.2f} s, one process per core"}
     kt, _ = W.medium(name, channel_factor=W.target_factor(4))
     T = oracle.stack_A(oracle.forward(cfg, kt, l, workers=workers), cfg)
@@ -219,7 +227,8 @@ def solve_flops(runner, level_idx: int, iters: np.ndarray, levels: np.ndarray, a
     nfree = (NC - 1) ** cfg.dim
     m = runner.plan.m
     its = iters[levels == level_idx + 1].astype(np.float64)
-    return float(its.sum()) * (FLOPS_PER_NODE_ITER * nfree + 2 * m * m + 2 * m)
+    per_node = FLOPS_PER_NODE_ITER if cfg.dim == 2 else (FLOPS_PER_NODE_ITER_3D_FINE if r == 1 else FLOPS_PER_NODE_ITER_3D_GAL)
+    return float(its.sum()) * (per_node * nfree + 2 * m * m + 2 * m)
 
 
 def main():
@@ -284,7 +293,7 @@ def main():
         "wall_s": wall,
         "ms_per_step_graph_replay": ms_graph,
     }
-    flat = args.flat or ("c2flat" if args.workload == "c2" else None)
+    flat = args.flat or {"c2": "c2flat", "c3": "c3flat"}.get(args.workload)
     if flat == "none":
         flat = None
     if flat:

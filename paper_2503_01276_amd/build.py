@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmch.so")
-SOURCES = ["plan.cpp", "api.cpp", "setup2d.hip", "solve2d.hip", "backward2d.hip"]
+SOURCES = ["plan.cpp", "api.cpp", "setup2d.hip", "solve2d.hip", "backward2d.hip", "cells3d.hip"]
 HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-munsafe-fp-atomics",

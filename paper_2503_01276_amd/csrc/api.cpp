@@ -55,7 +55,7 @@ extern "C" int mch_solve_cells(mch_plan* p, const double* kappa, const uint8_t* 
   int rc = enter(p, stream, &s);
   if (rc) return rc;
   if (!kappa || !label) return set_error(MCH_EINVAL, "null kappa or label");
-  rc = run_graph(p, p->g_fwd, kappa, label, nullptr, s, [&] { return launch_forward_2d(p, kappa, label, s); });
+  rc = run_graph(p, p->g_fwd, kappa, label, nullptr, s, [&] { return p->dim == 3 ? launch_forward_3d(p, kappa, label, s) : launch_forward_2d(p, kappa, label, s); });
   if (rc) return rc;
   p->forward_done = 1;
   p->fwd_kappa = kappa;
@@ -70,7 +70,7 @@ extern "C" int mch_effective_coeffs(mch_plan* p, const double* kappa, double* A,
   if (rc) return rc;
   if (!kappa || !A) return set_error(MCH_EINVAL, "null kappa or A_eff");
   if (!p->forward_done) return set_error(MCH_ESTALE, "no forward solve has been issued on this plan");
-  rc = run_graph(p, p->g_eff, kappa, A, p->fwd_label, s, [&] { return launch_eff_2d(p, kappa, A, s); });
+  rc = run_graph(p, p->g_eff, kappa, A, p->fwd_label, s, [&] { return p->dim == 3 ? launch_eff_3d(p, kappa, A, s) : launch_eff_2d(p, kappa, A, s); });
   if (!rc) p->last_stream = s;
   return rc;
 }
@@ -82,7 +82,9 @@ extern "C" int mch_effective_coeffs_backward(mch_plan* p, const double* kappa, c
   if (rc) return rc;
   if (!kappa || !gA || !glogk) return set_error(MCH_EINVAL, "null argument");
   if (!p->forward_done) return set_error(MCH_ESTALE, "no forward solve has been issued on this plan");
-  rc = run_graph(p, p->g_bwd, kappa, gA, glogk, s, [&] { return launch_backward_2d(p, kappa, gA, glogk, s); });
+  rc = run_graph(p, p->g_bwd, kappa, gA, glogk, s, [&] {
+    return p->dim == 3 ? launch_backward_3d(p, kappa, gA, glogk, s) : launch_backward_2d(p, kappa, gA, glogk, s);
+  });
   if (!rc) p->last_stream = s;
   return rc;
 }
@@ -96,5 +98,5 @@ extern "C" int mch_local_solutions(mch_plan* p, const int64_t* cells, int64_t n,
   for (int64_t k = 0; k < n; ++k)
     if (cells[k] < 0 || cells[k] >= p->P) return set_error(MCH_EINVAL, "macropoint index out of range");
   if (n == 0) return MCH_OK;
-  return launch_local_solutions_2d(p, cells, n, out, s);
+  return p->dim == 3 ? launch_local_solutions_3d(p, cells, n, out, s) : launch_local_solutions_2d(p, cells, n, out, s);
 }

@@ -121,6 +121,15 @@ struct CellArgs {
   const int32_t* slot;    // [P] index of the point within its level
   double rtol;
   int max_iter;
+  // 3D cells (unused in 2D): windows, D^-1 and Krylov vectors of this level,
+  // and Phi on the K_p nodes of every point
+  double* kw;             // fine level: [count][NC^3] kappa*h/12
+  uint8_t* labw;          // fine level: [count][NC^3] labels
+  double* dinv;           // [count][NC^3]
+  double* vr;             // [count][M][(NC+1)^3]
+  double* vp;
+  double* vap;
+  double* phikp;          // [P][M][(H+1)^3]
 };
 
 // Fine local solution Phi_alpha = I + P xi of cell ci (index within its level)

@@ -143,6 +143,44 @@ static void galerkin_tables(int r, std::vector<double>& tk, std::vector<double>&
     }
 }
 
+// 3D version: trilinear R, the Q1 hexahedron element matrix h*(4, 0, -1, -1)/12
+// (diagonal, edge, face-diagonal, body-diagonal corner pairs); corners in
+// tensor order a = ax + 2 ay + 4 az. Tables T[r^3][64] and rho[r^3][8].
+static void galerkin_tables_3d(int r, double h, std::vector<double>& tk, std::vector<double>& tr) {
+  double kref[8][8];
+  for (int a = 0; a < 8; ++a)
+    for (int b = 0; b < 8; ++b) {
+      const int dif = __builtin_popcount(a ^ b);
+      kref[a][b] = h * (dif == 0 ? 4.0 : dif == 1 ? 0.0 : -1.0) / 12.0;
+    }
+  const size_t r3 = (size_t)r * r * r;
+  tk.assign(r3 * 64, 0.0);
+  tr.assign(r3 * 8, 0.0);
+  for (int w = 0; w < r; ++w)
+    for (int v = 0; v < r; ++v)
+      for (int u = 0; u < r; ++u) {
+        double R[8][8];
+        for (int dl = 0; dl < 8; ++dl) {
+          const double xi = (u + (dl & 1)) / (double)r, et = (v + ((dl >> 1) & 1)) / (double)r,
+                       ze = (w + (dl >> 2)) / (double)r;
+          for (int a = 0; a < 8; ++a)
+            R[dl][a] = ((a & 1) ? xi : 1.0 - xi) * (((a >> 1) & 1) ? et : 1.0 - et) * ((a >> 2) ? ze : 1.0 - ze);
+        }
+        const int pos = u + r * (v + r * w);
+        for (int a = 0; a < 8; ++a) {
+          double sr = 0;
+          for (int dl = 0; dl < 8; ++dl) sr += R[dl][a];
+          tr[pos * 8 + a] = sr;
+          for (int b = 0; b < 8; ++b) {
+            double t = 0;
+            for (int x = 0; x < 8; ++x)
+              for (int y = 0; y < 8; ++y) t += R[x][a] * kref[x][y] * R[y][b];
+            tk[pos * 64 + a * 8 + b] = t;
+          }
+        }
+      }
+}
+
 ProfScope::ProfScope(mch_plan* plan, const char* name, hipStream_t stream) : p(plan), s(stream), idx(0), on(false) {
   if (!p || !p->profiling) return;
   if (p->prof_used == p->prof.size()) {
@@ -220,7 +258,6 @@ extern "C" int mch_build_levels(const mch_config* cfg, mch_plan** out) {
   *out = nullptr;
   const mch_config& c = *cfg;
   if (c.dim != 2 && c.dim != 3) return set_error(MCH_EINVAL, "dim must be 2 or 3");
-  if (c.dim == 3) return set_error(MCH_ENOTIMPL, "3D cells are not implemented in this build");
   const int d = c.dim, n = c.n_fine[0], nm = c.n_macro[0];
   for (int a = 0; a < d; ++a) {
     if (c.n_fine[a] != n || c.n_macro[a] != nm) return set_error(MCH_EINVAL, "grid must be cubic (equal sizes per axis)");
@@ -282,9 +319,19 @@ extern "C" int mch_build_levels(const mch_config* cfg, mch_plan** out) {
     lv.count = (int)lv.cells.size();
     const int sbw = nc / c.n_sub / lv.r;
     lv.shape.NC = lv.NC;
-    lv.shape.rpt = default_rpt(lv.NC, sbw);
-    lv.shape.threads = lv.NC * lv.NC / lv.shape.rpt;
-    if (!shape_supported_2d(lv.NC, lv.shape.rpt, c.n_cont, lv.r > 1)) {
+    if (d == 3) {
+      lv.shape.rpt = 0;
+      lv.shape.threads = ipow(lv.NC, 3) >= 1024 ? 1024 : ipow(lv.NC, 3);
+      if (!shape_supported_3d(lv.NC, c.n_sub, c.n_cont)) {
+        rc = set_error(MCH_ENOTIMPL, "no 3D kernel instantiated for level cell width " + std::to_string(lv.NC) +
+                                         " n_sub=" + std::to_string(c.n_sub) + " N=" + std::to_string(c.n_cont));
+        break;
+      }
+    } else {
+      lv.shape.rpt = default_rpt(lv.NC, sbw);
+      lv.shape.threads = lv.NC * lv.NC / lv.shape.rpt;
+    }
+    if (d == 2 && !shape_supported_2d(lv.NC, lv.shape.rpt, c.n_cont, lv.r > 1)) {
       rc = set_error(MCH_ENOTIMPL, "no kernel instantiated for level cell width " + std::to_string(lv.NC) +
                                        " rows/thread " + std::to_string(lv.shape.rpt) + " N=" +
                                        std::to_string(c.n_cont));
@@ -301,16 +348,30 @@ extern "C" int mch_build_levels(const mch_config* cfg, mch_plan** out) {
     size_t vec = (l == 0) ? (size_t)p->nn : (size_t)ipow(lv.NC + 1, d);
     if ((rc = dev_alloc(p, &lv.d_out, (size_t)lv.count * p->M * vec))) break;
     if ((rc = dev_alloc(p, &lv.d_w, (size_t)lv.count * p->M * vec))) break;
+    const size_t nodes = (size_t)ipow(lv.NC, d);
     if (lv.r > 1) {
       std::vector<double> tk, tr;
-      galerkin_tables(lv.r, tk, tr);
+      if (d == 3)
+        galerkin_tables_3d(lv.r, c.h, tk, tr);
+      else
+        galerkin_tables(lv.r, tk, tr);
       if ((rc = upload(p, &lv.d_tabK, tk))) break;
       if ((rc = upload(p, &lv.d_tabR, tr))) break;
-      const size_t nodes = (size_t)ipow(lv.NC, d);
-      if ((rc = dev_alloc(p, &lv.d_nodeW, (size_t)lv.count * nodes * 9))) break;
-      if ((rc = dev_alloc(p, &lv.d_nodeB, (size_t)lv.count * nodes * 4 * c.n_cont))) break;
+      if ((rc = dev_alloc(p, &lv.d_nodeW, (size_t)lv.count * nodes * ipow(3, d)))) break;
+      if ((rc = dev_alloc(p, &lv.d_nodeB, (size_t)lv.count * nodes * ipow(2, d) * c.n_cont))) break;
       if ((rc = dev_alloc(p, &lv.d_fin, (size_t)lv.count * p->M * nodes))) break;
       if ((rc = dev_alloc(p, &lv.d_gin, (size_t)lv.count * p->M * p->m))) break;
+    }
+    if (d == 3) {
+      if (lv.r == 1) {
+        if ((rc = dev_alloc(p, &lv.d_kw, (size_t)lv.count * nodes))) break;
+        if ((rc = dev_alloc(p, &lv.d_labw, (size_t)lv.count * nodes))) break;
+      }
+      const size_t padded = (size_t)lv.count * p->M * ipow(lv.NC + 1, 3);
+      if ((rc = dev_alloc(p, &lv.d_dinv, (size_t)lv.count * nodes))) break;
+      if ((rc = dev_alloc(p, &lv.d_vr, padded))) break;
+      if ((rc = dev_alloc(p, &lv.d_vp, padded))) break;
+      if ((rc = dev_alloc(p, &lv.d_vap, padded))) break;
     }
   }
   const size_t P = p->P, M = p->M, m = p->m;
@@ -330,6 +391,7 @@ extern "C" int mch_build_levels(const mch_config* cfg, mch_plan** out) {
   if (!rc) rc = dev_alloc(p, &p->d_iters_adj, P * M);
   if (!rc) rc = dev_alloc(p, &p->d_resid_adj, P * M);
   if (!rc) rc = upload(p, &p->d_level, p->level);
+  if (!rc && d == 3) rc = dev_alloc(p, &p->d_phikp, P * M * (size_t)ipow(H + 1, 3));
   if (!rc) {
     std::vector<int32_t> ptr(n1 + 1, 0), child;
     for (int q = 0; q < p->P; ++q)

@@ -35,6 +35,15 @@ struct Level {
   float* d_nodeB = nullptr;     // Galerkin constraint weights [count][NC^d][4][N]
   double* d_fin = nullptr;      // inherited right-hand sides [count][M][NC^d]
   double* d_gin = nullptr;      // [count][M][m]
+  // 3D cells only: fine-level windows kappa*h/12 and labels [count][NC^3],
+  // 1/diag(K_n) per level node [count][NC^3], and the Krylov vectors
+  // r, p, K_n p of every (cell, rhs) [count][M][(NC+1)^3] (zero boundary)
+  double* d_kw = nullptr;
+  uint8_t* d_labw = nullptr;
+  double* d_dinv = nullptr;
+  double* d_vr = nullptr;
+  double* d_vp = nullptr;
+  double* d_vap = nullptr;
   KernelShape shape;
 };
 
@@ -81,6 +90,7 @@ struct mch_plan {
   int32_t* d_level = nullptr;    // [P]
   int32_t* d_child_ptr = nullptr;  // [n1+1] CSR of inheriting points per level-1 slot
   int32_t* d_child = nullptr;      // [P - n1] macropoint ids
+  double* d_phikp = nullptr;       // 3D: Phi on the K_p nodes [P][M][(H+1)^3]
   hipStream_t last_stream = nullptr;
   int forward_done = 0;
   const double* fwd_kappa = nullptr;
@@ -131,4 +141,9 @@ int launch_eff_2d(mch_plan* p, const double* kappa, double* A, hipStream_t s);
 int launch_backward_2d(mch_plan* p, const double* kappa, const double* gA, double* glogk, hipStream_t s);
 int launch_local_solutions_2d(mch_plan* p, const int64_t* cells, int64_t n, double* out, hipStream_t s);
 bool shape_supported_2d(int NC, int rpt, int N, bool galerkin);
+int launch_forward_3d(mch_plan* p, const double* kappa, const uint8_t* label, hipStream_t s);
+int launch_eff_3d(mch_plan* p, const double* kappa, double* A, hipStream_t s);
+int launch_backward_3d(mch_plan* p, const double* kappa, const double* gA, double* glogk, hipStream_t s);
+int launch_local_solutions_3d(mch_plan* p, const int64_t* cells, int64_t n, double* out, hipStream_t s);
+bool shape_supported_3d(int NC, int s, int N);
 }  // namespace mch

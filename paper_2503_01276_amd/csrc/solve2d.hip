@@ -577,6 +577,13 @@ CellArgs base_args(mch_plan* pl, const double* kappa, const uint8_t* label, int 
   a.slot = pl->d_slot;
   a.rtol = pl->cfg.rtol;
   a.max_iter = pl->cfg.max_iter;
+  a.kw = lv.d_kw;
+  a.labw = lv.d_labw;
+  a.dinv = lv.d_dinv;
+  a.vr = lv.d_vr;
+  a.vp = lv.d_vp;
+  a.vap = lv.d_vap;
+  a.phikp = pl->d_phikp;
   return a;
 }
 

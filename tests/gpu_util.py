@@ -50,3 +50,73 @@ def A_rel_err(gpu: np.ndarray, ref: np.ndarray) -> np.ndarray:
     num = np.linalg.norm((gpu - ref).reshape(len(ref), -1), axis=1)
     den = np.linalg.norm(ref.reshape(len(ref), -1), axis=1)
     return num / den
+
+
+PHI_TOL = 1e-8
+A_TOL = 1e-9
+GRAD_TOL = 1e-8
+
+
+def check_forward(name, cfg, k, l, phi_cells, a_points=None, workers=None):
+    """GPU forward vs the oracle: Phi on phi_cells (1e-8), A_eff on a_points
+    (default all, 1e-9), fine constraints of the GPU solutions (1e-12)."""
+    import oracle
+    from oracle import cells as ocells
+
+    say(f"[gpu] {name}: forward on the GPU ({cfg})")
+    plan, A, Phi, it, rs, _ = gpu_forward(cfg, k, l, cells=phi_cells)
+    say(f"[gpu] {name}: iterations min/median/max {it.min()}/{int(np.median(it))}/{it.max()}, "
+        f"max resid {rs.max():.2e}")
+    pts = np.arange(cfg.n_points) if a_points is None else np.asarray(a_points)
+    need = sorted(set(int(p) for p in pts) | set(int(p) for p in phi_cells))
+    say(f"[gpu] {name}: oracle on {len(need)} cells")
+    ref = oracle.forward(cfg, k, l, points=need, workers=workers)
+    Aref = np.stack([ref.A[int(p)] for p in pts])
+    ea = A_rel_err(A[pts], Aref)
+    ep = max(phi_rel_err(Phi[p], ref.Phi[p]) for p in phi_cells) if len(phi_cells) else 0.0
+    say(f"[gpu] {name}: max A rel err {ea.max():.3e}, max Phi rel err {ep:.3e}")
+    for p in phi_cells[:8]:
+        cs = ocells.assemble_cell(cfg, k, l, int(p), int(ref.level[p]))
+        cres = np.abs(cs.Bf @ Phi[p][cs.free] - cs.g).max()
+        assert cres < 1e-12, (p, cres)
+    assert ep <= PHI_TOL, ep
+    assert ea.max() <= A_TOL, ea.max()
+    sym = np.abs(A - A.transpose(0, 2, 1)).max() / np.abs(A).max()
+    assert sym < 1e-14
+    return plan, A
+
+
+def grad_case(name, cfg, seed, workers=1):
+    """GPU adjoint gradient of sum_p ||A - T||_F^2 vs the oracle's (same dLoss/dA)."""
+    import torch
+
+    import oracle
+    from paper_2503_01276_amd import mch
+    from paper_2503_01276_amd import workloads as W
+
+    k, l = W.medium_for(cfg, seed)
+    kt, _ = W.medium_for(cfg, seed, channel_factor=W.target_factor(4))
+    say(f"[gpu] {name}: oracle forward (target and medium)")
+    T = oracle.stack_A(oracle.forward(cfg, kt, l, workers=workers), cfg)
+    fwd = oracle.forward(cfg, k, l, workers=workers)
+    A = oracle.stack_A(fwd, cfg)
+    gA = 2.0 * (A - T)
+    say(f"[gpu] {name}: oracle backward")
+    gref = oracle.backward(cfg, k, l, fwd, {p: gA[p] for p in range(cfg.n_points)}, workers=workers).reshape(-1)
+    say(f"[gpu] {name}: GPU forward + backward")
+    plan = mch.Plan(cfg)
+    dev = torch.device("cuda:0")
+    kd = torch.from_numpy(k.reshape(-1).copy()).to(dev)
+    ld = torch.from_numpy(l.reshape(-1).copy()).to(dev)
+    plan.solve_cells(kd, ld)
+    Ad = torch.empty(plan.P * plan.M * plan.M, dtype=torch.float64, device=dev)
+    plan.effective_coeffs(kd, Ad)
+    gAd = torch.from_numpy(gA.reshape(-1).copy()).to(dev)
+    gd = torch.empty_like(kd)
+    plan.effective_coeffs_backward(kd, gAd, gd)
+    torch.cuda.synchronize()
+    g = gd.cpu().numpy()
+    err = np.linalg.norm(g - gref) / np.linalg.norm(gref)
+    say(f"[gpu] {name}: grad rel err {err:.3e} (|g| = {np.linalg.norm(gref):.3e})")
+    assert err <= GRAD_TOL, err
+    return g, gref

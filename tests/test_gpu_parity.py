@@ -8,40 +8,13 @@ import numpy as np
 import pytest
 
 import oracle
-from oracle import cells as ocells
 from paper_2503_01276_amd import workloads as W
 
-from gpu_util import A_rel_err, gpu_forward, phi_rel_err, say
+from gpu_util import check_forward, gpu_forward
 
 pytestmark = pytest.mark.gpu
 
-PHI_TOL = 1e-8
-A_TOL = 1e-9
-
-
-def _check(name, cfg, k, l, phi_cells, a_points=None, workers=None):
-    say(f"[gpu] {name}: forward on the GPU ({cfg})")
-    plan, A, Phi, it, rs, _ = gpu_forward(cfg, k, l, cells=phi_cells)
-    say(f"[gpu] {name}: iterations min/median/max {it.min()}/{int(np.median(it))}/{it.max()}, "
-        f"max resid {rs.max():.2e}")
-    pts = np.arange(cfg.n_points) if a_points is None else np.asarray(a_points)
-    need = sorted(set(int(p) for p in pts) | set(int(p) for p in phi_cells))
-    say(f"[gpu] {name}: oracle on {len(need)} cells")
-    ref = oracle.forward(cfg, k, l, points=need, workers=workers)
-    Aref = np.stack([ref.A[int(p)] for p in pts])
-    ea = A_rel_err(A[pts], Aref)
-    ep = max(phi_rel_err(Phi[p], ref.Phi[p]) for p in phi_cells) if len(phi_cells) else 0.0
-    say(f"[gpu] {name}: max A rel err {ea.max():.3e}, max Phi rel err {ep:.3e}")
-    # constraints on the GPU solutions, fine rows assembled by the oracle
-    for p in phi_cells[:8]:
-        cs = ocells.assemble_cell(cfg, k, l, int(p), int(ref.level[p]))
-        cres = np.abs(cs.Bf @ Phi[p][cs.free] - cs.g).max()
-        assert cres < 1e-12, (p, cres)
-    assert ep <= PHI_TOL, ep
-    assert ea.max() <= A_TOL, ea.max()
-    sym = np.abs(A - A.transpose(0, 2, 1)).max() / np.abs(A).max()
-    assert sym < 1e-14
-    return plan, A
+_check = check_forward
 
 
 def test_hierarchy_matches_oracle():
