@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
+#include <type_traits>
 #include <vector>
 
 #include "kernels2d.h"
@@ -197,12 +198,13 @@ __global__ __launch_bounds__(T3) void k_setup3d(CellArgs a) {
     __syncthreads();
     for (int nd = tid; nd < (int)nodes; nd += T3) {
       const int X = nd % NC, Y = (nd / NC) % NC, Z = nd / (NC * NC);
-      double ks = 0.0;
       if (X >= 1 && Y >= 1 && Z >= 1) {
+        double k8[8];
 #pragma unroll
         for (int o = 0; o < 8; ++o)
-          ks += kwc[(X - 1 + (o & 1)) + NC * ((Y - 1 + ((o >> 1) & 1)) + NC * (Z - 1 + (o >> 2)))];
-        dinv[nd] = 1.0 / (4.0 * ks);
+          k8[o] = kwc[(X - 1 + (o & 1)) + NC * ((Y - 1 + ((o >> 1) & 1)) + NC * (Z - 1 + (o >> 2)))];
+        // same order as the diagonal of the solve kernel's operator
+        dinv[nd] = 1.0 / (4.0 * (((k8[0] + k8[1]) + (k8[2] + k8[3])) + ((k8[4] + k8[5]) + (k8[6] + k8[7]))));
       } else {
         dinv[nd] = 0.0;
       }
@@ -474,10 +476,15 @@ __global__ __launch_bounds__(T3) void k_inherit3d(CellArgs a) {
 // ---------------------------------------------------------------------------
 constexpr int ZPERIOD3 = 16;
 
+// 512 threads: the sweep bodies need about 250 VGPRs, which a 1024-thread
+// workgroup cannot give (it would spill to scratch inside the loop).
 template <int NC>
 constexpr int nt3() {
-  return NC * NC * NC >= 1024 ? 1024 : NC * NC * NC;
+  return NC * NC * NC >= 512 ? 512 : NC * NC * NC;
 }
+
+template <int V>
+using IC = std::integral_constant<int, V>;
 
 template <int NC, int N, bool GAL>
 __global__ __launch_bounds__(nt3<NC>()) void k_solve3d(CellArgs a) {
@@ -485,8 +492,10 @@ __global__ __launch_bounds__(nt3<NC>()) void k_solve3d(CellArgs a) {
   constexpr int NW = NT / 64;
   constexpr int NP = NC + 1;
   constexpr int NODES = NC * NC * NC;
-  constexpr int SPT = NODES / NT;
-  constexpr int G = NT / (NC * NC);
+  constexpr int CPT = NC * NC > NT ? NC * NC / NT : 1;  // node columns per thread
+  constexpr int G = NT > NC * NC ? NT / (NC * NC) : 1;  // plane groups
+  constexpr int SPT = NC / G;                           // planes per thread
+  constexpr int YS = NC / CPT;                          // row stride between a thread's columns
   constexpr int S = S3D;
   constexpr int PARTV = G * NC * 2 * S * S * N;
   constexpr long SY = NP, SZ = (long)NP * NP;
@@ -501,7 +510,9 @@ __global__ __launch_bounds__(nt3<NC>()) void k_solve3d(CellArgs a) {
   double* vW = uW + NW * m;         // NW*m
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int X = tid % NC, Y = (tid / NC) % NC, g = tid / (NC * NC);
+  // columns (X, Y0 + c YS), c < CPT; planes Z = g + G i (g uniform across a wave)
+  const int X = tid % NC, Y0 = (tid / NC) % YS;
+  const int g = __builtin_amdgcn_readfirstlane(tid / (NC * YS));
   const int ci = blockIdx.x / M, alpha = blockIdx.x % M;
   const int p = a.cells[ci];
   const size_t vbase = ((size_t)ci * M + alpha) * (size_t)NP * NP * NP;
@@ -514,9 +525,32 @@ __global__ __launch_bounds__(nt3<NC>()) void k_solve3d(CellArgs a) {
   const uint8_t* __restrict__ lbc = GAL ? nullptr : a.labw + (size_t)ci * NODES;
   const double* __restrict__ nW = GAL ? a.nodeW + (size_t)ci * NODES * 27 : nullptr;
   const float* __restrict__ nB = GAL ? a.nodeB + (size_t)ci * NODES * 8 * N : nullptr;
-  const bool colfree = X >= 1 && Y >= 1;
   const int qx0 = (X >= 1 ? X - 1 : 0) / sbw, qx1 = X / sbw;
-  const int qy0 = (Y >= 1 ? Y - 1 : 0) / sbw, qy1 = Y / sbw;
+  auto Yc = [&](int c) { return Y0 + c * YS; };
+  auto colfree = [&](int c) { return X >= 1 && Yc(c) >= 1; };
+
+  // Planes of this thread: Z = g + G i (plane 0 is the Dirichlet boundary).
+  // The lower octants (elements of layer Z-1) of plane Z lie in constraint
+  // region m0 = (Z-1)/sbw and the upper ones in m1 = Z/sbw. A sweep visits the
+  // thread's planes in order; consecutive planes with the same (m0, m1) form a
+  // segment (at most three). Per-octant sums are kept by octant (oz) and
+  // mapped to regions only when a segment ends, so the loop body carries no
+  // region logic.
+  const int iFirst = (g == 0) ? 1 : 0;
+  auto sweep = [&](auto&& seg_begin, auto&& body, auto&& seg_end) {
+#pragma unroll 1
+    for (int i = iFirst; i < SPT; ++i) {
+      const int Z = g + G * i;
+      const int m0 = (Z - 1) / sbw, m1 = Z / sbw;
+      const int Zp = Z - G, Zn = Z + G;
+      if (i == iFirst || (Zp - 1) / sbw != m0 || Zp / sbw != m1) seg_begin(m0, m1);
+#pragma unroll
+      for (int c = 0; c < CPT; ++c)
+        if (colfree(c)) body(c, Z);
+      if (i + 1 == SPT || (Zn - 1) / sbw != m0 || Zn / sbw != m1) seg_end(m0, m1);
+    }
+  };
+  auto nop2 = [](int, int) {};
 
   for (int k = tid; k < MS * 64; k += NT) {
     const int t = k / 64, L = k % 64, row = L / J, col = L % J + J * t;
@@ -525,24 +559,37 @@ __global__ __launch_bounds__(nt3<NC>()) void k_solve3d(CellArgs a) {
   for (int k = tid; k < m; k += NT) cwS[k] = a.cw[(size_t)p * m + k];
 
   // ---- building blocks -------------------------------------------------------
-  auto node_of = [&](int Z) -> size_t { return (size_t)X + NC * ((size_t)Y + NC * (size_t)Z); };
+  auto node_of = [&](int Y, int Z) -> size_t { return (size_t)X + NC * ((size_t)Y + NC * (size_t)Z); };
 
   // (K_n v) at node (X, Y, Z) from the padded global vector v.
-  auto applyK = [&](const double* __restrict__ v, int Z) -> double {
+  auto applyK = [&](const double* __restrict__ v, int Y, int Z) -> double {
     const long c = (long)nidx3(X, Y, Z, NP);
     if constexpr (!GAL) {
-      double diag = 0.0, off = 0.0;
+      double k8[8];
 #pragma unroll
-      for (int o = 0; o < 8; ++o) {
-        const int ex_ = o & 1, ey_ = (o >> 1) & 1, ez_ = o >> 2;
-        const double k = kwc[(X - 1 + ex_) + NC * ((Y - 1 + ey_) + NC * (Z - 1 + ez_))];
-        const long sx = 2 * ex_ - 1, sy = (2 * ey_ - 1) * SY, sz = (2 * ez_ - 1) * SZ;
-        diag += k;
-        off += k * ((v[c + sx + sy] + v[c + sx + sz]) + (v[c + sy + sz] + v[c + sx + sy + sz]));
+      for (int o = 0; o < 8; ++o)
+        k8[o] = kwc[(X - 1 + (o & 1)) + NC * ((Y - 1 + ((o >> 1) & 1)) + NC * (Z - 1 + (o >> 2)))];
+      // plane Z: the four (x, y) diagonals couple through both element layers
+      double t = 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const long sx = 2 * (q & 1) - 1, sy = (2 * (q >> 1) - 1) * SY;
+        t += (k8[q] + k8[q + 4]) * v[c + sx + sy];
       }
-      return 4.0 * diag * v[c] - off;
+      // planes Z -+ 1: edge-adjacent in-plane offsets and the corners
+#pragma unroll
+      for (int oz = 0; oz < 2; ++oz) {
+        const long sz = (2 * oz - 1) * SZ;
+        const double* k4 = k8 + 4 * oz;
+        t += (k4[0] + k4[2]) * v[c - 1 + sz] + (k4[1] + k4[3]) * v[c + 1 + sz];
+        t += (k4[0] + k4[1]) * v[c - SY + sz] + (k4[2] + k4[3]) * v[c + SY + sz];
+        t += k4[0] * v[c - 1 - SY + sz] + k4[1] * v[c + 1 - SY + sz] + k4[2] * v[c - 1 + SY + sz] +
+             k4[3] * v[c + 1 + SY + sz];
+      }
+      const double D = 4.0 * (((k8[0] + k8[1]) + (k8[2] + k8[3])) + ((k8[4] + k8[5]) + (k8[6] + k8[7])));
+      return D * v[c] - t;
     } else {
-      const double* w = nW + node_of(Z) * 27;
+      const double* w = nW + node_of(Y, Z) * 27;
       double t = 0.0;
 #pragma unroll
       for (int k = 0; k < 27; ++k) {
@@ -554,7 +601,7 @@ __global__ __launch_bounds__(nt3<NC>()) void k_solve3d(CellArgs a) {
   };
 
   // Constraint weights of node (X, Y, Z) per octant element and continuum.
-  auto node_weights = [&](int Z, float (&w)[8][N]) {
+  auto node_weights = [&](int Y, int Z, float (&w)[8][N]) {
     if constexpr (!GAL) {
 #pragma unroll
       for (int o = 0; o < 8; ++o) {
@@ -563,7 +610,7 @@ __global__ __launch_bounds__(nt3<NC>()) void k_solve3d(CellArgs a) {
         for (int j = 0; j < N; ++j) w[o][j] = (lab == j) ? 1.0f : 0.0f;
       }
     } else {
-      const float* b = nB + node_of(Z) * 8 * N;
+      const float* b = nB + node_of(Y, Z) * 8 * N;
 #pragma unroll
       for (int o = 0; o < 8; ++o)
 #pragma unroll
@@ -571,37 +618,58 @@ __global__ __launch_bounds__(nt3<NC>()) void k_solve3d(CellArgs a) {
     }
   };
 
-  // acc[ox][oy][qz][j] += w * tv for the node's octants.
-  auto accB = [&](double (&acc)[2][2][S][N], const float (&w)[8][N], double tv, int Z) {
-    const int qz0 = (Z - 1) / sbw, qz1 = Z / sbw;
+  using Acc = double[CPT][2][2][2][N];
+
+  // acc[c][ox][oy][oz][j] += w * tv over the node's octants.
+  auto accB = [&](Acc& acc, int c, const float (&w)[8][N], double tv) {
 #pragma unroll
-    for (int o = 0; o < 8; ++o) {
-      const int ex_ = o & 1, ey_ = (o >> 1) & 1;
-      const int qz = (o >> 2) ? qz1 : qz0;
+    for (int o = 0; o < 8; ++o)
 #pragma unroll
-      for (int j = 0; j < N; ++j) {
-        const double c = (double)w[o][j] * tv;
-        if (qz == 0)
-          acc[ex_][ey_][0][j] += c;
-        else
-          acc[ex_][ey_][1][j] += c;
-      }
+      for (int j = 0; j < N; ++j) acc[c][o & 1][(o >> 1) & 1][o >> 2][j] += (double)w[o][j] * tv;
+  };
+
+  // Element-column combination and segment sums over each region's columns of
+  // the octant sums; the leader lane of every region adds them to the per-(g, Y)
+  // partials of B_n tv (without cw) in part[vec], regions m0 (oz = 0) and m1.
+  auto flushB = [&](Acc& acc, int vec, int m0, int m1) {
+#pragma unroll
+    for (int c = 0; c < CPT; ++c)
+#pragma unroll
+      for (int ey_ = 0; ey_ < 2; ++ey_)
+#pragma unroll
+        for (int oz = 0; oz < 2; ++oz)
+#pragma unroll
+          for (int j = 0; j < N; ++j) {
+            double v = acc[c][1][ey_][oz][j] + from_right(acc[c][0][ey_][oz][j], X, NC);
+            v = seg_sum(v, sbw);
+            const int qz = oz ? m1 : m0;
+            if (X % sbw == 0)
+              part[vec * PARTV + ((((g * NC + Yc(c)) * 2 + ey_) * S + X / sbw) * S + qz) * N + j] += v;
+          }
+  };
+
+  // Clear the partials owned by this lane (region leaders) before a sweep.
+  auto clear_part = [&](int vec) {
+    if (X % sbw == 0) {
+      for (int c = 0; c < CPT; ++c)
+        for (int ey_ = 0; ey_ < 2; ++ey_)
+          for (int qz = 0; qz < S; ++qz)
+            for (int j = 0; j < N; ++j)
+              part[vec * PARTV + ((((g * NC + Yc(c)) * 2 + ey_) * S + X / sbw) * S + qz) * N + j] = 0.0;
     }
   };
 
-  // Element-column combination, segment sums over each region's columns and
-  // the per-(g, Y) partials of B_n tv (without cw) into part[vec].
-  auto flushB = [&](double (&acc)[2][2][S][N], int vec) {
+  auto zero_acc = [&](Acc& acc) {
 #pragma unroll
-    for (int ey_ = 0; ey_ < 2; ++ey_)
+    for (int c = 0; c < CPT; ++c)
 #pragma unroll
-      for (int qz = 0; qz < S; ++qz)
+      for (int ex_ = 0; ex_ < 2; ++ex_)
 #pragma unroll
-        for (int j = 0; j < N; ++j) {
-          double v = acc[1][ey_][qz][j] + from_right(acc[0][ey_][qz][j], X, NC);
-          v = seg_sum(v, sbw);
-          if (X % sbw == 0) part[vec * PARTV + ((((g * NC + Y) * 2 + ey_) * S + X / sbw) * S + qz) * N + j] = v;
-        }
+        for (int ey_ = 0; ey_ < 2; ++ey_)
+#pragma unroll
+          for (int oz = 0; oz < 2; ++oz)
+#pragma unroll
+            for (int j = 0; j < N; ++j) acc[c][ex_][ey_][oz][j] = 0.0;
   };
 
   // Row k of B_n (vector vec) summed over planes and node rows in fixed order.
@@ -639,52 +707,42 @@ __global__ __launch_bounds__(nt3<NC>()) void k_solve3d(CellArgs a) {
     return wave_sum(vu);
   };
 
-  // cw*v of the thread's octant regions: vs[ox][oy][qz][j].
-  auto load_vs = [&](double (&vs)[2][2][S][N]) {
+  // cw*v of the octant regions of the thread's columns for a segment.
+  auto load_vs = [&](Acc& vs, int m0, int m1) {
     const double* vv = vW + wave * m;
 #pragma unroll
-    for (int ex_ = 0; ex_ < 2; ++ex_)
+    for (int c = 0; c < CPT; ++c) {
+      const int Y = Yc(c);
+      const int qy0 = (Y >= 1 ? Y - 1 : 0) / sbw, qy1 = Y / sbw;
 #pragma unroll
-      for (int ey_ = 0; ey_ < 2; ++ey_)
+      for (int ex_ = 0; ex_ < 2; ++ex_)
 #pragma unroll
-        for (int qz = 0; qz < S; ++qz)
+        for (int ey_ = 0; ey_ < 2; ++ey_)
 #pragma unroll
-          for (int j = 0; j < N; ++j) {
-            const int qx = ex_ ? qx1 : qx0, qy = ey_ ? qy1 : qy0;
-            vs[ex_][ey_][qz][j] = vv[((qz * S + qy) * S + qx) * N + j];
-          }
+          for (int oz = 0; oz < 2; ++oz)
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+              const int qx = ex_ ? qx1 : qx0, qy = ey_ ? qy1 : qy0, qz = oz ? m1 : m0;
+              vs[c][ex_][ey_][oz][j] = vv[((qz * S + qy) * S + qx) * N + j];
+            }
+    }
   };
 
-  // (B_n^T cw v) at node (X, Y, Z).
-  auto scatB = [&](const double (&vs)[2][2][S][N], const float (&w)[8][N], int Z) -> double {
-    const int qz0 = (Z - 1) / sbw, qz1 = Z / sbw;
+  // (B_n^T cw v) at a node of column c.
+  auto scatB = [&](const Acc& vs, int c, const float (&w)[8][N]) -> double {
     double t = 0.0;
 #pragma unroll
-    for (int o = 0; o < 8; ++o) {
-      const int ex_ = o & 1, ey_ = (o >> 1) & 1;
-      const int qz = (o >> 2) ? qz1 : qz0;
+    for (int o = 0; o < 8; ++o)
 #pragma unroll
-      for (int j = 0; j < N; ++j) t += (double)w[o][j] * (qz == 0 ? vs[ex_][ey_][0][j] : vs[ex_][ey_][1][j]);
-    }
+      for (int j = 0; j < N; ++j) t += (double)w[o][j] * vs[c][o & 1][(o >> 1) & 1][o >> 2][j];
     return t;
-  };
-
-  auto zero_acc = [&](double (&acc)[2][2][S][N]) {
-#pragma unroll
-    for (int ex_ = 0; ex_ < 2; ++ex_)
-#pragma unroll
-      for (int ey_ = 0; ey_ < 2; ++ey_)
-#pragma unroll
-        for (int qz = 0; qz < S; ++qz)
-#pragma unroll
-          for (int j = 0; j < N; ++j) acc[ex_][ey_][qz][j] = 0.0;
   };
 
   // Right-hand side f at node (X, Y, Z).
   const int nn1 = a.nc + 1;
-  auto rhs = [&](int Z) -> double {
+  auto rhs = [&](int Y, int Z) -> double {
     if (!a.adjoint) {
-      if constexpr (GAL) return a.fin[((size_t)ci * M + alpha) * NODES + node_of(Z)];
+      if constexpr (GAL) return a.fin[((size_t)ci * M + alpha) * NODES + node_of(Y, Z)];
       return 0.0;
     }
     const int r = a.r, H = a.H, Hp = H + 1, k0 = (a.nc - H) / 2;
@@ -715,59 +773,67 @@ __global__ __launch_bounds__(nt3<NC>()) void k_solve3d(CellArgs a) {
 
   // ---- feasible start x0 = D^-1 B^T S^-1 g' -----------------------------------
   double Vacc = 0.0, vk = 0.0;
-  double vs[2][2][S][N];
   (void)wave_schur(&vk);
-  load_vs(vs);
-  for (int i = 0; i < SPT; ++i) {
-    const int Z = g + G * i;
-    if (!colfree || Z < 1) continue;
-    float w[8][N];
-    node_weights(Z, w);
-    const double x0 = dinv[node_of(Z)] * scatB(vs, w, Z);
-    const size_t c = nidx3(X, Y, Z, NP);
-    pv[c] = x0;
-    xv[c] = x0;
+  {
+    Acc vs;
+    sweep([&](int m0, int m1) { load_vs(vs, m0, m1); },
+          [&](int c, int Z) {
+            const int Y = Yc(c);
+            float w[8][N];
+            node_weights(Y, Z, w);
+            const double x0 = dinv[node_of(Y, Z)] * scatB(vs, c, w);
+            const size_t q = nidx3(X, Y, Z, NP);
+            pv[q] = x0;
+            xv[q] = x0;
+          },
+          nop2);
   }
   __syncthreads();
   // r0 = K x0 - f, t0 = D^-1 r0, r0.t0 and B t0
   {
-    double acc[2][2][S][N];
+    Acc acc;
     zero_acc(acc);
+    clear_part(0);
     double s_rr = 0.0;
-    for (int i = 0; i < SPT; ++i) {
-      const int Z = g + G * i;
-      if (!colfree || Z < 1) continue;
-      float w[8][N];
-      node_weights(Z, w);
-      const size_t c = nidx3(X, Y, Z, NP);
-      const double rr0 = applyK(pv, Z) - rhs(Z);
-      const double t = dinv[node_of(Z)] * rr0;
-      s_rr += rr0 * t;
-      accB(acc, w, t, Z);
-      rv[c] = rr0;
-    }
-    flushB(acc, 0);
+    sweep(nop2,
+          [&](int c, int Z) {
+            const int Y = Yc(c);
+            float w[8][N];
+            node_weights(Y, Z, w);
+            const size_t q = nidx3(X, Y, Z, NP);
+            const double rr0 = applyK(pv, Y, Z) - rhs(Y, Z);
+            const double t = dinv[node_of(Y, Z)] * rr0;
+            s_rr += rr0 * t;
+            accB(acc, c, w, t);
+            rv[q] = rr0;
+          },
+          [&](int m0, int m1) {
+            flushB(acc, 0, m0, m1);
+            zero_acc(acc);
+          });
     s_rr = wave_sum(s_rr);
     if (lane == 0) red[wave * 4] = s_rr;
   }
   __syncthreads();
-  double rr = 0.0;
-  for (int w2 = 0; w2 < NW; ++w2) rr += red[w2 * 4];
+  const double rr = wave_sum(lane < NW ? red[lane * 4] : 0.0);
   for (int k = lane; k < m; k += 64) uw[k] = cwS[k] * zsum(0, k);
   double vu = wave_schur(&vk);
   Vacc = vk;
   double rz = rr - vu;
   const double rz0 = rz;
-  load_vs(vs);
-  for (int i = 0; i < SPT; ++i) {
-    const int Z = g + G * i;
-    if (!colfree || Z < 1) continue;
-    float w[8][N];
-    node_weights(Z, w);
-    const size_t c = nidx3(X, Y, Z, NP);
-    const double rp = rv[c] - scatB(vs, w, Z);
-    rv[c] = rp;
-    pv[c] = -dinv[node_of(Z)] * rp;
+  {
+    Acc vs;
+    sweep([&](int m0, int m1) { load_vs(vs, m0, m1); },
+          [&](int c, int Z) {
+            const int Y = Yc(c);
+            float w[8][N];
+            node_weights(Y, Z, w);
+            const size_t q = nidx3(X, Y, Z, NP);
+            const double rp = rv[q] - scatB(vs, c, w);
+            rv[q] = rp;
+            pv[q] = -dinv[node_of(Y, Z)] * rp;
+          },
+          nop2);
   }
   __syncthreads();
 
@@ -775,33 +841,51 @@ __global__ __launch_bounds__(nt3<NC>()) void k_solve3d(CellArgs a) {
   int it = 0;
   bool done = !(rz0 > 0.0);
   while (!done) {
-    // phase A: K p, the fused reductions and the constraint partials
     const bool withz0 = (it % ZPERIOD3) == 0;
     double s4[4] = {0.0, 0.0, 0.0, 0.0};
+    // phase A: K p, the dot products and the constraint partials B D^-1 Ap
     {
-      double accA[2][2][S][N], accT[2][2][S][N];
+      Acc accA;
       zero_acc(accA);
+      clear_part(1);
+      sweep(nop2,
+            [&](int c, int Z) {
+              const int Y = Yc(c);
+              const size_t q = nidx3(X, Y, Z, NP);
+              const double Ap = applyK(pv, Y, Z);
+              av[q] = Ap;
+              const double rn = rv[q], pn = pv[q];
+              const double di = dinv[node_of(Y, Z)];
+              const double t = di * rn, tA = di * Ap;
+              s4[0] += pn * Ap;
+              s4[1] += rn * t;
+              s4[2] += t * Ap;
+              s4[3] += Ap * tA;
+              float w[8][N];
+              node_weights(Y, Z, w);
+              accB(accA, c, w, tA);
+            },
+            [&](int m0, int m1) {
+              flushB(accA, 1, m0, m1);
+              zero_acc(accA);
+            });
+    }
+    // every ZPERIOD3 iterations: B D^-1 r' from scratch (a separate sweep)
+    if (withz0) {
+      Acc accT;
       zero_acc(accT);
-      for (int i = 0; i < SPT; ++i) {
-        const int Z = g + G * i;
-        if (!colfree || Z < 1) continue;
-        float w[8][N];
-        node_weights(Z, w);
-        const size_t c = nidx3(X, Y, Z, NP);
-        const double Ap = applyK(pv, Z);
-        av[c] = Ap;
-        const double d = dinv[node_of(Z)];
-        const double rn = rv[c], pn = pv[c];
-        const double t = d * rn, tA = d * Ap;
-        s4[0] += pn * Ap;
-        s4[1] += rn * t;
-        s4[2] += t * Ap;
-        s4[3] += Ap * tA;
-        accB(accA, w, tA, Z);
-        if (withz0) accB(accT, w, t, Z);
-      }
-      if (withz0) flushB(accT, 0);
-      flushB(accA, 1);
+      clear_part(0);
+      sweep(nop2,
+            [&](int c, int Z) {
+              const int Y = Yc(c);
+              float w[8][N];
+              node_weights(Y, Z, w);
+              accB(accT, c, w, dinv[node_of(Y, Z)] * rv[nidx3(X, Y, Z, NP)]);
+            },
+            [&](int m0, int m1) {
+              flushB(accT, 0, m0, m1);
+              zero_acc(accT);
+            });
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -809,13 +893,11 @@ __global__ __launch_bounds__(nt3<NC>()) void k_solve3d(CellArgs a) {
       if (lane == 0) red[wave * 4 + q] = v;
     }
     __syncthreads();
-    double pAp = 0.0, rrk = 0.0, rA = 0.0, AA = 0.0;
-    for (int w2 = 0; w2 < NW; ++w2) {
-      pAp += red[w2 * 4 + 0];
-      rrk += red[w2 * 4 + 1];
-      rA += red[w2 * 4 + 2];
-      AA += red[w2 * 4 + 3];
-    }
+    // cross-wave sums: lane w2 < NW holds wave w2's partials (fixed DPP order)
+    const double pAp = wave_sum(lane < NW ? red[lane * 4 + 0] : 0.0);
+    const double rrk = wave_sum(lane < NW ? red[lane * 4 + 1] : 0.0);
+    const double rA = wave_sum(lane < NW ? red[lane * 4 + 2] : 0.0);
+    const double AA = wave_sum(lane < NW ? red[lane * 4 + 3] : 0.0);
     const double al = rrk / pAp;
     const double rDr = rrk + 2.0 * al * rA + al * al * AA;
     for (int k = lane; k < m; k += 64) uw[k] = cwS[k] * ((withz0 ? zsum(0, k) : 0.0) + al * zsum(1, k));
@@ -824,30 +906,33 @@ __global__ __launch_bounds__(nt3<NC>()) void k_solve3d(CellArgs a) {
     const double rzn = rDr - vu;
     ++it;
     if (rzn <= tol2 || it >= a.max_iter) {
-      for (int i = 0; i < SPT; ++i) {
-        const int Z = g + G * i;
-        if (!colfree || Z < 1) continue;
-        const size_t c = nidx3(X, Y, Z, NP);
-        xv[c] += al * pv[c];
-      }
+      sweep(nop2,
+            [&](int c, int Z) {
+              const size_t q = nidx3(X, Yc(c), Z, NP);
+              xv[q] += al * pv[q];
+            },
+            nop2);
       rz = rzn;
       break;
     }
     const double be = rzn / rrk;
     rz = rzn;
     // phase B: x, projected residual and the new direction
-    load_vs(vs);
-    for (int i = 0; i < SPT; ++i) {
-      const int Z = g + G * i;
-      if (!colfree || Z < 1) continue;
-      float w[8][N];
-      node_weights(Z, w);
-      const size_t c = nidx3(X, Y, Z, NP);
-      const double pn = pv[c];
-      xv[c] += al * pn;
-      const double rn = rv[c] + al * av[c] - scatB(vs, w, Z);
-      rv[c] = rn;
-      pv[c] = -dinv[node_of(Z)] * rn + be * pn;
+    {
+      Acc vs;
+      sweep([&](int m0, int m1) { load_vs(vs, m0, m1); },
+            [&](int c, int Z) {
+              const int Y = Yc(c);
+              float w[8][N];
+              node_weights(Y, Z, w);
+              const size_t q = nidx3(X, Y, Z, NP);
+              const double pn = pv[q];
+              xv[q] += al * pn;
+              const double rn = rv[q] + al * av[q] - scatB(vs, c, w);
+              rv[q] = rn;
+              pv[q] = -dinv[node_of(Y, Z)] * rn + be * pn;
+            },
+            nop2);
     }
     __syncthreads();
   }
@@ -1222,7 +1307,7 @@ bool shape_supported_3d(int NC, int s, int N) {
 template <int NC, int N, bool GAL>
 static int launch_solve3_t(const CellArgs& a, hipStream_t s) {
   constexpr int NT = nt3<NC>();
-  constexpr int NW = NT / 64, G = NT / (NC * NC);
+  constexpr int NW = NT / 64, G = NT > NC * NC ? NT / (NC * NC) : 1;
   const int MS = (a.m + a.J - 1) / a.J;
   const size_t lds =
       ((size_t)4 * NW + 2 * (size_t)G * NC * 2 * S3D * S3D * N + (size_t)MS * 64 + a.m + 2 * (size_t)NW * a.m) *
