@@ -274,11 +274,14 @@ def main():
     roof = None
     if dom.startswith(("solve_L", "adjsolve_L")):
         li = int(dom.split("_L")[1]) - 1
-        flops = solve_flops(run, li, aiters if dom.startswith("adj") else iters, lev_pm)
+        # a level may run as several launches (chunks); per launch = per step / launches
+        nl = ktab[dom]["launches_per_step"]
+        flops = solve_flops(run, li, aiters if dom.startswith("adj") else iters, lev_pm) / nl
         achieved = flops / (ktab[dom]["avg_ms"] * 1e-3) / 1e12
         roof = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
-                "traffic": measured_traffic(args.workload, dom), "flops_per_launch": flops}
+                "traffic": measured_traffic(args.workload, dom), "flops_per_launch": flops,
+                "launches_per_step": nl}
     solves = plan.P * plan.M
     fwd_ms = phases["solve_ms"]
     detail = {

@@ -30,7 +30,7 @@ __global__ __launch_bounds__(BT) void k_seed2d(CellArgs a, const double* gA, dou
   double* ph = sm;                // [MM][Hp*Hp]
   double* G = ph + MM * Hp * Hp;  // [MM*MM]
   const int tid = threadIdx.x;
-  const int ci = blockIdx.x;
+  const int ci = a.ci0 + blockIdx.x;
   const int p = a.cells[ci];
   const int k0 = (a.nc - H) / 2;
   for (int k = tid; k < MM * Hp * Hp; k += BT) {
@@ -95,7 +95,7 @@ __global__ __launch_bounds__(BT) void k_grad2d(CellArgs a, const double* w, doub
   double* pwS = phS + nn1 * nn1;     // [nn1^2]
   double* gS = pwS + nn1 * nn1;      // [nc^2]
   const int tid = threadIdx.x;
-  const int ci = blockIdx.x;
+  const int ci = a.ci0 + blockIdx.x;
   const int p = a.cells[ci];
   const size_t NNl = (size_t)(a.NC + 1) * (a.NC + 1);
   for (int e = tid; e < nc * nc; e += BT) gS[e] = 0.0;
@@ -141,7 +141,7 @@ __global__ __launch_bounds__(BT) void k_ibar2d(CellArgs a, LevelTab lt, const in
   double* cmS = kS + nc * nc;        // [m] cw * mu
   uint8_t* labS = reinterpret_cast<uint8_t*>(cmS + m);  // [nc^2]
   const int tid = threadIdx.x;
-  const int t = blockIdx.x / a.M, al = blockIdx.x % a.M;
+  const int t = a.ci0 + blockIdx.x / a.M, al = blockIdx.x % a.M;
   const int k0 = (nc - H) / 2, sb = nc / s;
   for (int nd = tid; nd < nn1 * nn1; nd += BT) accS[nd] = 0.0;
   for (int ch = child_ptr[t]; ch < child_ptr[t + 1]; ++ch) {
@@ -224,9 +224,11 @@ static int set_lds(F fn, size_t lds) {
   return MCH_OK;
 }
 
-// Backward DAG: seeds of every level in parallel; the inheriting levels'
-// adjoint solves and gradient windows on their side streams; the level-1
-// seeds from the inheriting cells, the level-1 adjoint and the gather on s.
+// Backward DAG: seeds of every level in parallel; each inheriting level's
+// adjoint solves and gradient windows on its side stream; on s, once all of
+// them are done, the level-1 seeds from the inheriting cells, the level-1
+// adjoint and gradient, and the gather. (The level-1 seeds are latency-bound
+// per workgroup, so splitting them into chunks would lengthen the path.)
 int launch_backward_2d(mch_plan* pl, const double* kappa, const double* gA, double* glogk, hipStream_t s) {
   const int M = pl->M, nc = pl->cfg.n_cell, nn1 = nc + 1;
   char name[32];
@@ -236,94 +238,84 @@ int launch_backward_2d(mch_plan* pl, const double* kappa, const double* gA, doub
   const size_t lds_grad = ((size_t)2 * nn1 * nn1 + (size_t)nc * nc) * sizeof(double);
   rc = set_lds(k_grad2d, lds_grad);
   if (rc) return rc;
-  for (int l = pl->L - 1; l >= 0; --l) {
-    if (pl->lev[l].count == 0) continue;
-    hipStream_t t = l == 0 ? s : pl->side[l];
+  void (*seed)(CellArgs, const double*, double*, double*) = nullptr;
+  switch (M) {
+    case 3: seed = k_seed2d<3>; break;
+    case 6: seed = k_seed2d<6>; break;
+    case 9: seed = k_seed2d<9>; break;
+    default: return set_error(MCH_ENOTIMPL, "M");
+  }
+  auto launch_grad = [&](const CellArgs& g, hipStream_t t, int l) -> int {
+    if (g.count == 0) return MCH_OK;
+    std::snprintf(name, sizeof(name), "grad_L%d", l + 1);
+    ProfScope ps(pl, name, t);
+    hipLaunchKernelGGL(k_grad2d, dim3(g.count), dim3(BT), lds_grad, t, g, pl->lev[l].d_w, pl->d_gcell);
+    return hip_check(hipGetLastError(), "launch k_grad2d");
+  };
+  auto adjoint_args = [&](int l) {
     CellArgs a = base_args(pl, kappa, pl->fwd_label, l);
-    const size_t lds = ((size_t)M * (a.H + 1) * (a.H + 1) + (size_t)M * M) * sizeof(double);
-    void (*fn)(CellArgs, const double*, double*, double*) = nullptr;
-    switch (M) {
-      case 3: fn = k_seed2d<3>; break;
-      case 6: fn = k_seed2d<6>; break;
-      case 9: fn = k_seed2d<9>; break;
-      default: return set_error(MCH_ENOTIMPL, "M");
-    }
-    rc = set_lds(fn, lds);
-    if (rc) return rc;
-    std::snprintf(name, sizeof(name), "seed_L%d", l + 1);
-    {
-      ProfScope ps(pl, name, t);
-      hipLaunchKernelGGL(fn, dim3(a.count), dim3(BT), lds, t, a, gA, pl->d_seed_kp, pl->d_gk);
-    }
-    if ((rc = hip_check(hipGetLastError(), "launch k_seed2d"))) return rc;
-    if (l == 0) continue;
     a.adjoint = 1;
     a.out = pl->lev[l].d_w;
     a.beta = pl->d_mu;
     a.iters = pl->d_iters_adj;
     a.resid = pl->d_resid_adj;
+    return a;
+  };
+  for (int l = pl->L - 1; l >= 0; --l) {
+    if (pl->lev[l].count == 0) continue;
+    hipStream_t t = l == 0 ? s : pl->side[l];
+    CellArgs a = base_args(pl, kappa, pl->fwd_label, l);
+    const size_t lds = ((size_t)M * (a.H + 1) * (a.H + 1) + (size_t)M * M) * sizeof(double);
+    rc = set_lds(seed, lds);
+    if (rc) return rc;
+    std::snprintf(name, sizeof(name), "seed_L%d", l + 1);
+    {
+      ProfScope ps(pl, name, t);
+      hipLaunchKernelGGL(seed, dim3(a.count), dim3(BT), lds, t, a, gA, pl->d_seed_kp, pl->d_gk);
+    }
+    if ((rc = hip_check(hipGetLastError(), "launch k_seed2d"))) return rc;
+    if (l == 0) continue;
     std::snprintf(name, sizeof(name), "adjsolve_L%d", l + 1);
     {
       ProfScope ps(pl, name, t);
-      rc = launch_solve(a, pl->lev[l].shape.rpt, t);
+      rc = launch_solve(adjoint_args(l), pl->lev[l].shape.rpt, t);
     }
+    if (!rc) rc = launch_grad(base_args(pl, kappa, pl->fwd_label, l), t, l);
     if (rc) return rc;
-    CellArgs g = base_args(pl, kappa, pl->fwd_label, l);
-    std::snprintf(name, sizeof(name), "grad_L%d", l + 1);
-    {
-      ProfScope ps(pl, name, t);
-      hipLaunchKernelGGL(k_grad2d, dim3(g.count), dim3(BT), lds_grad, t, g, pl->lev[l].d_w, pl->d_gcell);
-    }
-    if ((rc = hip_check(hipGetLastError(), "launch k_grad2d"))) return rc;
   }
+  const int n1 = pl->lev[0].count;
+  const bool inherit = pl->L > 1 && n1 > 0 && n1 < pl->P;
+  CellArgs a1 = base_args(pl, kappa, pl->fwd_label, 0);
+  LevelTab lt{};
+  for (int l = 0; l < pl->L; ++l) {
+    lt.r[l] = pl->lev[l].r;
+    lt.NC[l] = pl->lev[l].NC;
+    lt.w[l] = pl->lev[l].d_w;
+  }
+  const size_t lds_ibar = ((size_t)2 * nn1 * nn1 + (size_t)nc * nc + pl->m) * sizeof(double) + (size_t)nc * nc;
+  if (inherit && (rc = set_lds(k_ibar2d, lds_ibar))) return rc;
   rc = join_levels(pl, s);
-  if (rc) return rc;
-  // seeds of the level-1 cells from their inheriting cells
-  const bool inherit = pl->L > 1 && pl->lev[0].count > 0 && pl->lev[0].count < pl->P;
-  if (inherit) {
-    CellArgs a = base_args(pl, kappa, pl->fwd_label, 0);
-    LevelTab lt{};
-    for (int l = 0; l < pl->L; ++l) {
-      lt.r[l] = pl->lev[l].r;
-      lt.NC[l] = pl->lev[l].NC;
-      lt.w[l] = pl->lev[l].d_w;
-    }
-    const size_t lds = ((size_t)2 * nn1 * nn1 + (size_t)nc * nc + pl->m) * sizeof(double) + (size_t)nc * nc;
-    rc = set_lds(k_ibar2d, lds);
-    if (rc) return rc;
-    {
+  if (!rc && n1 > 0) {
+    if (inherit) {
       ProfScope ps(pl, "ibar", s);
-      hipLaunchKernelGGL(k_ibar2d, dim3(pl->lev[0].count * M), dim3(BT), lds, s, a, lt, pl->d_level, pl->d_child_ptr,
+      hipLaunchKernelGGL(k_ibar2d, dim3(n1 * M), dim3(BT), lds_ibar, s, a1, lt, pl->d_level, pl->d_child_ptr,
                          pl->d_child, pl->d_mu, pl->d_seed_par);
+      rc = hip_check(hipGetLastError(), "launch k_ibar2d");
     }
-    if ((rc = hip_check(hipGetLastError(), "launch k_ibar2d"))) return rc;
-  }
-  if (pl->lev[0].count > 0) {
-    CellArgs a = base_args(pl, kappa, pl->fwd_label, 0);
-    a.adjoint = 1;
-    a.out = pl->lev[0].d_w;
-    a.beta = pl->d_mu;
-    a.iters = pl->d_iters_adj;
-    a.resid = pl->d_resid_adj;
-    a.seed_par = inherit ? pl->d_seed_par : nullptr;
-    {
+    if (!rc) {
+      CellArgs a = adjoint_args(0);
+      a.seed_par = inherit ? pl->d_seed_par : nullptr;
       ProfScope ps(pl, "adjsolve_L1", s);
       rc = launch_solve(a, pl->lev[0].shape.rpt, s);
     }
-    if (rc) return rc;
-    CellArgs g = base_args(pl, kappa, pl->fwd_label, 0);
-    {
-      ProfScope ps(pl, "grad_L1", s);
-      hipLaunchKernelGGL(k_grad2d, dim3(g.count), dim3(BT), lds_grad, s, g, pl->lev[0].d_w, pl->d_gcell);
-    }
-    if ((rc = hip_check(hipGetLastError(), "launch k_grad2d"))) return rc;
+    if (!rc) rc = launch_grad(a1, s, 0);
   }
-  CellArgs a = base_args(pl, kappa, pl->fwd_label, 0);
+  if (rc) return rc;
   const size_t total = (size_t)pl->n * pl->n;
   const unsigned blocks = (unsigned)((total + 255) / 256 < 65536 ? (total + 255) / 256 : 65536);
   {
     ProfScope ps(pl, "gather", s);
-    hipLaunchKernelGGL(k_gather_grad2d, dim3(blocks), dim3(256), 0, s, a, pl->d_gk, pl->d_gcell, glogk);
+    hipLaunchKernelGGL(k_gather_grad2d, dim3(blocks), dim3(256), 0, s, a1, pl->d_gk, pl->d_gcell, glogk);
   }
   return hip_check(hipGetLastError(), "launch k_gather_grad2d");
 }

@@ -108,7 +108,7 @@ __global__ __launch_bounds__(T3) void k_setup3d(CellArgs a) {
   double* partS = wred + (T3 / 64) * N * 4;  // npairs*NC
   __shared__ int singular;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int ci = blockIdx.x;
+  const int ci = a.ci0 + blockIdx.x;
   const int p = a.cells[ci];
   int ox, oy, oz;
   cell_origin3(a, p, ox, oy, oz);
@@ -375,7 +375,7 @@ __global__ __launch_bounds__(T3) void k_inherit3d(CellArgs a) {
   double* F = sm;                 // [2][L2][8]
   double* accR = F + 2 * L2 * 8;  // [T3][2][N]
   const int tid = threadIdx.x;
-  const int ci = blockIdx.x / M, al = blockIdx.x % M;
+  const int ci = a.ci0 + blockIdx.x / M, al = blockIdx.x % M;
   const int p = a.cells[ci];
   int ox, oy, oz;
   cell_origin3(a, p, ox, oy, oz);
@@ -513,7 +513,7 @@ __global__ __launch_bounds__(nt3<NC>()) void k_solve3d(CellArgs a) {
   // columns (X, Y0 + c YS), c < CPT; planes Z = g + G i (g uniform across a wave)
   const int X = tid % NC, Y0 = (tid / NC) % YS;
   const int g = __builtin_amdgcn_readfirstlane(tid / (NC * YS));
-  const int ci = blockIdx.x / M, alpha = blockIdx.x % M;
+  const int ci = a.ci0 + blockIdx.x / M, alpha = blockIdx.x % M;
   const int p = a.cells[ci];
   const size_t vbase = ((size_t)ci * M + alpha) * (size_t)NP * NP * NP;
   double* __restrict__ xv = a.out + vbase;
@@ -951,7 +951,7 @@ __global__ __launch_bounds__(nt3<NC>()) void k_solve3d(CellArgs a) {
 // Phi on the K_p nodes of every cell of a level: phikp[p][alpha][(H+1)^3].
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(T3) void k_phikp3d(CellArgs a) {
-  const int ci = blockIdx.x / a.M, al = blockIdx.x % a.M;
+  const int ci = a.ci0 + blockIdx.x / a.M, al = blockIdx.x % a.M;
   const int p = a.cells[ci];
   const int H = a.H, Hp = H + 1, k0 = (a.nc - H) / 2;
   const int tot = Hp * Hp * Hp;
@@ -975,7 +975,7 @@ __global__ __launch_bounds__(T3) void k_eff3d(CellArgs a, double* A) {
   __shared__ double wr[T3 / 64][MM * MM];
   const int H = a.H, Hp = H + 1, n = a.n, nm = a.n_macro;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int p = a.cells[blockIdx.x];
+  const int p = a.cells[a.ci0 + blockIdx.x];
   const int jx = p % nm, jy = (p / nm) % nm, jz = p / (nm * nm);
   const size_t tot = (size_t)Hp * Hp * Hp;
   const double* ph = a.phikp + (size_t)p * MM * tot;
@@ -1029,7 +1029,7 @@ __global__ __launch_bounds__(T3) void k_seed3d(CellArgs a, const double* gA, dou
   __shared__ double G[MM * MM];
   const int H = a.H, Hp = H + 1, n = a.n, nm = a.n_macro;
   const int tid = threadIdx.x;
-  const int p = a.cells[blockIdx.x];
+  const int p = a.cells[a.ci0 + blockIdx.x];
   const int jx = p % nm, jy = (p / nm) % nm, jz = p / (nm * nm);
   const size_t tot = (size_t)Hp * Hp * Hp;
   const double* ph = a.phikp + (size_t)p * MM * tot;
@@ -1092,7 +1092,7 @@ __global__ __launch_bounds__(T3) void k_seed3d(CellArgs a, const double* gA, dou
 // the nc^3 fine elements of the cell (one workgroup per cell).
 __global__ __launch_bounds__(T3) void k_grad3d(CellArgs a, const double* w, double* gcell) {
   const int nc = a.nc, nn1 = nc + 1, r = a.r, NC = a.NC, NP = NC + 1, M = a.M;
-  const int ci = blockIdx.x;
+  const int ci = a.ci0 + blockIdx.x;
   const int p = a.cells[ci];
   const size_t NN = (size_t)NP * NP * NP, nn = (size_t)nn1 * nn1 * nn1;
   const double hk = a.h / 12.0, inv_r = 1.0 / r;
@@ -1162,7 +1162,7 @@ __global__ __launch_bounds__(T3) void k_ibar3d(CellArgs a, LevelTab3 lt, const i
                                                const int32_t* child, const double* mu, double* seed_par) {
   const int nc = a.nc, nn1 = nc + 1, H = a.H, Hp = H + 1, m = a.m, N = a.N, s = a.s, M = a.M;
   const int tid = threadIdx.x;
-  const int t = blockIdx.x / M, al = blockIdx.x % M;
+  const int t = a.ci0 + blockIdx.x / M, al = blockIdx.x % M;
   const int k0 = (nc - H) / 2, sb = nc / s;
   const size_t nn = (size_t)nn1 * nn1 * nn1;
   double* acc = seed_par + ((size_t)t * M + al) * nn;
@@ -1319,6 +1319,30 @@ static int launch_solve3_t(const CellArgs& a, hipStream_t s) {
   return hip_check(hipGetLastError(), "launch k_solve3d");
 }
 
+int solve_blocks_per_cu_3d(mch_plan* pl) {
+  CellArgs a = base_args(pl, nullptr, nullptr, 0);
+  a.J = schur_lanes3(a.m);
+  const void* fn = nullptr;
+  int threads = 0;
+  size_t lds = 0;
+#define X(nc_, n_, g_)                                                                                  \
+  if (!g_ && a.NC == nc_ && a.N == n_) {                                                                \
+    constexpr int NT = nt3<nc_>(), NW = NT / 64, G = NT > nc_ * nc_ ? NT / (nc_ * nc_) : 1;             \
+    const int MS = (a.m + a.J - 1) / a.J;                                                               \
+    lds = ((size_t)4 * NW + 2 * (size_t)G * nc_ * 2 * S3D * S3D * n_ + (size_t)MS * 64 + a.m +          \
+           2 * (size_t)NW * a.m) * sizeof(double);                                                      \
+    fn = reinterpret_cast<const void*>(k_solve3d<nc_, n_, false>);                                      \
+    threads = NT;                                                                                       \
+  }
+  MCH_SHAPES3(X)
+#undef X
+  if (!fn) return set_error(MCH_ENOTIMPL, "no 3D solve kernel for this cell shape");
+  int nb = 0;
+  int rc = hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, threads, lds),
+                     "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+  return rc ? rc : nb;
+}
+
 static int launch_solve3(const CellArgs& a_in, hipStream_t s) {
   CellArgs a = a_in;
   a.J = schur_lanes3(a.m);
@@ -1365,8 +1389,9 @@ static int launch_phikp3(const CellArgs& a, hipStream_t s) {
 }
 
 // Forward DAG, as in 2D: setups of levels >= 2 on their side streams from the
-// start; level 1 set-up and solve on s; then every level >= 2 inherits,
-// solves and writes Phi on K_p on its own stream; Phi on K_p of level 1 on s.
+// start; level 1 set-up and solve on s in two chunks; every level >= 2
+// inherits, solves and writes Phi on K_p for the cells of chunk A once chunk
+// A is done, the rest once level 1 is done; Phi on K_p of level 1 on s.
 int launch_forward_3d(mch_plan* pl, const double* kappa, const uint8_t* label, hipStream_t s) {
   char name[32];
   int rc = ensure_streams(pl);
@@ -1378,40 +1403,54 @@ int launch_forward_3d(mch_plan* pl, const double* kappa, const uint8_t* label, h
     ProfScope ps(pl, name, pl->side[l]);
     rc = launch_setup3(a, pl->side[l]);
   }
-  if (!rc && pl->lev[0].count) {
+  const int n1 = pl->lev[0].count, n1a = pl->n1a;
+  if (!rc && n1) {
     CellArgs a = base_args(pl, kappa, label, 0);
     {
       ProfScope ps(pl, "setup_L1", s);
       rc = launch_setup3(a, s);
     }
-    if (!rc) {
+    if (!rc && n1a > 0) {
       ProfScope ps(pl, "solve_L1", s);
-      rc = launch_solve3(a, s);
+      rc = launch_solve3(chunk_args(a, 0, n1a), s);
     }
+    if (!rc) rc = hip_check(hipEventRecord(pl->ev_l1a, s), "hipEventRecord");
+    if (!rc && n1 > n1a) {
+      ProfScope ps(pl, "solve_L1", s);
+      rc = launch_solve3(chunk_args(a, n1a, n1 - n1a), s);
+    }
+  } else if (!rc) {
+    rc = hip_check(hipEventRecord(pl->ev_l1a, s), "hipEventRecord");
   }
   if (!rc) rc = hip_check(hipEventRecord(pl->ev_l1, s), "hipEventRecord");
   for (int l = 1; l < pl->L && !rc; ++l) {
-    if (pl->lev[l].count == 0) continue;
+    const int cnt = pl->lev[l].count, ca = pl->cntA[l];
+    if (cnt == 0) continue;
     hipStream_t t = pl->side[l];
-    rc = hip_check(hipStreamWaitEvent(t, pl->ev_l1, 0), "hipStreamWaitEvent");
     CellArgs a = base_args(pl, kappa, label, l);
-    if (!rc) {
-      std::snprintf(name, sizeof(name), "inherit_L%d", l + 1);
-      ProfScope ps(pl, name, t);
-      rc = launch_inherit3(a, t);
-    }
-    if (!rc) {
-      std::snprintf(name, sizeof(name), "solve_L%d", l + 1);
-      ProfScope ps(pl, name, t);
-      rc = launch_solve3(a, t);
-    }
-    if (!rc) {
-      std::snprintf(name, sizeof(name), "phikp_L%d", l + 1);
-      ProfScope ps(pl, name, t);
-      rc = launch_phikp3(a, t);
+    for (int part = 0; part < 2 && !rc; ++part) {
+      const int start = part ? ca : 0, num = part ? cnt - ca : ca;
+      rc = hip_check(hipStreamWaitEvent(t, part ? pl->ev_l1 : pl->ev_l1a, 0), "hipStreamWaitEvent");
+      if (rc || num == 0) continue;
+      const CellArgs c = chunk_args(a, start, num);
+      {
+        std::snprintf(name, sizeof(name), "inherit_L%d", l + 1);
+        ProfScope ps(pl, name, t);
+        rc = launch_inherit3(c, t);
+      }
+      if (!rc) {
+        std::snprintf(name, sizeof(name), "solve_L%d", l + 1);
+        ProfScope ps(pl, name, t);
+        rc = launch_solve3(c, t);
+      }
+      if (!rc) {
+        std::snprintf(name, sizeof(name), "phikp_L%d", l + 1);
+        ProfScope ps(pl, name, t);
+        rc = launch_phikp3(c, t);
+      }
     }
   }
-  if (!rc && pl->lev[0].count) {
+  if (!rc && n1) {
     CellArgs a = base_args(pl, kappa, label, 0);
     ProfScope ps(pl, "phikp_L1", s);
     rc = launch_phikp3(a, s);
@@ -1460,6 +1499,22 @@ int launch_backward_3d(mch_plan* pl, const double* kappa, const double* gA, doub
     case 12: seed = k_seed3d<12>; break;
     default: return set_error(MCH_ENOTIMPL, "M");
   }
+  auto launch_grad = [&](const CellArgs& g, hipStream_t t, int l) -> int {
+    if (g.count == 0) return MCH_OK;
+    std::snprintf(name, sizeof(name), "grad_L%d", l + 1);
+    ProfScope ps(pl, name, t);
+    hipLaunchKernelGGL(k_grad3d, dim3(g.count), dim3(T3), 0, t, g, pl->lev[l].d_w, pl->d_gcell);
+    return hip_check(hipGetLastError(), "launch k_grad3d");
+  };
+  auto adjoint_args = [&](int l) {
+    CellArgs a = base_args(pl, kappa, pl->fwd_label, l);
+    a.adjoint = 1;
+    a.out = pl->lev[l].d_w;
+    a.beta = pl->d_mu;
+    a.iters = pl->d_iters_adj;
+    a.resid = pl->d_resid_adj;
+    return a;
+  };
   for (int l = pl->L - 1; l >= 0; --l) {
     if (pl->lev[l].count == 0) continue;
     hipStream_t t = l == 0 ? s : pl->side[l];
@@ -1471,69 +1526,45 @@ int launch_backward_3d(mch_plan* pl, const double* kappa, const double* gA, doub
     }
     if ((rc = hip_check(hipGetLastError(), "launch k_seed3d"))) return rc;
     if (l == 0) continue;
-    a.adjoint = 1;
-    a.out = pl->lev[l].d_w;
-    a.beta = pl->d_mu;
-    a.iters = pl->d_iters_adj;
-    a.resid = pl->d_resid_adj;
     std::snprintf(name, sizeof(name), "adjsolve_L%d", l + 1);
     {
       ProfScope ps(pl, name, t);
-      rc = launch_solve3(a, t);
+      rc = launch_solve3(adjoint_args(l), t);
     }
+    if (!rc) rc = launch_grad(base_args(pl, kappa, pl->fwd_label, l), t, l);
     if (rc) return rc;
-    CellArgs gg = base_args(pl, kappa, pl->fwd_label, l);
-    std::snprintf(name, sizeof(name), "grad_L%d", l + 1);
-    {
-      ProfScope ps(pl, name, t);
-      hipLaunchKernelGGL(k_grad3d, dim3(gg.count), dim3(T3), 0, t, gg, pl->lev[l].d_w, pl->d_gcell);
-    }
-    if ((rc = hip_check(hipGetLastError(), "launch k_grad3d"))) return rc;
+  }
+  const int n1 = pl->lev[0].count;
+  const bool inherit = pl->L > 1 && n1 > 0 && n1 < pl->P;
+  CellArgs a1 = base_args(pl, kappa, pl->fwd_label, 0);
+  LevelTab3 lt{};
+  for (int l = 0; l < pl->L; ++l) {
+    lt.r[l] = pl->lev[l].r;
+    lt.NC[l] = pl->lev[l].NC;
+    lt.w[l] = pl->lev[l].d_w;
   }
   rc = join_levels(pl, s);
-  if (rc) return rc;
-  const bool inherit = pl->L > 1 && pl->lev[0].count > 0 && pl->lev[0].count < pl->P;
-  if (inherit) {
-    CellArgs a = base_args(pl, kappa, pl->fwd_label, 0);
-    LevelTab3 lt{};
-    for (int l = 0; l < pl->L; ++l) {
-      lt.r[l] = pl->lev[l].r;
-      lt.NC[l] = pl->lev[l].NC;
-      lt.w[l] = pl->lev[l].d_w;
-    }
-    {
+  if (!rc && n1 > 0) {
+    if (inherit) {
       ProfScope ps(pl, "ibar", s);
-      hipLaunchKernelGGL(k_ibar3d, dim3(pl->lev[0].count * M), dim3(T3), 0, s, a, lt, pl->d_level, pl->d_child_ptr,
-                         pl->d_child, pl->d_mu, pl->d_seed_par);
+      hipLaunchKernelGGL(k_ibar3d, dim3(n1 * M), dim3(T3), 0, s, a1, lt, pl->d_level, pl->d_child_ptr, pl->d_child,
+                         pl->d_mu, pl->d_seed_par);
+      rc = hip_check(hipGetLastError(), "launch k_ibar3d");
     }
-    if ((rc = hip_check(hipGetLastError(), "launch k_ibar3d"))) return rc;
-  }
-  if (pl->lev[0].count > 0) {
-    CellArgs a = base_args(pl, kappa, pl->fwd_label, 0);
-    a.adjoint = 1;
-    a.out = pl->lev[0].d_w;
-    a.beta = pl->d_mu;
-    a.iters = pl->d_iters_adj;
-    a.resid = pl->d_resid_adj;
-    a.seed_par = inherit ? pl->d_seed_par : nullptr;
-    {
+    if (!rc) {
+      CellArgs a = adjoint_args(0);
+      a.seed_par = inherit ? pl->d_seed_par : nullptr;
       ProfScope ps(pl, "adjsolve_L1", s);
       rc = launch_solve3(a, s);
     }
-    if (rc) return rc;
-    CellArgs gg = base_args(pl, kappa, pl->fwd_label, 0);
-    {
-      ProfScope ps(pl, "grad_L1", s);
-      hipLaunchKernelGGL(k_grad3d, dim3(gg.count), dim3(T3), 0, s, gg, pl->lev[0].d_w, pl->d_gcell);
-    }
-    if ((rc = hip_check(hipGetLastError(), "launch k_grad3d"))) return rc;
+    if (!rc) rc = launch_grad(a1, s, 0);
   }
-  CellArgs a = base_args(pl, kappa, pl->fwd_label, 0);
+  if (rc) return rc;
   const size_t total = (size_t)pl->n * pl->n * pl->n;
   const unsigned blocks = (unsigned)((total + 255) / 256 < 65536 ? (total + 255) / 256 : 65536);
   {
     ProfScope ps(pl, "gather", s);
-    hipLaunchKernelGGL(k_gather_grad3d, dim3(blocks), dim3(256), 0, s, a, pl->d_gk, pl->d_gcell, glogk);
+    hipLaunchKernelGGL(k_gather_grad3d, dim3(blocks), dim3(256), 0, s, a1, pl->d_gk, pl->d_gcell, glogk);
   }
   return hip_check(hipGetLastError(), "launch k_gather_grad3d");
 }

@@ -90,7 +90,8 @@ struct CellArgs {
   int sbw;                // sub-block width in level elements (nc / s / r)
   const int32_t* cells;   // [count] macropoint ids of this level
   const int32_t* pslot;   // [count] level-1 slot of the inherited point (levels >= 2)
-  int count;
+  int count;              // cells in this launch (a chunk of the level)
+  int ci0;                // index within the level of the launch's first cell
   // per-point data
   double* cw;             // [P][m] 1 / (4 n_qj), 0 for inactive rows
   double* g;              // [P][M][m]

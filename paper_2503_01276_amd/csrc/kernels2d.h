@@ -7,6 +7,8 @@
 namespace mch {
 // Kernel arguments for the cells of level l (0-based) of a plan.
 CellArgs base_args(mch_plan* pl, const double* kappa, const uint8_t* label, int l);
+// The same arguments restricted to cells [start, start + count) of the level.
+CellArgs chunk_args(const CellArgs& a, int start, int count);
 // Launch the constrained Krylov solve of every (cell, right-hand side) of a.
 int launch_solve(const CellArgs& a, int rpt, hipStream_t s);
 // Per-cell setup (constraint rows, right-hand sides, Galerkin data, S^-1).

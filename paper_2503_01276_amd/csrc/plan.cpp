@@ -1,6 +1,7 @@
 // Plan construction: configuration checks, the macrogrid hierarchy
 // (Sec. 3.1, Eq. defi_Sn), per-level kernel shapes, Galerkin tables for the
 // nested spaces V_n (Sec. 3.2) and device scratch.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -111,6 +112,13 @@ static void build_hierarchy(mch_plan* p) {
     p->slot[q] = (int32_t)lv.cells.size();
     lv.cells.push_back(q);
   }
+  // levels >= 2: order by the slot of the inherited level-1 cell (stable)
+  for (int n = 1; n < L; ++n) {
+    std::vector<int32_t>& c = p->lev[n].cells;
+    std::stable_sort(c.begin(), c.end(),
+                     [&](int32_t a, int32_t b) { return p->slot[p->parent[a]] < p->slot[p->parent[b]]; });
+    for (size_t k = 0; k < c.size(); ++k) p->slot[c[k]] = (int32_t)k;
+  }
 }
 
 // Coarse-element tables of the Galerkin operator for a level with ratio r:
@@ -201,6 +209,7 @@ int ensure_streams(mch_plan* p) {
   if (p->ev_fork) return MCH_OK;
   int rc = hip_check(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming), "hipEventCreate");
   if (!rc) rc = hip_check(hipEventCreateWithFlags(&p->ev_l1, hipEventDisableTiming), "hipEventCreate");
+  if (!rc) rc = hip_check(hipEventCreateWithFlags(&p->ev_l1a, hipEventDisableTiming), "hipEventCreate");
   for (int l = 1; l < p->L && !rc; ++l) {
     rc = hip_check(hipStreamCreateWithFlags(&p->side[l], hipStreamNonBlocking), "hipStreamCreate");
     if (!rc) rc = hip_check(hipEventCreateWithFlags(&p->ev_join[l], hipEventDisableTiming), "hipEventCreate");
@@ -244,6 +253,7 @@ extern "C" void mch_destroy(mch_plan* plan) {
   }
   if (plan->ev_fork) (void)hipEventDestroy(plan->ev_fork);
   if (plan->ev_l1) (void)hipEventDestroy(plan->ev_l1);
+  if (plan->ev_l1a) (void)hipEventDestroy(plan->ev_l1a);
   for (auto& r : plan->prof) {
     if (r.start) (void)hipEventDestroy(r.start);
     if (r.stop) (void)hipEventDestroy(r.stop);
@@ -403,6 +413,30 @@ extern "C" int mch_build_levels(const mch_config* cfg, mch_plan** out) {
       if (p->parent[q] >= 0) child[fill[p->slot[p->parent[q]]]++] = q;
     rc = upload(p, &p->d_child_ptr, ptr);
     if (!rc) rc = upload(p, &p->d_child, child);
+  }
+  // level-1 chunks (see plan.h): the tail is the last partial round of
+  // workgroups; with no partial round, or a single level, there is one chunk
+  if (!rc) {
+    const size_t n1c = p->lev[0].count;
+    p->n1a = (int)n1c;
+    int cus = 0;
+    rc = hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device),
+                   "hipDeviceGetAttribute");
+    int bpc = 0;
+    if (!rc && p->L > 1 && n1c > 0) {
+      bpc = d == 3 ? solve_blocks_per_cu_3d(p) : solve_blocks_per_cu_2d(p);
+      if (bpc < 0) rc = bpc;
+    }
+    if (!rc && bpc > 0) {
+      const size_t slots = (size_t)cus * bpc, W = n1c * p->M, T = W % slots;
+      if (W > slots && T != 0) p->n1a = (int)(n1c - (T + p->M - 1) / p->M);
+    }
+    for (int l = 1; l < p->L && !rc; ++l) {
+      int c = 0;
+      for (int32_t q : p->lev[l].cells)
+        if (p->slot[p->parent[q]] < p->n1a) ++c;
+      p->cntA[l] = c;
+    }
   }
   if (rc) {
     mch_destroy(p);

@@ -100,6 +100,13 @@ struct mch_plan {
   // levels >= 2 depend only on level 1, so they run as parallel branches
   hipStream_t side[mch::MAX_LEVELS] = {};
   hipEvent_t ev_fork = nullptr, ev_l1 = nullptr;
+  // Level 1 runs in two chunks: cells [0, n1a) fill the GPU n times over and
+  // the rest form the tail of the last round. The cells of every level >= 2
+  // are ordered by the slot of their level-1 cell, so the first cntA[l] of
+  // them inherit from chunk A and can run while the tail still solves.
+  int n1a = 0;
+  int cntA[mch::MAX_LEVELS] = {};
+  hipEvent_t ev_l1a = nullptr;
   hipEvent_t ev_join[mch::MAX_LEVELS] = {};
   // captured launch sequences, replayed while the arguments are unchanged
   struct Graph {
@@ -146,4 +153,7 @@ int launch_eff_3d(mch_plan* p, const double* kappa, double* A, hipStream_t s);
 int launch_backward_3d(mch_plan* p, const double* kappa, const double* gA, double* glogk, hipStream_t s);
 int launch_local_solutions_3d(mch_plan* p, const int64_t* cells, int64_t n, double* out, hipStream_t s);
 bool shape_supported_3d(int NC, int s, int N);
+// Workgroups of the level-1 solve kernel that fit on one CU at once.
+int solve_blocks_per_cu_2d(mch_plan* p);
+int solve_blocks_per_cu_3d(mch_plan* p);
 }  // namespace mch

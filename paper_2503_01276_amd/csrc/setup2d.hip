@@ -79,7 +79,7 @@ __global__ __launch_bounds__(SETUP_T) void k_setup2d(CellArgs a) {
   uint8_t* labS = reinterpret_cast<uint8_t*>(partS + npairs * R);  // fine: NC*NC
   __shared__ int singular;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int ci = blockIdx.x;
+  const int ci = a.ci0 + blockIdx.x;
   const int p = a.cells[ci];
   const int jx = p % a.n_macro, jy = p / a.n_macro;
   const int ox = a.H * jx + a.H / 2 - nc / 2, oy = a.H * jy + a.H / 2 - nc / 2;
@@ -321,7 +321,7 @@ __global__ __launch_bounds__(SETUP_T) void k_inherit2d(CellArgs a) {
   double* accq = FE + NC * NC * 4;    // NC^2 * N element sums of I per continuum
   uint8_t* labS = reinterpret_cast<uint8_t*>(accq + NC * NC * N);  // nc^2
   const int tid = threadIdx.x;
-  const int ci = blockIdx.x;
+  const int ci = a.ci0 + blockIdx.x;
   const int p = a.cells[ci];
   const int jx = p % a.n_macro, jy = p / a.n_macro;
   const int ox = a.H * jx + a.H / 2 - nc / 2, oy = a.H * jy + a.H / 2 - nc / 2;

@@ -65,7 +65,7 @@ __global__ __launch_bounds__(NC* NC / RPT) void k_solve2d(CellArgs a) {
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int c = tid % NC, band = tid / NC, y0 = band * RPT;
-  const int ci = blockIdx.x / M, alpha = blockIdx.x % M;
+  const int ci = a.ci0 + blockIdx.x / M, alpha = blockIdx.x % M;
   const int p = a.cells[ci];
   const int jx = p % a.n_macro, jy = p / a.n_macro;
   const int ox = a.H * jx + a.H / 2 - a.nc / 2, oy = a.H * jy + a.H / 2 - a.nc / 2;
@@ -479,7 +479,7 @@ __global__ __launch_bounds__(EFF_T) void k_eff2d(CellArgs a, double* A) {
   double* ph = sm;  // [MM][Hp*Hp]
   double* wr = ph + MM * Hp * Hp;  // [EFF_T/64][MM*MM]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int ci = blockIdx.x;
+  const int ci = a.ci0 + blockIdx.x;
   const int p = a.cells[ci];
   const int k0 = (a.nc - H) / 2;
   for (int k = tid; k < MM * Hp * Hp; k += EFF_T) {
@@ -647,10 +647,43 @@ int launch_solve(const CellArgs& a_in, int rpt, hipStream_t s) {
   return set_error(MCH_ENOTIMPL, "no kernel for this cell shape");
 }
 
+int solve_blocks_per_cu_2d(mch_plan* pl) {
+  CellArgs a = base_args(pl, nullptr, nullptr, 0);
+  const int rpt = pl->lev[0].shape.rpt;
+  const size_t lds = solve_lds_bytes(a.NC, rpt, a.s, a.N, a.m, false);
+  const void* fn = nullptr;
+  int threads = 0;
+#define X(nc_, r_, n_, g_)                                              \
+  if (!g_ && a.NC == nc_ && rpt == r_ && a.N == n_) {                   \
+    fn = reinterpret_cast<const void*>(k_solve2d<nc_, r_, n_, false>); \
+    threads = nc_ * nc_ / r_;                                           \
+  }
+  MCH_SHAPES(X)
+#undef X
+  if (!fn) return set_error(MCH_ENOTIMPL, "no kernel for this cell shape");
+  if (lds > 64 * 1024) {
+    int rc = hip_check(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
+                       "hipFuncSetAttribute");
+    if (rc) return rc;
+  }
+  int nb = 0;
+  int rc = hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, threads, lds),
+                     "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+  return rc ? rc : nb;
+}
+
+CellArgs chunk_args(const CellArgs& a, int start, int count) {
+  CellArgs c = a;
+  c.ci0 = start;
+  c.count = count;
+  return c;
+}
+
 // Forward DAG: the setups of levels >= 2 need only kappa and labels and run
 // on their side streams from the start (they fill the CUs left idle by the
-// level-1 solve); each level >= 2 then waits for level 1 and runs its
-// inherit and solve kernels on its own stream, in parallel with the others.
+// level-1 solve). Level 1 solves in two chunks; each level >= 2 inherits and
+// solves the cells of chunk A once chunk A is done (alongside the tail chunk
+// B of level 1), then the rest once level 1 is done.
 int launch_forward_2d(mch_plan* pl, const double* kappa, const uint8_t* label, hipStream_t s) {
   char name[32];
   int rc = ensure_streams(pl);
@@ -662,32 +695,46 @@ int launch_forward_2d(mch_plan* pl, const double* kappa, const uint8_t* label, h
     ProfScope ps(pl, name, pl->side[l]);
     rc = launch_setup(a, pl->side[l]);
   }
-  if (!rc && pl->lev[0].count) {
+  const int n1 = pl->lev[0].count, n1a = pl->n1a;
+  if (!rc && n1) {
     CellArgs a = base_args(pl, kappa, label, 0);
     {
       ProfScope ps(pl, "setup_L1", s);
       rc = launch_setup(a, s);
     }
-    if (!rc) {
+    if (!rc && n1a > 0) {
       ProfScope ps(pl, "solve_L1", s);
-      rc = launch_solve(a, pl->lev[0].shape.rpt, s);
+      rc = launch_solve(chunk_args(a, 0, n1a), pl->lev[0].shape.rpt, s);
     }
+    if (!rc) rc = hip_check(hipEventRecord(pl->ev_l1a, s), "hipEventRecord");
+    if (!rc && n1 > n1a) {
+      ProfScope ps(pl, "solve_L1", s);
+      rc = launch_solve(chunk_args(a, n1a, n1 - n1a), pl->lev[0].shape.rpt, s);
+    }
+  } else if (!rc) {
+    rc = hip_check(hipEventRecord(pl->ev_l1a, s), "hipEventRecord");
   }
   if (!rc) rc = hip_check(hipEventRecord(pl->ev_l1, s), "hipEventRecord");
   for (int l = 1; l < pl->L && !rc; ++l) {
-    if (pl->lev[l].count == 0) continue;
+    const int cnt = pl->lev[l].count, ca = pl->cntA[l];
+    if (cnt == 0) continue;
     hipStream_t t = pl->side[l];
-    rc = hip_check(hipStreamWaitEvent(t, pl->ev_l1, 0), "hipStreamWaitEvent");
     CellArgs a = base_args(pl, kappa, label, l);
-    if (!rc) {
-      std::snprintf(name, sizeof(name), "inherit_L%d", l + 1);
-      ProfScope ps(pl, name, t);
-      rc = launch_inherit(a, t);
-    }
-    if (!rc) {
-      std::snprintf(name, sizeof(name), "solve_L%d", l + 1);
-      ProfScope ps(pl, name, t);
-      rc = launch_solve(a, pl->lev[l].shape.rpt, t);
+    for (int part = 0; part < 2 && !rc; ++part) {
+      const int start = part ? ca : 0, num = part ? cnt - ca : ca;
+      rc = hip_check(hipStreamWaitEvent(t, part ? pl->ev_l1 : pl->ev_l1a, 0), "hipStreamWaitEvent");
+      if (rc || num == 0) continue;
+      const CellArgs c = chunk_args(a, start, num);
+      {
+        std::snprintf(name, sizeof(name), "inherit_L%d", l + 1);
+        ProfScope ps(pl, name, t);
+        rc = launch_inherit(c, t);
+      }
+      if (!rc) {
+        std::snprintf(name, sizeof(name), "solve_L%d", l + 1);
+        ProfScope ps(pl, name, t);
+        rc = launch_solve(c, pl->lev[l].shape.rpt, t);
+      }
     }
   }
   if (!rc) rc = join_levels(pl, s);
