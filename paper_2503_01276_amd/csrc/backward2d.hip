@@ -88,39 +88,54 @@ __global__ __launch_bounds__(BT) void k_seed2d(CellArgs a, const double* gA, dou
 }
 
 // Per-cell gradient window: gcell[p][e] = -sum_a (P w_a)|_e^T K_ref Phi_a|_e.
+// A thread owns fine elements and loops over the right-hand sides; Phi and
+// P w at the element's corners come from the coarse element's corner values
+// (no LDS, so many workgroups share a CU).
 __global__ __launch_bounds__(BT) void k_grad2d(CellArgs a, const double* w, double* gcell) {
-  extern __shared__ double sm[];
-  const int nc = a.nc, nn1 = nc + 1;
-  double* phS = sm;                  // [nn1^2]
-  double* pwS = phS + nn1 * nn1;     // [nn1^2]
-  double* gS = pwS + nn1 * nn1;      // [nc^2]
-  const int tid = threadIdx.x;
+  const int nc = a.nc, nn1 = nc + 1, r = a.r, NC = a.NC, NP = NC + 1, M = a.M;
   const int ci = a.ci0 + blockIdx.x;
   const int p = a.cells[ci];
-  const size_t NNl = (size_t)(a.NC + 1) * (a.NC + 1);
-  for (int e = tid; e < nc * nc; e += BT) gS[e] = 0.0;
-  for (int al = 0; al < a.M; ++al) {
-    const double* wv = w + ((size_t)ci * a.M + al) * NNl;
-    for (int nd = tid; nd < nn1 * nn1; nd += BT) {
-      const int X = nd % nn1, Y = nd / nn1;
-      phS[nd] = phi_at(a, ci, al, X, Y);
-      pwS[nd] = prolong_at(wv, a.r, a.NC, X, Y);
-    }
-    __syncthreads();
-    for (int e = tid; e < nc * nc; e += BT) {
-      const int ex = e % nc, ey = e / nc;
-      double v[4], y[4];
+  const size_t NN = (size_t)NP * NP, nn = (size_t)nn1 * nn1;
+  const double inv_r = 1.0 / r;
+  for (int e = threadIdx.x; e < nc * nc; e += BT) {
+    const int fx = e % nc, fy = e / nc;
+    const int EX = fx / r, EY = fy / r, ux = fx - EX * r, uy = fy - EY * r;
+    double acc = 0.0;
+    for (int al = 0; al < M; ++al) {
+      const double* wv = w + ((size_t)ci * M + al) * NN;
+      double phi[4], pw[4], y[4];
+      if (r == 1) {
+        const double* xv = a.out + ((size_t)ci * M + al) * nn;
 #pragma unroll
-      for (int d = 0; d < 4; ++d) v[d] = phS[(ey + (d >> 1)) * nn1 + ex + (d & 1)];
-      kref6_apply(v, y);
-      double t = 0.0;
+        for (int d = 0; d < 4; ++d) {
+          const size_t q = (size_t)(fy + (d >> 1)) * nn1 + fx + (d & 1);
+          phi[d] = xv[q];
+          pw[d] = wv[q];
+        }
+      } else {
+        const double* I = a.phi1 + ((size_t)a.pslot[ci] * M + al) * nn;
+        const double* xi = a.out + ((size_t)ci * M + al) * NN;
+        double xe[4], we[4];
 #pragma unroll
-      for (int d = 0; d < 4; ++d) t += pwS[(ey + (d >> 1)) * nn1 + ex + (d & 1)] * y[d];
-      gS[e] -= t * (1.0 / 6.0);
+        for (int c = 0; c < 4; ++c) {
+          const size_t q = (size_t)(EY + (c >> 1)) * NP + EX + (c & 1);
+          xe[c] = xi[q];
+          we[c] = wv[q];
+        }
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+          const double tx = (ux + (d & 1)) * inv_r, ty = (uy + (d >> 1)) * inv_r;
+          const double w00 = (1.0 - tx) * (1.0 - ty), w10 = tx * (1.0 - ty), w01 = (1.0 - tx) * ty, w11 = tx * ty;
+          phi[d] = I[(size_t)(fy + (d >> 1)) * nn1 + fx + (d & 1)] +
+                   ((w00 * xe[0] + w10 * xe[1]) + (w01 * xe[2] + w11 * xe[3]));
+          pw[d] = (w00 * we[0] + w10 * we[1]) + (w01 * we[2] + w11 * we[3]);
+        }
+      }
+      kref6_apply(phi, y);
+      acc -= (pw[0] * y[0] + pw[1] * y[1]) + (pw[2] * y[2] + pw[3] * y[3]);
     }
-    __syncthreads();
+    gcell[(size_t)p * nc * nc + e] = acc * (1.0 / 6.0);
   }
-  for (int e = tid; e < nc * nc; e += BT) gcell[(size_t)p * nc * nc + e] = gS[e];
 }
 
 struct LevelTab {
@@ -131,19 +146,27 @@ struct LevelTab {
 
 // Seeds of level-1 cell t for right-hand side alpha: sum over its inheriting
 // cells c of Ibar_c = Phibar_c - K_h(c) P w_c - B_h(c)^T mu_c on the fine nodes.
-__global__ __launch_bounds__(BT) void k_ibar2d(CellArgs a, LevelTab lt, const int32_t* level, const int32_t* child_ptr,
-                                               const int32_t* child, const double* mu, double* seed_par) {
+// 1024 threads; a thread owns up to IB_NODES fine nodes and keeps their sums
+// in registers; per child the LDS holds P w, kappa/6, labels and cw*mu (about
+// 70 KB for 64^2 cells).
+constexpr int IBT = 1024;
+constexpr int IB_NODES = 5;  // ceil(65^2 / 1024): cells up to 64 elements wide
+
+__global__ __launch_bounds__(IBT) void k_ibar2d(CellArgs a, LevelTab lt, const int32_t* level, const int32_t* child_ptr,
+                                                const int32_t* child, const double* mu, double* seed_par) {
   extern __shared__ double sm[];
   const int nc = a.nc, nn1 = nc + 1, H = a.H, Hp = H + 1, m = a.m, N = a.N, s = a.s;
-  double* accS = sm;                 // [nn1^2]
-  double* pwS = accS + nn1 * nn1;    // [nn1^2]
-  double* kS = pwS + nn1 * nn1;      // [nc^2] kappa/6
+  const int nn = nn1 * nn1;
+  double* pwS = sm;                  // [nn1^2]
+  double* kS = pwS + nn;             // [nc^2] kappa/6
   double* cmS = kS + nc * nc;        // [m] cw * mu
   uint8_t* labS = reinterpret_cast<uint8_t*>(cmS + m);  // [nc^2]
   const int tid = threadIdx.x;
   const int t = a.ci0 + blockIdx.x / a.M, al = blockIdx.x % a.M;
   const int k0 = (nc - H) / 2, sb = nc / s;
-  for (int nd = tid; nd < nn1 * nn1; nd += BT) accS[nd] = 0.0;
+  double acc[IB_NODES];
+#pragma unroll
+  for (int i = 0; i < IB_NODES; ++i) acc[i] = 0.0;
   for (int ch = child_ptr[t]; ch < child_ptr[t + 1]; ++ch) {
     const int p = child[ch];
     const int l = level[p] - 1;
@@ -151,41 +174,52 @@ __global__ __launch_bounds__(BT) void k_ibar2d(CellArgs a, LevelTab lt, const in
     const int jx = p % a.n_macro, jy = p / a.n_macro;
     const int ox = H * jx + H / 2 - nc / 2, oy = H * jy + H / 2 - nc / 2;
     __syncthreads();  // previous child's data fully consumed
-    for (int e = tid; e < nc * nc; e += BT) {
+    for (int e = tid; e < nc * nc; e += IBT) {
       const int ex = e % nc, ey = e / nc;
       const size_t ge = (size_t)wrapi(oy + ey, a.n) * a.n + wrapi(ox + ex, a.n);
       kS[e] = a.kappa[ge] * (1.0 / 6.0);
       labS[e] = a.label[ge];
     }
-    for (int k = tid; k < m; k += BT) cmS[k] = a.cw[(size_t)p * m + k] * mu[((size_t)p * a.M + al) * m + k];
+    for (int k = tid; k < m; k += IBT) cmS[k] = a.cw[(size_t)p * m + k] * mu[((size_t)p * a.M + al) * m + k];
     const double* wv = lt.w[l] + ((size_t)ci * a.M + al) * (size_t)(lt.NC[l] + 1) * (lt.NC[l] + 1);
-    for (int nd = tid; nd < nn1 * nn1; nd += BT) pwS[nd] = prolong_at(wv, lt.r[l], lt.NC[l], nd % nn1, nd / nn1);
+    for (int nd = tid; nd < nn; nd += IBT) pwS[nd] = prolong_at(wv, lt.r[l], lt.NC[l], nd % nn1, nd / nn1);
     __syncthreads();
     const double* skp = a.seed_kp + ((size_t)p * a.M + al) * Hp * Hp;
-    for (int nd = tid; nd < nn1 * nn1; nd += BT) {
+#pragma unroll
+    for (int i = 0; i < IB_NODES; ++i) {
+      const int nd = tid + i * IBT;
+      if (nd >= nn) break;
       const int X = nd % nn1, Y = nd / nn1;
       if (X < 1 || Y < 1 || X >= nc || Y >= nc) continue;
+      double v[3][3];
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) v[dy][dx] = pwS[(Y - 1 + dy) * nn1 + X - 1 + dx];
       double kpw = 0.0, btmu = 0.0;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int ex = X - 1 + (q & 1), ey = Y - 1 + (q >> 1);
+        const int qx = q & 1, qy = q >> 1;
+        const int ex = X - 1 + qx, ey = Y - 1 + qy;
         const int e = ey * nc + ex;
-        double v[4], y[4];
-#pragma unroll
-        for (int d = 0; d < 4; ++d) v[d] = pwS[(ey + (d >> 1)) * nn1 + ex + (d & 1)];
-        kref6_apply(v, y);
-        kpw += kS[e] * y[(X - ex) + 2 * (Y - ey)];
+        const double c[4] = {v[qy][qx], v[qy][qx + 1], v[qy + 1][qx], v[qy + 1][qx + 1]};
+        double y[4];
+        kref6_apply(c, y);
+        kpw += kS[e] * y[(1 - qx) + 2 * (1 - qy)];
         const int lab = labS[e];
         if (lab < N) btmu += cmS[((ey / sb) * s + ex / sb) * N + lab];
       }
       double pb = 0.0;
       if (X >= k0 && Y >= k0 && X <= k0 + H && Y <= k0 + H) pb = skp[(Y - k0) * Hp + (X - k0)];
-      accS[nd] += pb - kpw - btmu;
+      acc[i] += pb - kpw - btmu;
     }
   }
-  __syncthreads();
-  double* dst = seed_par + ((size_t)t * a.M + al) * nn1 * nn1;
-  for (int nd = tid; nd < nn1 * nn1; nd += BT) dst[nd] = accS[nd];
+  double* dst = seed_par + ((size_t)t * a.M + al) * nn;
+#pragma unroll
+  for (int i = 0; i < IB_NODES; ++i) {
+    const int nd = tid + i * IBT;
+    if (nd < nn) dst[nd] = acc[i];
+  }
 }
 
 MCH_DEV int floordiv(int a, int b) {
@@ -235,9 +269,6 @@ int launch_backward_2d(mch_plan* pl, const double* kappa, const double* gA, doub
   int rc = ensure_streams(pl);
   if (!rc) rc = fork_levels(pl, s);
   if (rc) return rc;
-  const size_t lds_grad = ((size_t)2 * nn1 * nn1 + (size_t)nc * nc) * sizeof(double);
-  rc = set_lds(k_grad2d, lds_grad);
-  if (rc) return rc;
   void (*seed)(CellArgs, const double*, double*, double*) = nullptr;
   switch (M) {
     case 3: seed = k_seed2d<3>; break;
@@ -249,7 +280,7 @@ int launch_backward_2d(mch_plan* pl, const double* kappa, const double* gA, doub
     if (g.count == 0) return MCH_OK;
     std::snprintf(name, sizeof(name), "grad_L%d", l + 1);
     ProfScope ps(pl, name, t);
-    hipLaunchKernelGGL(k_grad2d, dim3(g.count), dim3(BT), lds_grad, t, g, pl->lev[l].d_w, pl->d_gcell);
+    hipLaunchKernelGGL(k_grad2d, dim3(g.count), dim3(BT), 0, t, g, pl->lev[l].d_w, pl->d_gcell);
     return hip_check(hipGetLastError(), "launch k_grad2d");
   };
   auto adjoint_args = [&](int l) {
@@ -263,7 +294,7 @@ int launch_backward_2d(mch_plan* pl, const double* kappa, const double* gA, doub
   };
   for (int l = pl->L - 1; l >= 0; --l) {
     if (pl->lev[l].count == 0) continue;
-    hipStream_t t = l == 0 ? s : pl->side[l];
+    hipStream_t t = level_stream(pl, l, s);
     CellArgs a = base_args(pl, kappa, pl->fwd_label, l);
     const size_t lds = ((size_t)M * (a.H + 1) * (a.H + 1) + (size_t)M * M) * sizeof(double);
     rc = set_lds(seed, lds);
@@ -292,13 +323,14 @@ int launch_backward_2d(mch_plan* pl, const double* kappa, const double* gA, doub
     lt.NC[l] = pl->lev[l].NC;
     lt.w[l] = pl->lev[l].d_w;
   }
-  const size_t lds_ibar = ((size_t)2 * nn1 * nn1 + (size_t)nc * nc + pl->m) * sizeof(double) + (size_t)nc * nc;
+  if (nc > 64) return set_error(MCH_ENOTIMPL, "2D cells wider than 64 elements");
+  const size_t lds_ibar = ((size_t)nn1 * nn1 + (size_t)nc * nc + pl->m) * sizeof(double) + (size_t)nc * nc;
   if (inherit && (rc = set_lds(k_ibar2d, lds_ibar))) return rc;
   rc = join_levels(pl, s);
   if (!rc && n1 > 0) {
     if (inherit) {
       ProfScope ps(pl, "ibar", s);
-      hipLaunchKernelGGL(k_ibar2d, dim3(n1 * M), dim3(BT), lds_ibar, s, a1, lt, pl->d_level, pl->d_child_ptr,
+      hipLaunchKernelGGL(k_ibar2d, dim3(n1 * M), dim3(IBT), lds_ibar, s, a1, lt, pl->d_level, pl->d_child_ptr,
                          pl->d_child, pl->d_mu, pl->d_seed_par);
       rc = hip_check(hipGetLastError(), "launch k_ibar2d");
     }

@@ -1400,8 +1400,8 @@ int launch_forward_3d(mch_plan* pl, const double* kappa, const uint8_t* label, h
     if (pl->lev[l].count == 0) continue;
     CellArgs a = base_args(pl, kappa, label, l);
     std::snprintf(name, sizeof(name), "setup_L%d", l + 1);
-    ProfScope ps(pl, name, pl->side[l]);
-    rc = launch_setup3(a, pl->side[l]);
+    ProfScope ps(pl, name, level_stream(pl, l, s));
+    rc = launch_setup3(a, level_stream(pl, l, s));
   }
   const int n1 = pl->lev[0].count, n1a = pl->n1a;
   if (!rc && n1) {
@@ -1426,7 +1426,7 @@ int launch_forward_3d(mch_plan* pl, const double* kappa, const uint8_t* label, h
   for (int l = 1; l < pl->L && !rc; ++l) {
     const int cnt = pl->lev[l].count, ca = pl->cntA[l];
     if (cnt == 0) continue;
-    hipStream_t t = pl->side[l];
+    hipStream_t t = level_stream(pl, l, s);
     CellArgs a = base_args(pl, kappa, label, l);
     for (int part = 0; part < 2 && !rc; ++part) {
       const int start = part ? ca : 0, num = part ? cnt - ca : ca;
@@ -1464,7 +1464,7 @@ int launch_eff_3d(mch_plan* pl, const double* kappa, double* A, hipStream_t s) {
   if (!rc) rc = fork_levels(pl, s);
   for (int l = 0; l < pl->L && !rc; ++l) {
     if (pl->lev[l].count == 0) continue;
-    hipStream_t t = l == 0 ? s : pl->side[l];
+    hipStream_t t = level_stream(pl, l, s);
     CellArgs a = base_args(pl, kappa, pl->fwd_label, l);
     void (*fn)(CellArgs, double*) = nullptr;
     switch (a.M) {
@@ -1517,7 +1517,7 @@ int launch_backward_3d(mch_plan* pl, const double* kappa, const double* gA, doub
   };
   for (int l = pl->L - 1; l >= 0; --l) {
     if (pl->lev[l].count == 0) continue;
-    hipStream_t t = l == 0 ? s : pl->side[l];
+    hipStream_t t = level_stream(pl, l, s);
     CellArgs a = base_args(pl, kappa, pl->fwd_label, l);
     std::snprintf(name, sizeof(name), "seed_L%d", l + 1);
     {

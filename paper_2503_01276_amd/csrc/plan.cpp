@@ -218,6 +218,7 @@ int ensure_streams(mch_plan* p) {
 }
 
 int fork_levels(mch_plan* p, hipStream_t s) {
+  if (p->serial) return MCH_OK;
   int rc = hip_check(hipEventRecord(p->ev_fork, s), "hipEventRecord");
   for (int l = 1; l < p->L && !rc; ++l)
     if (p->lev[l].count) rc = hip_check(hipStreamWaitEvent(p->side[l], p->ev_fork, 0), "hipStreamWaitEvent");
@@ -225,6 +226,7 @@ int fork_levels(mch_plan* p, hipStream_t s) {
 }
 
 int join_levels(mch_plan* p, hipStream_t s) {
+  if (p->serial) return MCH_OK;
   int rc = MCH_OK;
   for (int l = 1; l < p->L && !rc; ++l) {
     if (!p->lev[l].count) continue;
@@ -315,6 +317,7 @@ extern "C" int mch_build_levels(const mch_config* cfg, mch_plan** out) {
                                         " free unknowns at the coarsest level");
   }
   if (const char* v = std::getenv("MCH_GRAPHS")) p->use_graphs = std::atoi(v) != 0;
+  if (const char* v = std::getenv("MCH_SERIAL")) p->serial = std::atoi(v) != 0;
   if (hipGetDevice(&p->device) != hipSuccess) {
     delete p;
     return set_error(MCH_EHIP, "no HIP device");

@@ -116,6 +116,7 @@ struct mch_plan {
     hipGraph_t graph = nullptr;
   } g_fwd, g_eff, g_bwd;
   int use_graphs = 1;
+  int serial = 0;  // run every level on the caller's stream (kernel-by-kernel timing)
   // profiling (off by default)
   int profiling = 0;
   std::vector<mch::ProfRec> prof;
@@ -140,6 +141,8 @@ int ensure_streams(mch_plan* p);
 int fork_levels(mch_plan* p, hipStream_t s);
 // Join: s waits for every side stream of levels 2..L.
 int join_levels(mch_plan* p, hipStream_t s);
+// Stream of level l (0-based) in a DAG issued on s.
+inline hipStream_t level_stream(const mch_plan* p, int l, hipStream_t s) { return (l == 0 || p->serial) ? s : p->side[l]; }
 int hip_check(hipError_t e, const char* what);
 
 // Launchers implemented in the .hip translation units.

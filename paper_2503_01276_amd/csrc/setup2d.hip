@@ -309,85 +309,84 @@ __global__ __launch_bounds__(SETUP_T) void k_setup2d(CellArgs a) {
   }
 }
 
-// Inherited right-hand sides of a level >= 2 cell for every alpha:
-// f = -P^T K_h I on the owned level nodes, g' = g - B_h I.
+// Inherited right-hand sides of a level >= 2 cell, one workgroup per
+// (cell, alpha): f = -P^T K_h I on the level nodes and g' = g - B_h I, with I
+// the inherited level-1 solution. A thread computes the load of one level
+// node from the fine elements of its four coarse elements (I, kappa and labels
+// straight from global memory, so the kernel needs no LDS arrays and many
+// workgroups share a CU); B_h I is summed region by region in a fixed order.
 template <int N>
 __global__ __launch_bounds__(SETUP_T) void k_inherit2d(CellArgs a) {
-  extern __shared__ double sm[];
-  const int nc = a.nc, nn1 = nc + 1, NC = a.NC, r = a.r, m = a.m, s = a.s, sbw = a.sbw, M = a.M;
-  double* IS = sm;                    // nn1^2 inherited solution
-  double* kS = IS + nn1 * nn1;        // nc^2 kappa/6
-  double* FE = kS + nc * nc;          // NC^2 * 4 coarse-element load vectors
-  double* accq = FE + NC * NC * 4;    // NC^2 * N element sums of I per continuum
-  uint8_t* labS = reinterpret_cast<uint8_t*>(accq + NC * NC * N);  // nc^2
-  const int tid = threadIdx.x;
-  const int ci = a.ci0 + blockIdx.x;
+  __shared__ double wred[SETUP_T / 64][N];
+  __shared__ double bI[64];
+  const int nc = a.nc, nn1 = nc + 1, NC = a.NC, r = a.r, m = a.m, s = a.s, M = a.M;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int ci = a.ci0 + blockIdx.x / M, al = blockIdx.x % M;
   const int p = a.cells[ci];
   const int jx = p % a.n_macro, jy = p / a.n_macro;
   const int ox = a.H * jx + a.H / 2 - nc / 2, oy = a.H * jy + a.H / 2 - nc / 2;
-  for (int e = tid; e < nc * nc; e += SETUP_T) {
-    const size_t ge = (size_t)wrapi(oy + e / nc, a.n) * a.n + wrapi(ox + e % nc, a.n);
-    kS[e] = a.kappa[ge] * (1.0 / 6.0);
-    labS[e] = a.label[ge];
-  }
+  const double* I = a.phi1 + ((size_t)a.pslot[ci] * M + al) * (size_t)nn1 * nn1;
   const double inv_r = 1.0 / r;
-  for (int al = 0; al < M; ++al) {
-    const double* I = a.phi1 + ((size_t)a.pslot[ci] * M + al) * (size_t)nn1 * nn1;
-    for (int k = tid; k < nn1 * nn1; k += SETUP_T) IS[k] = I[k];
-    __syncthreads();
-    for (int E = tid; E < NC * NC; E += SETUP_T) {
-      const int EX = E % NC, EY = E / NC;
-      double F[4] = {0.0, 0.0, 0.0, 0.0};
-      double acc[N];
+  double* fo = a.fin + ((size_t)ci * M + al) * NC * NC;
+  for (int nd = tid; nd < NC * NC; nd += SETUP_T) {
+    const int Xn = nd % NC, Yn = nd / NC;
+    double t = 0.0;
+    if (Xn >= 1 && Yn >= 1) {
 #pragma unroll
-      for (int j = 0; j < N; ++j) acc[j] = 0.0;
-      for (int v = 0; v < r; ++v)
-        for (int u = 0; u < r; ++u) {
-          const int fx = EX * r + u, fy = EY * r + v;
-          double Iv[4], y[4];
+      for (int q = 0; q < 4; ++q) {
+        const int qx = q & 1, qy = q >> 1;
+        const int EX = Xn - 1 + qx, EY = Yn - 1 + qy;
+        const int cx = 1 - qx, cy = 1 - qy;  // corner of the node in coarse element E
+        for (int v = 0; v < r; ++v)
+          for (int u = 0; u < r; ++u) {
+            const int fx = EX * r + u, fy = EY * r + v;
+            double Iv[4], y[4];
 #pragma unroll
-          for (int d = 0; d < 4; ++d) Iv[d] = IS[(fy + (d >> 1)) * nn1 + fx + (d & 1)];
-          kref6_apply(Iv, y);
-          const double k6 = kS[fy * nc + fx];
+            for (int d = 0; d < 4; ++d) Iv[d] = I[(size_t)(fy + (d >> 1)) * nn1 + fx + (d & 1)];
+            kref6_apply(Iv, y);
+            const double k6 = a.kappa[(size_t)wrapi(oy + fy, a.n) * a.n + wrapi(ox + fx, a.n)] * (1.0 / 6.0);
+            double acc = 0.0;
 #pragma unroll
-          for (int d = 0; d < 4; ++d) {
-            const double xi = (u + (d & 1)) * inv_r, ze = (v + (d >> 1)) * inv_r;
-            const double yd = k6 * y[d];
-            F[0] += (1.0 - xi) * (1.0 - ze) * yd;
-            F[1] += xi * (1.0 - ze) * yd;
-            F[2] += (1.0 - xi) * ze * yd;
-            F[3] += xi * ze * yd;
+            for (int d = 0; d < 4; ++d) {
+              const double tx = (u + (d & 1)) * inv_r, ty = (v + (d >> 1)) * inv_r;
+              acc += (cx ? tx : 1.0 - tx) * (cy ? ty : 1.0 - ty) * y[d];
+            }
+            t += k6 * acc;
           }
-          const int lab = labS[fy * nc + fx];
-          const double es = Iv[0] + Iv[1] + Iv[2] + Iv[3];
+      }
+    }
+    fo[nd] = -t;
+  }
+  // B_h I: element sums of I per region and continuum, region by region
+  const int sb = nc / s;
+  for (int reg = 0; reg < s * s; ++reg) {
+    const int x0 = (reg % s) * sb, y0 = (reg / s) * sb;
+    double acc[N];
 #pragma unroll
-          for (int j = 0; j < N; ++j) acc[j] += (lab == j) ? es : 0.0;
-        }
+    for (int j = 0; j < N; ++j) acc[j] = 0.0;
+    for (int k = tid; k < sb * sb; k += SETUP_T) {
+      const int ex = x0 + k % sb, ey = y0 + k / sb;
+      const int lab = a.label[(size_t)wrapi(oy + ey, a.n) * a.n + wrapi(ox + ex, a.n)];
+      const double es = (I[(size_t)ey * nn1 + ex] + I[(size_t)ey * nn1 + ex + 1]) +
+                        (I[(size_t)(ey + 1) * nn1 + ex] + I[(size_t)(ey + 1) * nn1 + ex + 1]);
 #pragma unroll
-      for (int d = 0; d < 4; ++d) FE[E * 4 + d] = F[d];
+      for (int j = 0; j < N; ++j) acc[j] += (lab == j) ? es : 0.0;
+    }
 #pragma unroll
-      for (int j = 0; j < N; ++j) accq[E * N + j] = acc[j];
+    for (int j = 0; j < N; ++j) {
+      const double v = wave_sum(acc[j]);
+      if (lane == 0) wred[wave][j] = v;
     }
     __syncthreads();
-    double* fo = a.fin + ((size_t)ci * M + al) * NC * NC;
-    for (int nd = tid; nd < NC * NC; nd += SETUP_T) {
-      const int Xn = nd % NC, Yn = nd / NC;
-      double t = 0.0;
-      if (Xn >= 1 && Yn >= 1) {
-        t = FE[(Yn * NC + Xn) * 4 + 0] + FE[(Yn * NC + Xn - 1) * 4 + 1] + FE[((Yn - 1) * NC + Xn) * 4 + 2] +
-            FE[((Yn - 1) * NC + Xn - 1) * 4 + 3];
-      }
-      fo[nd] = -t;
-    }
-    for (int k = tid; k < m; k += SETUP_T) {
-      const int q = k / N, j = k % N, qx = q % s, qy = q / s;
-      double bI = 0.0;
-      for (int ey = qy * sbw; ey < (qy + 1) * sbw; ++ey)
-        for (int ex = qx * sbw; ex < (qx + 1) * sbw; ++ex) bI += accq[(ey * NC + ex) * N + j];
-      a.gin[((size_t)ci * M + al) * m + k] = a.g[((size_t)p * M + al) * m + k] - a.cw[(size_t)p * m + k] * bI;
+    if (tid < N) {
+      double v = 0.0;
+      for (int w2 = 0; w2 < SETUP_T / 64; ++w2) v += wred[w2][tid];
+      bI[reg * N + tid] = v;
     }
     __syncthreads();
   }
+  for (int k = tid; k < m; k += SETUP_T)
+    a.gin[((size_t)ci * M + al) * m + k] = a.g[((size_t)p * M + al) * m + k] - a.cw[(size_t)p * m + k] * bI[k];
 }
 
 static size_t setup_lds_bytes(const CellArgs& a) {
@@ -421,16 +420,13 @@ int launch_setup(const CellArgs& a, hipStream_t s) {
 }
 
 int launch_inherit(const CellArgs& a, hipStream_t s) {
-  const size_t nn1 = a.nc + 1, nc = a.nc, NC = a.NC;
-  const size_t lds = (nn1 * nn1 + nc * nc + NC * NC * 4 + NC * NC * a.N) * sizeof(double) + nc * nc;
+  if (a.m > 64) return set_error(MCH_ENOTIMPL, "more than 64 constraint rows");
   void (*fn)(CellArgs) = nullptr;
   if (a.N == 1) fn = k_inherit2d<1>;
   if (a.N == 2) fn = k_inherit2d<2>;
   if (a.N == 3) fn = k_inherit2d<3>;
   if (!fn) return set_error(MCH_ENOTIMPL, "n_cont");
-  int rc = lds_attr(fn, lds);
-  if (rc) return rc;
-  hipLaunchKernelGGL(fn, dim3(a.count), dim3(SETUP_T), lds, s, a);
+  hipLaunchKernelGGL(fn, dim3(a.count * a.M), dim3(SETUP_T), 0, s, a);
   return hip_check(hipGetLastError(), "launch k_inherit2d");
 }
 

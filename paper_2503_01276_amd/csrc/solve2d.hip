@@ -692,8 +692,8 @@ int launch_forward_2d(mch_plan* pl, const double* kappa, const uint8_t* label, h
     if (pl->lev[l].count == 0) continue;
     CellArgs a = base_args(pl, kappa, label, l);
     std::snprintf(name, sizeof(name), "setup_L%d", l + 1);
-    ProfScope ps(pl, name, pl->side[l]);
-    rc = launch_setup(a, pl->side[l]);
+    ProfScope ps(pl, name, level_stream(pl, l, s));
+    rc = launch_setup(a, level_stream(pl, l, s));
   }
   const int n1 = pl->lev[0].count, n1a = pl->n1a;
   if (!rc && n1) {
@@ -718,7 +718,7 @@ int launch_forward_2d(mch_plan* pl, const double* kappa, const uint8_t* label, h
   for (int l = 1; l < pl->L && !rc; ++l) {
     const int cnt = pl->lev[l].count, ca = pl->cntA[l];
     if (cnt == 0) continue;
-    hipStream_t t = pl->side[l];
+    hipStream_t t = level_stream(pl, l, s);
     CellArgs a = base_args(pl, kappa, label, l);
     for (int part = 0; part < 2 && !rc; ++part) {
       const int start = part ? ca : 0, num = part ? cnt - ca : ca;
@@ -746,7 +746,7 @@ int launch_eff_2d(mch_plan* pl, const double* kappa, double* A, hipStream_t s) {
   if (!rc) rc = fork_levels(pl, s);
   for (int l = 0; l < pl->L && !rc; ++l) {
     if (pl->lev[l].count == 0) continue;
-    hipStream_t t = l == 0 ? s : pl->side[l];
+    hipStream_t t = level_stream(pl, l, s);
     CellArgs a = base_args(pl, kappa, pl->fwd_label, l);
     const size_t lds = ((size_t)a.M * (a.H + 1) * (a.H + 1) + (EFF_T / 64) * (size_t)a.M * a.M) * sizeof(double);
     if (lds > 160 * 1024) return set_error(MCH_EINVAL, "effective-tensor kernel exceeds the LDS budget");
