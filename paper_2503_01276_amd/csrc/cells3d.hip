@@ -476,19 +476,21 @@ __global__ __launch_bounds__(T3) void k_inherit3d(CellArgs a) {
 // ---------------------------------------------------------------------------
 constexpr int ZPERIOD3 = 16;
 
-// 512 threads: the sweep bodies need about 250 VGPRs, which a 1024-thread
-// workgroup cannot give (it would spill to scratch inside the loop).
-template <int NC>
+// At most 512 threads: the sweep bodies need about 250 VGPRs, which a
+// 1024-thread workgroup cannot give (it would spill inside the loop). The
+// fine level uses at most NC^2 threads, so every thread walks whole node
+// columns plane by plane (one plane group), which the z-march below needs.
+template <int NC, bool GAL>
 constexpr int nt3() {
-  return NC * NC * NC >= 512 ? 512 : NC * NC * NC;
+  return GAL ? (NC * NC * NC >= 512 ? 512 : NC * NC * NC) : (NC * NC >= 512 ? 512 : NC * NC);
 }
 
 template <int V>
 using IC = std::integral_constant<int, V>;
 
 template <int NC, int N, bool GAL>
-__global__ __launch_bounds__(nt3<NC>()) void k_solve3d(CellArgs a) {
-  constexpr int NT = nt3<NC>();
+__global__ __launch_bounds__((nt3<NC, GAL>())) void k_solve3d(CellArgs a) {
+  constexpr int NT = nt3<NC, GAL>();
   constexpr int NW = NT / 64;
   constexpr int NP = NC + 1;
   constexpr int NODES = NC * NC * NC;
@@ -761,6 +763,118 @@ __global__ __launch_bounds__(nt3<NC>()) void k_solve3d(CellArgs a) {
     return t;
   };
 
+  // Phase A on the fine level as a z-march: every thread walks its columns
+  // plane by plane with a register window of p (planes Z-1, Z, Z+1 x rows
+  // Y-1, Y, Y+1 at its own x) and of the element coefficients of its x
+  // column; x-1 / x+1 values come from the neighbouring lanes by DPP (lanes of
+  // a row hold consecutive x). One new plane of p and one new element layer
+  // are loaded per step. Every lane runs the march (DPP needs them all);
+  // nodes off the free set contribute nothing.
+  constexpr bool ZM = !GAL && G == 1;
+  auto phaseA_zmarch = [&](double (&s4)[4]) {
+    if constexpr (ZM) {
+      Acc accA;
+      zero_acc(accA);
+      clear_part(1);
+      auto ld_p = [&](int Yr, int Z) -> double {
+        return (Yr >= 0 && Yr <= NC) ? pv[nidx3(X, Yr, Z, NP)] : 0.0;
+      };
+      auto ld_k = [&](int Ye, int layer) -> double {
+        return (Ye >= 0 && Ye <= NC - 1) ? kwc[X + NC * (Ye + NC * layer)] : 0.0;
+      };
+      double wp[CPT][3][3];     // [column][plane Z-1, Z, Z+1][row Y-1, Y, Y+1]
+      double kr[CPT][2][2];     // [column][layer Z-1, Z][oy]: elements (X, Y-1+oy)
+      double kl[CPT][2][2];     // the same for the elements (X-1, Y-1+oy)
+#pragma unroll
+      for (int c = 0; c < CPT; ++c) {
+        const int Y = Yc(c);
+#pragma unroll
+        for (int row = 0; row < 3; ++row) {
+          wp[c][0][row] = 0.0;
+          wp[c][1][row] = ld_p(Y - 1 + row, 1);
+        }
+#pragma unroll
+        for (int oy = 0; oy < 2; ++oy) {
+          kr[c][0][oy] = ld_k(Y - 1 + oy, 0);
+          kl[c][0][oy] = from_left(kr[c][0][oy], X);
+        }
+      }
+#pragma unroll 1
+      for (int Z = 1; Z <= NC - 1; ++Z) {
+        const int m0 = (Z - 1) / sbw, m1 = Z / sbw;
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+          const int Y = Yc(c);
+#pragma unroll
+          for (int row = 0; row < 3; ++row) wp[c][2][row] = (Z + 1 <= NC - 1) ? ld_p(Y - 1 + row, Z + 1) : 0.0;
+#pragma unroll
+          for (int oy = 0; oy < 2; ++oy) kr[c][1][oy] = ld_k(Y - 1 + oy, Z);
+        }
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+          const int Y = Yc(c);
+#pragma unroll
+          for (int oy = 0; oy < 2; ++oy) kl[c][1][oy] = from_left(kr[c][1][oy], X);
+          double k8[8];
+#pragma unroll
+          for (int oz = 0; oz < 2; ++oz)
+#pragma unroll
+            for (int oy = 0; oy < 2; ++oy) {
+              k8[2 * oy + 4 * oz] = kl[c][oz][oy];
+              k8[1 + 2 * oy + 4 * oz] = kr[c][oz][oy];
+            }
+          // neighbour (dx, dy, dz) of the node from the window
+          auto nb = [&](int dx, int dy, int dz) -> double {
+            const double v = wp[c][dz + 1][dy + 1];
+            return dx == 0 ? v : (dx < 0 ? from_left(v, X) : from_right(v, X, NC));
+          };
+          double t = 0.0;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) t += (k8[q] + k8[q + 4]) * nb(2 * (q & 1) - 1, 2 * (q >> 1) - 1, 0);
+#pragma unroll
+          for (int oz = 0; oz < 2; ++oz) {
+            const int sz = 2 * oz - 1;
+            const double* k4 = k8 + 4 * oz;
+            t += (k4[0] + k4[2]) * nb(-1, 0, sz) + (k4[1] + k4[3]) * nb(1, 0, sz);
+            t += (k4[0] + k4[1]) * nb(0, -1, sz) + (k4[2] + k4[3]) * nb(0, 1, sz);
+            t += k4[0] * nb(-1, -1, sz) + k4[1] * nb(1, -1, sz) + k4[2] * nb(-1, 1, sz) + k4[3] * nb(1, 1, sz);
+          }
+          const double D = 4.0 * (((k8[0] + k8[1]) + (k8[2] + k8[3])) + ((k8[4] + k8[5]) + (k8[6] + k8[7])));
+          const double Ap = D * wp[c][1][1] - t;
+          if (colfree(c)) {
+            const size_t q = nidx3(X, Y, Z, NP);
+            av[q] = Ap;
+            const double rn = rv[q], pn = wp[c][1][1];
+            const double di = dinv[node_of(Y, Z)];
+            const double tr = di * rn, tA = di * Ap;
+            s4[0] += pn * Ap;
+            s4[1] += rn * tr;
+            s4[2] += tr * Ap;
+            s4[3] += Ap * tA;
+            float w[8][N];
+            node_weights(Y, Z, w);
+            accB(accA, c, w, tA);
+          }
+#pragma unroll
+          for (int row = 0; row < 3; ++row) {
+            wp[c][0][row] = wp[c][1][row];
+            wp[c][1][row] = wp[c][2][row];
+          }
+#pragma unroll
+          for (int oy = 0; oy < 2; ++oy) {
+            kr[c][0][oy] = kr[c][1][oy];
+            kl[c][0][oy] = kl[c][1][oy];
+          }
+        }
+        const int Zn = Z + 1;
+        if (Z == NC - 1 || (Zn - 1) / sbw != m0 || Zn / sbw != m1) {
+          flushB(accA, 1, m0, m1);
+          zero_acc(accA);
+        }
+      }
+    }
+  };
+
   // ---- right-hand side of the constraints -------------------------------------
   double* uw = uW + wave * m;
   if (!a.adjoint) {
@@ -844,7 +958,9 @@ __global__ __launch_bounds__(nt3<NC>()) void k_solve3d(CellArgs a) {
     const bool withz0 = (it % ZPERIOD3) == 0;
     double s4[4] = {0.0, 0.0, 0.0, 0.0};
     // phase A: K p, the dot products and the constraint partials B D^-1 Ap
-    {
+    if constexpr (ZM) {
+      phaseA_zmarch(s4);
+    } else {
       Acc accA;
       zero_acc(accA);
       clear_part(1);
@@ -1306,7 +1422,7 @@ bool shape_supported_3d(int NC, int s, int N) {
 
 template <int NC, int N, bool GAL>
 static int launch_solve3_t(const CellArgs& a, hipStream_t s) {
-  constexpr int NT = nt3<NC>();
+  constexpr int NT = nt3<NC, GAL>();
   constexpr int NW = NT / 64, G = NT > NC * NC ? NT / (NC * NC) : 1;
   const int MS = (a.m + a.J - 1) / a.J;
   const size_t lds =
@@ -1326,13 +1442,15 @@ int solve_blocks_per_cu_3d(mch_plan* pl) {
   int threads = 0;
   size_t lds = 0;
 #define X(nc_, n_, g_)                                                                                  \
-  if (!g_ && a.NC == nc_ && a.N == n_) {                                                                \
-    constexpr int NT = nt3<nc_>(), NW = NT / 64, G = NT > nc_ * nc_ ? NT / (nc_ * nc_) : 1;             \
-    const int MS = (a.m + a.J - 1) / a.J;                                                               \
-    lds = ((size_t)4 * NW + 2 * (size_t)G * nc_ * 2 * S3D * S3D * n_ + (size_t)MS * 64 + a.m +          \
-           2 * (size_t)NW * a.m) * sizeof(double);                                                      \
-    fn = reinterpret_cast<const void*>(k_solve3d<nc_, n_, false>);                                      \
-    threads = NT;                                                                                       \
+  if constexpr (!g_) {                                                                                  \
+    if (a.NC == nc_ && a.N == n_) {                                                                     \
+      constexpr int NT = nt3<nc_, false>(), NW = NT / 64, G = NT > nc_ * nc_ ? NT / (nc_ * nc_) : 1;    \
+      const int MS = (a.m + a.J - 1) / a.J;                                                             \
+      lds = ((size_t)4 * NW + 2 * (size_t)G * nc_ * 2 * S3D * S3D * n_ + (size_t)MS * 64 + a.m +        \
+             2 * (size_t)NW * a.m) * sizeof(double);                                                    \
+      fn = reinterpret_cast<const void*>(k_solve3d<nc_, n_, false>);                                    \
+      threads = NT;                                                                                     \
+    }                                                                                                   \
   }
   MCH_SHAPES3(X)
 #undef X
