@@ -477,12 +477,12 @@ __global__ __launch_bounds__(T3) void k_inherit3d(CellArgs a) {
 constexpr int ZPERIOD3 = 16;
 
 // At most 512 threads: the sweep bodies need about 250 VGPRs, which a
-// 1024-thread workgroup cannot give (it would spill inside the loop). The
-// fine level uses at most NC^2 threads, so every thread walks whole node
-// columns plane by plane (one plane group), which the z-march below needs.
+// 1024-thread workgroup cannot give (it would spill inside the loop). At most
+// NC^2 threads, so every thread walks whole node columns plane by plane (one
+// plane group), which the z-march below needs.
 template <int NC, bool GAL>
 constexpr int nt3() {
-  return GAL ? (NC * NC * NC >= 512 ? 512 : NC * NC * NC) : (NC * NC >= 512 ? 512 : NC * NC);
+  return NC * NC >= 512 ? 512 : NC * NC;
 }
 
 template <int V>
@@ -770,7 +770,7 @@ __global__ __launch_bounds__((nt3<NC, GAL>())) void k_solve3d(CellArgs a) {
   // a row hold consecutive x). One new plane of p and one new element layer
   // are loaded per step. Every lane runs the march (DPP needs them all);
   // nodes off the free set contribute nothing.
-  constexpr bool ZM = !GAL && G == 1;
+  constexpr bool ZM = G == 1;
   auto phaseA_zmarch = [&](double (&s4)[4]) {
     if constexpr (ZM) {
       Acc accA;
@@ -782,9 +782,10 @@ __global__ __launch_bounds__((nt3<NC, GAL>())) void k_solve3d(CellArgs a) {
       auto ld_k = [&](int Ye, int layer) -> double {
         return (Ye >= 0 && Ye <= NC - 1) ? kwc[X + NC * (Ye + NC * layer)] : 0.0;
       };
+      constexpr int KW = GAL ? 1 : 2;  // element windows only on the fine level
       double wp[CPT][3][3];     // [column][plane Z-1, Z, Z+1][row Y-1, Y, Y+1]
-      double kr[CPT][2][2];     // [column][layer Z-1, Z][oy]: elements (X, Y-1+oy)
-      double kl[CPT][2][2];     // the same for the elements (X-1, Y-1+oy)
+      double kr[CPT][KW][KW];   // [column][layer Z-1, Z][oy]: elements (X, Y-1+oy)
+      double kl[CPT][KW][KW];   // the same for the elements (X-1, Y-1+oy)
 #pragma unroll
       for (int c = 0; c < CPT; ++c) {
         const int Y = Yc(c);
@@ -793,10 +794,12 @@ __global__ __launch_bounds__((nt3<NC, GAL>())) void k_solve3d(CellArgs a) {
           wp[c][0][row] = 0.0;
           wp[c][1][row] = ld_p(Y - 1 + row, 1);
         }
+        if constexpr (!GAL) {
 #pragma unroll
-        for (int oy = 0; oy < 2; ++oy) {
-          kr[c][0][oy] = ld_k(Y - 1 + oy, 0);
-          kl[c][0][oy] = from_left(kr[c][0][oy], X);
+          for (int oy = 0; oy < 2; ++oy) {
+            kr[c][0][oy] = ld_k(Y - 1 + oy, 0);
+            kl[c][0][oy] = from_left(kr[c][0][oy], X);
+          }
         }
       }
 #pragma unroll 1
@@ -807,40 +810,52 @@ __global__ __launch_bounds__((nt3<NC, GAL>())) void k_solve3d(CellArgs a) {
           const int Y = Yc(c);
 #pragma unroll
           for (int row = 0; row < 3; ++row) wp[c][2][row] = (Z + 1 <= NC - 1) ? ld_p(Y - 1 + row, Z + 1) : 0.0;
+          if constexpr (!GAL) {
 #pragma unroll
-          for (int oy = 0; oy < 2; ++oy) kr[c][1][oy] = ld_k(Y - 1 + oy, Z);
+            for (int oy = 0; oy < 2; ++oy) kr[c][1][oy] = ld_k(Y - 1 + oy, Z);
+          }
         }
 #pragma unroll
         for (int c = 0; c < CPT; ++c) {
           const int Y = Yc(c);
-#pragma unroll
-          for (int oy = 0; oy < 2; ++oy) kl[c][1][oy] = from_left(kr[c][1][oy], X);
-          double k8[8];
-#pragma unroll
-          for (int oz = 0; oz < 2; ++oz)
-#pragma unroll
-            for (int oy = 0; oy < 2; ++oy) {
-              k8[2 * oy + 4 * oz] = kl[c][oz][oy];
-              k8[1 + 2 * oy + 4 * oz] = kr[c][oz][oy];
-            }
           // neighbour (dx, dy, dz) of the node from the window
           auto nb = [&](int dx, int dy, int dz) -> double {
             const double v = wp[c][dz + 1][dy + 1];
             return dx == 0 ? v : (dx < 0 ? from_left(v, X) : from_right(v, X, NC));
           };
-          double t = 0.0;
+          double Ap;
+          if constexpr (!GAL) {
 #pragma unroll
-          for (int q = 0; q < 4; ++q) t += (k8[q] + k8[q + 4]) * nb(2 * (q & 1) - 1, 2 * (q >> 1) - 1, 0);
+            for (int oy = 0; oy < 2; ++oy) kl[c][1][oy] = from_left(kr[c][1][oy], X);
+            double k8[8];
 #pragma unroll
-          for (int oz = 0; oz < 2; ++oz) {
-            const int sz = 2 * oz - 1;
-            const double* k4 = k8 + 4 * oz;
-            t += (k4[0] + k4[2]) * nb(-1, 0, sz) + (k4[1] + k4[3]) * nb(1, 0, sz);
-            t += (k4[0] + k4[1]) * nb(0, -1, sz) + (k4[2] + k4[3]) * nb(0, 1, sz);
-            t += k4[0] * nb(-1, -1, sz) + k4[1] * nb(1, -1, sz) + k4[2] * nb(-1, 1, sz) + k4[3] * nb(1, 1, sz);
+            for (int oz = 0; oz < 2; ++oz)
+#pragma unroll
+              for (int oy = 0; oy < 2; ++oy) {
+                k8[2 * oy + 4 * oz] = kl[c][oz][oy];
+                k8[1 + 2 * oy + 4 * oz] = kr[c][oz][oy];
+              }
+            double t = 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) t += (k8[q] + k8[q + 4]) * nb(2 * (q & 1) - 1, 2 * (q >> 1) - 1, 0);
+#pragma unroll
+            for (int oz = 0; oz < 2; ++oz) {
+              const int sz = 2 * oz - 1;
+              const double* k4 = k8 + 4 * oz;
+              t += (k4[0] + k4[2]) * nb(-1, 0, sz) + (k4[1] + k4[3]) * nb(1, 0, sz);
+              t += (k4[0] + k4[1]) * nb(0, -1, sz) + (k4[2] + k4[3]) * nb(0, 1, sz);
+              t += k4[0] * nb(-1, -1, sz) + k4[1] * nb(1, -1, sz) + k4[2] * nb(-1, 1, sz) + k4[3] * nb(1, 1, sz);
+            }
+            const double D = 4.0 * (((k8[0] + k8[1]) + (k8[2] + k8[3])) + ((k8[4] + k8[5]) + (k8[6] + k8[7])));
+            Ap = D * wp[c][1][1] - t;
+          } else {
+            // Galerkin level: the node's 27 stored weights (row of K_n)
+            const double* w = nW + node_of(Y, Z) * 27;
+            double t = 0.0;
+#pragma unroll
+            for (int k = 0; k < 27; ++k) t += w[k] * nb(k % 3 - 1, (k / 3) % 3 - 1, k / 9 - 1);
+            Ap = t;
           }
-          const double D = 4.0 * (((k8[0] + k8[1]) + (k8[2] + k8[3])) + ((k8[4] + k8[5]) + (k8[6] + k8[7])));
-          const double Ap = D * wp[c][1][1] - t;
           if (colfree(c)) {
             const size_t q = nidx3(X, Y, Z, NP);
             av[q] = Ap;
@@ -860,10 +875,12 @@ __global__ __launch_bounds__((nt3<NC, GAL>())) void k_solve3d(CellArgs a) {
             wp[c][0][row] = wp[c][1][row];
             wp[c][1][row] = wp[c][2][row];
           }
+          if constexpr (!GAL) {
 #pragma unroll
-          for (int oy = 0; oy < 2; ++oy) {
-            kr[c][0][oy] = kr[c][1][oy];
-            kl[c][0][oy] = kl[c][1][oy];
+            for (int oy = 0; oy < 2; ++oy) {
+              kr[c][0][oy] = kr[c][1][oy];
+              kl[c][0][oy] = kl[c][1][oy];
+            }
           }
         }
         const int Zn = Z + 1;
