@@ -312,11 +312,12 @@ __global__ __launch_bounds__(SETUP_T) void k_setup2d(CellArgs a) {
 // Inherited right-hand sides of a level >= 2 cell, one workgroup per
 // (cell, alpha): f = -P^T K_h I on the level nodes and g' = g - B_h I, with I
 // the inherited level-1 solution. A thread computes the load of one level
-// node from the fine elements of its four coarse elements (I, kappa and labels
-// straight from global memory, so the kernel needs no LDS arrays and many
-// workgroups share a CU); B_h I is summed region by region in a fixed order.
+// node from the fine elements of one of its four coarse elements (I, kappa and
+// labels straight from global memory); the four are summed in a fixed order.
+// B_h I is summed region by region in a fixed order.
 template <int N>
 __global__ __launch_bounds__(SETUP_T) void k_inherit2d(CellArgs a) {
+  extern __shared__ double quad[];  // [NC^2][4]
   __shared__ double wred[SETUP_T / 64][N];
   __shared__ double bI[64];
   const int nc = a.nc, nn1 = nc + 1, NC = a.NC, r = a.r, m = a.m, s = a.s, M = a.M;
@@ -328,35 +329,38 @@ __global__ __launch_bounds__(SETUP_T) void k_inherit2d(CellArgs a) {
   const double* I = a.phi1 + ((size_t)a.pslot[ci] * M + al) * (size_t)nn1 * nn1;
   const double inv_r = 1.0 / r;
   double* fo = a.fin + ((size_t)ci * M + al) * NC * NC;
-  for (int nd = tid; nd < NC * NC; nd += SETUP_T) {
+  // one item per (node, coarse element of the node): quadrant loads in LDS,
+  // then each node sums its four in a fixed order
+  for (int it = tid; it < NC * NC * 4; it += SETUP_T) {
+    const int nd = it >> 2, q = it & 3;
     const int Xn = nd % NC, Yn = nd / NC;
     double t = 0.0;
     if (Xn >= 1 && Yn >= 1) {
+      const int qx = q & 1, qy = q >> 1;
+      const int EX = Xn - 1 + qx, EY = Yn - 1 + qy;
+      const int cx = 1 - qx, cy = 1 - qy;  // corner of the node in coarse element E
+      for (int v = 0; v < r; ++v)
+        for (int u = 0; u < r; ++u) {
+          const int fx = EX * r + u, fy = EY * r + v;
+          double Iv[4], y[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int qx = q & 1, qy = q >> 1;
-        const int EX = Xn - 1 + qx, EY = Yn - 1 + qy;
-        const int cx = 1 - qx, cy = 1 - qy;  // corner of the node in coarse element E
-        for (int v = 0; v < r; ++v)
-          for (int u = 0; u < r; ++u) {
-            const int fx = EX * r + u, fy = EY * r + v;
-            double Iv[4], y[4];
+          for (int d = 0; d < 4; ++d) Iv[d] = I[(size_t)(fy + (d >> 1)) * nn1 + fx + (d & 1)];
+          kref6_apply(Iv, y);
+          const double k6 = a.kappa[(size_t)wrapi(oy + fy, a.n) * a.n + wrapi(ox + fx, a.n)] * (1.0 / 6.0);
+          double acc = 0.0;
 #pragma unroll
-            for (int d = 0; d < 4; ++d) Iv[d] = I[(size_t)(fy + (d >> 1)) * nn1 + fx + (d & 1)];
-            kref6_apply(Iv, y);
-            const double k6 = a.kappa[(size_t)wrapi(oy + fy, a.n) * a.n + wrapi(ox + fx, a.n)] * (1.0 / 6.0);
-            double acc = 0.0;
-#pragma unroll
-            for (int d = 0; d < 4; ++d) {
-              const double tx = (u + (d & 1)) * inv_r, ty = (v + (d >> 1)) * inv_r;
-              acc += (cx ? tx : 1.0 - tx) * (cy ? ty : 1.0 - ty) * y[d];
-            }
-            t += k6 * acc;
+          for (int d = 0; d < 4; ++d) {
+            const double tx = (u + (d & 1)) * inv_r, ty = (v + (d >> 1)) * inv_r;
+            acc += (cx ? tx : 1.0 - tx) * (cy ? ty : 1.0 - ty) * y[d];
           }
-      }
+          t += k6 * acc;
+        }
     }
-    fo[nd] = -t;
+    quad[it] = t;
   }
+  __syncthreads();
+  for (int nd = tid; nd < NC * NC; nd += SETUP_T)
+    fo[nd] = -((quad[4 * nd] + quad[4 * nd + 1]) + (quad[4 * nd + 2] + quad[4 * nd + 3]));
   // B_h I: element sums of I per region and continuum, region by region
   const int sb = nc / s;
   for (int reg = 0; reg < s * s; ++reg) {
@@ -426,7 +430,10 @@ int launch_inherit(const CellArgs& a, hipStream_t s) {
   if (a.N == 2) fn = k_inherit2d<2>;
   if (a.N == 3) fn = k_inherit2d<3>;
   if (!fn) return set_error(MCH_ENOTIMPL, "n_cont");
-  hipLaunchKernelGGL(fn, dim3(a.count * a.M), dim3(SETUP_T), 0, s, a);
+  const size_t lds = (size_t)a.NC * a.NC * 4 * sizeof(double);
+  int rc = lds_attr(fn, lds);
+  if (rc) return rc;
+  hipLaunchKernelGGL(fn, dim3(a.count * a.M), dim3(SETUP_T), lds, s, a);
   return hip_check(hipGetLastError(), "launch k_inherit2d");
 }
 
