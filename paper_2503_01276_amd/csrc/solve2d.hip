@@ -621,7 +621,7 @@ static int launch_solve_t(const CellArgs& a, size_t lds, hipStream_t s) {
   X(64, 4, 1, false) X(64, 4, 2, false) X(64, 4, 3, false)                                     \
   X(64, 8, 1, false) X(64, 8, 2, false) X(64, 8, 3, false)                                     \
   X(32, 4, 1, false) X(32, 4, 2, false) X(32, 4, 3, false)                                     \
-  X(32, 1, 2, false) X(32, 1, 3, false) X(16, 4, 2, false) X(16, 4, 3, false)                 \
+  X(32, 1, 2, false) X(32, 1, 3, false) X(16, 4, 1, false) X(16, 4, 2, false) X(16, 4, 3, false) \
   X(32, 4, 1, true) X(32, 4, 2, true) X(32, 4, 3, true) X(32, 2, 2, true) X(32, 2, 3, true)    \
   X(32, 1, 2, true) X(32, 1, 3, true) X(16, 4, 1, true) X(16, 4, 2, true) X(16, 4, 3, true)    \
   X(16, 1, 2, true) X(16, 1, 3, true) X(8, 1, 1, true) X(8, 1, 2, true) X(8, 1, 3, true)

@@ -1,0 +1,135 @@
+"""Edge cases of the HIP path (needs an MI355X): one and three continua in 2D
+and 3D, non-convergence reporting, unsupported shapes, call-order errors and
+degenerate argument lists, all through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2503_01276_amd import workloads as W
+
+from gpu_util import check_forward, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _inclusion_blocks_3d(lab: np.ndarray, seed: int, count: int) -> np.ndarray:
+    """Mark `count` seeded 2x2x2 element blocks as the third continuum."""
+    rng = np.random.default_rng(seed)
+    n = lab.shape[0]
+    out = lab.copy()
+    for c in rng.integers(0, n, size=(count, 3)):
+        for dz in range(2):
+            for dy in range(2):
+                for dx in range(2):
+                    out[(c[2] + dz) % n, (c[1] + dy) % n, (c[0] + dx) % n] = W.INCLUSION
+    return out
+
+
+def test_single_continuum_2d():
+    cfg = W.PRESETS["t2"].replace(n_cont=1)
+    k, _ = W.medium("t2")
+    l = np.zeros_like(k, dtype=np.uint8)
+    check_forward("t2 N=1", cfg, k, l, phi_cells=list(range(cfg.n_points)), workers=4)
+
+
+def test_single_continuum_3d():
+    cfg = W.PRESETS["t3d"].replace(n_cont=1)
+    k, _ = W.medium("t3d")
+    l = np.zeros_like(k, dtype=np.uint8)
+    check_forward("t3d N=1", cfg, k, l, phi_cells=list(range(0, cfg.n_points, 5)), workers=4)
+
+
+def test_three_continua_3d_and_adjoint():
+    import torch
+
+    from paper_2503_01276_amd import mch
+
+    cfg = W.PRESETS["t3d"].replace(n_cont=3)
+    _, l0 = W.medium("t3d")
+    l = _inclusion_blocks_3d(l0, seed=91, count=60)
+    k = W.kappa_from_labels(l)
+    say(f"[gpu] t3d N=3: label counts {np.bincount(l.reshape(-1), minlength=3).tolist()}")
+    check_forward("t3d N=3", cfg, k, l, phi_cells=list(range(0, cfg.n_points, 3)), workers=4)
+    # adjoint against the oracle's with a seeded dLoss/dA
+    fwd = oracle.forward(cfg, k, l, workers=4)
+    rng = np.random.default_rng(92)
+    gA = rng.standard_normal((cfg.n_points, cfg.n_rhs, cfg.n_rhs))
+    gref = oracle.backward(cfg, k, l, fwd, {p: gA[p] for p in range(cfg.n_points)}, workers=4).reshape(-1)
+    plan = mch.Plan(cfg)
+    dev = torch.device("cuda:0")
+    kd = torch.from_numpy(k.reshape(-1).copy()).to(dev)
+    ld = torch.from_numpy(l.reshape(-1).copy()).to(dev)
+    plan.solve_cells(kd, ld)
+    A = torch.empty(plan.P * plan.M * plan.M, dtype=torch.float64, device=dev)
+    plan.effective_coeffs(kd, A)
+    g = torch.empty_like(kd)
+    plan.effective_coeffs_backward(kd, torch.from_numpy(gA.reshape(-1).copy()).to(dev), g)
+    torch.cuda.synchronize()
+    err = np.linalg.norm(g.cpu().numpy() - gref) / np.linalg.norm(gref)
+    say(f"[gpu] t3d N=3: grad rel err {err:.3e}")
+    assert err <= 1e-8, err
+
+
+def test_no_convergence_is_reported():
+    import torch
+
+    from paper_2503_01276_amd import mch
+
+    for name in ("t2", "t3d"):
+        cfg = W.PRESETS[name].replace(max_iter=3)
+        k, l = W.medium(name)
+        plan = mch.Plan(cfg)
+        dev = torch.device("cuda:0")
+        plan.solve_cells(torch.from_numpy(k.reshape(-1).copy()).to(dev), torch.from_numpy(l.reshape(-1).copy()).to(dev))
+        torch.cuda.synchronize()
+        with pytest.raises(mch.MchError) as ei:
+            plan.diagnostics()
+        assert ei.value.code == mch.MCH_ENOCONV
+        it, rs = plan.diagnostics(allow_noconv=True)
+        assert it.max() == 3 and rs.max() > cfg.rtol
+
+
+def test_unsupported_3d_shapes_are_refused():
+    from paper_2503_01276_amd import mch
+
+    base = W.PRESETS["t3d"]
+    for cfg in (base.replace(n_sub=1), base.replace(n_fine=128, n_macro=2, n_cell=64, levels=1)):
+        with pytest.raises(mch.MchError) as ei:
+            mch.Plan(cfg)
+        assert ei.value.code == mch.MCH_ENOTIMPL, (cfg, ei.value)
+
+
+def test_call_order_and_argument_errors():
+    import torch
+
+    from paper_2503_01276_amd import mch
+
+    cfg = W.PRESETS["t2"]
+    k, l = W.medium("t2")
+    dev = torch.device("cuda:0")
+    kd = torch.from_numpy(k.reshape(-1).copy()).to(dev)
+    ld = torch.from_numpy(l.reshape(-1).copy()).to(dev)
+    plan = mch.Plan(cfg)
+    A = torch.empty(plan.P * plan.M * plan.M, dtype=torch.float64, device=dev)
+    g = torch.empty_like(kd)
+    with pytest.raises(mch.MchError) as ei:
+        plan.effective_coeffs(kd, A)
+    assert ei.value.code == mch.MCH_ESTALE
+    with pytest.raises(mch.MchError) as ei:
+        plan.effective_coeffs_backward(kd, torch.zeros_like(A), g)
+    assert ei.value.code == mch.MCH_ESTALE
+    plan.solve_cells(kd, ld)
+    # empty list of local solutions is a no-op; an out-of-range index is refused
+    plan.local_solutions(np.zeros(0, np.int64), torch.empty(0, dtype=torch.float64, device=dev))
+    nn = (cfg.n_cell + 1) ** cfg.dim
+    with pytest.raises(mch.MchError) as ei:
+        plan.local_solutions(np.array([cfg.n_points]), torch.empty(plan.M * nn, dtype=torch.float64, device=dev))
+    assert ei.value.code == mch.MCH_EINVAL
+    # wrong dtype / size of a device buffer
+    with pytest.raises(mch.MchError):
+        plan.effective_coeffs(kd, torch.empty(3, dtype=torch.float64, device=dev))
+    # a zero gradient of the loss gives a zero gradient field
+    plan.effective_coeffs(kd, A)
+    plan.effective_coeffs_backward(kd, torch.zeros_like(A), g)
+    torch.cuda.synchronize()
+    assert float(g.abs().max()) == 0.0
