@@ -12,7 +12,11 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmch.so")
-SOURCES = ["plan.cpp", "api.cpp", "setup2d.hip", "solve2d.hip", "backward2d.hip", "cells3d.hip"]
+# (source, object name, extra flags); the 2D solve kernel is compiled once per
+# number of sub-blocks per axis
+SOURCES = [("plan.cpp", "plan", []), ("api.cpp", "api", []), ("setup2d.hip", "setup2d", []),
+           ("solve2d.hip", "solve2d", []), ("backward2d.hip", "backward2d", []), ("cells3d.hip", "cells3d", [])] + \
+          [("solve2d_inst.hip", f"solve2d_s{s}", [f"-DMCH_SUB={s}"]) for s in (1, 2, 4, 8)]
 HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-munsafe-fp-atomics",
@@ -29,19 +33,32 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = False, extra: list[str] | None = None) -> str:
+    from concurrent.futures import ThreadPoolExecutor
+
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
-    objs = []
-    for src in SOURCES:
-        obj = os.path.join(objdir, src + ".o")
-        cmd = [hipcc(), *HIP_FLAGS, *(extra or []), "-I", os.path.join(HERE, "..", "include"),
+    cmds, objs = [], []
+    for src, name, flags in SOURCES:
+        obj = os.path.join(objdir, name + ".o")
+        cmd = [hipcc(), *HIP_FLAGS, *flags, *(extra or []), "-I", os.path.join(HERE, "..", "include"),
                "-c", os.path.join(CSRC, src), "-o", obj]
         if src.endswith(".cpp"):
             cmd[1:1] = ["-x", "hip"]
+        cmds.append(cmd)
+        objs.append(obj)
+
+    def run(cmd):
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
-        objs.append(obj)
+        return subprocess.run(cmd, capture_output=True, text=True)
+
+    workers = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        results = list(ex.map(run, cmds))
+    for cmd, res in zip(cmds, results):
+        if res.returncode != 0:
+            sys.stderr.write(res.stdout + res.stderr)
+            raise subprocess.CalledProcessError(res.returncode, cmd)
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     subprocess.run(cmd, check=True)

@@ -58,6 +58,53 @@ MCH_DEV double seg_sum(double v, int width) {
 // Sum over all 64 lanes; every lane gets the result.
 MCH_DEV double wave_sum(double v) { return seg_sum(v, 64); }
 
+// seg_sum of K independent values: each DPP step is issued for all K values
+// before their adds, so the K dependency chains overlap instead of queueing.
+// Per value the additions are those of seg_sum, in the same order.
+template <int CTRL, int K>
+MCH_DEV void dpp_add_n(double (&v)[K]) {
+  double t[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) t[k] = dpp_f64<CTRL>(v[k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += t[k];
+}
+
+template <int K>
+MCH_DEV void seg_sum_n(double (&v)[K], int width) {
+  if (width >= 2) dpp_add_n<DPP_QUAD_XOR1>(v);
+  if (width >= 4) dpp_add_n<DPP_QUAD_XOR2>(v);
+  if (width >= 8) dpp_add_n<DPP_HALF_MIRROR>(v);
+  if (width >= 16) dpp_add_n<DPP_ROW_MIRROR>(v);
+  if (width >= 32) {
+    const bool lowhalf = (int)(threadIdx.x & 63) < 32;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const double r0 = readlane_f64(v[k], 0), r1 = readlane_f64(v[k], 16);
+      const double r2 = readlane_f64(v[k], 32), r3 = readlane_f64(v[k], 48);
+      if (width == 32)
+        v[k] = lowhalf ? r0 + r1 : r2 + r3;
+      else
+        v[k] = (r0 + r1) + (r2 + r3);
+    }
+  }
+}
+
+template <int K>
+MCH_DEV void wave_sum_n(double (&v)[K]) { seg_sum_n<K>(v, 64); }
+
+// Sum of K consecutive-stride values x[0], x[S], ..., x[(K-1)S] as a balanced
+// binary tree (fixed order; depth log2 K instead of K - 1).
+template <int K, int S>
+MCH_DEV double tree_sum(const double* x) {
+  if constexpr (K == 1) {
+    return x[0];
+  } else {
+    constexpr int H = K / 2;
+    return tree_sum<H, S>(x) + tree_sum<K - H, S>(x + H * S);
+  }
+}
+
 // Value held by lane+1 (0 for the last lane of a group of `width` lanes).
 MCH_DEV double from_right(double v, int c, int width) {
   const double t = dpp_f64<DPP_WAVE_SHL1>(v);

@@ -11,6 +11,29 @@ CellArgs base_args(mch_plan* pl, const double* kappa, const uint8_t* label, int 
 CellArgs chunk_args(const CellArgs& a, int start, int count);
 // Launch the constrained Krylov solve of every (cell, right-hand side) of a.
 int launch_solve(const CellArgs& a, int rpt, hipStream_t s);
+
+// Lanes per row of the per-wave Schur solve: the largest power of two J with
+// J m <= 64, so the m rows of S^-1 u fit one wave.
+constexpr int schur_lanes(int m) {
+  int J = 1;
+  while (J * 2 * m <= 64) J *= 2;
+  return J;
+}
+
+// Solve kernel for cells of S sub-blocks per axis (S = 1, 2, 4, 8; one
+// translation unit each): the kernel of a (cell width, node rows per thread,
+// continua, Galerkin) shape and its block size, or nullptr if that shape is
+// not instantiated.
+template <int S>
+const void* solve_kernel_sub(int NC, int rpt, int N, bool gal, int* threads);
+template <>
+const void* solve_kernel_sub<1>(int, int, int, bool, int*);
+template <>
+const void* solve_kernel_sub<2>(int, int, int, bool, int*);
+template <>
+const void* solve_kernel_sub<4>(int, int, int, bool, int*);
+template <>
+const void* solve_kernel_sub<8>(int, int, int, bool, int*);
 // Per-cell setup (constraint rows, right-hand sides, Galerkin data, S^-1).
 int launch_setup(const CellArgs& a, hipStream_t s);
 // Inherited right-hand sides of a level >= 2 (needs the level-1 solutions).

@@ -344,7 +344,7 @@ extern "C" int mch_build_levels(const mch_config* cfg, mch_plan** out) {
       lv.shape.rpt = default_rpt(lv.NC, sbw);
       lv.shape.threads = lv.NC * lv.NC / lv.shape.rpt;
     }
-    if (d == 2 && !shape_supported_2d(lv.NC, lv.shape.rpt, c.n_cont, lv.r > 1)) {
+    if (d == 2 && !shape_supported_2d(lv.NC, lv.shape.rpt, c.n_cont, lv.r > 1, c.n_sub)) {
       rc = set_error(MCH_ENOTIMPL, "no kernel instantiated for level cell width " + std::to_string(lv.NC) +
                                        " rows/thread " + std::to_string(lv.shape.rpt) + " N=" +
                                        std::to_string(c.n_cont));

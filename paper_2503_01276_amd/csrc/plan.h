@@ -150,7 +150,7 @@ int launch_forward_2d(mch_plan* p, const double* kappa, const uint8_t* label, hi
 int launch_eff_2d(mch_plan* p, const double* kappa, double* A, hipStream_t s);
 int launch_backward_2d(mch_plan* p, const double* kappa, const double* gA, double* glogk, hipStream_t s);
 int launch_local_solutions_2d(mch_plan* p, const int64_t* cells, int64_t n, double* out, hipStream_t s);
-bool shape_supported_2d(int NC, int rpt, int N, bool galerkin);
+bool shape_supported_2d(int NC, int rpt, int N, bool galerkin, int n_sub);
 int launch_forward_3d(mch_plan* p, const double* kappa, const uint8_t* label, hipStream_t s);
 int launch_eff_3d(mch_plan* p, const double* kappa, double* A, hipStream_t s);
 int launch_backward_3d(mch_plan* p, const double* kappa, const double* gA, double* glogk, hipStream_t s);
