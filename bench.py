@@ -39,22 +39,26 @@ FLOPS_PER_NODE_ITER_3D_GAL = 74
 # this script (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch), each scaled by what
 # the same counter reads for a plain device copy of known size (--copy-probe).
 # An entry holds only while the kernel sources hash to the recorded value.
-KERNEL_SOURCES = ("paper_2503_01276_amd/csrc/solve2d.hip", "paper_2503_01276_amd/csrc/device_common.h")
-_SHA_C2 = "aa4616ad7babc3e64b3a4761eec9f4dae41a725bb22d212c3d5098481f17d15b"
-_COPY_SCALE = {"fetch": 1048576.0 / 524304.8, "write": 1048576.0 / 1048576.0}  # 1 GiB copy
-TRAFFIC = {
-    ("c2", "solve_L1"): {"sha256": _SHA_C2, "fetch_kib": 16074.0, "write_kib": 31571.0,
-                         "fetch_scale": _COPY_SCALE["fetch"], "write_scale": _COPY_SCALE["write"]},
-    ("c2", "adjsolve_L1"): {"sha256": _SHA_C2, "fetch_kib": 22796.0, "write_kib": 31880.0,
-                            "fetch_scale": _COPY_SCALE["fetch"], "write_scale": _COPY_SCALE["write"]},
+# Sources of the kernels whose counters are recorded below, per dimension.
+KERNEL_SOURCES = {
+    2: ("paper_2503_01276_amd/csrc/solve2d_kernel.h", "paper_2503_01276_amd/csrc/solve2d_inst.hip",
+        "paper_2503_01276_amd/csrc/solve2d.hip", "paper_2503_01276_amd/csrc/kernels2d.h",
+        "paper_2503_01276_amd/csrc/device_common.h"),
+    3: ("paper_2503_01276_amd/csrc/cells3d.hip", "paper_2503_01276_amd/csrc/device_common.h"),
 }
+# HBM bytes per launch of a workload's dominant kernel: FETCH_SIZE and
+# WRITE_SIZE (KiB per dispatch, averaged over the kernel's dispatches) from two
+# rocprofv3 --pmc runs, each scaled by the ratio of a plain copy's known size
+# to what the same counter reads for it. An entry holds only while the kernel
+# sources hash to the recorded value; otherwise traffic is reported as null.
+TRAFFIC = {}
 
 
-def kernel_sources_sha256() -> str:
+def kernel_sources_sha256(dim: int) -> str:
     import hashlib
 
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in KERNEL_SOURCES[dim]:
         with open(os.path.join(HERE, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -62,7 +66,7 @@ def kernel_sources_sha256() -> str:
 
 def measured_traffic(workload: str, kernel: str):
     t = TRAFFIC.get((workload, kernel))
-    if t is None or t["sha256"] != kernel_sources_sha256():
+    if t is None or t["sha256"] != kernel_sources_sha256(W.PRESETS[workload].dim):
         return None
     return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0
 

@@ -29,6 +29,7 @@ namespace mch {
 
 constexpr int T3 = 256;   // threads of the set-up and auxiliary kernels
 constexpr int S3D = 2;    // constraint sub-blocks per axis handled by the 3D solve
+constexpr int kXcds = 8;  // accelerator complex dies; workgroups are dealt to them round robin
 
 MCH_DEV size_t nidx3(int X, int Y, int Z, int NP) {
   return (size_t)X + (size_t)NP * ((size_t)Y + (size_t)NP * (size_t)Z);
@@ -515,7 +516,17 @@ __global__ __launch_bounds__((nt3<NC, GAL>())) void k_solve3d(CellArgs a) {
   // columns (X, Y0 + c YS), c < CPT; planes Z = g + G i (g uniform across a wave)
   const int X = tid % NC, Y0 = (tid / NC) % YS;
   const int g = __builtin_amdgcn_readfirstlane(tid / (NC * YS));
-  const int ci = a.ci0 + blockIdx.x / M, alpha = blockIdx.x % M;
+  // Workgroups are dealt to the XCDs round robin (block b runs on XCD b % 8),
+  // and the M right-hand sides of a cell share its operator data (D^-1 and
+  // kappa/labels, or the Galerkin weights), which every iteration re-reads.
+  // Blocks are therefore numbered so that all right-hand sides of a cell land
+  // on one XCD and share its L2: in a group of 8 cells (8 M blocks), block b
+  // takes cell b % 8 of the group and right-hand side (b mod 8 M) / 8. The
+  // grid is padded to whole groups; padding blocks leave at once.
+  const int grp = blockIdx.x / (kXcds * M), rb = blockIdx.x % (kXcds * M);
+  const int cl = grp * kXcds + rb % kXcds, alpha = rb / kXcds;
+  if (cl >= a.count) return;
+  const int ci = a.ci0 + cl;
   const int p = a.cells[ci];
   const size_t vbase = ((size_t)ci * M + alpha) * (size_t)NP * NP * NP;
   double* __restrict__ xv = a.out + vbase;
@@ -1448,7 +1459,8 @@ static int launch_solve3_t(const CellArgs& a, hipStream_t s) {
   auto fn = k_solve3d<NC, N, GAL>;
   int rc = lds_attr3(fn, lds);
   if (rc) return rc;
-  hipLaunchKernelGGL(fn, dim3(a.count * a.M), dim3(NT), lds, s, a);
+  const int groups = (a.count + kXcds - 1) / kXcds;
+  hipLaunchKernelGGL(fn, dim3(groups * kXcds * a.M), dim3(NT), lds, s, a);
   return hip_check(hipGetLastError(), "launch k_solve3d");
 }
 

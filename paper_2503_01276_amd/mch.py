@@ -129,6 +129,9 @@ class Plan:
     def __init__(self, cfg):
         self.cfg = cfg
         self._c = to_c_config(cfg)
+        # the process whose device context owns the plan; a forked child (a
+        # CPU worker pool) inherits the object but must not touch the device
+        self._pid = os.getpid()
         h = ctypes.c_void_p()
         check(LIB.mch_build_levels(ctypes.byref(self._c), ctypes.byref(h)))
         self._h = h
@@ -140,7 +143,8 @@ class Plan:
 
     def close(self):
         if getattr(self, "_h", None):
-            LIB.mch_destroy(self._h)
+            if getattr(self, "_pid", None) == os.getpid():
+                LIB.mch_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -83,3 +83,23 @@ def test_config_struct_layout():
     assert c.dim.offset == 0 and c.n_fine.offset == 4 and c.h.offset == 16
     assert c.n_macro.offset == 24 and c.n_cell.offset == 36 and c.rtol.offset == 64
     assert ctypes.sizeof(c) == 80
+
+
+def test_plan_owned_by_another_process_is_not_destroyed(monkeypatch):
+    # A forked worker (the oracle's process pool) inherits Plan objects; when
+    # it collects one it must drop the handle without calling into the device.
+    calls = []
+
+    class FakeLib:
+        def mch_destroy(self, h):
+            calls.append(h)
+
+    monkeypatch.setattr(mch, "LIB", FakeLib())
+    p = mch.Plan.__new__(mch.Plan)
+    p._h, p._pid = ctypes.c_void_p(1234), os.getpid() + 1
+    p.close()
+    assert calls == [] and p._h is None
+    q = mch.Plan.__new__(mch.Plan)
+    q._h, q._pid = ctypes.c_void_p(5678), os.getpid()
+    q.close()
+    assert len(calls) == 1 and q._h is None
