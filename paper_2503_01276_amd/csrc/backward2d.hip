@@ -259,10 +259,12 @@ static int set_lds(F fn, size_t lds) {
 }
 
 // Backward DAG: seeds of every level in parallel; each inheriting level's
-// adjoint solves and gradient windows on its side stream; on s, once all of
-// them are done, the level-1 seeds from the inheriting cells, the level-1
-// adjoint and gradient, and the gather. (The level-1 seeds are latency-bound
-// per workgroup, so splitting them into chunks would lengthen the path.)
+// adjoint solves and gradient windows on its side stream; on s, once their
+// adjoint solves are done, the level-1 seeds from the inheriting cells, the
+// level-1 adjoint and gradient (alongside the other levels' gradient
+// windows), then the gather after the full join. (The level-1 seeds are
+// latency-bound per workgroup, so splitting them into chunks would lengthen
+// the path.)
 int launch_backward_2d(mch_plan* pl, const double* kappa, const double* gA, double* glogk, hipStream_t s) {
   const int M = pl->M, nc = pl->cfg.n_cell, nn1 = nc + 1;
   char name[32];
@@ -292,6 +294,8 @@ int launch_backward_2d(mch_plan* pl, const double* kappa, const double* gA, doub
     a.resid = pl->d_resid_adj;
     return a;
   };
+  const int n1 = pl->lev[0].count;
+  const bool inherit = pl->L > 1 && n1 > 0 && n1 < pl->P;
   for (int l = pl->L - 1; l >= 0; --l) {
     if (pl->lev[l].count == 0) continue;
     hipStream_t t = level_stream(pl, l, s);
@@ -311,11 +315,12 @@ int launch_backward_2d(mch_plan* pl, const double* kappa, const double* gA, doub
       ProfScope ps(pl, name, t);
       rc = launch_solve(adjoint_args(l), pl->lev[l].shape.rpt, t);
     }
+    // the parent seeds and the level-1 adjoint need this level's adjoint
+    // solution, not its gradient window, which runs on alongside them
+    if (!rc) rc = mark_level(pl, l, pl->ev_adj);
     if (!rc) rc = launch_grad(base_args(pl, kappa, pl->fwd_label, l), t, l);
     if (rc) return rc;
   }
-  const int n1 = pl->lev[0].count;
-  const bool inherit = pl->L > 1 && n1 > 0 && n1 < pl->P;
   CellArgs a1 = base_args(pl, kappa, pl->fwd_label, 0);
   LevelTab lt{};
   for (int l = 0; l < pl->L; ++l) {
@@ -326,7 +331,7 @@ int launch_backward_2d(mch_plan* pl, const double* kappa, const double* gA, doub
   if (nc > 64) return set_error(MCH_ENOTIMPL, "2D cells wider than 64 elements");
   const size_t lds_ibar = ((size_t)nn1 * nn1 + (size_t)nc * nc + pl->m) * sizeof(double) + (size_t)nc * nc;
   if (inherit && (rc = set_lds(k_ibar2d, lds_ibar))) return rc;
-  rc = join_levels(pl, s);
+  rc = wait_marks(pl, s, pl->ev_adj);
   if (!rc && n1 > 0) {
     if (inherit) {
       ProfScope ps(pl, "ibar", s);
@@ -340,8 +345,9 @@ int launch_backward_2d(mch_plan* pl, const double* kappa, const double* gA, doub
       ProfScope ps(pl, "adjsolve_L1", s);
       rc = launch_solve(a, pl->lev[0].shape.rpt, s);
     }
-    if (!rc) rc = launch_grad(a1, s, 0);
   }
+  if (!rc && n1 > 0) rc = launch_grad(a1, s, 0);
+  if (!rc) rc = join_levels(pl, s);  // the gradient windows of levels >= 2
   if (rc) return rc;
   const size_t total = (size_t)pl->n * pl->n;
   const unsigned blocks = (unsigned)((total + 255) / 256 < 65536 ? (total + 255) / 256 : 65536);

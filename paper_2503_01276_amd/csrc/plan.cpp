@@ -213,6 +213,7 @@ int ensure_streams(mch_plan* p) {
   for (int l = 1; l < p->L && !rc; ++l) {
     rc = hip_check(hipStreamCreateWithFlags(&p->side[l], hipStreamNonBlocking), "hipStreamCreate");
     if (!rc) rc = hip_check(hipEventCreateWithFlags(&p->ev_join[l], hipEventDisableTiming), "hipEventCreate");
+    if (!rc) rc = hip_check(hipEventCreateWithFlags(&p->ev_adj[l], hipEventDisableTiming), "hipEventCreate");
   }
   return rc;
 }
@@ -222,6 +223,19 @@ int fork_levels(mch_plan* p, hipStream_t s) {
   int rc = hip_check(hipEventRecord(p->ev_fork, s), "hipEventRecord");
   for (int l = 1; l < p->L && !rc; ++l)
     if (p->lev[l].count) rc = hip_check(hipStreamWaitEvent(p->side[l], p->ev_fork, 0), "hipStreamWaitEvent");
+  return rc;
+}
+
+int mark_level(mch_plan* p, int l, hipEvent_t* ev) {
+  if (p->serial || l < 1) return MCH_OK;
+  return hip_check(hipEventRecord(ev[l], p->side[l]), "hipEventRecord");
+}
+
+int wait_marks(mch_plan* p, hipStream_t s, hipEvent_t* ev) {
+  if (p->serial) return MCH_OK;
+  int rc = MCH_OK;
+  for (int l = 1; l < p->L && !rc; ++l)
+    if (p->lev[l].count) rc = hip_check(hipStreamWaitEvent(s, ev[l], 0), "hipStreamWaitEvent");
   return rc;
 }
 
@@ -252,6 +266,7 @@ extern "C" void mch_destroy(mch_plan* plan) {
   for (int l = 0; l < MAX_LEVELS; ++l) {
     if (plan->side[l]) (void)hipStreamDestroy(plan->side[l]);
     if (plan->ev_join[l]) (void)hipEventDestroy(plan->ev_join[l]);
+    if (plan->ev_adj[l]) (void)hipEventDestroy(plan->ev_adj[l]);
   }
   if (plan->ev_fork) (void)hipEventDestroy(plan->ev_fork);
   if (plan->ev_l1) (void)hipEventDestroy(plan->ev_l1);

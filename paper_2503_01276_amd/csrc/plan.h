@@ -108,6 +108,8 @@ struct mch_plan {
   int cntA[mch::MAX_LEVELS] = {};
   hipEvent_t ev_l1a = nullptr;
   hipEvent_t ev_join[mch::MAX_LEVELS] = {};
+  // backward: a level's adjoint solve is done (its gradient window may still run)
+  hipEvent_t ev_adj[mch::MAX_LEVELS] = {};
   // captured launch sequences, replayed while the arguments are unchanged
   struct Graph {
     const void* key[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -141,6 +143,11 @@ int ensure_streams(mch_plan* p);
 int fork_levels(mch_plan* p, hipStream_t s);
 // Join: s waits for every side stream of levels 2..L.
 int join_levels(mch_plan* p, hipStream_t s);
+// Record ev[l] on level l's stream (l >= 1), and make s wait for every
+// level's recorded event: a partial join that leaves the rest of each level
+// stream running (joined later by join_levels).
+int mark_level(mch_plan* p, int l, hipEvent_t* ev);
+int wait_marks(mch_plan* p, hipStream_t s, hipEvent_t* ev);
 // Stream of level l (0-based) in a DAG issued on s.
 inline hipStream_t level_stream(const mch_plan* p, int l, hipStream_t s) { return (l == 0 || p->serial) ? s : p->side[l]; }
 int hip_check(hipError_t e, const char* what);
