@@ -50,14 +50,17 @@ __global__ __launch_bounds__(BT) void k_seed2d(CellArgs a, const double* gA, dou
       const int ex = X - 1 + (q & 1), ey = Y - 1 + (q >> 1);
       if (ex < 0 || ey < 0 || ex >= H || ey >= H) continue;
       const double k6 = a.kappa[(size_t)(H * jy + ey) * a.n + (H * jx + ex)] * (1.0 / 6.0);
-      const int corner = (X - ex) + 2 * (Y - ey);
+      // node (X, Y) is corner c of the element; only row c of 6 K_ref is
+      // needed: 4 v_c - 2 v_(c^3) - v_(c^1) - v_(c^2)
+      const int c = (X - ex) + 2 * (Y - ey);
+      const int o0 = (ey + (c >> 1)) * Hp + ex + (c & 1);
+      const int o3 = (ey + ((c ^ 3) >> 1)) * Hp + ex + ((c ^ 3) & 1);
+      const int o1 = (ey + ((c ^ 1) >> 1)) * Hp + ex + ((c ^ 1) & 1);
+      const int o2 = (ey + ((c ^ 2) >> 1)) * Hp + ex + ((c ^ 2) & 1);
 #pragma unroll
       for (int b = 0; b < MM; ++b) {
-        double v[4], y[4];
-#pragma unroll
-        for (int d = 0; d < 4; ++d) v[d] = ph[b * Hp * Hp + (ey + (d >> 1)) * Hp + ex + (d & 1)];
-        kref6_apply(v, y);
-        kphi[b] += k6 * y[corner];
+        const double* pb = ph + b * Hp * Hp;
+        kphi[b] += k6 * (4.0 * pb[o0] - 2.0 * pb[o3] - pb[o1] - pb[o2]);
       }
     }
 #pragma unroll
@@ -68,21 +71,33 @@ __global__ __launch_bounds__(BT) void k_seed2d(CellArgs a, const double* gA, dou
       seed_kp[((size_t)p * MM + al) * Hp * Hp + nd] = s;
     }
   }
+  // explicit kappa term per element: sum_ab G_ab Phi_a^T K_ref Phi_b
+  // = sum_a Phi_a^T K_ref w_a with w_a = sum_b G_ab Phi_b (element corners)
   for (int e = tid; e < H * H; e += BT) {
     const int ex = e % H, ey = e / H;
-    double v[MM][4], y[MM][4];
+    double v[MM][4];
 #pragma unroll
     for (int al = 0; al < MM; ++al) {
 #pragma unroll
       for (int d = 0; d < 4; ++d) v[al][d] = ph[al * Hp * Hp + (ey + (d >> 1)) * Hp + ex + (d & 1)];
-      kref6_apply(v[al], y[al]);
     }
     double t = 0.0;
+#pragma unroll 1
+    for (int al = 0; al < MM; ++al) {
+      double w[4] = {0.0, 0.0, 0.0, 0.0}, y[4], va[4];
 #pragma unroll
-    for (int al = 0; al < MM; ++al)
+      for (int b = 0; b < MM; ++b) {
+        const double g = G[al * MM + b];
 #pragma unroll
-      for (int b = 0; b < MM; ++b)
-        t += G[al * MM + b] * (v[al][0] * y[b][0] + v[al][1] * y[b][1] + v[al][2] * y[b][2] + v[al][3] * y[b][3]);
+        for (int d = 0; d < 4; ++d) w[d] += g * v[b][d];
+      }
+      kref6_apply(w, y);
+      // Phi_a at the corners again from LDS (a runtime index into v would
+      // put the array in scratch memory)
+#pragma unroll
+      for (int d = 0; d < 4; ++d) va[d] = ph[al * Hp * Hp + (ey + (d >> 1)) * Hp + ex + (d & 1)];
+      t += va[0] * y[0] + va[1] * y[1] + va[2] * y[2] + va[3] * y[3];
+    }
     gk[(size_t)(H * jy + ey) * a.n + (H * jx + ex)] = t * (1.0 / 6.0);
   }
 }
