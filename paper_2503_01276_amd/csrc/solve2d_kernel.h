@@ -171,6 +171,15 @@ __global__ __launch_bounds__(NC* NC / RPT) void k_solve2d(CellArgs a) {
   }
 
   // ---- building blocks -------------------------------------------------------
+  // A constraint weight widened to binary64. With three continua the widened
+  // copies would take 2*RPT*N double registers for the whole solve, so there
+  // the binary32 value is made opaque at its point of use (the empty asm) and
+  // widened there; with fewer continua the compiler's hoisting is cheaper.
+  auto wide = [](float v) -> double {
+    if constexpr (N >= 3) asm volatile("" : "+v"(v));
+    return (double)v;
+  };
+
   auto P_at = [&](int xx, int yy) -> double { return pS[(yy + 1) * PW + xx + 1]; };
 
   // y = K_n v on the thread's nodes (own values in vv, neighbours from pS).
@@ -228,7 +237,7 @@ __global__ __launch_bounds__(NC* NC / RPT) void k_solve2d(CellArgs a) {
       for (int sd = 0; sd < 2; ++sd) {
         double acc = 0.0;
 #pragma unroll
-        for (int i = 0; i < RPT; ++i) acc += (double)w[sd][i][j] * tv[i];
+        for (int i = 0; i < RPT; ++i) acc += wide(w[sd][i][j]) * tv[i];
         up[sd] = acc;
       }
       // element column c collects side 1 of lane c and side 0 of lane c+1
@@ -237,7 +246,7 @@ __global__ __launch_bounds__(NC* NC / RPT) void k_solve2d(CellArgs a) {
     if (anysplit) {
 #pragma unroll
       for (int j = 0; j < N; ++j)
-        v[N + j] = (double)wlo[1][j] * tv[0] + from_right((double)wlo[0][j] * tv[0], c, NC);
+        v[N + j] = wide(wlo[1][j]) * tv[0] + from_right(wide(wlo[0][j]) * tv[0], c, NC);
       seg_sum_n<2 * N>(v, sbw);
     } else {
       double vu[N];
@@ -322,12 +331,12 @@ __global__ __launch_bounds__(NC* NC / RPT) void k_solve2d(CellArgs a) {
 #pragma unroll
       for (int sd = 0; sd < 2; ++sd)
 #pragma unroll
-        for (int j = 0; j < N; ++j) t += (double)w[sd][i][j] * vs[sd][1][j];
+        for (int j = 0; j < N; ++j) t += wide(w[sd][i][j]) * vs[sd][1][j];
       if (i == 0) {
 #pragma unroll
         for (int sd = 0; sd < 2; ++sd)
 #pragma unroll
-          for (int j = 0; j < N; ++j) t += (double)wlo[sd][j] * vs[sd][0][j];
+          for (int j = 0; j < N; ++j) t += wide(wlo[sd][j]) * vs[sd][0][j];
       }
       tv[i] += sign * t;
     }
