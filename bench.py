@@ -51,14 +51,14 @@ KERNEL_SOURCES = {
 # rocprofv3 --pmc runs, each scaled by the ratio of a plain copy's known size
 # to what the same counter reads for it. An entry holds only while the kernel
 # sources hash to the recorded value; otherwise traffic is reported as null.
-_SHA_2D = "1f2b830b2e1e6c0aa98582291849061349e20d4b08ef773e33e1316e29ab7194"
+_SHA_2D = "762473de9325f60ab167514dd75e39c399329bf85453e15b4d83d86008e4e099"
 _SHA_3D = "f8029b1a5d381b3384fd7329a271e0d57b365c7703b45c5611281b19a740a977"
 _COPY_SCALE = {"fetch": 1048576.0 / 524304.8, "write": 1048576.0 / 1048576.0}  # 1 GiB copy
 TRAFFIC = {
     # level-1 forward launches (two chunks per step) and the single adjoint launch
-    ("c2", "solve_L1"): {"sha256": _SHA_2D, "fetch_kib": 7574.3, "write_kib": 14367.0,
+    ("c2", "solve_L1"): {"sha256": _SHA_2D, "fetch_kib": 7571.8, "write_kib": 14367.0,
                          "fetch_scale": _COPY_SCALE["fetch"], "write_scale": _COPY_SCALE["write"]},
-    ("c2", "adjsolve_L1"): {"sha256": _SHA_2D, "fetch_kib": 19473.2, "write_kib": 26399.7,
+    ("c2", "adjsolve_L1"): {"sha256": _SHA_2D, "fetch_kib": 19463.1, "write_kib": 26375.0,
                             "fetch_scale": _COPY_SCALE["fetch"], "write_scale": _COPY_SCALE["write"]},
     # 3D fine level: forward and adjoint launches share kernel and grid; mean of both
     ("c3", "solve_L1"): {"sha256": _SHA_3D, "fetch_kib": 85376037.0, "write_kib": 99484283.7,
