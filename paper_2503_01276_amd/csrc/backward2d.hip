@@ -168,7 +168,8 @@ constexpr int IBT = 1024;
 constexpr int IB_NODES = 5;  // ceil(65^2 / 1024): cells up to 64 elements wide
 
 __global__ __launch_bounds__(IBT) void k_ibar2d(CellArgs a, LevelTab lt, const int32_t* level, const int32_t* child_ptr,
-                                                const int32_t* child, const double* mu, double* seed_par) {
+                                                const int32_t* child, const double* mu, double* seed_par,
+                                                int only_level, int accumulate) {
   extern __shared__ double sm[];
   const int nc = a.nc, nn1 = nc + 1, H = a.H, Hp = H + 1, m = a.m, N = a.N, s = a.s;
   const int nn = nn1 * nn1;
@@ -185,6 +186,7 @@ __global__ __launch_bounds__(IBT) void k_ibar2d(CellArgs a, LevelTab lt, const i
   for (int ch = child_ptr[t]; ch < child_ptr[t + 1]; ++ch) {
     const int p = child[ch];
     const int l = level[p] - 1;
+    if (only_level >= 0 && l != only_level) continue;  // uniform across the block
     const int ci = a.slot[p];
     const int jx = p % a.n_macro, jy = p / a.n_macro;
     const int ox = H * jx + H / 2 - nc / 2, oy = H * jy + H / 2 - nc / 2;
@@ -233,7 +235,7 @@ __global__ __launch_bounds__(IBT) void k_ibar2d(CellArgs a, LevelTab lt, const i
 #pragma unroll
   for (int i = 0; i < IB_NODES; ++i) {
     const int nd = tid + i * IBT;
-    if (nd < nn) dst[nd] = acc[i];
+    if (nd < nn) dst[nd] = accumulate ? dst[nd] + acc[i] : acc[i];
   }
 }
 
@@ -274,12 +276,11 @@ static int set_lds(F fn, size_t lds) {
 }
 
 // Backward DAG: seeds of every level in parallel; each inheriting level's
-// adjoint solves and gradient windows on its side stream; on s, once their
-// adjoint solves are done, the level-1 seeds from the inheriting cells, the
-// level-1 adjoint and gradient (alongside the other levels' gradient
-// windows), then the gather after the full join. (The level-1 seeds are
-// latency-bound per workgroup, so splitting them into chunks would lengthen
-// the path.)
+// adjoint solve, its pass of the level-1 parent seeds and its gradient window
+// on its side stream (the passes chained deepest level first); on s, after
+// the last pass, the level-1 adjoint and gradient, then the gather after the
+// full join. (A parent-seed pass is latency-bound per workgroup, so it is not
+// split into chunks of level-1 cells.)
 int launch_backward_2d(mch_plan* pl, const double* kappa, const double* gA, double* glogk, hipStream_t s) {
   const int M = pl->M, nc = pl->cfg.n_cell, nn1 = nc + 1;
   char name[32];
@@ -311,6 +312,35 @@ int launch_backward_2d(mch_plan* pl, const double* kappa, const double* gA, doub
   };
   const int n1 = pl->lev[0].count;
   const bool inherit = pl->L > 1 && n1 > 0 && n1 < pl->P;
+  CellArgs a1 = base_args(pl, kappa, pl->fwd_label, 0);
+  LevelTab lt{};
+  for (int l = 0; l < pl->L; ++l) {
+    lt.r[l] = pl->lev[l].r;
+    lt.NC[l] = pl->lev[l].NC;
+    lt.w[l] = pl->lev[l].d_w;
+  }
+  if (nc > 64) return set_error(MCH_ENOTIMPL, "2D cells wider than 64 elements");
+  const size_t lds_ibar = ((size_t)nn1 * nn1 + (size_t)nc * nc + pl->m) * sizeof(double) + (size_t)nc * nc;
+  if (inherit && (rc = set_lds(k_ibar2d, lds_ibar))) return rc;
+  // Parent seeds from the cells of one inheriting level, on that level's
+  // stream once its adjoint solve is done. The passes run deepest level first,
+  // each after the previous one (the first writes, the others add), so the
+  // sum has a fixed order and only the level-2 pass waits for the level-2
+  // adjoint, the longest of them.
+  int prev_pass = -1;
+  auto ibar_pass = [&](int l, hipStream_t t) -> int {
+    int r = MCH_OK;
+    if (prev_pass >= 0 && !pl->serial) r = hip_check(hipStreamWaitEvent(t, pl->ev_ibar[prev_pass], 0), "hipStreamWaitEvent");
+    if (!r) {
+      ProfScope ps(pl, "ibar", t);
+      hipLaunchKernelGGL(k_ibar2d, dim3(n1 * M), dim3(IBT), lds_ibar, t, a1, lt, pl->d_level, pl->d_child_ptr,
+                         pl->d_child, pl->d_mu, pl->d_seed_par, l, prev_pass >= 0 ? 1 : 0);
+      r = hip_check(hipGetLastError(), "launch k_ibar2d");
+    }
+    if (!r) r = mark_level(pl, l, pl->ev_ibar);
+    if (!r) prev_pass = l;
+    return r;
+  };
   for (int l = pl->L - 1; l >= 0; --l) {
     if (pl->lev[l].count == 0) continue;
     hipStream_t t = level_stream(pl, l, s);
@@ -332,34 +362,19 @@ int launch_backward_2d(mch_plan* pl, const double* kappa, const double* gA, doub
     }
     // the parent seeds and the level-1 adjoint need this level's adjoint
     // solution, not its gradient window, which runs on alongside them
-    if (!rc) rc = mark_level(pl, l, pl->ev_adj);
+    if (!rc && inherit) rc = ibar_pass(l, t);
     if (!rc) rc = launch_grad(base_args(pl, kappa, pl->fwd_label, l), t, l);
     if (rc) return rc;
   }
-  CellArgs a1 = base_args(pl, kappa, pl->fwd_label, 0);
-  LevelTab lt{};
-  for (int l = 0; l < pl->L; ++l) {
-    lt.r[l] = pl->lev[l].r;
-    lt.NC[l] = pl->lev[l].NC;
-    lt.w[l] = pl->lev[l].d_w;
-  }
-  if (nc > 64) return set_error(MCH_ENOTIMPL, "2D cells wider than 64 elements");
-  const size_t lds_ibar = ((size_t)nn1 * nn1 + (size_t)nc * nc + pl->m) * sizeof(double) + (size_t)nc * nc;
-  if (inherit && (rc = set_lds(k_ibar2d, lds_ibar))) return rc;
-  rc = wait_marks(pl, s, pl->ev_adj);
+  // the level-1 adjoint waits for the last parent-seed pass, which waited
+  // for all earlier ones and for every inheriting level's adjoint solve
+  if (inherit && prev_pass >= 0 && !pl->serial)
+    rc = hip_check(hipStreamWaitEvent(s, pl->ev_ibar[prev_pass], 0), "hipStreamWaitEvent");
   if (!rc && n1 > 0) {
-    if (inherit) {
-      ProfScope ps(pl, "ibar", s);
-      hipLaunchKernelGGL(k_ibar2d, dim3(n1 * M), dim3(IBT), lds_ibar, s, a1, lt, pl->d_level, pl->d_child_ptr,
-                         pl->d_child, pl->d_mu, pl->d_seed_par);
-      rc = hip_check(hipGetLastError(), "launch k_ibar2d");
-    }
-    if (!rc) {
-      CellArgs a = adjoint_args(0);
-      a.seed_par = inherit ? pl->d_seed_par : nullptr;
-      ProfScope ps(pl, "adjsolve_L1", s);
-      rc = launch_solve(a, pl->lev[0].shape.rpt, s);
-    }
+    CellArgs a = adjoint_args(0);
+    a.seed_par = inherit ? pl->d_seed_par : nullptr;
+    ProfScope ps(pl, "adjsolve_L1", s);
+    rc = launch_solve(a, pl->lev[0].shape.rpt, s);
   }
   if (!rc && n1 > 0) rc = launch_grad(a1, s, 0);
   if (!rc) rc = join_levels(pl, s);  // the gradient windows of levels >= 2

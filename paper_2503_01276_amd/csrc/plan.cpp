@@ -214,6 +214,7 @@ int ensure_streams(mch_plan* p) {
     rc = hip_check(hipStreamCreateWithFlags(&p->side[l], hipStreamNonBlocking), "hipStreamCreate");
     if (!rc) rc = hip_check(hipEventCreateWithFlags(&p->ev_join[l], hipEventDisableTiming), "hipEventCreate");
     if (!rc) rc = hip_check(hipEventCreateWithFlags(&p->ev_adj[l], hipEventDisableTiming), "hipEventCreate");
+    if (!rc) rc = hip_check(hipEventCreateWithFlags(&p->ev_ibar[l], hipEventDisableTiming), "hipEventCreate");
   }
   return rc;
 }
@@ -267,6 +268,7 @@ extern "C" void mch_destroy(mch_plan* plan) {
     if (plan->side[l]) (void)hipStreamDestroy(plan->side[l]);
     if (plan->ev_join[l]) (void)hipEventDestroy(plan->ev_join[l]);
     if (plan->ev_adj[l]) (void)hipEventDestroy(plan->ev_adj[l]);
+    if (plan->ev_ibar[l]) (void)hipEventDestroy(plan->ev_ibar[l]);
   }
   if (plan->ev_fork) (void)hipEventDestroy(plan->ev_fork);
   if (plan->ev_l1) (void)hipEventDestroy(plan->ev_l1);

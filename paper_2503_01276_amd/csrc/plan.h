@@ -110,6 +110,8 @@ struct mch_plan {
   hipEvent_t ev_join[mch::MAX_LEVELS] = {};
   // backward: a level's adjoint solve is done (its gradient window may still run)
   hipEvent_t ev_adj[mch::MAX_LEVELS] = {};
+  // backward, 2D: the parent-seed pass of a level's cells is done
+  hipEvent_t ev_ibar[mch::MAX_LEVELS] = {};
   // captured launch sequences, replayed while the arguments are unchanged
   struct Graph {
     const void* key[4] = {nullptr, nullptr, nullptr, nullptr};
