@@ -42,8 +42,7 @@ FLOPS_PER_NODE_ITER_3D_GAL = 74
 # Sources of the kernels whose counters are recorded below, per dimension.
 KERNEL_SOURCES = {
     2: ("paper_2503_01276_amd/csrc/solve2d_kernel.h", "paper_2503_01276_amd/csrc/solve2d_inst.hip",
-        "paper_2503_01276_amd/csrc/solve2d.hip", "paper_2503_01276_amd/csrc/kernels2d.h",
-        "paper_2503_01276_amd/csrc/device_common.h"),
+        "paper_2503_01276_amd/csrc/kernels2d.h", "paper_2503_01276_amd/csrc/device_common.h"),
     3: ("paper_2503_01276_amd/csrc/cells3d.hip", "paper_2503_01276_amd/csrc/device_common.h"),
 }
 # HBM bytes per launch of a workload's dominant kernel: FETCH_SIZE and
@@ -51,7 +50,7 @@ KERNEL_SOURCES = {
 # rocprofv3 --pmc runs, each scaled by the ratio of a plain copy's known size
 # to what the same counter reads for it. An entry holds only while the kernel
 # sources hash to the recorded value; otherwise traffic is reported as null.
-_SHA_2D = "762473de9325f60ab167514dd75e39c399329bf85453e15b4d83d86008e4e099"
+_SHA_2D = "802811401fb691adb8710b7ded748dcecd9bf9db50e590b98515addb230b638f"
 _SHA_3D = "f8029b1a5d381b3384fd7329a271e0d57b365c7703b45c5611281b19a740a977"
 _COPY_SCALE = {"fetch": 1048576.0 / 524304.8, "write": 1048576.0 / 1048576.0}  # 1 GiB copy
 TRAFFIC = {

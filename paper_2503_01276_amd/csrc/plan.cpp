@@ -212,7 +212,10 @@ int ensure_streams(mch_plan* p) {
   if (!rc) rc = hip_check(hipEventCreateWithFlags(&p->ev_l1a, hipEventDisableTiming), "hipEventCreate");
   for (int l = 1; l < p->L && !rc; ++l) {
     rc = hip_check(hipStreamCreateWithFlags(&p->side[l], hipStreamNonBlocking), "hipStreamCreate");
+    if (!rc) rc = hip_check(hipStreamCreateWithFlags(&p->side2[l], hipStreamNonBlocking), "hipStreamCreate");
     if (!rc) rc = hip_check(hipEventCreateWithFlags(&p->ev_join[l], hipEventDisableTiming), "hipEventCreate");
+    if (!rc) rc = hip_check(hipEventCreateWithFlags(&p->ev_join2[l], hipEventDisableTiming), "hipEventCreate");
+    if (!rc) rc = hip_check(hipEventCreateWithFlags(&p->ev_setup[l], hipEventDisableTiming), "hipEventCreate");
     if (!rc) rc = hip_check(hipEventCreateWithFlags(&p->ev_adj[l], hipEventDisableTiming), "hipEventCreate");
     if (!rc) rc = hip_check(hipEventCreateWithFlags(&p->ev_ibar[l], hipEventDisableTiming), "hipEventCreate");
   }
@@ -223,7 +226,10 @@ int fork_levels(mch_plan* p, hipStream_t s) {
   if (p->serial) return MCH_OK;
   int rc = hip_check(hipEventRecord(p->ev_fork, s), "hipEventRecord");
   for (int l = 1; l < p->L && !rc; ++l)
-    if (p->lev[l].count) rc = hip_check(hipStreamWaitEvent(p->side[l], p->ev_fork, 0), "hipStreamWaitEvent");
+    if (p->lev[l].count) {
+      rc = hip_check(hipStreamWaitEvent(p->side[l], p->ev_fork, 0), "hipStreamWaitEvent");
+      if (!rc) rc = hip_check(hipStreamWaitEvent(p->side2[l], p->ev_fork, 0), "hipStreamWaitEvent");
+    }
   return rc;
 }
 
@@ -247,6 +253,8 @@ int join_levels(mch_plan* p, hipStream_t s) {
     if (!p->lev[l].count) continue;
     rc = hip_check(hipEventRecord(p->ev_join[l], p->side[l]), "hipEventRecord");
     if (!rc) rc = hip_check(hipStreamWaitEvent(s, p->ev_join[l], 0), "hipStreamWaitEvent");
+    if (!rc) rc = hip_check(hipEventRecord(p->ev_join2[l], p->side2[l]), "hipEventRecord");
+    if (!rc) rc = hip_check(hipStreamWaitEvent(s, p->ev_join2[l], 0), "hipStreamWaitEvent");
   }
   return rc;
 }
@@ -266,7 +274,10 @@ extern "C" void mch_destroy(mch_plan* plan) {
   }
   for (int l = 0; l < MAX_LEVELS; ++l) {
     if (plan->side[l]) (void)hipStreamDestroy(plan->side[l]);
+    if (plan->side2[l]) (void)hipStreamDestroy(plan->side2[l]);
     if (plan->ev_join[l]) (void)hipEventDestroy(plan->ev_join[l]);
+    if (plan->ev_join2[l]) (void)hipEventDestroy(plan->ev_join2[l]);
+    if (plan->ev_setup[l]) (void)hipEventDestroy(plan->ev_setup[l]);
     if (plan->ev_adj[l]) (void)hipEventDestroy(plan->ev_adj[l]);
     if (plan->ev_ibar[l]) (void)hipEventDestroy(plan->ev_ibar[l]);
   }

@@ -108,6 +108,12 @@ struct mch_plan {
   int cntA[mch::MAX_LEVELS] = {};
   hipEvent_t ev_l1a = nullptr;
   hipEvent_t ev_join[mch::MAX_LEVELS] = {};
+  // Second stream per level for its cells inheriting from the level-1 tail
+  // chunk: they wait for the level's setup and the end of level 1 only, not
+  // for the level's first part. ev_setup marks the setup on the first stream.
+  hipStream_t side2[mch::MAX_LEVELS] = {};
+  hipEvent_t ev_setup[mch::MAX_LEVELS] = {};
+  hipEvent_t ev_join2[mch::MAX_LEVELS] = {};
   // backward: a level's adjoint solve is done (its gradient window may still run)
   hipEvent_t ev_adj[mch::MAX_LEVELS] = {};
   // backward, 2D: the parent-seed pass of a level's cells is done
@@ -152,6 +158,7 @@ int mark_level(mch_plan* p, int l, hipEvent_t* ev);
 int wait_marks(mch_plan* p, hipStream_t s, hipEvent_t* ev);
 // Stream of level l (0-based) in a DAG issued on s.
 inline hipStream_t level_stream(const mch_plan* p, int l, hipStream_t s) { return (l == 0 || p->serial) ? s : p->side[l]; }
+inline hipStream_t level_stream2(const mch_plan* p, int l, hipStream_t s) { return (l == 0 || p->serial) ? s : p->side2[l]; }
 int hip_check(hipError_t e, const char* what);
 
 // Launchers implemented in the .hip translation units.

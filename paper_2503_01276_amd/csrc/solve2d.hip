@@ -202,7 +202,8 @@ CellArgs chunk_args(const CellArgs& a, int start, int count) {
 // on their side streams from the start (they fill the CUs left idle by the
 // level-1 solve). Level 1 solves in two chunks; each level >= 2 inherits and
 // solves the cells of chunk A once chunk A is done (alongside the tail chunk
-// B of level 1), then the rest once level 1 is done.
+// B of level 1), and the rest, on a second stream of the level, as soon as
+// level 1 is done.
 int launch_forward_2d(mch_plan* pl, const double* kappa, const uint8_t* label, hipStream_t s) {
   char name[32];
   int rc = ensure_streams(pl);
@@ -211,8 +212,11 @@ int launch_forward_2d(mch_plan* pl, const double* kappa, const uint8_t* label, h
     if (pl->lev[l].count == 0) continue;
     CellArgs a = base_args(pl, kappa, label, l);
     std::snprintf(name, sizeof(name), "setup_L%d", l + 1);
-    ProfScope ps(pl, name, level_stream(pl, l, s));
-    rc = launch_setup(a, level_stream(pl, l, s));
+    {
+      ProfScope ps(pl, name, level_stream(pl, l, s));
+      rc = launch_setup(a, level_stream(pl, l, s));
+    }
+    if (!rc && !pl->serial) rc = hip_check(hipEventRecord(pl->ev_setup[l], pl->side[l]), "hipEventRecord");
   }
   const int n1 = pl->lev[0].count, n1a = pl->n1a;
   if (!rc && n1) {
@@ -237,11 +241,14 @@ int launch_forward_2d(mch_plan* pl, const double* kappa, const uint8_t* label, h
   for (int l = 1; l < pl->L && !rc; ++l) {
     const int cnt = pl->lev[l].count, ca = pl->cntA[l];
     if (cnt == 0) continue;
-    hipStream_t t = level_stream(pl, l, s);
     CellArgs a = base_args(pl, kappa, label, l);
     for (int part = 0; part < 2 && !rc; ++part) {
       const int start = part ? ca : 0, num = part ? cnt - ca : ca;
-      rc = hip_check(hipStreamWaitEvent(t, part ? pl->ev_l1 : pl->ev_l1a, 0), "hipStreamWaitEvent");
+      // the second part has a stream of its own: it waits for the level's
+      // setup and the end of level 1, not for the first part's solve
+      hipStream_t t = part ? level_stream2(pl, l, s) : level_stream(pl, l, s);
+      if (part && !pl->serial) rc = hip_check(hipStreamWaitEvent(t, pl->ev_setup[l], 0), "hipStreamWaitEvent");
+      if (!rc) rc = hip_check(hipStreamWaitEvent(t, part ? pl->ev_l1 : pl->ev_l1a, 0), "hipStreamWaitEvent");
       if (rc || num == 0) continue;
       const CellArgs c = chunk_args(a, start, num);
       {
