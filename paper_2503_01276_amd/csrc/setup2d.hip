@@ -10,7 +10,8 @@
 //     V_h): the coarse element matrices sum_s kappa_s R^T K_ref R assembled into
 //     a 9-point stencil per level node, and the constraint weights of B_n = B_h P
 //     per node, side and part (written to global memory for the solve kernel);
-//   * S = B_n D^-1 B_n^T with D = diag(K_n), and S^-1 by Cholesky.
+//   * S = B_n D^-1 B_n^T with D = diag(K_n), and S^-1 by Gauss-Jordan
+//     elimination (S is symmetric positive definite: no pivoting).
 // k_inherit2d (levels >= 2, one workgroup per cell): the inherited
 //   right-hand sides f = -P^T K_h I and g' = g - B_h I of Eqs.
 //   phi_avar_corrector / phi_grad_corrector, I = Phi of the inherited level-1 cell.
@@ -71,12 +72,14 @@ __global__ __launch_bounds__(SETUP_T) void k_setup2d(CellArgs a) {
   const int R = sbw + 1;                 // node rows per constraint-pair partial
   const int npairs = m * (m + 1) / 2;
   double* S = sm;                        // m*m
-  double* X = S + m * m;                 // m*m
-  double* stat = X + m * m;              // (s*s+1)*N*3
+  double* X = S + m * m;                 // 2*m: pivot row and column
+  double* stat = X + 2 * m;              // (s*s+1)*N*3
   double* wred = stat + (s * s + 1) * N * 3;  // 4*N*3
   double* Dn = wred + (SETUP_T / 64) * N * 3; // NCp*NCp
   double* partS = Dn + NCp * NCp;        // npairs*R
-  uint8_t* labS = reinterpret_cast<uint8_t*>(partS + npairs * R);  // fine: NC*NC
+  uint8_t* labS = reinterpret_cast<uint8_t*>(partS + npairs * R);  // fine: NC*NC labels
+  uint8_t* regS = labS + NC * NC;        // NC*NC sub-block of each element
+  uint16_t* pairS = reinterpret_cast<uint16_t*>(regS + NC * NC);  // npairs: (row a << 8) | row b
   __shared__ int singular;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int ci = a.ci0 + blockIdx.x;
@@ -188,7 +191,7 @@ __global__ __launch_bounds__(SETUP_T) void k_setup2d(CellArgs a) {
     }
     for (int k = tid; k < NCp * NCp; k += SETUP_T) {
       const int Xn = k % NCp, Yn = k / NCp;
-      Dn[k] = (Xn >= 1 && Yn >= 1 && Xn < NC && Yn < NC) ? nW[(Yn * NC + Xn) * 9 + 4] : 1.0;
+      Dn[k] = (Xn >= 1 && Yn >= 1 && Xn < NC && Yn < NC) ? 1.0 / nW[(Yn * NC + Xn) * 9 + 4] : 1.0;
     }
   } else {
     for (int e = tid; e < NC * NC; e += SETUP_T) {
@@ -206,22 +209,23 @@ __global__ __launch_bounds__(SETUP_T) void k_setup2d(CellArgs a) {
         return a.kappa[(size_t)wrapi(oy + ey, a.n) * a.n + wrapi(ox + ex, a.n)] * (1.0 / 6.0);
       };
       const double ks = kq(Xn - 1, Yn - 1) + kq(Xn, Yn - 1) + kq(Xn - 1, Yn) + kq(Xn, Yn);
-      Dn[k] = 4.0 * ks;
+      Dn[k] = 1.0 / (4.0 * ks);
     }
+  }
+  // sub-block of every level element and the (row a, row b) of every pair
+  for (int e = tid; e < NC * NC; e += SETUP_T) regS[e] = (uint8_t)(((e / NC) / sbw) * s + (e % NC) / sbw);
+  for (int ra = tid; ra < m; ra += SETUP_T) {
+    const int base = ra * m - ra * (ra - 1) / 2;  // pairs (a, b >= a) of rows a' < a come first
+    for (int rb = ra; rb < m; ++rb) pairS[base + rb - ra] = (uint16_t)((ra << 8) | rb);
   }
   __syncthreads();
 
   // ---- S = B_n D^-1 B_n^T --------------------------------------------------
   // partial (pair, node row) sums, then a fixed-order sum over the rows
   for (int item = tid; item < npairs * R; item += SETUP_T) {
-    int pr = item / R;
+    const int pr = item / R;
     const int yy = item % R;
-    int ra = 0;
-    while (pr >= m - ra) {
-      pr -= m - ra;
-      ++ra;
-    }
-    const int rb = ra + pr;
+    const int ra = pairS[pr] >> 8, rb = pairS[pr] & 0xff;
     const int qa = ra / N, ja = ra % N, qb = rb / N, jb = rb % N;
     const int qax = qa % s, qay = qa / s, qbx = qb % s, qby = qb / s;
     const double cwa = cwp[ra], cwb = cwp[rb];
@@ -236,7 +240,7 @@ __global__ __launch_bounds__(SETUP_T) void k_setup2d(CellArgs a) {
 #pragma unroll
           for (int Qd = 0; Qd < 4; ++Qd) {
             const int EX = Xn - 1 + (Qd & 1), EY = Yn - 1 + (Qd >> 1);
-            const int qE = (EY / sbw) * s + EX / sbw;
+            const int qE = regS[EY * NC + EX];
             double wa, wb;
             if (!gal) {
               const int lab = labS[EY * NC + EX];
@@ -251,7 +255,7 @@ __global__ __launch_bounds__(SETUP_T) void k_setup2d(CellArgs a) {
             if (qE == qa) ba += wa;
             if (qE == qb) bb += wb;
           }
-          acc += (cwa * ba) * (cwb * bb) * (1.0 / Dn[Yn * NCp + Xn]);
+          acc += (cwa * ba) * (cwb * bb) * Dn[Yn * NCp + Xn];
         }
       }
     }
@@ -259,12 +263,7 @@ __global__ __launch_bounds__(SETUP_T) void k_setup2d(CellArgs a) {
   }
   __syncthreads();
   for (int pr0 = tid; pr0 < npairs; pr0 += SETUP_T) {
-    int pr = pr0, ra = 0;
-    while (pr >= m - ra) {
-      pr -= m - ra;
-      ++ra;
-    }
-    const int rb = ra + pr;
+    const int ra = pairS[pr0] >> 8, rb = pairS[pr0] & 0xff;
     double acc = 0.0;
     for (int yy = 0; yy < R; ++yy) acc += partS[pr0 * R + yy];
     S[ra * m + rb] = acc;
@@ -272,41 +271,39 @@ __global__ __launch_bounds__(SETUP_T) void k_setup2d(CellArgs a) {
   }
   __syncthreads();
 
-  // ---- Cholesky S = L L^T in place, one wave; inactive rows get 1 ---------
-  if (wave == 0) {
-    for (int k = lane; k < m; k += 64)
-      if (cwp[k] == 0.0) S[k * m + k] = 1.0;
-    __builtin_amdgcn_wave_barrier();
-    for (int k = 0; k < m; ++k) {
-      const double piv = S[k * m + k];
-      if (!(piv > 0.0) && lane == 0) singular = 1;
-      const double lkk = sqrt(piv > 0.0 ? piv : 1.0);
-      __builtin_amdgcn_wave_barrier();
-      for (int i = k + 1 + lane; i < m; i += 64) S[i * m + k] /= lkk;
-      if (lane == 0) S[k * m + k] = lkk;
-      __builtin_amdgcn_wave_barrier();
-      for (int i = k + 1 + lane; i < m; i += 64) {
-        const double lik = S[i * m + k];
-        for (int jj = k + 1; jj <= i; ++jj) S[i * m + jj] -= lik * S[jj * m + k];
-      }
-      __builtin_amdgcn_wave_barrier();
+  // ---- S^-1 in place by Gauss-Jordan elimination; inactive rows get 1 -----
+  // Pivot k: p = S_kk; row k becomes S_kj / p, column k becomes -S_ik / p,
+  // the pivot 1 / p, and S_ij -= S_ik S_kj / p elsewhere. S is symmetric
+  // positive definite, so every pivot is positive without row exchanges.
+  for (int k = tid; k < m; k += SETUP_T)
+    if (cwp[k] == 0.0) S[k * m + k] = 1.0;
+  double* rowk = X;       // S_kj / p
+  double* colk = X + m;   // S_ik
+  for (int k = 0; k < m; ++k) {
+    __syncthreads();
+    const double piv = S[k * m + k];
+    if (!(piv > 0.0) && tid == 0) singular = 1;
+    const double ip = piv > 0.0 ? 1.0 / piv : 1.0;
+    for (int j = tid; j < m; j += SETUP_T) {
+      rowk[j] = S[k * m + j] * ip;
+      colk[j] = S[j * m + k];
     }
-    for (int col = lane; col < m; col += 64) {
-      for (int i = 0; i < m; ++i) {
-        double v = (i == col) ? 1.0 : 0.0;
-        for (int jj = col; jj < i; ++jj) v -= S[i * m + jj] * X[jj * m + col];
-        X[i * m + col] = (i >= col) ? v / S[i * m + i] : 0.0;
-      }
+    __syncthreads();
+    for (int e = tid; e < m * m; e += SETUP_T) {
+      const int i = e / m, j = e % m;
+      double v;
+      if (i == k)
+        v = (j == k) ? ip : rowk[j];
+      else if (j == k)
+        v = -colk[i] * ip;
+      else
+        v = S[e] - colk[i] * rowk[j];
+      S[e] = v;
     }
   }
   __syncthreads();
   const bool bad = singular != 0;
-  for (int k = tid; k < m * m; k += SETUP_T) {
-    const int i = k / m, j = k % m;
-    double v = 0.0;
-    for (int t = (i > j ? i : j); t < m; ++t) v += X[t * m + i] * X[t * m + j];
-    a.sinv[(size_t)p * m * m + k] = bad ? __builtin_nan("") : v;
-  }
+  for (int k = tid; k < m * m; k += SETUP_T) a.sinv[(size_t)p * m * m + k] = bad ? __builtin_nan("") : S[k];
 }
 
 // Inherited right-hand sides of a level >= 2 cell, one workgroup per
@@ -395,9 +392,10 @@ __global__ __launch_bounds__(SETUP_T) void k_inherit2d(CellArgs a) {
 
 static size_t setup_lds_bytes(const CellArgs& a) {
   const size_t NCp = a.NC + 1, R = a.sbw + 1, npairs = (size_t)a.m * (a.m + 1) / 2;
-  size_t d = (size_t)2 * a.m * a.m + (size_t)(a.s * a.s + 1) * a.N * 3 + (SETUP_T / 64) * a.N * 3 + NCp * NCp +
-             npairs * R;
-  return d * sizeof(double) + (a.r > 1 ? 0 : (size_t)a.NC * a.NC);
+  size_t d = (size_t)a.m * a.m + 2 * (size_t)a.m + (size_t)(a.s * a.s + 1) * a.N * 3 + (SETUP_T / 64) * a.N * 3 +
+             NCp * NCp + npairs * R;
+  // labels and sub-block per element (bytes), then the pair table (uint16)
+  return d * sizeof(double) + 2 * (size_t)a.NC * a.NC + 2 * npairs;
 }
 
 template <typename F>
