@@ -69,17 +69,13 @@ __global__ __launch_bounds__(SETUP_T) void k_setup2d(CellArgs a) {
   extern __shared__ double sm[];
   const int m = a.m, s = a.s, nc = a.nc, NC = a.NC, NCp = NC + 1, sbw = a.sbw;
   const bool gal = a.r > 1;
-  const int R = sbw + 1;                 // node rows per constraint-pair partial
-  const int npairs = m * (m + 1) / 2;
   double* S = sm;                        // m*m
   double* X = S + m * m;                 // 2*m: pivot row and column
   double* stat = X + 2 * m;              // (s*s+1)*N*3
   double* wred = stat + (s * s + 1) * N * 3;  // 4*N*3
-  double* Dn = wred + (SETUP_T / 64) * N * 3; // NCp*NCp
-  double* partS = Dn + NCp * NCp;        // npairs*R
-  uint8_t* labS = reinterpret_cast<uint8_t*>(partS + npairs * R);  // fine: NC*NC labels
+  double* Dn = wred + (SETUP_T / 64) * N * 3; // NCp*NCp, holds 1/D
+  uint8_t* labS = reinterpret_cast<uint8_t*>(Dn + NCp * NCp);  // fine: NC*NC labels
   uint8_t* regS = labS + NC * NC;        // NC*NC sub-block of each element
-  uint16_t* pairS = reinterpret_cast<uint16_t*>(regS + NC * NC);  // npairs: (row a << 8) | row b
   __shared__ int singular;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int ci = a.ci0 + blockIdx.x;
@@ -212,62 +208,78 @@ __global__ __launch_bounds__(SETUP_T) void k_setup2d(CellArgs a) {
       Dn[k] = 1.0 / (4.0 * ks);
     }
   }
-  // sub-block of every level element and the (row a, row b) of every pair
+  // sub-block of every level element
   for (int e = tid; e < NC * NC; e += SETUP_T) regS[e] = (uint8_t)(((e / NC) / sbw) * s + (e % NC) / sbw);
-  for (int ra = tid; ra < m; ra += SETUP_T) {
-    const int base = ra * m - ra * (ra - 1) / 2;  // pairs (a, b >= a) of rows a' < a come first
-    for (int rb = ra; rb < m; ++rb) pairS[base + rb - ra] = (uint16_t)((ra << 8) | rb);
-  }
   __syncthreads();
 
   // ---- S = B_n D^-1 B_n^T --------------------------------------------------
-  // partial (pair, node row) sums, then a fixed-order sum over the rows
-  for (int item = tid; item < npairs * R; item += SETUP_T) {
-    const int pr = item / R;
-    const int yy = item % R;
-    const int ra = pairS[pr] >> 8, rb = pairS[pr] & 0xff;
-    const int qa = ra / N, ja = ra % N, qb = rb / N, jb = rb % N;
-    const int qax = qa % s, qay = qa / s, qbx = qb % s, qby = qb / s;
-    const double cwa = cwp[ra], cwb = cwp[rb];
-    double acc = 0.0;
-    if (abs(qax - qbx) <= 1 && abs(qay - qby) <= 1 && cwa != 0.0 && cwb != 0.0) {
-      const int X0 = max(max(qax, qbx) * sbw, 1), X1 = min((min(qax, qbx) + 1) * sbw, NC - 1);
-      const int Y0 = max(max(qay, qby) * sbw, 1), Y1 = min((min(qay, qby) + 1) * sbw, NC - 1);
-      const int Yn = Y0 + yy;
-      if (Yn <= Y1) {
-        for (int Xn = X0; Xn <= X1; ++Xn) {
-          double ba = 0.0, bb = 0.0;
+  // One wave per pair of adjacent sub-blocks qa <= qb (blocks of sub-blocks
+  // further apart are zero): its lanes visit the level nodes the two share
+  // (the whole sub-block when qa = qb), take per continuum the weight of the
+  // node's elements in qa and in qb (element counts, or the Galerkin weights),
+  // and accumulate all N x N products times 1/D; a wave sum in fixed order
+  // gives the block, scaled by the row weights.
+  for (int k = tid; k < m * m; k += SETUP_T) S[k] = 0.0;
+  __syncthreads();
+  for (int t = wave; t < s * s * 9; t += SETUP_T / 64) {
+    const int qa = t / 9, d9 = t % 9;
+    const int qax = qa % s, qay = qa / s;
+    const int qbx = qax + d9 % 3 - 1, qby = qay + d9 / 3 - 1;
+    if (qbx < 0 || qby < 0 || qbx >= s || qby >= s) continue;  // uniform across the wave
+    const int qb = qby * s + qbx;
+    if (qb < qa) continue;
+    const int X0 = max(max(qax, qbx) * sbw, 1), X1 = min((min(qax, qbx) + 1) * sbw, NC - 1);
+    const int Y0 = max(max(qay, qby) * sbw, 1), Y1 = min((min(qay, qby) + 1) * sbw, NC - 1);
+    const int wX = X1 - X0 + 1, wY = Y1 - Y0 + 1;
+    double acc[N * N];
 #pragma unroll
-          for (int Qd = 0; Qd < 4; ++Qd) {
-            const int EX = Xn - 1 + (Qd & 1), EY = Yn - 1 + (Qd >> 1);
-            const int qE = regS[EY * NC + EX];
-            double wa, wb;
-            if (!gal) {
-              const int lab = labS[EY * NC + EX];
-              wa = (lab == ja) ? 1.0 : 0.0;
-              wb = (lab == jb) ? 1.0 : 0.0;
-            } else {
-              const int side = Qd & 1, part = Qd >> 1;
-              const float* w4 = nB + ((Yn * NC + Xn) * 4 + side * 2 + part) * N;
-              wa = (double)w4[ja];
-              wb = (double)w4[jb];
-            }
-            if (qE == qa) ba += wa;
-            if (qE == qb) bb += wb;
+    for (int k = 0; k < N * N; ++k) acc[k] = 0.0;
+    const int nodes = (wX > 0 && wY > 0) ? wX * wY : 0;
+    for (int k = lane; k < nodes; k += 64) {
+      const int Xn = X0 + k % wX, Yn = Y0 + k / wX;
+      double ba[N], bb[N];
+#pragma unroll
+      for (int j = 0; j < N; ++j) ba[j] = bb[j] = 0.0;
+#pragma unroll
+      for (int Qd = 0; Qd < 4; ++Qd) {
+        const int EX = Xn - 1 + (Qd & 1), EY = Yn - 1 + (Qd >> 1);
+        const int qE = regS[EY * NC + EX];
+        if (!gal) {
+          const int lab = labS[EY * NC + EX];
+#pragma unroll
+          for (int j = 0; j < N; ++j) {
+            if (qE == qa && lab == j) ba[j] += 1.0;
+            if (qE == qb && lab == j) bb[j] += 1.0;
           }
-          acc += (cwa * ba) * (cwb * bb) * Dn[Yn * NCp + Xn];
+        } else {
+          const int side = Qd & 1, part = Qd >> 1;
+          const float* w4 = nB + ((Yn * NC + Xn) * 4 + side * 2 + part) * N;
+#pragma unroll
+          for (int j = 0; j < N; ++j) {
+            const double wj = (double)w4[j];
+            if (qE == qa) ba[j] += wj;
+            if (qE == qb) bb[j] += wj;
+          }
         }
       }
+      const double id = Dn[Yn * NCp + Xn];
+#pragma unroll
+      for (int j = 0; j < N; ++j)
+#pragma unroll
+        for (int j2 = 0; j2 < N; ++j2) acc[j * N + j2] += ba[j] * bb[j2] * id;
     }
-    partS[item] = acc;
-  }
-  __syncthreads();
-  for (int pr0 = tid; pr0 < npairs; pr0 += SETUP_T) {
-    const int ra = pairS[pr0] >> 8, rb = pairS[pr0] & 0xff;
-    double acc = 0.0;
-    for (int yy = 0; yy < R; ++yy) acc += partS[pr0 * R + yy];
-    S[ra * m + rb] = acc;
-    S[rb * m + ra] = acc;
+    wave_sum_n<N * N>(acc);
+    if (lane == 0) {
+#pragma unroll
+      for (int j = 0; j < N; ++j)
+#pragma unroll
+        for (int j2 = 0; j2 < N; ++j2) {
+          const int ra = qa * N + j, rb = qb * N + j2;
+          const double v = cwp[ra] * cwp[rb] * acc[j * N + j2];
+          S[ra * m + rb] = v;
+          S[rb * m + ra] = v;
+        }
+    }
   }
   __syncthreads();
 
@@ -391,11 +403,11 @@ __global__ __launch_bounds__(SETUP_T) void k_inherit2d(CellArgs a) {
 }
 
 static size_t setup_lds_bytes(const CellArgs& a) {
-  const size_t NCp = a.NC + 1, R = a.sbw + 1, npairs = (size_t)a.m * (a.m + 1) / 2;
+  const size_t NCp = a.NC + 1;
   size_t d = (size_t)a.m * a.m + 2 * (size_t)a.m + (size_t)(a.s * a.s + 1) * a.N * 3 + (SETUP_T / 64) * a.N * 3 +
-             NCp * NCp + npairs * R;
-  // labels and sub-block per element (bytes), then the pair table (uint16)
-  return d * sizeof(double) + 2 * (size_t)a.NC * a.NC + 2 * npairs;
+             NCp * NCp;
+  // labels and sub-block per element (bytes)
+  return d * sizeof(double) + 2 * (size_t)a.NC * a.NC;
 }
 
 template <typename F>
