@@ -320,15 +320,16 @@ __global__ __launch_bounds__(SETUP_T) void k_setup2d(CellArgs a) {
 
 // Inherited right-hand sides of a level >= 2 cell, one workgroup per
 // (cell, alpha): f = -P^T K_h I on the level nodes and g' = g - B_h I, with I
-// the inherited level-1 solution. A thread computes the load of one level
-// node from the fine elements of one of its four coarse elements (I, kappa and
-// labels straight from global memory); the four are summed in a fixed order.
-// B_h I is summed region by region in a fixed order.
+// the inherited level-1 solution. First R = K_h I at every interior fine node
+// (each node from its four fine elements, kappa and I straight from global
+// memory) into LDS; then f at a level node is minus the hat-weighted sum of R
+// over the node's support. B_h I is summed sub-block by sub-block, each wave
+// keeping its partial per sub-block and continuum; one barrier, then the
+// waves' partials in a fixed order.
 template <int N>
 __global__ __launch_bounds__(SETUP_T) void k_inherit2d(CellArgs a) {
-  extern __shared__ double quad[];  // [NC^2][4]
-  __shared__ double wred[SETUP_T / 64][N];
-  __shared__ double bI[64];
+  extern __shared__ double Rs[];  // [(nc+1)^2] R = K_h I, then [s*s][NW][N] partials
+  constexpr int NW = SETUP_T / 64;
   const int nc = a.nc, nn1 = nc + 1, NC = a.NC, r = a.r, m = a.m, s = a.s, M = a.M;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int ci = a.ci0 + blockIdx.x / M, al = blockIdx.x % M;
@@ -338,39 +339,39 @@ __global__ __launch_bounds__(SETUP_T) void k_inherit2d(CellArgs a) {
   const double* I = a.phi1 + ((size_t)a.pslot[ci] * M + al) * (size_t)nn1 * nn1;
   const double inv_r = 1.0 / r;
   double* fo = a.fin + ((size_t)ci * M + al) * NC * NC;
-  // one item per (node, coarse element of the node): quadrant loads in LDS,
-  // then each node sums its four in a fixed order
-  for (int it = tid; it < NC * NC * 4; it += SETUP_T) {
-    const int nd = it >> 2, q = it & 3;
-    const int Xn = nd % NC, Yn = nd / NC;
+  double* wred = Rs + nn1 * nn1;
+  // R at fine node (x, y): node (x, y) is corner c of the element, and row c
+  // of 6 K_ref is 4 v_c - 2 v_(c^3) - v_(c^1) - v_(c^2)
+  for (int nd = tid; nd < nn1 * nn1; nd += SETUP_T) {
+    const int x = nd % nn1, y = nd / nn1;
     double t = 0.0;
-    if (Xn >= 1 && Yn >= 1) {
-      const int qx = q & 1, qy = q >> 1;
-      const int EX = Xn - 1 + qx, EY = Yn - 1 + qy;
-      const int cx = 1 - qx, cy = 1 - qy;  // corner of the node in coarse element E
-      for (int v = 0; v < r; ++v)
-        for (int u = 0; u < r; ++u) {
-          const int fx = EX * r + u, fy = EY * r + v;
-          double Iv[4], y[4];
+    if (x >= 1 && y >= 1 && x < nc && y < nc) {
 #pragma unroll
-          for (int d = 0; d < 4; ++d) Iv[d] = I[(size_t)(fy + (d >> 1)) * nn1 + fx + (d & 1)];
-          kref6_apply(Iv, y);
-          const double k6 = a.kappa[(size_t)wrapi(oy + fy, a.n) * a.n + wrapi(ox + fx, a.n)] * (1.0 / 6.0);
-          double acc = 0.0;
-#pragma unroll
-          for (int d = 0; d < 4; ++d) {
-            const double tx = (u + (d & 1)) * inv_r, ty = (v + (d >> 1)) * inv_r;
-            acc += (cx ? tx : 1.0 - tx) * (cy ? ty : 1.0 - ty) * y[d];
-          }
-          t += k6 * acc;
-        }
+      for (int q = 0; q < 4; ++q) {
+        const int ex = x - 1 + (q & 1), ey = y - 1 + (q >> 1);
+        const int c = (x - ex) + 2 * (y - ey);
+        auto Iv = [&](int cc) { return I[(size_t)(ey + (cc >> 1)) * nn1 + ex + (cc & 1)]; };
+        const double k6 = a.kappa[(size_t)wrapi(oy + ey, a.n) * a.n + wrapi(ox + ex, a.n)] * (1.0 / 6.0);
+        t += k6 * (4.0 * Iv(c) - 2.0 * Iv(c ^ 3) - Iv(c ^ 1) - Iv(c ^ 2));
+      }
     }
-    quad[it] = t;
+    Rs[nd] = t;
   }
   __syncthreads();
-  for (int nd = tid; nd < NC * NC; nd += SETUP_T)
-    fo[nd] = -((quad[4 * nd] + quad[4 * nd + 1]) + (quad[4 * nd + 2] + quad[4 * nd + 3]));
-  // B_h I: element sums of I per region and continuum, region by region
+  for (int nd = tid; nd < NC * NC; nd += SETUP_T) {
+    const int Xn = nd % NC, Yn = nd / NC;
+    double acc = 0.0;
+    if (Xn >= 1 && Yn >= 1) {
+      for (int dy = 1 - r; dy <= r - 1; ++dy) {
+        const double* row = Rs + (size_t)(Yn * r + dy) * nn1 + Xn * r;
+        double racc = 0.0;
+        for (int dx = 1 - r; dx <= r - 1; ++dx) racc += (1.0 - abs(dx) * inv_r) * row[dx];
+        acc += (1.0 - abs(dy) * inv_r) * racc;
+      }
+    }
+    fo[nd] = -acc;
+  }
+  // B_h I: element sums of I per sub-block and continuum
   const int sb = nc / s;
   for (int reg = 0; reg < s * s; ++reg) {
     const int x0 = (reg % s) * sb, y0 = (reg / s) * sb;
@@ -385,21 +386,19 @@ __global__ __launch_bounds__(SETUP_T) void k_inherit2d(CellArgs a) {
 #pragma unroll
       for (int j = 0; j < N; ++j) acc[j] += (lab == j) ? es : 0.0;
     }
+    wave_sum_n<N>(acc);
+    if (lane == 0) {
 #pragma unroll
-    for (int j = 0; j < N; ++j) {
-      const double v = wave_sum(acc[j]);
-      if (lane == 0) wred[wave][j] = v;
+      for (int j = 0; j < N; ++j) wred[(reg * NW + wave) * N + j] = acc[j];
     }
-    __syncthreads();
-    if (tid < N) {
-      double v = 0.0;
-      for (int w2 = 0; w2 < SETUP_T / 64; ++w2) v += wred[w2][tid];
-      bI[reg * N + tid] = v;
-    }
-    __syncthreads();
   }
-  for (int k = tid; k < m; k += SETUP_T)
-    a.gin[((size_t)ci * M + al) * m + k] = a.g[((size_t)p * M + al) * m + k] - a.cw[(size_t)p * m + k] * bI[k];
+  __syncthreads();
+  for (int k = tid; k < m; k += SETUP_T) {
+    const int q = k / N, j = k % N;
+    double bI = 0.0;
+    for (int w2 = 0; w2 < NW; ++w2) bI += wred[(q * NW + w2) * N + j];
+    a.gin[((size_t)ci * M + al) * m + k] = a.g[((size_t)p * M + al) * m + k] - a.cw[(size_t)p * m + k] * bI;
+  }
 }
 
 static size_t setup_lds_bytes(const CellArgs& a) {
@@ -440,7 +439,7 @@ int launch_inherit(const CellArgs& a, hipStream_t s) {
   if (a.N == 2) fn = k_inherit2d<2>;
   if (a.N == 3) fn = k_inherit2d<3>;
   if (!fn) return set_error(MCH_ENOTIMPL, "n_cont");
-  const size_t lds = (size_t)a.NC * a.NC * 4 * sizeof(double);
+  const size_t lds = ((size_t)(a.nc + 1) * (a.nc + 1) + (size_t)a.s * a.s * (SETUP_T / 64) * a.N) * sizeof(double);
   int rc = lds_attr(fn, lds);
   if (rc) return rc;
   hipLaunchKernelGGL(fn, dim3(a.count * a.M), dim3(SETUP_T), lds, s, a);
