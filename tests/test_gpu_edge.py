@@ -7,7 +7,7 @@ import pytest
 import oracle
 from paper_2503_01276_amd import workloads as W
 
-from gpu_util import check_forward, say
+from gpu_util import check_forward, grad_case, say
 
 pytestmark = pytest.mark.gpu
 
@@ -133,3 +133,17 @@ def test_call_order_and_argument_errors():
     plan.effective_coeffs_backward(kd, torch.zeros_like(A), g)
     torch.cuda.synchronize()
     assert float(g.abs().max()) == 0.0
+
+
+def test_one_and_eight_subblocks_2d():
+    # the solve kernels are compiled per number of sub-blocks per axis; the
+    # workloads use 2 and 4, these cover 1 (m = N) and 8 (m = 64, the largest)
+    from paper_2503_01276_amd import workloads as W2
+
+    c1 = W.PRESETS["t2"].replace(n_sub=1)
+    k, l = W.medium("t2")
+    check_forward("t2 s=1", c1, k, l, phi_cells=list(range(0, c1.n_points, 4)), workers=4)
+    grad_case("adj-t2 s=1", c1, 21, workers=4)
+    c8 = W2.Config(dim=2, n_fine=256, n_macro=8, n_cell=64, n_sub=8, n_cont=1, levels=2)
+    k8, l8 = W2.medium_for(c8, seed=23)
+    check_forward("s=8 N=1", c8, k8, l8, phi_cells=[0, 1, 9, 63], workers=8)
