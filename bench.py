@@ -302,8 +302,11 @@ def main():
     aiters, _ = plan.diagnostics(adjoint=True)
     lev, _ = plan.hierarchy()
     lev_pm = np.repeat(lev[:, None], plan.M, axis=1)
-    # dominant kernel and its algorithmic flops per launch
-    dom = max(ktab, key=lambda k: ktab[k]["avg_ms"] * ktab[k]["launches_per_step"])
+    # dominant kernel (the solve launches, whose roofline the flop and byte
+    # models describe; the auxiliary kernels' event times include the time they
+    # share the GPU with concurrent solves) and its algorithmic work per launch
+    solve_kernels = [k for k in ktab if k.startswith(("solve_L", "adjsolve_L"))]
+    dom = max(solve_kernels or ktab, key=lambda k: ktab[k]["avg_ms"] * ktab[k]["launches_per_step"])
     roof = None
     if dom.startswith(("solve_L", "adjsolve_L")):
         li = int(dom.split("_L")[1]) - 1

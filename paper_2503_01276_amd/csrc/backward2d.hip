@@ -257,6 +257,19 @@ __global__ __launch_bounds__(IBT) void k_ibar2d(CellArgs a, LevelTab lt, const i
   }
 }
 
+// dst[i] += b_1[i] + ... in the order given (the per-level parent seeds)
+struct SeedBufs {
+  const double* b[MAX_LEVELS];
+  int n;
+};
+__global__ void k_sum_seeds(size_t count, double* dst, SeedBufs sb) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) {
+    double v = dst[i];
+    for (int k = 0; k < sb.n; ++k) v += sb.b[k][i];
+    dst[i] = v;
+  }
+}
+
 MCH_DEV int floordiv(int a, int b) {
   int q = a / b;
   return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
@@ -341,22 +354,23 @@ int launch_backward_2d(mch_plan* pl, const double* kappa, const double* gA, doub
   const size_t lds_ibar = ((size_t)nn1 * nn1 + (size_t)nc * nc + pl->m) * sizeof(double) + (size_t)nc * nc;
   if (inherit && (rc = set_lds(k_ibar2d, lds_ibar))) return rc;
   // Parent seeds from the cells of one inheriting level, on that level's
-  // stream once its adjoint solve is done. The passes run deepest level first,
-  // each after the previous one (the first writes, the others add), so the
-  // sum has a fixed order and only the level-2 pass waits for the level-2
-  // adjoint, the longest of them.
-  int prev_pass = -1;
+  // stream once its adjoint solve is done, into a buffer of its own (the
+  // deepest level's straight into d_seed_par), so the passes run in parallel;
+  // the others are then added deepest level first, a fixed order.
+  int deepest = -1;
+  SeedBufs extra{};
   auto ibar_pass = [&](int l, hipStream_t t) -> int {
+    if (deepest < 0) deepest = l;
+    double* dst = (l == deepest) ? pl->d_seed_par : pl->d_seed_lvl[l];
+    if (l != deepest) extra.b[extra.n++] = dst;
     int r = MCH_OK;
-    if (prev_pass >= 0 && !pl->serial) r = hip_check(hipStreamWaitEvent(t, pl->ev_ibar[prev_pass], 0), "hipStreamWaitEvent");
-    if (!r) {
+    {
       ProfScope ps(pl, "ibar", t);
       hipLaunchKernelGGL(k_ibar2d, dim3(n1 * M), dim3(IBT), lds_ibar, t, a1, lt, pl->d_level, pl->d_child_ptr,
-                         pl->d_child, pl->d_mu, pl->d_seed_par, l, prev_pass >= 0 ? 1 : 0);
+                         pl->d_child, pl->d_mu, dst, l, 0);
       r = hip_check(hipGetLastError(), "launch k_ibar2d");
     }
     if (!r) r = mark_level(pl, l, pl->ev_ibar);
-    if (!r) prev_pass = l;
     return r;
   };
   for (int l = pl->L - 1; l >= 0; --l) {
@@ -384,10 +398,18 @@ int launch_backward_2d(mch_plan* pl, const double* kappa, const double* gA, doub
     if (!rc) rc = launch_grad(base_args(pl, kappa, pl->fwd_label, l), t, l);
     if (rc) return rc;
   }
-  // the level-1 adjoint waits for the last parent-seed pass, which waited
-  // for all earlier ones and for every inheriting level's adjoint solve
-  if (inherit && prev_pass >= 0 && !pl->serial)
-    rc = hip_check(hipStreamWaitEvent(s, pl->ev_ibar[prev_pass], 0), "hipStreamWaitEvent");
+  // the level-1 adjoint waits for every level's parent-seed pass (each after
+  // its level's adjoint solve), then the passes' sum
+  if (inherit && deepest >= 0) {
+    if (!pl->serial) rc = wait_marks(pl, s, pl->ev_ibar);
+    if (!rc && extra.n > 0) {
+      const size_t count = (size_t)n1 * M * nn1 * nn1;
+      ProfScope ps(pl, "ibar_sum", s);
+      hipLaunchKernelGGL(k_sum_seeds, dim3((unsigned)std::min<size_t>((count + 255) / 256, 4096)), dim3(256), 0, s,
+                         count, pl->d_seed_par, extra);
+      rc = hip_check(hipGetLastError(), "launch k_sum_seeds");
+    }
+  }
   if (!rc && n1 > 0) {
     CellArgs a = adjoint_args(0);
     a.seed_par = inherit ? pl->d_seed_par : nullptr;

@@ -427,6 +427,10 @@ extern "C" int mch_build_levels(const mch_config* cfg, mch_plan** out) {
   if (!rc) rc = upload(p, &p->d_slot, p->slot);
   if (!rc) rc = dev_alloc(p, &p->d_seed_kp, P * M * (size_t)ipow(H + 1, d));
   if (!rc) rc = dev_alloc(p, &p->d_seed_par, n1 * M * (size_t)p->nn);
+  // 2D: each inheriting level but the deepest keeps its parent seeds apart
+  // (the deepest writes d_seed_par), so the per-level passes run in parallel
+  for (int l = 1; l + 1 < p->L && !rc && d == 2 && n1 < (size_t)p->P; ++l)
+    rc = dev_alloc(p, &p->d_seed_lvl[l], n1 * M * (size_t)p->nn);
   if (!rc) rc = dev_alloc(p, &p->d_gk, (size_t)ipow(n, d));
   if (!rc) rc = dev_alloc(p, &p->d_gcell, P * (size_t)ipow(nc, d));
   if (!rc) rc = dev_alloc(p, &p->d_iters_adj, P * M);

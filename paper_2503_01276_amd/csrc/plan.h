@@ -83,6 +83,7 @@ struct mch_plan {
   // adjoint scratch
   double* d_seed_kp = nullptr;   // [P][M][(H+1)^d]
   double* d_seed_par = nullptr;  // [n1][M][nn]
+  double* d_seed_lvl[mch::MAX_LEVELS] = {};  // 2D: parent seeds of one inheriting level [n1][M][nn]
   double* d_gk = nullptr;        // [n^d] explicit part of dLoss/dkappa (K_p terms)
   double* d_gcell = nullptr;     // [P][nc^d] per-cell part of dLoss/dkappa on the cell window
   int32_t* d_iters_adj = nullptr;
