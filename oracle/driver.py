@@ -13,7 +13,8 @@ G_p = dLoss/dA_eff(p), per cell
     [K_n B_n^T; B_n 0][w_a; mu_a] = [P_n^T Phibar_a; 0]
     dLoss/dkappa_e += -(P_n w_a)|_e^T K_ref Phi_a|_e              (every e in the cell)
                       + sum_ab G_ab Phi_a|_e^T K_ref Phi_b|_e   (e in K_p)
-    Ibar_a = Phibar_a - K_h P_n w_a - B_h^T mu_a   -> added to the parent's seed,
+    Ibar_a = Phibar_a - K_h P_n w_a - B_h^T mu_a   -> c_t Ibar_a added to the seed of
+                                                    every point t the cell inherits from,
 
 processed from level L down to level 1, and finally dLoss/dlog kappa = kappa * dLoss/dkappa.
 """
@@ -52,13 +53,23 @@ def _pool_map(fn, items, workers):
 
 
 class Forward:
-    def __init__(self, cfg, lev, par, A, Phi, beta):
-        self.cfg, self.level, self.parent = cfg, lev, par
+    def __init__(self, cfg, lev, par, inherit, A, Phi, beta):
+        self.cfg, self.level, self.parent, self.inherit = cfg, lev, par, inherit
         self.A, self.Phi, self.beta = A, Phi, beta
 
 
+def _inherited(inherit_p, Phi):
+    """I = sum_t c_t Phi_t (Eq. phiXiI_all), None for a level-1 point."""
+    if not inherit_p:
+        return None
+    I = None
+    for t, c in inherit_p:
+        I = c * Phi[t] if I is None else I + c * Phi[t]
+    return I
+
+
 def forward(cfg, kappa, label, points=None, workers: int | None = None) -> Forward:
-    """Solve the cells of ``points`` (default: all) plus the parents they need.
+    """Solve the cells of ``points`` (default: all) plus every point they inherit from.
 
     Returns per-point local solutions Phi [n_nodes, M] (all cell nodes), multipliers,
     and effective tensors A_eff [M, M] (dicts keyed by macropoint index).
@@ -66,19 +77,25 @@ def forward(cfg, kappa, label, points=None, workers: int | None = None) -> Forwa
     workers = workers if workers is not None else (os.cpu_count() or 1)
     lev = hierarchy.levels(cfg.n_macro, cfg.dim, cfg.levels, cfg.eta)
     par = hierarchy.parents(cfg.n_macro, cfg.dim, cfg.levels, cfg.eta)
+    inherit = hierarchy.interp_weights(cfg.n_macro, cfg.dim, cfg.levels, cfg.eta, cfg.interp)
     if points is None:
         points = np.arange(cfg.n_points)
-    points = np.asarray(points)
-    need = set(int(p) for p in points)
-    need |= set(int(par[p]) for p in points if par[p] >= 0)
+    need = set(int(p) for p in np.asarray(points))
+    todo = list(need)
+    while todo:  # close the set under "inherits from"
+        q = todo.pop()
+        for t, _ in inherit[q]:
+            if t not in need:
+                need.add(t)
+                todo.append(t)
     _init(cfg, kappa, label)
     Phi, A, beta = {}, {}, {}
     for n in range(1, cfg.levels + 1):
         todo = [p for p in sorted(need) if lev[p] == n]
-        items = [(p, n, Phi[par[p]] if n > 1 else None) for p in todo]
+        items = [(p, n, _inherited(inherit[p], Phi)) for p in todo]
         for p, ph, a, b in _pool_map(_fwd_one, items, workers):
             Phi[p], A[p], beta[p] = ph, a, b
-    return Forward(cfg, lev, par, A, Phi, beta)
+    return Forward(cfg, lev, par, inherit, A, Phi, beta)
 
 
 def _bwd_one(args):
@@ -122,14 +139,14 @@ def backward(cfg, kappa, label, fwd: Forward, gA: dict, workers: int | None = No
         todo = [p for p in range(cfg.n_points) if fwd.level[p] == lvl]
         items = []
         for p in todo:
-            I_full = fwd.Phi[fwd.parent[p]] if lvl > 1 else None
+            I_full = _inherited(fwd.inherit[p], fwd.Phi)
             items.append((p, lvl, I_full, fwd.Phi[p], np.asarray(gA[p]), seeds.get(p)))
         for p, gke, Ibar in _pool_map(_bwd_one, items, workers):
             idx = fem.window_flat_indices(n, cells.cell_origin(cfg, p), cfg.n_cell, cfg.dim)
             np.add.at(gk, idx, gke)
             if Ibar is not None:
-                t = int(fwd.parent[p])
-                seeds[t] = seeds.get(t, 0.0) + Ibar
+                for t, c in fwd.inherit[p]:
+                    seeds[t] = seeds.get(t, 0.0) + c * Ibar
     return (kappa.reshape(-1) * gk).reshape(kappa.shape)
 
 

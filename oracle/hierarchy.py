@@ -7,9 +7,17 @@ macropoint indices congruent to o modulo eta^(L-n), with o = floor(eta^(L-1)/2)
 (this phase reproduces the 8x8, L=3, eta=2 example of Figs. 2-3).
 S_1 = T_1 and S_n = T_n minus the union of earlier S_k.
 
-Interpolation (paper's experiments, Sec. 3.3): a macropoint of level n >= 2
-inherits the local solutions of the level-1 macropoint of its aligned
-eta^(L-1)-per-axis block of macropoints, with weight c_t = 1.
+Interpolation (Sec. 3.3, Eq. phiXiI_all): a macropoint of level n >= 2 takes
+I = sum_t c_t Phi_t over neighbours t in the union of S_k, k < n (= T_(n-1)),
+with sum_t c_t = 1.
+* interp = 0 (the paper's experiments): the single neighbour is the level-1
+  macropoint of the aligned eta^(L-1)-per-axis block, c_t = 1.
+* interp = 1 (multilinear): per axis, the two T_(n-1) lattice indices that
+  bracket the point's index (lattice step eta^(L-n+1), periodic in the
+  macropoint index), with the 1D linear-interpolation weights; the neighbours
+  are their tensor products with weight the product of the 1D weights (axis 1
+  fastest), zero weights left out. Every neighbour lies within one lattice
+  step per axis, i.e. within O(eta^(L-n) H).
 """
 from __future__ import annotations
 
@@ -51,3 +59,38 @@ def parents(n_macro: int, dim: int, L: int, eta: int) -> np.ndarray:
         stride *= n_macro
     par[lev == 1] = -1
     return par
+
+
+def _axis_bracket(i: int, step: int, o: int, n_macro: int):
+    """1D neighbours of index i on the lattice {o + k*step}, periodic in n_macro."""
+    lo = o + ((i - o) // step) * step
+    frac = (i - lo) / step
+    if frac == 0.0:
+        return [(lo % n_macro, 1.0)]
+    return [(lo % n_macro, 1.0 - frac), ((lo + step) % n_macro, frac)]
+
+
+def interp_weights(n_macro: int, dim: int, L: int, eta: int, interp: int):
+    """Per macropoint, the list [(t, c_t), ...] of Eq. phiXiI_all ([] on level 1)."""
+    lev = levels(n_macro, dim, L, eta)
+    j = macro_coords(n_macro, dim)
+    if interp == 0:
+        par = parents(n_macro, dim, L, eta)
+        return [[] if lev[p] == 1 else [(int(par[p]), 1.0)] for p in range(len(j))]
+    o = (eta ** (L - 1)) // 2
+    out = []
+    for p in range(len(j)):
+        n = int(lev[p])
+        if n == 1:
+            out.append([])
+            continue
+        step = eta ** (L - n + 1)
+        axes = [_axis_bracket(int(j[p, k]), step, o, n_macro) for k in range(dim)]
+        combos = [(0, 1.0)]
+        stride = 1
+        for k in range(dim):
+            # the new axis is the outer loop, so axis 1 varies fastest
+            combos = [(t + i * stride, c * w) for (i, w) in axes[k] for (t, c) in combos]
+            stride *= n_macro
+        out.append(combos)
+    return out
