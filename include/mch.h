@@ -32,8 +32,12 @@
  *   constraints delta_ij*(xbar_{m,qj} - c_mj), c_mj the continuum-j centroid in K_p).
  * Hierarchy: T_n keeps macropoints with index = o (mod eta^(L-n)) per axis,
  *   o = floor(eta^(L-1)/2); S_1 = T_1, S_n = T_n minus T_(n-1) (Sec. 3.1,
- *   Eq. defi_Sn). Level-n points inherit the level-1 point of their aligned
- *   eta^(L-1)-per-axis block with weight 1 (the rule of the paper's experiments).
+ *   Eq. defi_Sn). A level-n point inherits I = sum_t c_t Phi_t (Sec. 3.3,
+ *   Eq. phiXiI_all): with interp = 0 the level-1 point of its aligned
+ *   eta^(L-1)-per-axis block with weight 1 (the rule of the paper's
+ *   experiments); with interp = 1 the points of T_(n-1) that bracket it per
+ *   axis (lattice step eta^(L-n+1), periodic in the macropoint index) with
+ *   tensor-product linear weights, which sum to 1.
  * Precision: every floating-point quantity is IEEE binary64.
  *
  * Memory and streams
@@ -78,7 +82,8 @@ typedef struct {
   int32_t n_cont;       /* number of continua N (1..3) */
   int32_t levels;       /* L >= 1; L = 1 is the flat method */
   int32_t eta;          /* coarsening factor >= 1; n_macro divisible by eta^(L-1) */
-  int32_t interp;       /* 0: inherit the level-1 solution of the group (only mode implemented) */
+  int32_t interp;       /* 0: inherit the level-1 solution of the group (the paper's experiments);
+                           1: multilinear interpolation from T_(n-1) (2D only) */
   int32_t bc;           /* 0: homogeneous Dirichlet on the cell boundary (only mode implemented) */
   double rtol;          /* relative tolerance on the projected preconditioned residual norm */
   int32_t max_iter;     /* Krylov iteration cap per solve */
@@ -100,6 +105,16 @@ int mch_build_levels(const mch_config* cfg, mch_plan** out);
  * (only dim, n_macro, levels and eta are read), into host arrays of length
  * n_macro^dim. Synchronous. MCH_EINVAL for inconsistent sizes. */
 int mch_build_hierarchy(const mch_config* cfg, int32_t* level, int32_t* parent);
+
+/* Host-only: the neighbours and weights of the multilinear rule (interp = 1,
+ * Sec. 3.3, Eq. phiXiI_all) for every macropoint, whatever cfg->interp says.
+ * nbr [n_macro^dim][2^dim] receives neighbour macropoint indices (-1 where
+ * unused, and for every slot of a level-1 point), weight the same shape
+ * (0 where unused); per point the entries are the tensor products of the
+ * per-axis (lower, upper) choices, axis 1 fastest, aligned axes contributing
+ * the lower one only. Only dim, n_macro, levels and eta are read. Host
+ * arrays owned by the caller. Synchronous. MCH_EINVAL for inconsistent sizes. */
+int mch_build_interp(const mch_config* cfg, int32_t* nbr, double* weight);
 
 /* Static description of a built plan (host memory, synchronous):
  * info[0] = P (macropoints), info[1] = M (right-hand sides per macropoint),

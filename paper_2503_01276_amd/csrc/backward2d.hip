@@ -312,7 +312,87 @@ static int set_lds(F fn, size_t lds) {
 // the last pass, the level-1 adjoint and gradient, then the gather after the
 // full join. (A parent-seed pass is latency-bound per workgroup, so it is not
 // split into chunks of level-1 cells.)
+// interp = 1: levels from L down to 1 as a chain on s. Per level: the
+// explicit seeds, the adjoint solve (its right-hand side includes the seeds
+// the level's cells received from the levels above, for n < L), then for
+// n >= 2 Ibar of each cell and c_t Ibar into its neighbours' seeds, and the
+// gradient window; the gather at the end.
+static int launch_backward_2d_chain(mch_plan* pl, const double* kappa, const double* gA, double* glogk,
+                                    hipStream_t s) {
+  const int M = pl->M, nc = pl->cfg.n_cell, nn1 = nc + 1;
+  char name[32];
+  void (*seed)(CellArgs, const double*, double*, double*) = nullptr;
+  switch (M) {
+    case 3: seed = k_seed2d<3>; break;
+    case 6: seed = k_seed2d<6>; break;
+    case 9: seed = k_seed2d<9>; break;
+    default: return set_error(MCH_ENOTIMPL, "M");
+  }
+  if (nc > 64) return set_error(MCH_ENOTIMPL, "2D cells wider than 64 elements");
+  const size_t lds_ibar = ((size_t)nn1 * nn1 + (size_t)nc * nc + pl->m) * sizeof(double) + (size_t)nc * nc;
+  int rc = set_lds(k_ibar2d, lds_ibar);
+  if (!rc) rc = launch_zero(pl->d_seedT, (size_t)pl->nT * M * pl->nn, s);
+  const CellArgs a1 = base_args(pl, kappa, pl->fwd_label, 0);
+  LevelTab lt{};
+  for (int l = 0; l < pl->L; ++l) {
+    lt.r[l] = pl->lev[l].r;
+    lt.NC[l] = pl->lev[l].NC;
+    lt.w[l] = pl->lev[l].d_w;
+  }
+  for (int l = pl->L - 1; l >= 0 && !rc; --l) {
+    const Level& lv = pl->lev[l];
+    if (lv.count == 0) continue;
+    CellArgs a = base_args(pl, kappa, pl->fwd_label, l);
+    const size_t lds = ((size_t)M * (a.H + 1) * (a.H + 1) + (size_t)M * M) * sizeof(double);
+    if ((rc = set_lds(seed, lds))) break;
+    std::snprintf(name, sizeof(name), "seed_L%d", l + 1);
+    {
+      ProfScope ps(pl, name, s);
+      hipLaunchKernelGGL(seed, dim3(a.count), dim3(BT), lds, s, a, gA, pl->d_seed_kp, pl->d_gk);
+    }
+    if ((rc = hip_check(hipGetLastError(), "launch k_seed2d"))) break;
+    CellArgs b = a;
+    b.adjoint = 1;
+    b.out = lv.d_w;
+    b.beta = pl->d_mu;
+    b.iters = pl->d_iters_adj;
+    b.resid = pl->d_resid_adj;
+    b.seed_par = (l + 1 < pl->L) ? pl->d_seedT + (size_t)lv.toff * M * pl->nn : nullptr;
+    std::snprintf(name, sizeof(name), "adjsolve_L%d", l + 1);
+    {
+      ProfScope ps(pl, name, s);
+      rc = launch_solve(b, lv.shape.rpt, s);
+    }
+    if (!rc && l > 0) {
+      // Ibar per cell: the parent-seed kernel over the identity map (each
+      // cell its own single "child") into d_ibar, row = cell index
+      {
+        ProfScope ps(pl, "ibar", s);
+        hipLaunchKernelGGL(k_ibar2d, dim3(lv.count * M), dim3(IBT), lds_ibar, s, a1, lt, pl->d_level, pl->d_iptr,
+                           lv.d_cells, pl->d_mu, pl->d_ibar, l, 0);
+        rc = hip_check(hipGetLastError(), "launch k_ibar2d");
+      }
+      if (!rc) rc = launch_distribute_2d(pl, l, s);
+    }
+    if (!rc && a.count) {
+      std::snprintf(name, sizeof(name), "grad_L%d", l + 1);
+      ProfScope ps(pl, name, s);
+      hipLaunchKernelGGL(k_grad2d, dim3(a.count), dim3(BT), 0, s, a, lv.d_w, pl->d_gcell);
+      rc = hip_check(hipGetLastError(), "launch k_grad2d");
+    }
+  }
+  if (rc) return rc;
+  const size_t total = (size_t)pl->n * pl->n;
+  const unsigned blocks = (unsigned)((total + 255) / 256 < 65536 ? (total + 255) / 256 : 65536);
+  {
+    ProfScope ps(pl, "gather", s);
+    hipLaunchKernelGGL(k_gather_grad2d, dim3(blocks), dim3(256), 0, s, a1, pl->d_gk, pl->d_gcell, glogk);
+  }
+  return hip_check(hipGetLastError(), "launch k_gather_grad2d");
+}
+
 int launch_backward_2d(mch_plan* pl, const double* kappa, const double* gA, double* glogk, hipStream_t s) {
+  if (pl->nT > 0) return launch_backward_2d_chain(pl, kappa, gA, glogk, s);
   const int M = pl->M, nc = pl->cfg.n_cell, nn1 = nc + 1;
   char name[32];
   int rc = ensure_streams(pl);

@@ -121,6 +121,50 @@ static void build_hierarchy(mch_plan* p) {
   }
 }
 
+// Multilinear neighbours (interp = 1, Sec. 3.3, Eq. phiXiI_all): a level-n
+// point takes the T_(n-1) lattice indices (step eta^(L-n+1), phase o) that
+// bracket its index per axis, periodic in the macropoint index, with the 1D
+// linear weights (1 - f, f); the neighbours are the tensor products, axis 1
+// fastest, weight = product of the 1D weights, zero weights left out.
+static int floor_div(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+static void build_interp(mch_plan* p) {
+  const int d = p->dim, nm = p->nm, L = p->L, eta = p->cfg.eta, K = 1 << d;
+  const int o = ipow(eta, L - 1) / 2;
+  p->nbr.assign((size_t)p->P * K, -1);
+  p->nbw.assign((size_t)p->P * K, 0.0);
+  for (int q = 0; q < p->P; ++q) {
+    const int n = p->level[q];
+    if (n == 1) continue;
+    const int step = ipow(eta, L - n + 1);
+    const int j[3] = {q % nm, (q / nm) % nm, (q / (nm * nm)) % nm};
+    int cnt = 1, ids[8] = {0}, str = 1;
+    double ws[8] = {1.0};
+    for (int a = 0; a < d; ++a) {
+      const int lo = o + floor_div(j[a] - o, step) * step;
+      const double f = (double)(j[a] - lo) / (double)step;
+      const int lw = ((lo % nm) + nm) % nm, hi = (lo + step) % nm;
+      if (f == 0.0) {
+        for (int k = 0; k < cnt; ++k) ids[k] += lw * str;
+      } else {
+        // the new axis is the outer loop: entries [0, cnt) take lo, [cnt, 2 cnt) take hi
+        for (int k = 0; k < cnt; ++k) {
+          ids[cnt + k] = ids[k] + hi * str;
+          ws[cnt + k] = ws[k] * f;
+          ids[k] += lw * str;
+          ws[k] = ws[k] * (1.0 - f);
+        }
+        cnt *= 2;
+      }
+      str *= nm;
+    }
+    for (int k = 0; k < cnt; ++k) {
+      p->nbr[(size_t)q * K + k] = ids[k];
+      p->nbw[(size_t)q * K + k] = ws[k];
+    }
+  }
+}
+
 // Coarse-element tables of the Galerkin operator for a level with ratio r:
 // fine element at position (u, v) inside a coarse element contributes
 // kappa_s * R^T K_ref R to the coarse element matrix, and rho[a] = sum of
@@ -310,7 +354,8 @@ extern "C" int mch_build_levels(const mch_config* cfg, mch_plan** out) {
   if (c.eta < 1) return set_error(MCH_EINVAL, "eta must be >= 1");
   if (c.n_cont < 1 || c.n_cont > 3) return set_error(MCH_EINVAL, "n_cont must be 1..3");
   if (c.n_sub < 1) return set_error(MCH_EINVAL, "n_sub must be >= 1");
-  if (c.interp != 0) return set_error(MCH_ENOTIMPL, "only interp = 0 (inherit the group's level-1 solution) is implemented");
+  if (c.interp != 0 && c.interp != 1) return set_error(MCH_EINVAL, "interp must be 0 or 1");
+  if (c.interp == 1 && d == 3) return set_error(MCH_ENOTIMPL, "multilinear interpolation (interp = 1) is implemented in 2D only");
   if (c.bc != 0) return set_error(MCH_ENOTIMPL, "only bc = 0 (homogeneous Dirichlet) is implemented");
   if (!(c.rtol > 0.0) || c.max_iter < 1) return set_error(MCH_EINVAL, "rtol must be > 0 and max_iter >= 1");
   const int nc = c.n_cell;
@@ -351,7 +396,19 @@ extern "C" int mch_build_levels(const mch_config* cfg, mch_plan** out) {
     return set_error(MCH_EHIP, "no HIP device");
   }
   build_hierarchy(p);
+  // interp = 1 with more than one level: multilinear neighbours, T slots
+  const bool ml = c.interp == 1 && p->L > 1;
+  if (ml) {
+    build_interp(p);
+    int off = 0;
+    for (int l = 0; l + 1 < p->L; ++l) {
+      p->lev[l].toff = off;
+      off += (int)p->lev[l].cells.size();
+    }
+    p->nT = off;
+  }
   int rc = MCH_OK;
+  size_t max_count = 0;
   for (int l = 0; l < p->L && rc == MCH_OK; ++l) {
     Level& lv = p->lev[l];
     lv.n = l + 1;
@@ -379,15 +436,19 @@ extern "C" int mch_build_levels(const mch_config* cfg, mch_plan** out) {
       break;
     }
     if (lv.count == 0) continue;
+    if (l > 0) max_count = std::max(max_count, (size_t)lv.count);
     std::vector<int32_t> ps(lv.count, -1);
     for (int k = 0; k < lv.count; ++k) {
       int q = lv.cells[k];
-      ps[k] = (p->parent[q] >= 0) ? p->slot[p->parent[q]] : -1;
+      // interp = 1: I of a level >= 2 cell is its own row of d_I
+      ps[k] = ml ? k : (p->parent[q] >= 0) ? p->slot[p->parent[q]] : -1;
     }
     if ((rc = upload(p, &lv.d_cells, lv.cells))) break;
     if ((rc = upload(p, &lv.d_pslot, ps))) break;
     size_t vec = (l == 0) ? (size_t)p->nn : (size_t)ipow(lv.NC + 1, d);
-    if ((rc = dev_alloc(p, &lv.d_out, (size_t)lv.count * p->M * vec))) break;
+    // interp = 1: level 1's output holds the fine Phi of every T point
+    const size_t rows = (l == 0 && ml) ? (size_t)p->nT : (size_t)lv.count;
+    if ((rc = dev_alloc(p, &lv.d_out, rows * p->M * vec))) break;
     if ((rc = dev_alloc(p, &lv.d_w, (size_t)lv.count * p->M * vec))) break;
     const size_t nodes = (size_t)ipow(lv.NC, d);
     if (lv.r > 1) {
@@ -402,6 +463,44 @@ extern "C" int mch_build_levels(const mch_config* cfg, mch_plan** out) {
       if ((rc = dev_alloc(p, &lv.d_nodeB, (size_t)lv.count * nodes * ipow(2, d) * c.n_cont))) break;
       if ((rc = dev_alloc(p, &lv.d_fin, (size_t)lv.count * p->M * nodes))) break;
       if ((rc = dev_alloc(p, &lv.d_gin, (size_t)lv.count * p->M * p->m))) break;
+    }
+    if (ml && l > 0) {
+      const int K = 1 << d;
+      std::vector<int32_t> nb((size_t)lv.count * 4, 0);
+      std::vector<double> nw((size_t)lv.count * 4, 0.0);
+      // CSR over the T slots of the levels below: this level's cells that
+      // inherit from each, in increasing cell order
+      const int rows_below = (l + 1 < p->L) ? lv.toff : p->nT;  // T slots of levels < l
+      std::vector<int32_t> ptr((size_t)rows_below + 1, 0), ch;
+      std::vector<double> cw;
+      for (int k = 0; k < lv.count; ++k) {
+        const int q = lv.cells[k];
+        for (int e = 0; e < K; ++e) {
+          const int t = p->nbr[(size_t)q * K + e];
+          if (t < 0) continue;
+          const int ts = p->lev[p->level[t] - 1].toff + p->slot[t];
+          nb[(size_t)k * 4 + e] = ts;
+          nw[(size_t)k * 4 + e] = p->nbw[(size_t)q * K + e];
+          ptr[ts + 1]++;
+        }
+      }
+      for (size_t t = 0; t + 1 < ptr.size(); ++t) ptr[t + 1] += ptr[t];
+      ch.assign(ptr.back(), 0);
+      cw.assign(ptr.back(), 0.0);
+      std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+      for (int k = 0; k < lv.count; ++k)
+        for (int e = 0; e < K; ++e)
+          if (nw[(size_t)k * 4 + e] != 0.0) {
+            const int ts = nb[(size_t)k * 4 + e];
+            ch[fill[ts]] = k;
+            cw[fill[ts]++] = nw[(size_t)k * 4 + e];
+          }
+      if ((rc = upload(p, &lv.d_nbr, nb))) break;
+      if ((rc = upload(p, &lv.d_nbw, nw))) break;
+      if ((rc = upload(p, &lv.d_dptr, ptr))) break;
+      if ((rc = upload(p, &lv.d_dch, ch))) break;
+      if ((rc = upload(p, &lv.d_dw, cw))) break;
+      if ((rc = dev_alloc(p, &lv.d_I, (size_t)lv.count * p->M * p->nn))) break;
     }
     if (d == 3) {
       if (lv.r == 1) {
@@ -431,6 +530,13 @@ extern "C" int mch_build_levels(const mch_config* cfg, mch_plan** out) {
   // (the deepest writes d_seed_par), so the per-level passes run in parallel
   for (int l = 1; l + 1 < p->L && !rc && d == 2 && n1 < (size_t)p->P; ++l)
     rc = dev_alloc(p, &p->d_seed_lvl[l], n1 * M * (size_t)p->nn);
+  if (!rc && ml) {
+    rc = dev_alloc(p, &p->d_seedT, (size_t)p->nT * M * p->nn);
+    if (!rc) rc = dev_alloc(p, &p->d_ibar, max_count * M * p->nn);
+    std::vector<int32_t> id(max_count + 1);
+    for (size_t k = 0; k <= max_count; ++k) id[k] = (int32_t)k;
+    if (!rc) rc = upload(p, &p->d_iptr, id);
+  }
   if (!rc) rc = dev_alloc(p, &p->d_gk, (size_t)ipow(n, d));
   if (!rc) rc = dev_alloc(p, &p->d_gcell, P * (size_t)ipow(nc, d));
   if (!rc) rc = dev_alloc(p, &p->d_iters_adj, P * M);
@@ -462,7 +568,7 @@ extern "C" int mch_build_levels(const mch_config* cfg, mch_plan** out) {
       bpc = d == 3 ? solve_blocks_per_cu_3d(p) : solve_blocks_per_cu_2d(p);
       if (bpc < 0) rc = bpc;
     }
-    if (!rc && bpc > 0) {
+    if (!rc && bpc > 0 && !ml) {  // interp = 1 runs the levels as a chain: one chunk
       const size_t slots = (size_t)cus * bpc, W = n1c * p->M, T = W % slots;
       if (W > slots && T != 0) p->n1a = (int)(n1c - (T + p->M - 1) / p->M);
     }
@@ -501,6 +607,30 @@ extern "C" int mch_build_hierarchy(const mch_config* cfg, int32_t* level, int32_
   build_hierarchy(&tmp);
   std::memcpy(level, tmp.level.data(), sizeof(int32_t) * tmp.P);
   std::memcpy(parent, tmp.parent.data(), sizeof(int32_t) * tmp.P);
+  return MCH_OK;
+}
+
+extern "C" int mch_build_interp(const mch_config* cfg, int32_t* nbr, double* weight) {
+  g_last_error.clear();
+  if (!cfg || !nbr || !weight) return set_error(MCH_EINVAL, "null argument");
+  const mch_config& c = *cfg;
+  if (c.dim != 2 && c.dim != 3) return set_error(MCH_EINVAL, "dim must be 2 or 3");
+  const int nm = c.n_macro[0];
+  for (int a = 0; a < c.dim; ++a)
+    if (c.n_macro[a] != nm) return set_error(MCH_EINVAL, "n_macro must be equal on every axis");
+  if (nm < 1 || c.levels < 1 || c.levels > MAX_LEVELS || c.eta < 1)
+    return set_error(MCH_EINVAL, "bad n_macro, levels or eta");
+  if (nm % ipow(c.eta, c.levels - 1) != 0) return set_error(MCH_EINVAL, "n_macro must be divisible by eta^(L-1)");
+  mch_plan tmp;
+  tmp.cfg = c;
+  tmp.dim = c.dim;
+  tmp.nm = nm;
+  tmp.L = c.levels;
+  tmp.P = ipow(nm, c.dim);
+  build_hierarchy(&tmp);
+  build_interp(&tmp);
+  std::memcpy(nbr, tmp.nbr.data(), sizeof(int32_t) * tmp.nbr.size());
+  std::memcpy(weight, tmp.nbw.data(), sizeof(double) * tmp.nbw.size());
   return MCH_OK;
 }
 

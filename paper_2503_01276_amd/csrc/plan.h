@@ -44,6 +44,19 @@ struct Level {
   double* d_vr = nullptr;
   double* d_vp = nullptr;
   double* d_vap = nullptr;
+  // multilinear interpolation (interp = 1, 2D). Levels >= 2: the inherited
+  // fine vectors I = sum_t c_t Phi_t [count][M][nn] (d_pslot is then the
+  // identity), the T slots and weights of each cell's neighbours [count][4]
+  // (weight 0 = unused), and the CSR over the T slots of the levels below of
+  // this level's cells that inherit from them (cell index and weight), for
+  // passing c_t Ibar back. Levels < L: toff = first T slot of the level.
+  double* d_I = nullptr;
+  int32_t* d_nbr = nullptr;
+  double* d_nbw = nullptr;
+  int toff = 0;
+  int32_t* d_dptr = nullptr;
+  int32_t* d_dch = nullptr;
+  double* d_dw = nullptr;
   KernelShape shape;
 };
 
@@ -70,6 +83,15 @@ struct mch_plan {
   int nn = 0;       // fine nodes per cell, (nc+1)^d
   int device = 0;
   std::vector<int32_t> level, parent, slot;  // host, per macropoint
+  // interp = 1: neighbours (point ids, -1 = unused) and weights, [P][2^d]
+  std::vector<int32_t> nbr;
+  std::vector<double> nbw;
+  // interp = 1: the points of levels 1..L-1 (T_(L-1)) in level-major order
+  // ("T slots"); level 1's output holds the fine Phi of all of them
+  int nT = 0;
+  double* d_seedT = nullptr;   // [nT][M][nn] seeds on the Phi of the T points
+  double* d_ibar = nullptr;    // [max level count][M][nn] Ibar of one level's cells
+  int32_t* d_iptr = nullptr;   // [max level count + 1] identity CSR (0, 1, 2, ...)
   mch::Level lev[mch::MAX_LEVELS];
   // per-point device scratch
   double* d_cw = nullptr;

@@ -104,7 +104,9 @@ CellArgs base_args(mch_plan* pl, const double* kappa, const uint8_t* label, int 
   a.beta = pl->d_beta;
   a.iters = pl->d_iters;
   a.resid = pl->d_resid;
-  a.phi1 = pl->lev[0].d_out;
+  // inherited fine vectors: level 1's solutions (interp = 0, indexed by the
+  // level-1 slot) or the level's own interpolated I (interp = 1, identity slot)
+  a.phi1 = (pl->nT > 0 && l > 0) ? lv.d_I : pl->lev[0].d_out;
   a.out = lv.d_out;
   a.tabK = lv.d_tabK;
   a.tabR = lv.d_tabR;
@@ -198,6 +200,37 @@ CellArgs chunk_args(const CellArgs& a, int start, int count) {
   return c;
 }
 
+// interp = 1: level n inherits from every level below it, so the levels run
+// as a chain on s: level 1, then per level n >= 2 the interpolation of I, the
+// setup, the inherited right-hand sides and the solve, and for n < L the
+// fine Phi = I + P xi into the level's T slots.
+static int launch_forward_2d_chain(mch_plan* pl, const double* kappa, const uint8_t* label, hipStream_t s) {
+  char name[32];
+  int rc = MCH_OK;
+  for (int l = 0; l < pl->L && !rc; ++l) {
+    if (pl->lev[l].count == 0) continue;
+    CellArgs a = base_args(pl, kappa, label, l);
+    if (l > 0) rc = launch_interp_2d(pl, l, s);
+    if (!rc) {
+      std::snprintf(name, sizeof(name), "setup_L%d", l + 1);
+      ProfScope ps(pl, name, s);
+      rc = launch_setup(a, s);
+    }
+    if (!rc && l > 0) {
+      std::snprintf(name, sizeof(name), "inherit_L%d", l + 1);
+      ProfScope ps(pl, name, s);
+      rc = launch_inherit(a, s);
+    }
+    if (!rc) {
+      std::snprintf(name, sizeof(name), "solve_L%d", l + 1);
+      ProfScope ps(pl, name, s);
+      rc = launch_solve(a, pl->lev[l].shape.rpt, s);
+    }
+    if (!rc && l > 0 && l + 1 < pl->L) rc = launch_recon_2d(pl, a, l, s);
+  }
+  return rc;
+}
+
 // Forward DAG: the setups of levels >= 2 need only kappa and labels and run
 // on their side streams from the start (they fill the CUs left idle by the
 // level-1 solve). Level 1 solves in two chunks; each level >= 2 inherits and
@@ -205,6 +238,7 @@ CellArgs chunk_args(const CellArgs& a, int start, int count) {
 // B of level 1), and the rest, on a second stream of the level, as soon as
 // level 1 is done.
 int launch_forward_2d(mch_plan* pl, const double* kappa, const uint8_t* label, hipStream_t s) {
+  if (pl->nT > 0) return launch_forward_2d_chain(pl, kappa, label, s);
   char name[32];
   int rc = ensure_streams(pl);
   if (!rc) rc = fork_levels(pl, s);

@@ -373,9 +373,18 @@ __global__ __launch_bounds__(NC* NC / RPT) void k_solve2d(CellArgs a) {
             const double wgt = (1.0 - fabs((double)du) / rr) * (1.0 - fabs((double)dv) / rr);
             t += wgt * skp[fy * (a.H + 1) + fx];
           }
-        if (rr == 1 && a.seed_par != nullptr) {
+        if (a.seed_par != nullptr) {
+          // seeds from the cells that inherit from this one, on all fine nodes
           const double* sp = a.seed_par + ((size_t)a.slot[p] * M + alpha) * (size_t)(nn1 * nn1);
-          t += sp[(size_t)Y * nn1 + X];
+          if (rr == 1) {
+            t += sp[(size_t)Y * nn1 + X];
+          } else {
+            for (int dv = -(rr - 1); dv <= rr - 1; ++dv)
+              for (int du = -(rr - 1); du <= rr - 1; ++du) {
+                const double wgt = (1.0 - fabs((double)du) / rr) * (1.0 - fabs((double)dv) / rr);
+                t += wgt * sp[(size_t)(Y * rr + dv) * nn1 + X * rr + du];
+              }
+          }
         }
       }
       f[i] = t;
@@ -500,6 +509,46 @@ __global__ __launch_bounds__(NC* NC / RPT) void k_solve2d(CellArgs a) {
       pS[(y0 + i + 1) * PW + c + 1] = pv[i];
     }
     __syncthreads();
+  }
+
+  // ---- final projection onto B_n x = g' -------------------------------------
+  // The directions keep the iterate feasible only up to the accuracy of S^-1
+  // and the rounding of each projection; one correction
+  // x -= D^-1 B_n^T S^-1 (B_n x - g') brings the constraint residual back to
+  // rounding level. Every wave leaves the loop in the same iteration, and the
+  // barrier keeps the band partials until every wave has read them.
+  {
+    double xr[RPT], tc[RPT];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      if constexpr (BIG)
+        xr[i] = xS[(y0 + i) * NC + c];
+      else
+        xr[i] = x[i];
+      tc[i] = 0.0;
+    }
+    __syncthreads();
+    accumulate_B(xr, 0);
+    __syncthreads();
+    if (lane < m) {
+      double gk = 0.0;
+      if (!a.adjoint) {
+        if constexpr (GAL)
+          gk = a.gin[((size_t)ci * M + alpha) * m + lane];
+        else
+          gk = a.g[((size_t)p * M + alpha) * m + lane];
+      }
+      uw[lane] = zcw * zsum(0) - gk;
+    }
+    (void)wave_schur(&vk);
+    scatter_B(tc, 1.0);
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      if constexpr (BIG)
+        xS[(y0 + i) * NC + c] = xr[i] - Dinv[i] * tc[i];
+      else
+        x[i] = xr[i] - Dinv[i] * tc[i];
+    }
   }
 
   // ---- outputs ---------------------------------------------------------------

@@ -19,7 +19,7 @@ MCH_OK, MCH_EINVAL, MCH_ESINGULAR, MCH_ENOCONV, MCH_EHIP, MCH_ESTALE, MCH_ENOTIM
 CODE_NAMES = {MCH_EINVAL: "MCH_EINVAL", MCH_ESINGULAR: "MCH_ESINGULAR", MCH_ENOCONV: "MCH_ENOCONV",
               MCH_EHIP: "MCH_EHIP", MCH_ESTALE: "MCH_ESTALE", MCH_ENOTIMPL: "MCH_ENOTIMPL"}
 
-EXPORTS = ["mch_build_levels", "mch_build_hierarchy", "mch_plan_info", "mch_hierarchy", "mch_solve_cells", "mch_effective_coeffs",
+EXPORTS = ["mch_build_levels", "mch_build_hierarchy", "mch_build_interp", "mch_plan_info", "mch_hierarchy", "mch_solve_cells", "mch_effective_coeffs",
            "mch_effective_coeffs_backward", "mch_local_solutions", "mch_diagnostics", "mch_adjoint_diagnostics", "mch_profile",
            "mch_profile_read", "mch_destroy", "mch_last_error"]
 
@@ -62,6 +62,7 @@ def _load():
     lib.mch_build_levels.argtypes = [ctypes.POINTER(CConfig), ctypes.POINTER(vp)]
     lib.mch_plan_info.argtypes = [vp, i64p]
     lib.mch_build_hierarchy.argtypes = [ctypes.POINTER(CConfig), i32p, i32p]
+    lib.mch_build_interp.argtypes = [ctypes.POINTER(CConfig), i32p, dp]
     lib.mch_hierarchy.argtypes = [vp, i32p, i32p]
     lib.mch_solve_cells.argtypes = [vp, vp, vp, vp]
     lib.mch_effective_coeffs.argtypes = [vp, vp, vp, vp]
@@ -110,6 +111,17 @@ def build_hierarchy(cfg):
     check(LIB.mch_build_hierarchy(ctypes.byref(c), lev.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                   par.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
     return lev, par
+
+
+def build_interp(cfg):
+    """Host-only multilinear neighbours and weights, each [P][2^dim]; needs no device."""
+    c = to_c_config(cfg)
+    shape = (cfg.n_macro ** cfg.dim, 2 ** cfg.dim)
+    nbr = np.zeros(shape, np.int32)
+    w = np.zeros(shape, np.float64)
+    check(LIB.mch_build_interp(ctypes.byref(c), nbr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                               w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return nbr, w
 
 
 def _ptr(t) -> ctypes.c_void_p:

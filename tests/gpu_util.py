@@ -77,8 +77,11 @@ def check_forward(name, cfg, k, l, phi_cells, a_points=None, workers=None):
     say(f"[gpu] {name}: max A rel err {ea.max():.3e}, max Phi rel err {ep:.3e}")
     for p in phi_cells[:8]:
         cs = ocells.assemble_cell(cfg, k, l, int(p), int(ref.level[p]))
-        cres = np.abs(cs.Bf @ Phi[p][cs.free] - cs.g).max()
-        assert cres < 1e-12, (p, cres)
+        r = np.abs(cs.Bf @ Phi[p][cs.free] - cs.g)
+        a = int(np.argmax(r.max(axis=0)))
+        say(f"[gpu] {name}: cell {p} level {ref.level[p]} constraint residual {r.max():.2e} (rhs {a}, "
+            f"max|g| {np.abs(cs.g[:, a]).max():.2e}, max|Phi| {np.abs(Phi[p][:, a]).max():.2e})")
+        assert r.max() < 1e-12, (p, r.max())
     assert ep <= PHI_TOL, ep
     assert ea.max() <= A_TOL, ea.max()
     sym = np.abs(A - A.transpose(0, 2, 1)).max() / np.abs(A).max()

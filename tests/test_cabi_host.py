@@ -36,6 +36,21 @@ def test_host_hierarchy_equals_oracle(name):
     assert np.array_equal(lev, olev) and np.array_equal(par, opar)
 
 
+@pytest.mark.parametrize("name,levels,eta", [("c2", 3, 2), ("c5", 4, 2), ("t3", 3, 2), ("t2", 2, 2),
+                                             ("t3d", 2, 2), ("c1", 3, 2), ("t3", 2, 4)])
+def test_host_multilinear_neighbours_equal_oracle(name, levels, eta):
+    # interp = 1 lists, bit for bit (same neighbours, order and binary64 weights)
+    cfg = W.PRESETS[name].replace(levels=levels, eta=eta, interp=1)
+    nbr, w = mch.build_interp(cfg)
+    ref = oracle.hierarchy.interp_weights(cfg.n_macro, cfg.dim, cfg.levels, cfg.eta, 1)
+    K = 2 ** cfg.dim
+    for p in range(cfg.n_points):
+        k = len(ref[p])
+        assert nbr[p, :k].tolist() == [t for t, _ in ref[p]]
+        assert w[p, :k].tolist() == [c for _, c in ref[p]]
+        assert np.all(nbr[p, k:K] == -1) and np.all(w[p, k:K] == 0.0)
+
+
 def test_host_hierarchy_paper_example_counts():
     cfg = W.Config(dim=2, n_fine=64, n_macro=8, n_cell=16, n_sub=2, n_cont=2, levels=3)
     lev, par = mch.build_hierarchy(cfg)
@@ -56,7 +71,8 @@ def test_invalid_configurations():
     _expect(good.replace(n_cell=18), mch.MCH_EINVAL)          # not divisible by n_sub*eta^(L-1)
     _expect(good.replace(n_cont=4), mch.MCH_EINVAL)
     _expect(good.replace(levels=0), mch.MCH_EINVAL)
-    _expect(good.replace(interp=1), mch.MCH_ENOTIMPL)
+    _expect(good.replace(interp=2), mch.MCH_EINVAL)
+    _expect(W.PRESETS["t3d"].replace(interp=1), mch.MCH_ENOTIMPL)  # multilinear: 2D only
     _expect(good.replace(bc=1), mch.MCH_ENOTIMPL)
     _expect(good.replace(rtol=0.0), mch.MCH_EINVAL)
     # over-constrained coarsest level: 2 x 2 sub-blocks x 2 continua = 8 rows, 1 free node

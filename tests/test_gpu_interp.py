@@ -1,0 +1,126 @@
+"""Multilinear interpolation (interp = 1) on the HIP path, through the C ABI (needs an MI355X).
+
+A level-n point inherits I = sum_t c_t Phi_t over the points of T_(n-1) that
+bracket it (Sec. 3.3, Eq. phiXiI_all), so the levels form a chain: level n
+reads the fine solutions of every level below it, and the adjoint passes
+c_t Ibar back down. Same bars as the paper-mode parity tests: Phi 1e-8,
+A_eff 1e-9, gradient 1e-8 relative; finite differences 1e-4.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2503_01276_amd import workloads as W
+
+from gpu_util import check_forward, gpu_forward, grad_case, say
+
+pytestmark = pytest.mark.gpu
+
+
+def test_t3_multilinear_full():
+    cfg = W.PRESETS["t3"].replace(interp=1)
+    k, l = W.medium("t3")
+    check_forward("t3 ml", cfg, k, l, phi_cells=list(range(cfg.n_points)), workers=8)
+
+
+def test_t2_multilinear_full():
+    # L = 2: every neighbour is a level-1 point, 2 or 4 of them per point
+    cfg = W.PRESETS["t2"].replace(interp=1)
+    k, l = W.medium("t2")
+    check_forward("t2 ml", cfg, k, l, phi_cells=list(range(cfg.n_points)), workers=8)
+
+
+def test_t3_multilinear_adjoint():
+    grad_case("adj-t3 ml", W.PRESETS["t3"].replace(interp=1), 8, workers=8)
+
+
+def test_c2_multilinear_all_tensors_sampled_phi():
+    cfg = W.PRESETS["c2"].replace(interp=1)
+    k, l = W.medium("c2")
+    lev = oracle.hierarchy.levels(cfg.n_macro, 2, cfg.levels, cfg.eta)
+    sample = sorted(set(int(p) for p in np.flatnonzero(lev == 3)[:6]) | set(range(0, cfg.n_points, 97)))
+    check_forward("c2 ml", cfg, k, l, phi_cells=sample, workers=8)
+
+
+def _loss_and_grad(plan, kd, ld, T, want_grad):
+    import torch
+
+    A = torch.empty(plan.P * plan.M * plan.M, dtype=torch.float64, device=kd.device)
+    plan.solve_cells(kd, ld)
+    plan.effective_coeffs(kd, A)
+    loss = float(((A - T) ** 2).sum())
+    g = None
+    if want_grad:
+        g = torch.empty_like(kd)
+        plan.effective_coeffs_backward(kd, 2.0 * (A - T), g)
+        torch.cuda.synchronize()
+        g = g.cpu().numpy()
+    return loss, g
+
+
+def test_c2_multilinear_finite_differences():
+    import torch
+
+    from paper_2503_01276_amd import mch
+
+    cfg = W.PRESETS["c2"].replace(interp=1)
+    k, l = W.medium("c2")
+    kt, _ = W.medium("c2", channel_factor=W.target_factor(4))
+    dev = torch.device("cuda:0")
+    plan = mch.Plan(cfg)
+    ld = torch.from_numpy(l.reshape(-1).copy()).to(dev)
+    T = torch.empty(plan.P * plan.M * plan.M, dtype=torch.float64, device=dev)
+    plan.solve_cells(torch.from_numpy(kt.reshape(-1).copy()).to(dev), ld)
+    plan.effective_coeffs(torch.from_numpy(kt.reshape(-1).copy()).to(dev), T)
+    base = torch.from_numpy(k.reshape(-1).copy()).to(dev)
+    _, g = _loss_and_grad(plan, base, ld, T, True)
+    d = 1e-3
+    worst = 0.0
+    for e in W.fd_elements(l, seed=44, n_each=3):
+        vals = []
+        for sgn in (1.0, -1.0):
+            kd = base.clone()
+            kd[int(e)] *= np.exp(sgn * d)
+            vals.append(_loss_and_grad(plan, kd, ld, T, False)[0])
+        fd = (vals[0] - vals[1]) / (2 * d)
+        worst = max(worst, abs(fd - g[e]) / max(abs(fd), 1e-300))
+        assert abs(fd - g[e]) <= 1e-4 * abs(fd) + 1e-8 * np.abs(g).max(), (int(e), fd, g[e])
+    say(f"[gpu] c2 ml: worst FD relative difference {worst:.2e}")
+
+
+def test_multilinear_eager_equals_graph_replays():
+    import torch
+
+    from paper_2503_01276_amd import mch
+
+    cfg = W.PRESETS["t3"].replace(interp=1)
+    k, l = W.medium("t3")
+    dev = torch.device("cuda:0")
+    plan = mch.Plan(cfg)
+    kd = torch.from_numpy(k.reshape(-1).copy()).to(dev)
+    ld = torch.from_numpy(l.reshape(-1).copy()).to(dev)
+    n = plan.P * plan.M * plan.M
+    A0 = torch.empty(n, dtype=torch.float64, device=dev)
+    g0 = torch.empty_like(kd)
+    plan.solve_cells(kd, ld)
+    plan.effective_coeffs(kd, A0)
+    gA = (A0 * 1e-3).contiguous()
+    plan.effective_coeffs_backward(kd, gA, g0)
+    torch.cuda.synchronize()
+    st = torch.cuda.Stream()
+    A = torch.empty_like(A0)
+    g = torch.empty_like(g0)
+    with torch.cuda.stream(st):
+        for rep in range(3):
+            plan.solve_cells(kd, ld)
+            plan.effective_coeffs(kd, A)
+            plan.effective_coeffs_backward(kd, gA, g)
+            st.synchronize()
+            assert torch.equal(A, A0), rep
+            assert torch.equal(g, g0), rep
+            A.zero_()
+            g.zero_()
+            _ = (kd * 2.0).sum().item()
+    _, A2, _, _, _, _ = gpu_forward(cfg, k, l)
+    assert np.array_equal(A2, A0.cpu().numpy().reshape(A2.shape))
+    say("[gpu] t3 ml: eager, 3 graph replays and a fresh plan agree bitwise")
