@@ -50,15 +50,16 @@ KERNEL_SOURCES = {
 # rocprofv3 --pmc runs, each scaled by the ratio of a plain copy's known size
 # to what the same counter reads for it. An entry holds only while the kernel
 # sources hash to the recorded value; otherwise traffic is reported as null.
-_SHA_2D = "802811401fb691adb8710b7ded748dcecd9bf9db50e590b98515addb230b638f"
+_SHA_2D = "e251efa1f401997393b905a11893cda1153bbcd84679ed5ae82d492dfd2dd2b7"
 _SHA_3D = "f8029b1a5d381b3384fd7329a271e0d57b365c7703b45c5611281b19a740a977"
 _COPY_SCALE = {"fetch": 1048576.0 / 524304.8, "write": 1048576.0 / 1048576.0}  # 1 GiB copy
+_COPY_SCALE_2D = {"fetch": 1048576.0 / 524305.1, "write": 1048576.0 / 1048576.0}  # the same, with the 2D counters
 TRAFFIC = {
     # level-1 forward launches (two chunks per step) and the single adjoint launch
-    ("c2", "solve_L1"): {"sha256": _SHA_2D, "fetch_kib": 7571.8, "write_kib": 14367.0,
-                         "fetch_scale": _COPY_SCALE["fetch"], "write_scale": _COPY_SCALE["write"]},
-    ("c2", "adjsolve_L1"): {"sha256": _SHA_2D, "fetch_kib": 19463.1, "write_kib": 26375.0,
-                            "fetch_scale": _COPY_SCALE["fetch"], "write_scale": _COPY_SCALE["write"]},
+    ("c2", "solve_L1"): {"sha256": _SHA_2D, "fetch_kib": 8682.6, "write_kib": 16287.0,
+                         "fetch_scale": _COPY_SCALE_2D["fetch"], "write_scale": _COPY_SCALE_2D["write"]},
+    ("c2", "adjsolve_L1"): {"sha256": _SHA_2D, "fetch_kib": 20956.1, "write_kib": 29449.1,
+                            "fetch_scale": _COPY_SCALE_2D["fetch"], "write_scale": _COPY_SCALE_2D["write"]},
     # 3D fine level: forward and adjoint launches share kernel and grid; mean of both
     ("c3", "solve_L1"): {"sha256": _SHA_3D, "fetch_kib": 85376037.0, "write_kib": 99484283.7,
                          "fetch_scale": _COPY_SCALE["fetch"], "write_scale": _COPY_SCALE["write"]},
@@ -99,6 +100,8 @@ def copy_probe(mib: int, reps: int = 3):
 DESCR = {
     "c2": "hierarchical L=3 eta=2, 2D 512^2 fine grid, 32x32 macropoints, 64^2-element cells "
           "(levels 64^2/32^2/16^2), N=2, contrast 1e4",
+    "c2ml": "hierarchical L=3 eta=2 with multilinear inheritance from T_(n-1), 2D 512^2 fine grid, "
+            "32x32 macropoints, 64^2-element cells (levels 64^2/32^2/16^2), N=2, contrast 1e4",
     "c2flat": "flat L=1, 2D 512^2 fine grid, 32x32 macropoints, 64^2-element cells, N=2, contrast 1e4",
     "c1": "flat L=1, 2D 128^2 fine grid, 8x8 macropoints, 32^2-element cells, N=2, contrast 1e4",
     "c5": "hierarchical L=4 eta=2, 2D 2048^2 fine grid, 256x256 macropoints, 64^2-element cells "
@@ -342,7 +345,7 @@ def main():
         "wall_s": wall,
         "ms_per_step_graph_replay": ms_graph,
     }
-    flat = args.flat or {"c2": "c2flat", "c3": "c3flat"}.get(args.workload)
+    flat = args.flat or {"c2": "c2flat", "c2ml": "c2flat", "c3": "c3flat"}.get(args.workload)
     if flat == "none":
         flat = None
     if flat:

@@ -312,11 +312,12 @@ static int set_lds(F fn, size_t lds) {
 // the last pass, the level-1 adjoint and gradient, then the gather after the
 // full join. (A parent-seed pass is latency-bound per workgroup, so it is not
 // split into chunks of level-1 cells.)
-// interp = 1: levels from L down to 1 as a chain on s. Per level: the
-// explicit seeds, the adjoint solve (its right-hand side includes the seeds
-// the level's cells received from the levels above, for n < L), then for
-// n >= 2 Ibar of each cell and c_t Ibar into its neighbours' seeds, and the
-// gradient window; the gather at the end.
+// interp = 1: levels from L down to 1 as a chain on s. Per level the
+// adjoint solve (its right-hand side includes the seeds the level's cells
+// received from the levels above, for n < L), then for n >= 2 Ibar of each
+// cell and c_t Ibar into its neighbours' seeds. The explicit seeds of levels
+// >= 2 run on their level streams from the start, and each level's gradient
+// window there once its adjoint solve is done; the gather after the join.
 static int launch_backward_2d_chain(mch_plan* pl, const double* kappa, const double* gA, double* glogk,
                                     hipStream_t s) {
   const int M = pl->M, nc = pl->cfg.n_cell, nn1 = nc + 1;
@@ -331,7 +332,9 @@ static int launch_backward_2d_chain(mch_plan* pl, const double* kappa, const dou
   if (nc > 64) return set_error(MCH_ENOTIMPL, "2D cells wider than 64 elements");
   const size_t lds_ibar = ((size_t)nn1 * nn1 + (size_t)nc * nc + pl->m) * sizeof(double) + (size_t)nc * nc;
   int rc = set_lds(k_ibar2d, lds_ibar);
+  if (!rc) rc = ensure_streams(pl);
   if (!rc) rc = launch_zero(pl->d_seedT, (size_t)pl->nT * M * pl->nn, s);
+  if (!rc) rc = fork_levels(pl, s);
   const CellArgs a1 = base_args(pl, kappa, pl->fwd_label, 0);
   LevelTab lt{};
   for (int l = 0; l < pl->L; ++l) {
@@ -339,18 +342,26 @@ static int launch_backward_2d_chain(mch_plan* pl, const double* kappa, const dou
     lt.NC[l] = pl->lev[l].NC;
     lt.w[l] = pl->lev[l].d_w;
   }
-  for (int l = pl->L - 1; l >= 0 && !rc; --l) {
-    const Level& lv = pl->lev[l];
-    if (lv.count == 0) continue;
+  for (int l = 0; l < pl->L && !rc; ++l) {
+    if (pl->lev[l].count == 0) continue;
+    hipStream_t t = level_stream(pl, l, s);
     CellArgs a = base_args(pl, kappa, pl->fwd_label, l);
     const size_t lds = ((size_t)M * (a.H + 1) * (a.H + 1) + (size_t)M * M) * sizeof(double);
     if ((rc = set_lds(seed, lds))) break;
     std::snprintf(name, sizeof(name), "seed_L%d", l + 1);
     {
-      ProfScope ps(pl, name, s);
-      hipLaunchKernelGGL(seed, dim3(a.count), dim3(BT), lds, s, a, gA, pl->d_seed_kp, pl->d_gk);
+      ProfScope ps(pl, name, t);
+      hipLaunchKernelGGL(seed, dim3(a.count), dim3(BT), lds, t, a, gA, pl->d_seed_kp, pl->d_gk);
     }
     if ((rc = hip_check(hipGetLastError(), "launch k_seed2d"))) break;
+    if (l > 0 && !pl->serial) rc = hip_check(hipEventRecord(pl->ev_setup[l], t), "hipEventRecord");
+  }
+  for (int l = pl->L - 1; l >= 0 && !rc; --l) {
+    const Level& lv = pl->lev[l];
+    if (lv.count == 0) continue;
+    CellArgs a = base_args(pl, kappa, pl->fwd_label, l);
+    if (l > 0 && !pl->serial && (rc = hip_check(hipStreamWaitEvent(s, pl->ev_setup[l], 0), "hipStreamWaitEvent")))
+      break;
     CellArgs b = a;
     b.adjoint = 1;
     b.out = lv.d_w;
@@ -374,13 +385,20 @@ static int launch_backward_2d_chain(mch_plan* pl, const double* kappa, const dou
       }
       if (!rc) rc = launch_distribute_2d(pl, l, s);
     }
-    if (!rc && a.count) {
+    // the gradient window needs only this level's adjoint solution
+    hipStream_t t = level_stream(pl, l, s);
+    if (!rc && t != s) {
+      rc = hip_check(hipEventRecord(pl->ev_adj[l], s), "hipEventRecord");
+      if (!rc) rc = hip_check(hipStreamWaitEvent(t, pl->ev_adj[l], 0), "hipStreamWaitEvent");
+    }
+    if (!rc) {
       std::snprintf(name, sizeof(name), "grad_L%d", l + 1);
-      ProfScope ps(pl, name, s);
-      hipLaunchKernelGGL(k_grad2d, dim3(a.count), dim3(BT), 0, s, a, lv.d_w, pl->d_gcell);
+      ProfScope ps(pl, name, t);
+      hipLaunchKernelGGL(k_grad2d, dim3(a.count), dim3(BT), 0, t, a, lv.d_w, pl->d_gcell);
       rc = hip_check(hipGetLastError(), "launch k_grad2d");
     }
   }
+  if (!rc) rc = join_levels(pl, s);
   if (rc) return rc;
   const size_t total = (size_t)pl->n * pl->n;
   const unsigned blocks = (unsigned)((total + 255) / 256 < 65536 ? (total + 255) / 256 : 65536);

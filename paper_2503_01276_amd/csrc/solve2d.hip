@@ -202,24 +202,37 @@ CellArgs chunk_args(const CellArgs& a, int start, int count) {
 
 // interp = 1: level n inherits from every level below it, so the levels run
 // as a chain on s: level 1, then per level n >= 2 the interpolation of I, the
-// setup, the inherited right-hand sides and the solve, and for n < L the
-// fine Phi = I + P xi into the level's T slots.
+// inherited right-hand sides and the solve, and for n < L the fine
+// Phi = I + P xi into the level's T slots. The setups need only kappa and
+// labels; they run on the level streams from the start, beside level 1.
 static int launch_forward_2d_chain(mch_plan* pl, const double* kappa, const uint8_t* label, hipStream_t s) {
   char name[32];
-  int rc = MCH_OK;
+  int rc = ensure_streams(pl);
+  if (!rc) rc = fork_levels(pl, s);
+  for (int l = 1; l < pl->L && !rc; ++l) {
+    if (pl->lev[l].count == 0) continue;
+    hipStream_t t = level_stream(pl, l, s);
+    std::snprintf(name, sizeof(name), "setup_L%d", l + 1);
+    {
+      ProfScope ps(pl, name, t);
+      rc = launch_setup(base_args(pl, kappa, label, l), t);
+    }
+    if (!rc && !pl->serial) rc = hip_check(hipEventRecord(pl->ev_setup[l], t), "hipEventRecord");
+  }
   for (int l = 0; l < pl->L && !rc; ++l) {
     if (pl->lev[l].count == 0) continue;
     CellArgs a = base_args(pl, kappa, label, l);
-    if (l > 0) rc = launch_interp_2d(pl, l, s);
-    if (!rc) {
-      std::snprintf(name, sizeof(name), "setup_L%d", l + 1);
-      ProfScope ps(pl, name, s);
+    if (l == 0) {
+      ProfScope ps(pl, "setup_L1", s);
       rc = launch_setup(a, s);
-    }
-    if (!rc && l > 0) {
-      std::snprintf(name, sizeof(name), "inherit_L%d", l + 1);
-      ProfScope ps(pl, name, s);
-      rc = launch_inherit(a, s);
+    } else {
+      rc = launch_interp_2d(pl, l, s);
+      if (!rc && !pl->serial) rc = hip_check(hipStreamWaitEvent(s, pl->ev_setup[l], 0), "hipStreamWaitEvent");
+      if (!rc) {
+        std::snprintf(name, sizeof(name), "inherit_L%d", l + 1);
+        ProfScope ps(pl, name, s);
+        rc = launch_inherit(a, s);
+      }
     }
     if (!rc) {
       std::snprintf(name, sizeof(name), "solve_L%d", l + 1);
@@ -228,6 +241,7 @@ static int launch_forward_2d_chain(mch_plan* pl, const double* kappa, const uint
     }
     if (!rc && l > 0 && l + 1 < pl->L) rc = launch_recon_2d(pl, a, l, s);
   }
+  if (!rc) rc = join_levels(pl, s);
   return rc;
 }
 

@@ -75,6 +75,8 @@ PRESETS = {
     # hierarchical L=3, eta=2, 512^2 fine grid, 32x32 macropoints, 64^2 cells
     "c2": Config(dim=2, n_fine=512, n_macro=32, n_cell=64, n_sub=4, n_cont=2, levels=3),
     "c2flat": Config(dim=2, n_fine=512, n_macro=32, n_cell=64, n_sub=4, n_cont=2, levels=1),
+    # the same with multilinear inheritance from T_(n-1)
+    "c2ml": Config(dim=2, n_fine=512, n_macro=32, n_cell=64, n_sub=4, n_cont=2, levels=3, interp=1),
     # 3D hierarchical L=2, 128^3, 8^3 macropoints, 32^3 cells
     "c3": Config(dim=3, n_fine=128, n_macro=8, n_cell=32, n_sub=2, n_cont=2, levels=2),
     "c3flat": Config(dim=3, n_fine=128, n_macro=8, n_cell=32, n_sub=2, n_cont=2, levels=1),
@@ -85,7 +87,7 @@ PRESETS = {
     "t3": Config(dim=2, n_fine=128, n_macro=16, n_cell=32, n_sub=2, n_cont=2, levels=3),
     "t3d": Config(dim=3, n_fine=32, n_macro=4, n_cell=16, n_sub=2, n_cont=2, levels=2),
 }
-PRESET_SEEDS = {"c1": 1, "c2": 2, "c2flat": 2, "c3": 3, "c3flat": 3, "c5": 5, "t2": 7, "t3": 8, "t3d": 9}
+PRESET_SEEDS = {"c1": 1, "c2": 2, "c2flat": 2, "c2ml": 2, "c3": 3, "c3flat": 3, "c5": 5, "t2": 7, "t3": 8, "t3d": 9}
 
 
 def _modulation(n: int, dim: int) -> np.ndarray:
