@@ -34,6 +34,23 @@ def test_t3_multilinear_adjoint():
     grad_case("adj-t3 ml", W.PRESETS["t3"].replace(interp=1), 8, workers=8)
 
 
+def _t4_three_continua():
+    # L = 4 with three continua (contrast 1e8): levels 2 and 3 both receive
+    # seeds from above and pass them down; the kernel shapes of the 2048^2
+    # workload (64^2 cells, s = 2, N = 3)
+    return W.Config(dim=2, n_fine=256, n_macro=16, n_cell=64, n_sub=2, n_cont=3, levels=4, interp=1)
+
+
+def test_L4_three_continua_multilinear_full():
+    cfg = _t4_three_continua()
+    k, l = W.medium_for(cfg, 12)
+    check_forward("t4 ml N=3", cfg, k, l, phi_cells=list(range(0, cfg.n_points, 5)), workers=8)
+
+
+def test_L4_three_continua_multilinear_adjoint():
+    grad_case("adj-t4 ml N=3", _t4_three_continua(), 12, workers=8)
+
+
 def test_c2_multilinear_all_tensors_sampled_phi():
     cfg = W.PRESETS["c2"].replace(interp=1)
     k, l = W.medium("c2")
