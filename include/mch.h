@@ -83,7 +83,7 @@ typedef struct {
   int32_t levels;       /* L >= 1; L = 1 is the flat method */
   int32_t eta;          /* coarsening factor >= 1; n_macro divisible by eta^(L-1) */
   int32_t interp;       /* 0: inherit the level-1 solution of the group (the paper's experiments);
-                           1: multilinear interpolation from T_(n-1) (2D only) */
+                           1: multilinear interpolation from T_(n-1) */
   int32_t bc;           /* 0: homogeneous Dirichlet on the cell boundary (only mode implemented) */
   double rtol;          /* relative tolerance on the projected preconditioned residual norm */
   int32_t max_iter;     /* Krylov iteration cap per solve */

@@ -383,7 +383,7 @@ static int launch_backward_2d_chain(mch_plan* pl, const double* kappa, const dou
                            lv.d_cells, pl->d_mu, pl->d_ibar, l, 0);
         rc = hip_check(hipGetLastError(), "launch k_ibar2d");
       }
-      if (!rc) rc = launch_distribute_2d(pl, l, s);
+      if (!rc) rc = launch_distribute(pl, l, s);
     }
     // the gradient window needs only this level's adjoint solution
     hipStream_t t = level_stream(pl, l, s);

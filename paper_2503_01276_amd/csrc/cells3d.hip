@@ -769,8 +769,21 @@ __global__ __launch_bounds__((nt3<NC, GAL>())) void k_solve3d(CellArgs a) {
           const double wgt = (1.0 - fabs((double)du) / r) * (1.0 - fabs((double)dv) / r) * (1.0 - fabs((double)dw) / r);
           t += wgt * skp[nidx3(fx, fy, fz, Hp)];
         }
-    if (r == 1 && a.seed_par != nullptr)
-      t += a.seed_par[((size_t)a.slot[p] * M + alpha) * (size_t)nn1 * nn1 * nn1 + nidx3(X, Y, Z, nn1)];
+    if (a.seed_par != nullptr) {
+      // seeds from the cells that inherit from this one, on all fine nodes
+      const double* sp = a.seed_par + ((size_t)a.slot[p] * M + alpha) * (size_t)nn1 * nn1 * nn1;
+      if (r == 1) {
+        t += sp[nidx3(X, Y, Z, nn1)];
+      } else {
+        for (int dw = -(r - 1); dw <= r - 1; ++dw)
+          for (int dv = -(r - 1); dv <= r - 1; ++dv)
+            for (int du = -(r - 1); du <= r - 1; ++du) {
+              const double wgt =
+                  (1.0 - fabs((double)du) / r) * (1.0 - fabs((double)dv) / r) * (1.0 - fabs((double)dw) / r);
+              t += wgt * sp[nidx3(X * r + du, Y * r + dv, Z * r + dw, nn1)];
+            }
+      }
+    }
     return t;
   };
 
@@ -1369,6 +1382,17 @@ __global__ __launch_bounds__(T3) void k_ibar3d(CellArgs a, LevelTab3 lt, const i
   }
 }
 
+// Multilinear mode (interp = 1): Phi = I + P xi of each cell of a level on
+// every fine node of its cell, into T slot toff + ci of the store.
+__global__ __launch_bounds__(T3) void k_recon3d(CellArgs a, int toff, double* phiT) {
+  const int ci = blockIdx.x / a.M, al = blockIdx.x % a.M;
+  const int nn1 = a.nc + 1;
+  const size_t nn = (size_t)nn1 * nn1 * nn1;
+  double* dst = phiT + ((size_t)(toff + ci) * a.M + al) * nn;
+  for (size_t nd = threadIdx.x; nd < nn; nd += T3)
+    dst[nd] = phi_at3(a, ci, al, (int)(nd % nn1), (int)((nd / nn1) % nn1), (int)(nd / ((size_t)nn1 * nn1)));
+}
+
 MCH_DEV int floordiv3(int a, int b) {
   int q = a / b;
   return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
@@ -1539,7 +1563,63 @@ static int launch_phikp3(const CellArgs& a, hipStream_t s) {
 // start; level 1 set-up and solve on s in two chunks; every level >= 2
 // inherits, solves and writes Phi on K_p for the cells of chunk A once chunk
 // A is done, the rest once level 1 is done; Phi on K_p of level 1 on s.
+// interp = 1: the levels run as a chain on s (level n reads the fine Phi of
+// every level below it), as in 2D: the setups of levels >= 2 on their level
+// streams from the start; then per level the interpolation of I, the
+// inherited right-hand sides, the solve, Phi on K_p and, below L, the fine
+// Phi into the level's T slots.
+static int launch_forward_3d_chain(mch_plan* pl, const double* kappa, const uint8_t* label, hipStream_t s) {
+  char name[32];
+  int rc = ensure_streams(pl);
+  if (!rc) rc = fork_levels(pl, s);
+  for (int l = 1; l < pl->L && !rc; ++l) {
+    if (pl->lev[l].count == 0) continue;
+    hipStream_t t = level_stream(pl, l, s);
+    std::snprintf(name, sizeof(name), "setup_L%d", l + 1);
+    {
+      ProfScope ps(pl, name, t);
+      rc = launch_setup3(base_args(pl, kappa, label, l), t);
+    }
+    if (!rc && !pl->serial) rc = hip_check(hipEventRecord(pl->ev_setup[l], t), "hipEventRecord");
+  }
+  for (int l = 0; l < pl->L && !rc; ++l) {
+    const Level& lv = pl->lev[l];
+    if (lv.count == 0) continue;
+    CellArgs a = base_args(pl, kappa, label, l);
+    if (l == 0) {
+      ProfScope ps(pl, "setup_L1", s);
+      rc = launch_setup3(a, s);
+    } else {
+      rc = launch_interp(pl, l, s);
+      if (!rc && !pl->serial) rc = hip_check(hipStreamWaitEvent(s, pl->ev_setup[l], 0), "hipStreamWaitEvent");
+      if (!rc) {
+        std::snprintf(name, sizeof(name), "inherit_L%d", l + 1);
+        ProfScope ps(pl, name, s);
+        rc = launch_inherit3(a, s);
+      }
+    }
+    if (!rc) {
+      std::snprintf(name, sizeof(name), "solve_L%d", l + 1);
+      ProfScope ps(pl, name, s);
+      rc = launch_solve3(a, s);
+    }
+    if (!rc) {
+      std::snprintf(name, sizeof(name), "phikp_L%d", l + 1);
+      ProfScope ps(pl, name, s);
+      rc = launch_phikp3(a, s);
+    }
+    if (!rc && l > 0 && l + 1 < pl->L) {
+      ProfScope ps(pl, "recon", s);
+      hipLaunchKernelGGL(k_recon3d, dim3((unsigned)(lv.count * pl->M)), dim3(T3), 0, s, a, lv.toff, pl->lev[0].d_out);
+      rc = hip_check(hipGetLastError(), "launch k_recon3d");
+    }
+  }
+  if (!rc) rc = join_levels(pl, s);
+  return rc;
+}
+
 int launch_forward_3d(mch_plan* pl, const double* kappa, const uint8_t* label, hipStream_t s) {
+  if (pl->nT > 0) return launch_forward_3d_chain(pl, kappa, label, s);
   char name[32];
   int rc = ensure_streams(pl);
   if (!rc) rc = fork_levels(pl, s);
@@ -1632,8 +1712,97 @@ int launch_eff_3d(mch_plan* pl, const double* kappa, double* A, hipStream_t s) {
   return rc;
 }
 
+// interp = 1, as in 2D: from level L down on s, each level's adjoint solve
+// (with the seeds its cells received from the levels above), then Ibar per
+// cell (the parent-seed kernel over an identity map) and c_t Ibar into the
+// neighbours' seeds; explicit seeds up front and the gradient windows on the
+// level streams.
+static int launch_backward_3d_chain(mch_plan* pl, const double* kappa, const double* gA, double* glogk,
+                                    hipStream_t s) {
+  const int M = pl->M;
+  char name[32];
+  void (*seed)(CellArgs, const double*, double*, double*) = nullptr;
+  switch (M) {
+    case 4: seed = k_seed3d<4>; break;
+    case 8: seed = k_seed3d<8>; break;
+    case 12: seed = k_seed3d<12>; break;
+    default: return set_error(MCH_ENOTIMPL, "M");
+  }
+  int rc = ensure_streams(pl);
+  if (!rc) rc = launch_zero(pl->d_seedT, (size_t)pl->nT * M * pl->nn, s);
+  if (!rc) rc = fork_levels(pl, s);
+  const CellArgs a1 = base_args(pl, kappa, pl->fwd_label, 0);
+  LevelTab3 lt{};
+  for (int l = 0; l < pl->L; ++l) {
+    lt.r[l] = pl->lev[l].r;
+    lt.NC[l] = pl->lev[l].NC;
+    lt.w[l] = pl->lev[l].d_w;
+  }
+  for (int l = 0; l < pl->L && !rc; ++l) {
+    if (pl->lev[l].count == 0) continue;
+    hipStream_t t = level_stream(pl, l, s);
+    CellArgs a = base_args(pl, kappa, pl->fwd_label, l);
+    std::snprintf(name, sizeof(name), "seed_L%d", l + 1);
+    {
+      ProfScope ps(pl, name, t);
+      hipLaunchKernelGGL(seed, dim3(a.count), dim3(T3), 0, t, a, gA, pl->d_seed_kp, pl->d_gk);
+    }
+    rc = hip_check(hipGetLastError(), "launch k_seed3d");
+    if (!rc && l > 0 && !pl->serial) rc = hip_check(hipEventRecord(pl->ev_setup[l], t), "hipEventRecord");
+  }
+  for (int l = pl->L - 1; l >= 0 && !rc; --l) {
+    const Level& lv = pl->lev[l];
+    if (lv.count == 0) continue;
+    CellArgs a = base_args(pl, kappa, pl->fwd_label, l);
+    if (l > 0 && !pl->serial && (rc = hip_check(hipStreamWaitEvent(s, pl->ev_setup[l], 0), "hipStreamWaitEvent")))
+      break;
+    CellArgs b = a;
+    b.adjoint = 1;
+    b.out = lv.d_w;
+    b.beta = pl->d_mu;
+    b.iters = pl->d_iters_adj;
+    b.resid = pl->d_resid_adj;
+    b.seed_par = (l + 1 < pl->L) ? pl->d_seedT + (size_t)lv.toff * M * pl->nn : nullptr;
+    std::snprintf(name, sizeof(name), "adjsolve_L%d", l + 1);
+    {
+      ProfScope ps(pl, name, s);
+      rc = launch_solve3(b, s);
+    }
+    if (!rc && l > 0) {
+      {
+        ProfScope ps(pl, "ibar", s);
+        hipLaunchKernelGGL(k_ibar3d, dim3(lv.count * M), dim3(T3), 0, s, a1, lt, pl->d_level, pl->d_iptr, lv.d_cells,
+                           pl->d_mu, pl->d_ibar);
+        rc = hip_check(hipGetLastError(), "launch k_ibar3d");
+      }
+      if (!rc) rc = launch_distribute(pl, l, s);
+    }
+    hipStream_t t = level_stream(pl, l, s);
+    if (!rc && t != s) {
+      rc = hip_check(hipEventRecord(pl->ev_adj[l], s), "hipEventRecord");
+      if (!rc) rc = hip_check(hipStreamWaitEvent(t, pl->ev_adj[l], 0), "hipStreamWaitEvent");
+    }
+    if (!rc) {
+      std::snprintf(name, sizeof(name), "grad_L%d", l + 1);
+      ProfScope ps(pl, name, t);
+      hipLaunchKernelGGL(k_grad3d, dim3(a.count), dim3(T3), 0, t, a, lv.d_w, pl->d_gcell);
+      rc = hip_check(hipGetLastError(), "launch k_grad3d");
+    }
+  }
+  if (!rc) rc = join_levels(pl, s);
+  if (rc) return rc;
+  const size_t total = (size_t)pl->n * pl->n * pl->n;
+  const unsigned blocks = (unsigned)((total + 255) / 256 < 65536 ? (total + 255) / 256 : 65536);
+  {
+    ProfScope ps(pl, "gather", s);
+    hipLaunchKernelGGL(k_gather_grad3d, dim3(blocks), dim3(256), 0, s, a1, pl->d_gk, pl->d_gcell, glogk);
+  }
+  return hip_check(hipGetLastError(), "launch k_gather_grad3d");
+}
+
 // Backward DAG, as in 2D.
 int launch_backward_3d(mch_plan* pl, const double* kappa, const double* gA, double* glogk, hipStream_t s) {
+  if (pl->nT > 0) return launch_backward_3d_chain(pl, kappa, gA, glogk, s);
   const int M = pl->M;
   char name[32];
   int rc = ensure_streams(pl);

@@ -39,10 +39,11 @@ int launch_setup(const CellArgs& a, hipStream_t s);
 // Inherited right-hand sides of a level >= 2 (needs the level-1 solutions).
 int launch_inherit(const CellArgs& a, hipStream_t s);
 // Multilinear inheritance (interp = 1): I of level l's cells from the T-slot
-// store; Phi = I + P xi of level l into its T slots; c_t Ibar of level l's
-// cells into the seeds of their neighbours; a fill with zeros.
-int launch_interp_2d(mch_plan* pl, int l, hipStream_t s);
+// store (2D and 3D); Phi = I + P xi of level l into its T slots (2D); c_t Ibar
+// of level l's cells into the seeds of their neighbours (2D and 3D); a fill
+// with zeros.
+int launch_interp(mch_plan* pl, int l, hipStream_t s);
 int launch_recon_2d(mch_plan* pl, const CellArgs& a, int l, hipStream_t s);
-int launch_distribute_2d(mch_plan* pl, int l, hipStream_t s);
+int launch_distribute(mch_plan* pl, int l, hipStream_t s);
 int launch_zero(double* p, size_t n, hipStream_t s);
 }  // namespace mch

@@ -355,7 +355,6 @@ extern "C" int mch_build_levels(const mch_config* cfg, mch_plan** out) {
   if (c.n_cont < 1 || c.n_cont > 3) return set_error(MCH_EINVAL, "n_cont must be 1..3");
   if (c.n_sub < 1) return set_error(MCH_EINVAL, "n_sub must be >= 1");
   if (c.interp != 0 && c.interp != 1) return set_error(MCH_EINVAL, "interp must be 0 or 1");
-  if (c.interp == 1 && d == 3) return set_error(MCH_ENOTIMPL, "multilinear interpolation (interp = 1) is implemented in 2D only");
   if (c.bc != 0) return set_error(MCH_ENOTIMPL, "only bc = 0 (homogeneous Dirichlet) is implemented");
   if (!(c.rtol > 0.0) || c.max_iter < 1) return set_error(MCH_EINVAL, "rtol must be > 0 and max_iter >= 1");
   const int nc = c.n_cell;
@@ -466,8 +465,8 @@ extern "C" int mch_build_levels(const mch_config* cfg, mch_plan** out) {
     }
     if (ml && l > 0) {
       const int K = 1 << d;
-      std::vector<int32_t> nb((size_t)lv.count * 4, 0);
-      std::vector<double> nw((size_t)lv.count * 4, 0.0);
+      std::vector<int32_t> nb((size_t)lv.count * K, 0);
+      std::vector<double> nw((size_t)lv.count * K, 0.0);
       // CSR over the T slots of the levels below: this level's cells that
       // inherit from each, in increasing cell order
       const int rows_below = (l + 1 < p->L) ? lv.toff : p->nT;  // T slots of levels < l
@@ -479,8 +478,8 @@ extern "C" int mch_build_levels(const mch_config* cfg, mch_plan** out) {
           const int t = p->nbr[(size_t)q * K + e];
           if (t < 0) continue;
           const int ts = p->lev[p->level[t] - 1].toff + p->slot[t];
-          nb[(size_t)k * 4 + e] = ts;
-          nw[(size_t)k * 4 + e] = p->nbw[(size_t)q * K + e];
+          nb[(size_t)k * K + e] = ts;
+          nw[(size_t)k * K + e] = p->nbw[(size_t)q * K + e];
           ptr[ts + 1]++;
         }
       }
@@ -490,10 +489,10 @@ extern "C" int mch_build_levels(const mch_config* cfg, mch_plan** out) {
       std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
       for (int k = 0; k < lv.count; ++k)
         for (int e = 0; e < K; ++e)
-          if (nw[(size_t)k * 4 + e] != 0.0) {
-            const int ts = nb[(size_t)k * 4 + e];
+          if (nw[(size_t)k * K + e] != 0.0) {
+            const int ts = nb[(size_t)k * K + e];
             ch[fill[ts]] = k;
-            cw[fill[ts]++] = nw[(size_t)k * 4 + e];
+            cw[fill[ts]++] = nw[(size_t)k * K + e];
           }
       if ((rc = upload(p, &lv.d_nbr, nb))) break;
       if ((rc = upload(p, &lv.d_nbw, nw))) break;

@@ -44,9 +44,9 @@ struct Level {
   double* d_vr = nullptr;
   double* d_vp = nullptr;
   double* d_vap = nullptr;
-  // multilinear interpolation (interp = 1, 2D). Levels >= 2: the inherited
+  // multilinear interpolation (interp = 1). Levels >= 2: the inherited
   // fine vectors I = sum_t c_t Phi_t [count][M][nn] (d_pslot is then the
-  // identity), the T slots and weights of each cell's neighbours [count][4]
+  // identity), the T slots and weights of each cell's neighbours [count][2^d]
   // (weight 0 = unused), and the CSR over the T slots of the levels below of
   // this level's cells that inherit from them (cell index and weight), for
   // passing c_t Ibar back. Levels < L: toff = first T slot of the level.

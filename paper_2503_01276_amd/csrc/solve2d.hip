@@ -226,7 +226,7 @@ static int launch_forward_2d_chain(mch_plan* pl, const double* kappa, const uint
       ProfScope ps(pl, "setup_L1", s);
       rc = launch_setup(a, s);
     } else {
-      rc = launch_interp_2d(pl, l, s);
+      rc = launch_interp(pl, l, s);
       if (!rc && !pl->serial) rc = hip_check(hipStreamWaitEvent(s, pl->ev_setup[l], 0), "hipStreamWaitEvent");
       if (!rc) {
         std::snprintf(name, sizeof(name), "inherit_L%d", l + 1);

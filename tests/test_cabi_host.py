@@ -72,7 +72,6 @@ def test_invalid_configurations():
     _expect(good.replace(n_cont=4), mch.MCH_EINVAL)
     _expect(good.replace(levels=0), mch.MCH_EINVAL)
     _expect(good.replace(interp=2), mch.MCH_EINVAL)
-    _expect(W.PRESETS["t3d"].replace(interp=1), mch.MCH_ENOTIMPL)  # multilinear: 2D only
     _expect(good.replace(bc=1), mch.MCH_ENOTIMPL)
     _expect(good.replace(rtol=0.0), mch.MCH_EINVAL)
     # over-constrained coarsest level: 2 x 2 sub-blocks x 2 continua = 8 rows, 1 free node
