@@ -51,17 +51,16 @@ KERNEL_SOURCES = {
 # to what the same counter reads for it. An entry holds only while the kernel
 # sources hash to the recorded value; otherwise traffic is reported as null.
 _SHA_2D = "e251efa1f401997393b905a11893cda1153bbcd84679ed5ae82d492dfd2dd2b7"
-_SHA_3D = "f8029b1a5d381b3384fd7329a271e0d57b365c7703b45c5611281b19a740a977"
-_COPY_SCALE = {"fetch": 1048576.0 / 524304.8, "write": 1048576.0 / 1048576.0}  # 1 GiB copy
-_COPY_SCALE_2D = {"fetch": 1048576.0 / 524305.1, "write": 1048576.0 / 1048576.0}  # the same, with the 2D counters
+_SHA_3D = "20fee8c7fb8143caea8d5f04397339869a096794af9029b054f8cbd62c45dd57"
+_COPY_SCALE = {"fetch": 1048576.0 / 524305.1, "write": 1048576.0 / 1048576.0}  # 1 GiB copy
 TRAFFIC = {
     # level-1 forward launches (two chunks per step) and the single adjoint launch
     ("c2", "solve_L1"): {"sha256": _SHA_2D, "fetch_kib": 8682.6, "write_kib": 16287.0,
-                         "fetch_scale": _COPY_SCALE_2D["fetch"], "write_scale": _COPY_SCALE_2D["write"]},
+                         "fetch_scale": _COPY_SCALE["fetch"], "write_scale": _COPY_SCALE["write"]},
     ("c2", "adjsolve_L1"): {"sha256": _SHA_2D, "fetch_kib": 20956.1, "write_kib": 29449.1,
-                            "fetch_scale": _COPY_SCALE_2D["fetch"], "write_scale": _COPY_SCALE_2D["write"]},
+                            "fetch_scale": _COPY_SCALE["fetch"], "write_scale": _COPY_SCALE["write"]},
     # 3D fine level: forward and adjoint launches share kernel and grid; mean of both
-    ("c3", "solve_L1"): {"sha256": _SHA_3D, "fetch_kib": 85376037.0, "write_kib": 99484283.7,
+    ("c3", "solve_L1"): {"sha256": _SHA_3D, "fetch_kib": 85402271.5, "write_kib": 99457282.3,
                          "fetch_scale": _COPY_SCALE["fetch"], "write_scale": _COPY_SCALE["write"]},
 }
 
