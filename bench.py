@@ -50,14 +50,14 @@ KERNEL_SOURCES = {
 # rocprofv3 --pmc runs, each scaled by the ratio of a plain copy's known size
 # to what the same counter reads for it. An entry holds only while the kernel
 # sources hash to the recorded value; otherwise traffic is reported as null.
-_SHA_2D = "e251efa1f401997393b905a11893cda1153bbcd84679ed5ae82d492dfd2dd2b7"
+_SHA_2D = "2b4319c02335be6a43dcd6aee6387c40b92ab6fdbce2bd6624c42b2c7f65a43f"
 _SHA_3D = "20fee8c7fb8143caea8d5f04397339869a096794af9029b054f8cbd62c45dd57"
 _COPY_SCALE = {"fetch": 1048576.0 / 524305.1, "write": 1048576.0 / 1048576.0}  # 1 GiB copy
 TRAFFIC = {
     # level-1 forward launches (two chunks per step) and the single adjoint launch
-    ("c2", "solve_L1"): {"sha256": _SHA_2D, "fetch_kib": 8682.6, "write_kib": 16287.0,
+    ("c2", "solve_L1"): {"sha256": _SHA_2D, "fetch_kib": 8680.8, "write_kib": 16287.0,
                          "fetch_scale": _COPY_SCALE["fetch"], "write_scale": _COPY_SCALE["write"]},
-    ("c2", "adjsolve_L1"): {"sha256": _SHA_2D, "fetch_kib": 20956.1, "write_kib": 29449.1,
+    ("c2", "adjsolve_L1"): {"sha256": _SHA_2D, "fetch_kib": 20944.6, "write_kib": 29490.6,
                             "fetch_scale": _COPY_SCALE["fetch"], "write_scale": _COPY_SCALE["write"]},
     # 3D fine level: forward and adjoint launches share kernel and grid; mean of both
     ("c3", "solve_L1"): {"sha256": _SHA_3D, "fetch_kib": 85402271.5, "write_kib": 99457282.3,
