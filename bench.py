@@ -105,6 +105,8 @@ DESCR = {
     "c1": "flat L=1, 2D 128^2 fine grid, 8x8 macropoints, 32^2-element cells, N=2, contrast 1e4",
     "c5": "hierarchical L=4 eta=2, 2D 2048^2 fine grid, 256x256 macropoints, 64^2-element cells "
           "(levels 64^2/32^2/16^2/8^2), N=3 with inclusions, contrast 1e8",
+    "c5ml": "hierarchical L=4 eta=2 with multilinear inheritance from T_(n-1), 2D 2048^2 fine grid, "
+            "256x256 macropoints, 64^2-element cells (levels 64^2/32^2/16^2/8^2), N=3 with inclusions, contrast 1e8",
     "c3": "hierarchical L=2 eta=2, 3D 128^3 fine grid, 8^3 macropoints, 32^3-element cells "
           "(levels 32^3/16^3), N=2, contrast 1e4",
     "c3flat": "flat L=1, 3D 128^3 fine grid, 8^3 macropoints, 32^3-element cells, N=2, contrast 1e4",
@@ -280,7 +282,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU sharding is a design described in DESIGN.md, not a measured path)",
+              "(the path shards by independent groups of macropoints, but only one GPU is driven here)",
               file=sys.stderr)
         sys.exit(2)
     if args.copy_probe:
@@ -330,8 +332,14 @@ def main():
                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
                     "traffic": measured_traffic(args.workload, dom), "flops_per_launch": flops,
                     "launches_per_step": nl}
+    if roof is not None and roof.get("traffic"):
+        # measured HBM bytes per launch over the launch's live average duration
+        roof["traffic_gbs"] = roof["traffic"] / (ktab[dom]["avg_ms"] * 1e-3) / 1e9
     solves = plan.P * plan.M
     fwd_ms = phases["solve_ms"]
+
+    def free_dof(n):  # free nodes of a level-(n+1) cell
+        return (cfg.n_cell // cfg.eta ** n - 1) ** cfg.dim
     detail = {
         **phases,
         "eff_tensor_time_ms": phases["solve_ms"] + phases["eff_ms"],
@@ -343,6 +351,11 @@ def main():
         "kernels": ktab,
         "wall_s": wall,
         "ms_per_step_graph_replay": ms_graph,
+        # degrees of freedom of all solves, hierarchical / flat (Sec. 3.4 models
+        # this as L eta^((1-L) d))
+        "dof_model": {"paper_model": cfg.levels * float(cfg.eta) ** ((1 - cfg.levels) * cfg.dim),
+                      "dof_ratio": sum(int((lev == n + 1).sum()) * free_dof(n) for n in range(cfg.levels)) /
+                                   (plan.P * free_dof(0))},
     }
     flat = args.flat or {"c2": "c2flat", "c2ml": "c2flat", "c3": "c3flat"}.get(args.workload)
     if flat == "none":
@@ -354,6 +367,13 @@ def main():
                           "speedup_step": fms / ms, "speedup_solve": fph["solve_ms"] / fwd_ms,
                           "speedup_eff_tensor_time": (fph["solve_ms"] + fph["eff_ms"]) /
                                                      (phases["solve_ms"] + phases["eff_ms"])}
+        if frun.cfg.levels == 1 and frun.cfg.n_cell == cfg.n_cell:
+            # forward work weighted by the measured iterations, hierarchical / flat
+            fits, _ = frun.plan.diagnostics()
+            work_flat = float(fits.astype(np.float64).sum()) * free_dof(0)
+            work_h = sum(float(iters[lev == n + 1].astype(np.float64).sum()) * free_dof(n) for n in range(cfg.levels))
+            detail["dof_model"]["work_ratio_iterations"] = work_h / work_flat
+            detail["dof_model"]["time_ratio_solve"] = fwd_ms / fph["solve_ms"]
         print(f"[bench] {flat}: {fms:.3f} ms/step", file=sys.stderr, flush=True)
     out = {
         "metric": "cell-solves/sec & eff-tensor+grad time, hier L=3 vs flat, 1 GPU, rel err <=1e-8",

@@ -82,12 +82,13 @@ PRESETS = {
     "c3flat": Config(dim=3, n_fine=128, n_macro=8, n_cell=32, n_sub=2, n_cont=2, levels=1),
     # large uneven batch: 2048^2, 256^2 macropoints, N=3, L=4
     "c5": Config(dim=2, n_fine=2048, n_macro=256, n_cell=64, n_sub=2, n_cont=3, levels=4),
+    "c5ml": Config(dim=2, n_fine=2048, n_macro=256, n_cell=64, n_sub=2, n_cont=3, levels=4, interp=1),
     # small cases for unit tests (several tiles, fast on the CPU)
     "t2": Config(dim=2, n_fine=64, n_macro=8, n_cell=16, n_sub=2, n_cont=2, levels=2),
     "t3": Config(dim=2, n_fine=128, n_macro=16, n_cell=32, n_sub=2, n_cont=2, levels=3),
     "t3d": Config(dim=3, n_fine=32, n_macro=4, n_cell=16, n_sub=2, n_cont=2, levels=2),
 }
-PRESET_SEEDS = {"c1": 1, "c2": 2, "c2flat": 2, "c2ml": 2, "c3": 3, "c3flat": 3, "c5": 5, "t2": 7, "t3": 8, "t3d": 9}
+PRESET_SEEDS = {"c1": 1, "c2": 2, "c2flat": 2, "c2ml": 2, "c3": 3, "c3flat": 3, "c5": 5, "c5ml": 5, "t2": 7, "t3": 8, "t3d": 9}
 
 
 def _modulation(n: int, dim: int) -> np.ndarray:
