@@ -105,13 +105,14 @@ def test_c2_multilinear_finite_differences():
     say(f"[gpu] c2 ml: worst FD relative difference {worst:.2e}")
 
 
-def test_multilinear_eager_equals_graph_replays():
+@pytest.mark.parametrize("preset", ["t3", "t3d"])
+def test_multilinear_eager_equals_graph_replays(preset):
     import torch
 
     from paper_2503_01276_amd import mch
 
-    cfg = W.PRESETS["t3"].replace(interp=1)
-    k, l = W.medium("t3")
+    cfg = W.PRESETS[preset].replace(interp=1)
+    k, l = W.medium(preset)
     dev = torch.device("cuda:0")
     plan = mch.Plan(cfg)
     kd = torch.from_numpy(k.reshape(-1).copy()).to(dev)
@@ -140,7 +141,7 @@ def test_multilinear_eager_equals_graph_replays():
             _ = (kd * 2.0).sum().item()
     _, A2, _, _, _, _ = gpu_forward(cfg, k, l)
     assert np.array_equal(A2, A0.cpu().numpy().reshape(A2.shape))
-    say("[gpu] t3 ml: eager, 3 graph replays and a fresh plan agree bitwise")
+    say(f"[gpu] {preset} ml: eager, 3 graph replays and a fresh plan agree bitwise")
 
 
 def test_t3d_multilinear_full():
