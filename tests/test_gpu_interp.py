@@ -59,6 +59,11 @@ def test_c2_multilinear_all_tensors_sampled_phi():
     check_forward("c2 ml", cfg, k, l, phi_cells=sample, workers=8)
 
 
+def test_c2_multilinear_gradient_full_field():
+    # the whole gradient field at full size against the oracle's backward
+    grad_case("adj-c2 ml", W.PRESETS["c2ml"], W.PRESET_SEEDS["c2ml"], workers=16)
+
+
 def _loss_and_grad(plan, kd, ld, T, want_grad):
     import torch
 
