@@ -211,11 +211,17 @@ class Runner:
         # per-phase events on the launch stream (the library forks and joins its level
         # streams inside each call, so these bracket each call's whole span)
         evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)] if profile else None
+        # step boundaries (the median step time of the replayed graphs is reported too)
+        sevs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)] if not profile else None
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         e0.record()
         for i in range(steps):
+            if sevs:
+                sevs[i].record()
             self.step(evs[i] if evs else None)
+        if sevs:
+            sevs[steps].record()
         e1.record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
@@ -224,7 +230,12 @@ class Runner:
         if evs:
             ph = np.array([[e[j].elapsed_time(e[j + 1]) for j in range(3)] for e in evs])
             phases = {"solve_ms": float(ph[:, 0].mean()), "eff_ms": float(ph[:, 1].mean()),
-                      "grad_ms_incl_loss": float(ph[:, 2].mean())}
+                      "grad_ms_incl_loss": float(ph[:, 2].mean()),
+                      "solve_ms_median": float(np.median(ph[:, 0])), "eff_ms_median": float(np.median(ph[:, 1])),
+                      "grad_ms_incl_loss_median": float(np.median(ph[:, 2]))}
+        if sevs:
+            phases = {"ms_per_step_median": float(np.median([sevs[i].elapsed_time(sevs[i + 1])
+                                                              for i in range(steps)]))}
         recs = self.plan.profile_records() if profile else []
         self.plan.profile(False)
         return ms, wall, recs, phases
@@ -299,7 +310,7 @@ def main():
     cfg, plan = run.cfg, run.plan
     ms, wall, recs, phases = run.time_steps(args.steps, args.warmup, profile=True)
     print(f"[bench] {args.workload}: {ms:.3f} ms/step (eager, per-kernel events)", file=sys.stderr, flush=True)
-    ms_graph, _, _, _ = run.time_steps(args.steps, 1, profile=False)
+    ms_graph, _, _, gph = run.time_steps(args.steps, 1, profile=False)
     print(f"[bench] {args.workload}: {ms_graph:.3f} ms/step (hipGraph replay)", file=sys.stderr, flush=True)
     ktab = kernel_table(recs, args.steps)
     iters, _ = plan.diagnostics()
@@ -351,6 +362,7 @@ def main():
         "kernels": ktab,
         "wall_s": wall,
         "ms_per_step_graph_replay": ms_graph,
+        "ms_per_step_graph_replay_median": gph["ms_per_step_median"],
         # degrees of freedom of all solves, hierarchical / flat (Sec. 3.4 models
         # this as L eta^((1-L) d))
         "dof_model": {"paper_model": cfg.levels * float(cfg.eta) ** ((1 - cfg.levels) * cfg.dim),
