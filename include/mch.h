@@ -7,8 +7,9 @@
  * homogenization (Xie, Hoang, Yang, Huang, arXiv 2503.01276, Sec. 2,
  * Eqs. phi_avar and phi_grad), either on the fine grid at every macropoint
  * (flat method, levels = 1) or hierarchically (Sec. 3, Algorithm 1): a
- * macropoint of level n >= 2 inherits the fine solution of the level-1
- * macropoint of its group and solves a correction on the coarsened mesh
+ * macropoint of level n >= 2 inherits fine solutions of lower levels (that of
+ * the level-1 macropoint of its group, or a multilinear interpolation of its
+ * neighbours in T_(n-1)) and solves a correction on the coarsened mesh
  * h*eta^(n-1) (Eqs. phi_avar_corrector and phi_grad_corrector). From the local
  * solutions it forms the effective coefficient tensors (Eq. Bs_defi) and the
  * adjoint gradient of a loss on them with respect to log kappa per fine element.
@@ -123,8 +124,9 @@ int mch_build_interp(const mch_config* cfg, int32_t* nbr, double* weight);
  * info[4+L..] unused. info must hold at least 16 entries. */
 int mch_plan_info(const mch_plan* plan, int64_t* info);
 
-/* Level (1..L) and inherited level-1 macropoint (-1 for level 1) of every
- * macropoint, into host arrays of length P. Synchronous. */
+/* Level (1..L) and the level-1 macropoint of its group (-1 for level 1) of
+ * every macropoint, into host arrays of length P (with interp = 1 the
+ * neighbours are those of mch_build_interp). Synchronous. */
 int mch_hierarchy(const mch_plan* plan, int32_t* level, int32_t* parent);
 
 /* Algorithm 1 steps 3-5 (Sec. 3.3): solve every cell problem, level by level,
@@ -144,8 +146,8 @@ int mch_effective_coeffs(mch_plan* plan, const double* kappa, double* A_eff, voi
 /* Adjoint of mch_effective_coeffs o mch_solve_cells: given gA[p][a][b] =
  * dLoss/dA_eff[p][a][b], writes glogk[e] = dLoss/dlog(kappa_e) for every
  * fine element (the gradient flows through the local solutions, through the
- * inherited solutions of level-1 cells, and through the explicit kappa in the
- * tensors). Uses the state of the most recent forward on this plan; kappa
+ * inherited solutions of the lower levels, and through the explicit kappa in
+ * the tensors). Uses the state of the most recent forward on this plan; kappa
  * must be that forward's array. gA: [P][M][M], glogk: [n_fine^d] f64 device.
  * Asynchronous. MCH_ESTALE if no forward solve has been issued. */
 int mch_effective_coeffs_backward(mch_plan* plan, const double* kappa, const double* gA,
