@@ -146,6 +146,21 @@ def kappa_from_labels(lab: np.ndarray, channel_factor: float = 1.0) -> np.ndarra
     return vals[lab] * _modulation(n, lab.ndim)
 
 
+def source_from_labels(lab: np.ndarray) -> np.ndarray:
+    """Source term per fine element, of the form used in the paper's examples
+    (Sec. 4): exp(-40 |x - 1/2|^2) at the element centroid, times 1e-4 outside
+    the high-conductivity channels (the contrast of the low-conductivity
+    continuum)."""
+    n = lab.shape[0]
+    x = (np.arange(n) + 0.5) / n
+    r2 = (x - 0.5) ** 2
+    if lab.ndim == 2:
+        g = np.exp(-40.0 * (r2[:, None] + r2[None, :]))
+    else:
+        g = np.exp(-40.0 * (r2[:, None, None] + r2[None, :, None] + r2[None, None, :]))
+    return np.where(lab == CHANNEL, 1.0, 1.0e-4) * g
+
+
 def medium(name: str, seed: int | None = None, channel_factor: float = 1.0):
     """Return (kappa float64, label uint8) on the preset's global fine grid."""
     cfg = PRESETS[name]
