@@ -100,3 +100,30 @@ extern "C" int mch_local_solutions(mch_plan* p, const int64_t* cells, int64_t n,
   if (n == 0) return MCH_OK;
   return p->dim == 3 ? launch_local_solutions_3d(p, cells, n, out, s) : launch_local_solutions_2d(p, cells, n, out, s);
 }
+
+extern "C" int mch_macro_load(mch_plan* p, const double* f, double* b, void* stream) {
+  hipStream_t s;
+  int rc = enter(p, stream, &s);
+  if (rc) return rc;
+  if (!f || !b) return set_error(MCH_EINVAL, "null f or b");
+  if (p->dim != 2) return set_error(MCH_ENOTIMPL, "the macroscopic system is implemented in 2D only");
+  if (!p->forward_done) return set_error(MCH_ESTALE, "no forward solve has been issued on this plan");
+  return launch_macro_load_2d(p, f, b, s);
+}
+
+extern "C" int mch_macro_solve(mch_plan* p, const double* A, const double* b, double* U, double* U_block,
+                               double rtol, int32_t max_iter, void* stream) {
+  hipStream_t s;
+  int rc = enter(p, stream, &s);
+  if (rc) return rc;
+  if (!A || !b || !U || !U_block) return set_error(MCH_EINVAL, "null argument");
+  if (p->dim != 2) return set_error(MCH_ENOTIMPL, "the macroscopic system is implemented in 2D only");
+  if (!(rtol > 0.0) || max_iter < 1) return set_error(MCH_EINVAL, "rtol must be > 0 and max_iter >= 1");
+  rc = launch_macro_solve_2d(p, A, b, U, U_block, rtol, max_iter, s);
+  if (rc) return rc;
+  p->macro_stream = s;
+  p->macro_done = 1;
+  p->macro_max_iter = max_iter;
+  p->macro_rtol = rtol;
+  return MCH_OK;
+}

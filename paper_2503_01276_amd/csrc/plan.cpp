@@ -609,6 +609,29 @@ extern "C" int mch_build_hierarchy(const mch_config* cfg, int32_t* level, int32_
   return MCH_OK;
 }
 
+int mch::ensure_macro_scratch(mch_plan* p) {
+  if (p->d_macroE) return MCH_OK;
+  const size_t K4 = 4 * (size_t)p->cfg.n_cont, nint = (size_t)(p->nm - 1) * (p->nm - 1) * p->cfg.n_cont;
+  int rc = dev_alloc(p, &p->d_macroE, (size_t)p->P * K4 * K4);
+  if (!rc) rc = dev_alloc(p, &p->d_mvec, 6 * nint);
+  if (!rc) rc = dev_alloc(p, &p->d_macro_iters, 1);
+  if (!rc) rc = dev_alloc(p, &p->d_macro_resid, 1);
+  return rc;
+}
+
+extern "C" int mch_macro_diagnostics(const mch_plan* p, int32_t* iters, double* resid) {
+  if (!p || !iters || !resid) return set_error(MCH_EINVAL, "null argument");
+  if (!p->macro_done) return set_error(MCH_ESTALE, "no macroscopic solve has been issued");
+  int rc = hip_check(hipSetDevice(p->device), "hipSetDevice");
+  if (!rc) rc = hip_check(hipStreamSynchronize(p->macro_stream), "hipStreamSynchronize");
+  if (!rc) rc = hip_check(hipMemcpy(iters, p->d_macro_iters, sizeof(int32_t), hipMemcpyDeviceToHost), "hipMemcpy");
+  if (!rc) rc = hip_check(hipMemcpy(resid, p->d_macro_resid, sizeof(double), hipMemcpyDeviceToHost), "hipMemcpy");
+  if (rc) return rc;
+  if (*iters >= p->macro_max_iter && !(*resid <= p->macro_rtol))
+    return set_error(MCH_ENOCONV, "the macroscopic solve reached max_iter before rtol");
+  return MCH_OK;
+}
+
 extern "C" int mch_build_interp(const mch_config* cfg, int32_t* nbr, double* weight) {
   g_last_error.clear();
   if (!cfg || !nbr || !weight) return set_error(MCH_EINVAL, "null argument");

@@ -114,6 +114,17 @@ struct mch_plan {
   int32_t* d_child_ptr = nullptr;  // [n1+1] CSR of inheriting points per level-1 slot
   int32_t* d_child = nullptr;      // [P - n1] macropoint ids
   double* d_phikp = nullptr;       // 3D: Phi on the K_p nodes [P][M][(H+1)^3]
+  // macroscopic system (2D, allocated on first use): element matrices
+  // [P][4N][4N], CG vectors x, r, z, p, q and D^-1 over the interior macro
+  // nodes [(n_macro-1)^2][N], iterations and final relative residual
+  double* d_macroE = nullptr;
+  double* d_mvec = nullptr;        // 6 consecutive vectors
+  int32_t* d_macro_iters = nullptr;
+  double* d_macro_resid = nullptr;
+  hipStream_t macro_stream = nullptr;  // stream of the last macroscopic solve (may be the default stream)
+  int macro_done = 0;
+  int macro_max_iter = 0;
+  double macro_rtol = 0.0;
   hipStream_t last_stream = nullptr;
   int forward_done = 0;
   const double* fwd_kappa = nullptr;
@@ -189,6 +200,13 @@ int launch_forward_2d(mch_plan* p, const double* kappa, const uint8_t* label, hi
 int launch_eff_2d(mch_plan* p, const double* kappa, double* A, hipStream_t s);
 int launch_backward_2d(mch_plan* p, const double* kappa, const double* gA, double* glogk, hipStream_t s);
 int launch_local_solutions_2d(mch_plan* p, const int64_t* cells, int64_t n, double* out, hipStream_t s);
+// Macroscopic system (2D): block loads from the local solutions, and the
+// assembly and CG solve on the macrogrid.
+int launch_macro_load_2d(mch_plan* p, const double* f, double* b, hipStream_t s);
+int launch_macro_solve_2d(mch_plan* p, const double* A, const double* b, double* U, double* Ub, double rtol,
+                          int max_iter, hipStream_t s);
+// Device scratch of the macroscopic solve (host-synchronous on first use).
+int ensure_macro_scratch(mch_plan* p);
 bool shape_supported_2d(int NC, int rpt, int N, bool galerkin, int n_sub);
 int launch_forward_3d(mch_plan* p, const double* kappa, const uint8_t* label, hipStream_t s);
 int launch_eff_3d(mch_plan* p, const double* kappa, double* A, hipStream_t s);

@@ -21,7 +21,8 @@ CODE_NAMES = {MCH_EINVAL: "MCH_EINVAL", MCH_ESINGULAR: "MCH_ESINGULAR", MCH_ENOC
 
 EXPORTS = ["mch_build_levels", "mch_build_hierarchy", "mch_build_interp", "mch_plan_info", "mch_hierarchy", "mch_solve_cells", "mch_effective_coeffs",
            "mch_effective_coeffs_backward", "mch_local_solutions", "mch_diagnostics", "mch_adjoint_diagnostics", "mch_profile",
-           "mch_profile_read", "mch_destroy", "mch_last_error"]
+           "mch_profile_read", "mch_macro_load", "mch_macro_solve", "mch_macro_diagnostics", "mch_destroy",
+           "mch_last_error"]
 
 
 class MchError(RuntimeError):
@@ -72,6 +73,9 @@ def _load():
     lib.mch_adjoint_diagnostics.argtypes = [vp, i32p, dp]
     lib.mch_profile.argtypes = [vp, ctypes.c_int32]
     lib.mch_profile_read.argtypes = [vp, ctypes.c_int32, ctypes.c_char_p, ctypes.c_int32, dp]
+    lib.mch_macro_load.argtypes = [vp, vp, vp, vp]
+    lib.mch_macro_solve.argtypes = [vp, vp, vp, vp, vp, ctypes.c_double, ctypes.c_int32, vp]
+    lib.mch_macro_diagnostics.argtypes = [vp, i32p, dp]
     lib.mch_destroy.argtypes = [vp]
     lib.mch_destroy.restype = None
     lib.mch_last_error.restype = ctypes.c_char_p
@@ -195,6 +199,29 @@ class Plan:
         _require(out, "float64", len(cells) * self.M * nn)
         check(LIB.mch_local_solutions(self._h, cells.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                       len(cells), _ptr(out), _stream(stream)))
+
+    def macro_load(self, f, b, stream=None):
+        """b[p][j] = int_{K_p} f phi_j from the last forward (2D)."""
+        _require(f, "float64", self.cfg.n_fine ** self.cfg.dim)
+        _require(b, "float64", self.P * self.cfg.n_cont)
+        check(LIB.mch_macro_load(self._h, _ptr(f), _ptr(b), _stream(stream)))
+
+    def macro_solve(self, A_eff, b, U, U_block, rtol=1e-12, max_iter=20000, stream=None):
+        """The macroscopic system from A_eff and b: nodal U and block averages (2D)."""
+        N, nm = self.cfg.n_cont, self.cfg.n_macro
+        _require(A_eff, "float64", self.P * self.M * self.M)
+        _require(b, "float64", self.P * N)
+        _require(U, "float64", (nm + 1) ** self.cfg.dim * N)
+        _require(U_block, "float64", self.P * N)
+        check(LIB.mch_macro_solve(self._h, _ptr(A_eff), _ptr(b), _ptr(U), _ptr(U_block), float(rtol), int(max_iter),
+                                  _stream(stream)))
+
+    def macro_diagnostics(self):
+        it = np.zeros(1, np.int32)
+        rs = np.zeros(1, np.float64)
+        check(LIB.mch_macro_diagnostics(self._h, it.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                        rs.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return int(it[0]), float(rs[0])
 
     def profile(self, on: bool):
         """Turn per-launch event timing on or off (clears the records)."""
