@@ -241,6 +241,33 @@ class Runner:
         return ms, wall, recs, phases
 
 
+def macro_measure(runner, reps: int = 3):
+    """Time the macroscopic system (block loads + assembly + CG) on the runner's
+    last forward and tensors; returns the timings and the block averages."""
+    torch = runner.torch
+    cfg, plan = runner.cfg, runner.plan
+    N, nm, dev = cfg.n_cont, cfg.n_macro, runner.k.device
+    lab = runner.l.cpu().numpy().reshape((cfg.n_fine,) * cfg.dim)
+    f = torch.from_numpy(W.source_from_labels(lab).reshape(-1).copy()).to(dev)
+    b = torch.empty(plan.P * N, dtype=torch.float64, device=dev)
+    U = torch.empty((nm + 1) ** cfg.dim * N, dtype=torch.float64, device=dev)
+    Ub = torch.empty(plan.P * N, dtype=torch.float64, device=dev)
+    with torch.cuda.stream(runner.stream):
+        plan.macro_load(f, b)
+        plan.macro_solve(runner.A, b, U, Ub, rtol=1e-12, max_iter=50000)  # allocates the scratch
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            plan.macro_load(f, b)
+            plan.macro_solve(runner.A, b, U, Ub, rtol=1e-12, max_iter=50000)
+        e1.record()
+        torch.cuda.synchronize()
+    it, rs = plan.macro_diagnostics()
+    return {"ms": e0.elapsed_time(e1) / reps, "cg_iterations": it, "relative_residual": rs,
+            "unknowns": (nm - 1) ** cfg.dim * N}, Ub.cpu().numpy().reshape(-1, N)
+
+
 def kernel_table(recs, steps):
     tab = {}
     for name, ms in recs:
@@ -387,6 +414,15 @@ def main():
             detail["dof_model"]["work_ratio_iterations"] = work_h / work_flat
             detail["dof_model"]["time_ratio_solve"] = fwd_ms / fph["solve_ms"]
         print(f"[bench] {flat}: {fms:.3f} ms/step", file=sys.stderr, flush=True)
+        if cfg.dim == 2 and frun.cfg.dim == 2 and frun.cfg.n_macro == cfg.n_macro:
+            # the macroscopic system from both sets of tensors, and the paper's
+            # Type-3 error (hierarchical against flat block averages, per continuum)
+            mh, ubh = macro_measure(run)
+            mf, ubf = macro_measure(frun)
+            e3 = np.sqrt(((ubf - ubh) ** 2).sum(axis=0) / (ubf ** 2).sum(axis=0))
+            detail["macro"] = {"hierarchical": mh, "flat": mf, "type3_error": e3.tolist()}
+            print(f"[bench] macroscopic system: {mh['ms']:.3f} ms, {mh['cg_iterations']} CG iterations; "
+                  f"Type-3 error {e3}", file=sys.stderr, flush=True)
     out = {
         "metric": "cell-solves/sec & eff-tensor+grad time, hier L=3 vs flat, 1 GPU, rel err <=1e-8",
         "value": solves / (ms * 1e-3),
