@@ -151,3 +151,40 @@ def test_type3_error_definition():
     assert np.all(macro.type3_error(Ua, Ua) == 0.0)
     e = macro.type3_error(Ua, Ua * 1.01)
     assert np.allclose(e, 0.01)
+
+
+def _type3(cfg, k, l, workers):
+    import oracle
+    from paper_2503_01276_amd import workloads as W
+
+    f = W.source_from_labels(l)
+    Ub = []
+    for L in (1, cfg.levels):
+        c = cfg.replace(levels=L)
+        fwd = oracle.forward(c, k, l, workers=workers)
+        b = macro.block_load(c, f, fwd.Phi)
+        Ub.append(macro.solve(oracle.stack_A(fwd, c), b, c.n_macro, c.n_cont, 2)[1])
+    return macro.type3_error(Ub[0], Ub[1])
+
+
+def test_type3_small_where_neighbouring_cells_are_alike():
+    # The hierarchy reproduces the flat method where the paper's premise
+    # holds: channels at the macro period H times the slowly varying
+    # g = 2 + sin(pi x1) sin(pi x2) of the paper's 2D examples, so that
+    # neighbouring cells are near-rescalings (P10 holds approximately). With
+    # channels jittered per channel the inherited solutions sit on the wrong
+    # channels and the 2h / 4h corrections cannot move them: Type 3 is large.
+    from paper_2503_01276_amd import workloads as W
+
+    cfg = W.PRESETS["t3"]
+    n = cfg.n_fine
+    lab = np.zeros((n, n), np.uint8)
+    for c in range(n // 8):
+        lab[(8 * c + 3 + np.arange(2)) % n, :] = 1
+    x = (np.arange(n) + 0.5) / n
+    g = 2.0 + np.sin(np.pi * x)[None, :] * np.sin(np.pi * x)[:, None]
+    e_alike = _type3(cfg, np.where(lab == 1, 1e4, 1.0) * g, lab, workers=4)
+    k, l = W.medium("t3")
+    e_jitter = _type3(cfg, k, l, workers=4)
+    assert np.all(e_alike < 1e-2), e_alike
+    assert np.all(e_jitter > 1e-1), e_jitter
