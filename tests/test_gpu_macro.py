@@ -114,3 +114,36 @@ def test_macro_type3_error_c2_matches_oracle():
     e_ref = macro.type3_error(res["c2flat"][1], res["c2"][1])
     say(f"[gpu] macro c2: Type-3 error per continuum GPU {e_gpu}, oracle {e_ref}")
     assert np.all(np.abs(e_gpu - e_ref) <= 1e-6 * np.maximum(e_ref, 1e-12) + 1e-12), (e_gpu, e_ref)
+
+
+def test_macro_type3_where_neighbouring_cells_are_alike():
+    # channels at the macro period times the paper's slowly varying g: the
+    # hierarchy reproduces the flat method; GPU and oracle agree on Type 3
+    import torch
+
+    from gpu_util import gpu_forward
+
+    base = W.PRESETS["t3"]
+    n = base.n_fine
+    lab = np.zeros((n, n), np.uint8)
+    for c in range(n // 8):
+        lab[(8 * c + 3 + np.arange(2)) % n, :] = 1
+    x = (np.arange(n) + 0.5) / n
+    g = 2.0 + np.sin(np.pi * x)[None, :] * np.sin(np.pi * x)[:, None]
+    k = np.where(lab == 1, 1e4, 1.0) * g
+    f = W.source_from_labels(lab)
+    ub, ub_ref = {}, {}
+    for L in (1, base.levels):
+        cfg = base.replace(levels=L)
+        plan, A, _, _, _, (kd, ld) = gpu_forward(cfg, k, lab)
+        bd = torch.empty(plan.P * cfg.n_cont, dtype=torch.float64, device=kd.device)
+        plan.macro_load(_dev(f), bd)
+        U, ub[L], _, _ = _gpu_macro(plan, _dev(A), bd)
+        fwd = oracle.forward(cfg, k, lab, workers=8)
+        ub_ref[L] = _check(f"macro t3 aligned L={L}", cfg, U, ub[L], oracle.stack_A(fwd, cfg),
+                           macro.block_load(cfg, f, fwd.Phi), False)
+    e_gpu = macro.type3_error(ub[1], ub[base.levels])
+    e_ref = macro.type3_error(ub_ref[1], ub_ref[base.levels])
+    say(f"[gpu] macro t3 aligned: Type-3 error GPU {e_gpu}, oracle {e_ref}")
+    assert np.all(e_gpu < 1e-2), e_gpu
+    assert np.all(np.abs(e_gpu - e_ref) <= 1e-6 * e_ref), (e_gpu, e_ref)
