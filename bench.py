@@ -414,7 +414,7 @@ def main():
             detail["dof_model"]["work_ratio_iterations"] = work_h / work_flat
             detail["dof_model"]["time_ratio_solve"] = fwd_ms / fph["solve_ms"]
         print(f"[bench] {flat}: {fms:.3f} ms/step", file=sys.stderr, flush=True)
-        if cfg.dim == 2 and frun.cfg.dim == 2 and frun.cfg.n_macro == cfg.n_macro:
+        if frun.cfg.dim == cfg.dim and frun.cfg.n_macro == cfg.n_macro:
             # the macroscopic system from both sets of tensors, and the paper's
             # Type-3 error (hierarchical against flat block averages, per continuum)
             mh, ubh = macro_measure(run)

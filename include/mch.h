@@ -154,11 +154,10 @@ int mch_effective_coeffs_backward(mch_plan* plan, const double* kappa, const dou
                                   double* glogk, void* hip_stream);
 
 /* The upscaled multicontinuum system (Sec. 2, Eq. macro_eq with the
- * coefficients of Eq. Bs_defi; the last step of Algorithm 1), 2D only
- * (MCH_ENOTIMPL in 3D).
+ * coefficients of Eq. Bs_defi; the last step of Algorithm 1).
  *
  * mch_macro_load: b[p][j] = int_{K_p} f phi_j for j < n_cont, with f
- * piecewise constant per fine element ([n_fine^2] f64 device array) and phi_j
+ * piecewise constant per fine element ([n_fine^d] f64 device array) and phi_j
  * the type-1 local solutions of the most recent forward on this plan.
  * b: [P][n_cont] f64 device array. Asynchronous. MCH_ESTALE without a
  * forward. */
@@ -166,14 +165,15 @@ int mch_macro_load(mch_plan* plan, const double* f, double* b, void* hip_stream)
 
 /* mch_macro_solve: the weak form sum_p int_{K_p} w_V^T (A_eff(p)/|K_p|) w_U =
  * sum_p int_{K_p} (b(p)/|K_p|) . V, with w = (U_j, d_m U_j) in the
- * right-hand-side order of the cell problems, discretised by bilinear
+ * right-hand-side order of the cell problems, discretised by multilinear
  * elements on the coarse blocks (nodes at the block corners of the unit
- * square, U = 0 on its boundary, the block densities integrated exactly),
+ * square or cube, U = 0 on its boundary, the block densities integrated exactly),
  * solved by Jacobi-preconditioned CG to the relative tolerance rtol on the
  * preconditioned residual, at most max_iter iterations. A_eff: [P][M][M] and
  * b: [P][n_cont] device inputs (any source, e.g. mch_effective_coeffs and
- * mch_macro_load); U: [(n_macro+1)^2][n_cont] nodal values (node
- * k1 + (n_macro+1) k2), U_block: [P][n_cont] block averages, device outputs.
+ * mch_macro_load); U: [(n_macro+1)^d][n_cont] nodal values (node
+ * k1 + (n_macro+1) (k2 + (n_macro+1) k3)), U_block: [P][n_cont] block
+ * averages, device outputs.
  * The plan allocates the solve's scratch on the first call (host-synchronous
  * then); otherwise asynchronous. MCH_EINVAL for bad arguments. */
 int mch_macro_solve(mch_plan* plan, const double* A_eff, const double* b, double* U, double* U_block,

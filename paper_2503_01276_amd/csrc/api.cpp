@@ -106,9 +106,8 @@ extern "C" int mch_macro_load(mch_plan* p, const double* f, double* b, void* str
   int rc = enter(p, stream, &s);
   if (rc) return rc;
   if (!f || !b) return set_error(MCH_EINVAL, "null f or b");
-  if (p->dim != 2) return set_error(MCH_ENOTIMPL, "the macroscopic system is implemented in 2D only");
   if (!p->forward_done) return set_error(MCH_ESTALE, "no forward solve has been issued on this plan");
-  return launch_macro_load_2d(p, f, b, s);
+  return launch_macro_load(p, f, b, s);
 }
 
 extern "C" int mch_macro_solve(mch_plan* p, const double* A, const double* b, double* U, double* U_block,
@@ -117,9 +116,8 @@ extern "C" int mch_macro_solve(mch_plan* p, const double* A, const double* b, do
   int rc = enter(p, stream, &s);
   if (rc) return rc;
   if (!A || !b || !U || !U_block) return set_error(MCH_EINVAL, "null argument");
-  if (p->dim != 2) return set_error(MCH_ENOTIMPL, "the macroscopic system is implemented in 2D only");
   if (!(rtol > 0.0) || max_iter < 1) return set_error(MCH_EINVAL, "rtol must be > 0 and max_iter >= 1");
-  rc = launch_macro_solve_2d(p, A, b, U, U_block, rtol, max_iter, s);
+  rc = launch_macro_solve(p, A, b, U, U_block, rtol, max_iter, s);
   if (rc) return rc;
   p->macro_stream = s;
   p->macro_done = 1;

@@ -1,0 +1,386 @@
+// The upscaled multicontinuum system on the macrogrid (Sec. 2, Eq. macro_eq
+// with the coefficients of Eq. Bs_defi; the last step of Algorithm 1), 2D and 3D.
+//
+// Weak form over the coarse blocks K_p: sum_p int_{K_p} w_V^T (A_eff(p)/|K_p|)
+// w_U = sum_p int_{K_p} (b(p)/|K_p|) . V, with w = (U_0 .. U_{N-1},
+// d_1 U_0 .. d_d U_0, d_1 U_1, ...) in the right-hand-side order of the cell
+// problems, so the blocks of A_eff are B_ji, B^m_ji, Bbar^n_ji and B^mn_ji.
+// U is continuous and multilinear on the blocks with nodes at the block
+// corners of [0, 1]^d and U = 0 on its boundary; the block densities are
+// integrated exactly against the Q1 functions; b_j(p) = int_{K_p} f phi_j.
+// The operator is symmetric positive semi-definite (a sum of Gram forms) and
+// is solved by Jacobi-preconditioned CG.
+//
+// Unknowns: interior node k (1 <= k_a <= n_macro - 1 per axis, axis 1
+// fastest), continuum j at (node index) N + j. Element matrices
+// E_p[(a, j), (b, i)] (index a N + j, corners a in tensor order) are formed
+// once per solve; the CG applies the operator by gathering, per node, the
+// rows of its 2^d blocks. The CG runs in one workgroup: the macro systems of
+// the workloads here have a few thousand unknowns, and one workgroup needs no
+// device-wide synchronisation (at 2048^2 it is bound by one CU's bandwidth).
+#include "kernels2d.h"
+
+namespace mch {
+
+constexpr int MT = 256;    // load and element kernels
+constexpr int CGT = 1024;  // the CG workgroup
+constexpr int CGW = CGT / 64;
+
+// 2D: b[p][j] = int_{K_p} f phi_j, j < N: per fine element of K_p, |e| f_e
+// times the mean of phi_j at its four corners (exact for bilinear phi_j).
+__global__ __launch_bounds__(MT) void k_macro_load2d(CellArgs a, const double* f, double* b) {
+  __shared__ double red[3][MT / 64];
+  const int ci = a.ci0 + blockIdx.x;
+  const int p = a.cells[ci];
+  const int H = a.H, N = a.N, k0 = (a.nc - H) / 2;
+  const int jx = p % a.n_macro, jy = p / a.n_macro;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int e = tid; e < H * H; e += MT) {
+    const int ex = e % H, ey = e / H;
+    const double fe = f[(size_t)(H * jy + ey) * a.n + (H * jx + ex)] * a.h * a.h;
+    for (int j = 0; j < N; ++j) {
+      const double m = 0.25 * ((phi_at(a, ci, j, k0 + ex, k0 + ey) + phi_at(a, ci, j, k0 + ex + 1, k0 + ey)) +
+                               (phi_at(a, ci, j, k0 + ex, k0 + ey + 1) + phi_at(a, ci, j, k0 + ex + 1, k0 + ey + 1)));
+      acc[j] += fe * m;
+    }
+  }
+  for (int j = 0; j < N; ++j) {
+    const double v = wave_sum(acc[j]);
+    if (lane == 0) red[j][wave] = v;
+  }
+  __syncthreads();
+  if (tid < N) b[(size_t)p * N + tid] = tree_sum<MT / 64, 1>(red[tid]);
+}
+
+// 3D: the same from Phi on the K_p nodes, phikp [P][M][(H+1)^3] (X fastest),
+// which the 3D forward stores for every point.
+__global__ __launch_bounds__(MT) void k_macro_load3d(const double* phikp, const double* f, int n, int nm, int H,
+                                                     int M, int N, double h, double* b) {
+  __shared__ double red[3][MT / 64];
+  const int p = blockIdx.x;
+  const int jx = p % nm, jy = (p / nm) % nm, jz = p / (nm * nm), Hp = H + 1;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int e = tid; e < H * H * H; e += MT) {
+    const int ex = e % H, ey = (e / H) % H, ez = e / (H * H);
+    const double fe = f[((size_t)(H * jz + ez) * n + (H * jy + ey)) * n + (H * jx + ex)] * h * h * h;
+    for (int j = 0; j < N; ++j) {
+      const double* ph = phikp + ((size_t)p * M + j) * (size_t)Hp * Hp * Hp;
+      double s = 0.0;
+      for (int c = 0; c < 8; ++c)
+        s += ph[(ex + (c & 1)) + Hp * ((ey + ((c >> 1) & 1)) + Hp * (ez + (c >> 2)))];
+      acc[j] += fe * (0.125 * s);
+    }
+  }
+  for (int j = 0; j < N; ++j) {
+    const double v = wave_sum(acc[j]);
+    if (lane == 0) red[j][wave] = v;
+  }
+  __syncthreads();
+  if (tid < N) b[(size_t)p * N + tid] = tree_sum<MT / 64, 1>(red[tid]);
+}
+
+// One-dimensional Q1 integrals on [0, Hc]: value or derivative of the test
+// function (corner x) against value or derivative of the trial function
+// (corner y).
+MCH_DEV double q1_1d(bool dtest, bool dtrial, int x, int y, double Hc) {
+  if (!dtest && !dtrial) return Hc * (x == y ? 1.0 / 3.0 : 1.0 / 6.0);
+  if (!dtest && dtrial) return y == 1 ? 0.5 : -0.5;
+  if (dtest && !dtrial) return x == 1 ? 0.5 : -0.5;
+  return (x == y ? 1.0 : -1.0) / Hc;
+}
+
+// E_p[(a, j), (b, i)] = (1/|K|) sum over the value / derivative components
+// (s of the test, t of the trial) of A_p[alpha(j, s)][alpha(i, t)] times the
+// Q1 integral of the two components, a product over the axes;
+// alpha(j, 0) = j, alpha(j, 1 + m) = N + D j + m.
+template <int D>
+__global__ __launch_bounds__(MT) void k_macro_elem(const double* A, int N, double Hc, double* E) {
+  constexpr int K = 1 << D;
+  const int p = blockIdx.x, M = (1 + D) * N, KN = K * N;
+  const double* Ap = A + (size_t)p * M * M;
+  double* Ep = E + (size_t)p * KN * KN;
+  double vol = 1.0;
+  for (int ax = 0; ax < D; ++ax) vol *= Hc;
+  for (int k = threadIdx.x; k < KN * KN; k += MT) {
+    const int row = k / KN, col = k % KN;
+    const int a = row / N, j = row % N, bc = col / N, i = col % N;
+    double s = 0.0;
+    for (int sa = 0; sa <= D; ++sa) {
+      const int al = sa == 0 ? j : N + D * j + sa - 1;
+      for (int tb = 0; tb <= D; ++tb) {
+        const int be = tb == 0 ? i : N + D * i + tb - 1;
+        double t = 1.0;
+        for (int ax = 0; ax < D; ++ax)
+          t *= q1_1d(sa == 1 + ax, tb == 1 + ax, (a >> ax) & 1, (bc >> ax) & 1, Hc);
+        s += Ap[(size_t)al * M + be] * t;
+      }
+    }
+    Ep[k] = s / vol;
+  }
+}
+
+// Sum over the workgroup in a fixed order; every thread gets the result.
+MCH_DEV double cg_sum(double v, double* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  v = wave_sum(v);
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  const double t = tree_sum<CGW, 1>(red);
+  __syncthreads();  // red is reused by the next sum
+  return t;
+}
+
+struct MacroArgs {
+  int nm, N;
+  const double* E;  // [P][2^D N][2^D N]
+  const double* b;  // [P][N]
+  double *x, *r, *z, *p, *q, *dinv;
+  double rtol;
+  int max_iter;
+  double* U;   // [(nm+1)^D][N]
+  double* Ub;  // [P][N]
+  int32_t* iters;
+  double* resid;
+};
+
+// Interior node index of multi-index k (1-based per axis), -1 on the boundary.
+template <int D>
+MCH_DEV int interior_index(const int (&k)[3], int ni) {
+  int idx = 0, str = 1;
+  for (int ax = 0; ax < D; ++ax) {
+    if (k[ax] < 1 || k[ax] > ni) return -1;
+    idx += (k[ax] - 1) * str;
+    str *= ni;
+  }
+  return idx;
+}
+
+// Block index of the block whose corner a node k is, and the block's corner
+// multi-index.
+template <int D>
+MCH_DEV int block_of(const int (&k)[3], int a, int nm, int (&B)[3]) {
+  int idx = 0, str = 1;
+  for (int ax = 0; ax < D; ++ax) {
+    B[ax] = k[ax] - ((a >> ax) & 1);
+    idx += B[ax] * str;
+    str *= nm;
+  }
+  return idx;
+}
+
+// Diagonal entry of unknown (interior node k; continuum j).
+template <int D>
+MCH_DEV double macro_diag(const MacroArgs& m, const int (&k)[3], int j) {
+  constexpr int K = 1 << D;
+  const int N = m.N, KN = K * N;
+  double d = 0.0;
+  for (int a = 0; a < K; ++a) {
+    int B[3];
+    const int pb = block_of<D>(k, a, m.nm, B);
+    d += m.E[((size_t)pb * KN + a * N + j) * KN + a * N + j];
+  }
+  return d;
+}
+
+// The row of that unknown applied to v.
+template <int D>
+MCH_DEV double macro_row(const MacroArgs& m, const int (&k)[3], int j, const double* v) {
+  constexpr int K = 1 << D;
+  const int N = m.N, KN = K * N, ni = m.nm - 1;
+  double y = 0.0;
+  for (int a = 0; a < K; ++a) {
+    int B[3];
+    const int pb = block_of<D>(k, a, m.nm, B);
+    const double* Er = m.E + ((size_t)pb * KN + a * N + j) * KN;
+    for (int bb = 0; bb < K; ++bb) {
+      int nb[3] = {0, 0, 0};
+      for (int ax = 0; ax < D; ++ax) nb[ax] = B[ax] + ((bb >> ax) & 1);
+      const int vi = interior_index<D>(nb, ni);
+      if (vi < 0) continue;  // boundary node: U = 0
+      const double* vv = v + (size_t)vi * N;
+      for (int i = 0; i < N; ++i) y += Er[bb * N + i] * vv[i];
+    }
+  }
+  return y;
+}
+
+// Jacobi-preconditioned CG in one workgroup; every thread reads the same
+// reduced scalars, so all leave the loop in the same iteration.
+template <int D>
+__global__ __launch_bounds__(CGT) void k_macro_cg(MacroArgs m) {
+  constexpr int K = 1 << D;
+  __shared__ double red[CGW];
+  const int nm = m.nm, N = m.N, ni = nm - 1;
+  int nint = 1;
+  for (int ax = 0; ax < D; ++ax) nint *= ni;
+  const int n = nint * N;
+  const int tid = threadIdx.x;
+  auto node = [&](int u, int (&k)[3], int& j) {
+    j = u % N;
+    int nd = u / N;
+    k[2] = 1;
+    for (int ax = 0; ax < D; ++ax) {
+      k[ax] = 1 + nd % ni;
+      nd /= ni;
+    }
+  };
+  // x = 0, r = F, z = D^-1 r, p = z
+  double rz = 0.0;
+  for (int u = tid; u < n; u += CGT) {
+    int k[3], j;
+    node(u, k, j);
+    double F = 0.0;
+    for (int a = 0; a < K; ++a) {
+      int B[3];
+      F += m.b[(size_t)block_of<D>(k, a, nm, B) * N + j] / K;
+    }
+    const double di = 1.0 / macro_diag<D>(m, k, j);
+    m.dinv[u] = di;
+    m.x[u] = 0.0;
+    m.r[u] = F;
+    const double zu = F * di;
+    m.z[u] = zu;
+    m.p[u] = zu;
+    rz += F * zu;
+  }
+  rz = cg_sum(rz, red);  // the barrier also publishes p
+  const double rz0 = rz;
+  int it = 0;
+  bool done = !(rz0 > 0.0);
+  while (!done) {
+    double pq = 0.0;
+    for (int u = tid; u < n; u += CGT) {
+      int k[3], j;
+      node(u, k, j);
+      const double qu = macro_row<D>(m, k, j, m.p);
+      m.q[u] = qu;
+      pq += m.p[u] * qu;
+    }
+    pq = cg_sum(pq, red);
+    const double al = rz / pq;
+    double rzn = 0.0;
+    for (int u = tid; u < n; u += CGT) {
+      m.x[u] += al * m.p[u];
+      const double ru = m.r[u] - al * m.q[u];
+      m.r[u] = ru;
+      const double zu = ru * m.dinv[u];
+      m.z[u] = zu;
+      rzn += ru * zu;
+    }
+    rzn = cg_sum(rzn, red);
+    ++it;
+    if (rzn <= m.rtol * m.rtol * rz0 || it >= m.max_iter) {
+      rz = rzn;
+      break;
+    }
+    const double be = rzn / rz;
+    rz = rzn;
+    for (int u = tid; u < n; u += CGT) m.p[u] = m.z[u] + be * m.p[u];
+    __syncthreads();  // p complete before the next product
+  }
+  // nodal values (zero on the boundary) and block averages
+  const int nn = nm + 1;
+  int nnodes = 1, nblocks = 1;
+  for (int ax = 0; ax < D; ++ax) {
+    nnodes *= nn;
+    nblocks *= nm;
+  }
+  for (int u = tid; u < nnodes * N; u += CGT) {
+    const int j = u % N;
+    int nd = u / N, k[3] = {0, 0, 1};
+    for (int ax = 0; ax < D; ++ax) {
+      k[ax] = nd % nn;
+      nd /= nn;
+    }
+    const int vi = interior_index<D>(k, ni);
+    m.U[u] = vi >= 0 ? m.x[(size_t)vi * N + j] : 0.0;
+  }
+  __syncthreads();
+  for (int u = tid; u < nblocks * N; u += CGT) {
+    const int j = u % N;
+    int pb = u / N, B[3] = {0, 0, 0};
+    for (int ax = 0; ax < D; ++ax) {
+      B[ax] = pb % nm;
+      pb /= nm;
+    }
+    double s = 0.0;
+    for (int c = 0; c < K; ++c) {
+      size_t idx = 0, str = 1;
+      for (int ax = 0; ax < D; ++ax) {
+        idx += (size_t)(B[ax] + ((c >> ax) & 1)) * str;
+        str *= nn;
+      }
+      s += m.U[idx * N + j];
+    }
+    m.Ub[u] = s / K;
+  }
+  if (tid == 0) {
+    *m.iters = it;
+    *m.resid = rz0 > 0.0 ? sqrt(fmax(rz, 0.0) / rz0) : 0.0;
+  }
+}
+
+int launch_macro_load(mch_plan* pl, const double* f, double* b, hipStream_t s) {
+  const int N = pl->cfg.n_cont;
+  if (pl->dim == 3) {
+    ProfScope ps(pl, "macro_load", s);
+    hipLaunchKernelGGL(k_macro_load3d, dim3(pl->P), dim3(MT), 0, s, pl->d_phikp, f, pl->n, pl->nm, pl->H, pl->M, N,
+                       pl->cfg.h, b);
+    return hip_check(hipGetLastError(), "launch k_macro_load3d");
+  }
+  for (int l = 0; l < pl->L; ++l) {
+    if (pl->lev[l].count == 0) continue;
+    CellArgs a = base_args(pl, pl->fwd_kappa, pl->fwd_label, l);
+    ProfScope ps(pl, "macro_load", s);
+    hipLaunchKernelGGL(k_macro_load2d, dim3(a.count), dim3(MT), 0, s, a, f, b);
+    int rc = hip_check(hipGetLastError(), "launch k_macro_load2d");
+    if (rc) return rc;
+  }
+  return MCH_OK;
+}
+
+int launch_macro_solve(mch_plan* pl, const double* A, const double* b, double* U, double* Ub, double rtol,
+                       int max_iter, hipStream_t s) {
+  const int N = pl->cfg.n_cont, nm = pl->nm, D = pl->dim;
+  if (nm < 2) return set_error(MCH_EINVAL, "the macroscopic system needs at least 2 blocks per axis");
+  int rc = ensure_macro_scratch(pl);
+  if (rc) return rc;
+  {
+    ProfScope ps(pl, "macro_elem", s);
+    if (D == 2)
+      hipLaunchKernelGGL(k_macro_elem<2>, dim3(pl->P), dim3(MT), 0, s, A, N, 1.0 / nm, pl->d_macroE);
+    else
+      hipLaunchKernelGGL(k_macro_elem<3>, dim3(pl->P), dim3(MT), 0, s, A, N, 1.0 / nm, pl->d_macroE);
+    rc = hip_check(hipGetLastError(), "launch k_macro_elem");
+  }
+  if (rc) return rc;
+  size_t nint = (size_t)N;
+  for (int ax = 0; ax < D; ++ax) nint *= (size_t)(nm - 1);
+  MacroArgs m{};
+  m.nm = nm;
+  m.N = N;
+  m.E = pl->d_macroE;
+  m.b = b;
+  m.x = pl->d_mvec;
+  m.r = m.x + nint;
+  m.z = m.r + nint;
+  m.p = m.z + nint;
+  m.q = m.p + nint;
+  m.dinv = m.q + nint;
+  m.rtol = rtol;
+  m.max_iter = max_iter;
+  m.U = U;
+  m.Ub = Ub;
+  m.iters = pl->d_macro_iters;
+  m.resid = pl->d_macro_resid;
+  ProfScope ps(pl, "macro_cg", s);
+  if (D == 2)
+    hipLaunchKernelGGL(k_macro_cg<2>, dim3(1), dim3(CGT), 0, s, m);
+  else
+    hipLaunchKernelGGL(k_macro_cg<3>, dim3(1), dim3(CGT), 0, s, m);
+  return hip_check(hipGetLastError(), "launch k_macro_cg");
+}
+
+}  // namespace mch

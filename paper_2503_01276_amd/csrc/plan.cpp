@@ -611,8 +611,9 @@ extern "C" int mch_build_hierarchy(const mch_config* cfg, int32_t* level, int32_
 
 int mch::ensure_macro_scratch(mch_plan* p) {
   if (p->d_macroE) return MCH_OK;
-  const size_t K4 = 4 * (size_t)p->cfg.n_cont, nint = (size_t)(p->nm - 1) * (p->nm - 1) * p->cfg.n_cont;
-  int rc = dev_alloc(p, &p->d_macroE, (size_t)p->P * K4 * K4);
+  const size_t KN = (size_t)ipow(2, p->dim) * p->cfg.n_cont;
+  const size_t nint = (size_t)ipow(p->nm - 1, p->dim) * p->cfg.n_cont;
+  int rc = dev_alloc(p, &p->d_macroE, (size_t)p->P * KN * KN);
   if (!rc) rc = dev_alloc(p, &p->d_mvec, 6 * nint);
   if (!rc) rc = dev_alloc(p, &p->d_macro_iters, 1);
   if (!rc) rc = dev_alloc(p, &p->d_macro_resid, 1);

@@ -114,9 +114,9 @@ struct mch_plan {
   int32_t* d_child_ptr = nullptr;  // [n1+1] CSR of inheriting points per level-1 slot
   int32_t* d_child = nullptr;      // [P - n1] macropoint ids
   double* d_phikp = nullptr;       // 3D: Phi on the K_p nodes [P][M][(H+1)^3]
-  // macroscopic system (2D, allocated on first use): element matrices
-  // [P][4N][4N], CG vectors x, r, z, p, q and D^-1 over the interior macro
-  // nodes [(n_macro-1)^2][N], iterations and final relative residual
+  // macroscopic system (allocated on first use): element matrices
+  // [P][2^d N][2^d N], CG vectors x, r, z, p, q and D^-1 over the interior
+  // macro nodes [(n_macro-1)^d][N], iterations and final relative residual
   double* d_macroE = nullptr;
   double* d_mvec = nullptr;        // 6 consecutive vectors
   int32_t* d_macro_iters = nullptr;
@@ -200,11 +200,11 @@ int launch_forward_2d(mch_plan* p, const double* kappa, const uint8_t* label, hi
 int launch_eff_2d(mch_plan* p, const double* kappa, double* A, hipStream_t s);
 int launch_backward_2d(mch_plan* p, const double* kappa, const double* gA, double* glogk, hipStream_t s);
 int launch_local_solutions_2d(mch_plan* p, const int64_t* cells, int64_t n, double* out, hipStream_t s);
-// Macroscopic system (2D): block loads from the local solutions, and the
-// assembly and CG solve on the macrogrid.
-int launch_macro_load_2d(mch_plan* p, const double* f, double* b, hipStream_t s);
-int launch_macro_solve_2d(mch_plan* p, const double* A, const double* b, double* U, double* Ub, double rtol,
-                          int max_iter, hipStream_t s);
+// Macroscopic system: block loads from the local solutions, and the
+// assembly and CG solve on the macrogrid (2D and 3D).
+int launch_macro_load(mch_plan* p, const double* f, double* b, hipStream_t s);
+int launch_macro_solve(mch_plan* p, const double* A, const double* b, double* U, double* Ub, double rtol,
+                       int max_iter, hipStream_t s);
 // Device scratch of the macroscopic solve (host-synchronous on first use).
 int ensure_macro_scratch(mch_plan* p);
 bool shape_supported_2d(int NC, int rpt, int N, bool galerkin, int n_sub);

@@ -201,13 +201,13 @@ class Plan:
                                       len(cells), _ptr(out), _stream(stream)))
 
     def macro_load(self, f, b, stream=None):
-        """b[p][j] = int_{K_p} f phi_j from the last forward (2D)."""
+        """b[p][j] = int_{K_p} f phi_j from the last forward."""
         _require(f, "float64", self.cfg.n_fine ** self.cfg.dim)
         _require(b, "float64", self.P * self.cfg.n_cont)
         check(LIB.mch_macro_load(self._h, _ptr(f), _ptr(b), _stream(stream)))
 
     def macro_solve(self, A_eff, b, U, U_block, rtol=1e-12, max_iter=20000, stream=None):
-        """The macroscopic system from A_eff and b: nodal U and block averages (2D)."""
+        """The macroscopic system from A_eff and b: nodal U and block averages."""
         N, nm = self.cfg.n_cont, self.cfg.n_macro
         _require(A_eff, "float64", self.P * self.M * self.M)
         _require(b, "float64", self.P * N)

@@ -33,7 +33,7 @@ def _gpu_macro(plan, A, b):
 
     N, nm = plan.cfg.n_cont, plan.cfg.n_macro
     dev = torch.device("cuda:0")
-    U = torch.empty((nm + 1) ** 2 * N, dtype=torch.float64, device=dev)
+    U = torch.empty((nm + 1) ** plan.cfg.dim * N, dtype=torch.float64, device=dev)
     Ub = torch.empty(plan.P * N, dtype=torch.float64, device=dev)
     plan.macro_solve(A, b, U, Ub, rtol=1e-13, max_iter=50000)
     it, rs = plan.macro_diagnostics()
@@ -41,10 +41,10 @@ def _gpu_macro(plan, A, b):
 
 
 def _check(name, cfg, U, Ub, Aref, bref, same_inputs):
-    K, F, keep = macro.assemble(Aref, bref, cfg.n_macro, cfg.n_cont, 2)
+    K, F, keep = macro.assemble(Aref, bref, cfg.n_macro, cfg.n_cont, cfg.dim)
     u = U.reshape(-1)[keep]
     res = np.linalg.norm(K @ u - F) / np.linalg.norm(F)
-    _, Ub_ref = macro.solve(Aref, bref, cfg.n_macro, cfg.n_cont, 2)
+    _, Ub_ref = macro.solve(Aref, bref, cfg.n_macro, cfg.n_cont, cfg.dim)
     err = np.linalg.norm(Ub - Ub_ref, axis=0) / np.linalg.norm(Ub_ref, axis=0)
     say(f"[gpu] {name}: residual of the oracle's system {res:.2e}, block-average rel err {err.max():.2e}")
     if same_inputs:
@@ -147,3 +147,31 @@ def test_macro_type3_where_neighbouring_cells_are_alike():
     say(f"[gpu] macro t3 aligned: Type-3 error GPU {e_gpu}, oracle {e_ref}")
     assert np.all(e_gpu < 1e-2), e_gpu
     assert np.all(np.abs(e_gpu - e_ref) <= 1e-6 * e_ref), (e_gpu, e_ref)
+
+
+def test_macro_3d_oracle_inputs_and_end_to_end():
+    # 3D (trilinear blocks): the solve on the oracle's A_eff and b, then the
+    # GPU chain (tensors, loads from Phi on the K_p nodes, solve)
+    import torch
+
+    from gpu_util import gpu_forward
+
+    from paper_2503_01276_amd import mch
+
+    cfg = W.PRESETS["t3d"]
+    k, l = W.medium("t3d")
+    f = W.source_from_labels(l)
+    fwd = oracle.forward(cfg, k, l, workers=8)
+    Aref = oracle.stack_A(fwd, cfg)
+    bref = macro.block_load(cfg, f, fwd.Phi)
+    U, Ub, it, rs = _gpu_macro(mch.Plan(cfg), _dev(Aref), _dev(bref))
+    say(f"[gpu] macro t3d: {it} CG iterations, relative residual {rs:.2e}")
+    _check("macro t3d (oracle inputs)", cfg, U, Ub, Aref, bref, True)
+    plan, A, _, _, _, (kd, ld) = gpu_forward(cfg, k, l)
+    bd = torch.empty(plan.P * cfg.n_cont, dtype=torch.float64, device=kd.device)
+    plan.macro_load(_dev(f), bd)
+    eb = np.abs(bd.cpu().numpy().reshape(-1, cfg.n_cont) - bref).max() / np.abs(bref).max()
+    say(f"[gpu] macro t3d: block load rel err {eb:.2e}")
+    assert eb <= 1e-9, eb
+    U, Ub, _, _ = _gpu_macro(plan, _dev(A), bd)
+    _check("macro t3d (GPU chain)", cfg, U, Ub, Aref, bref, False)

@@ -188,3 +188,24 @@ def test_type3_small_where_neighbouring_cells_are_alike():
     e_jitter = _type3(cfg, k, l, workers=4)
     assert np.all(e_alike < 1e-2), e_alike
     assert np.all(e_jitter > 1e-1), e_jitter
+
+
+def test_single_continuum_second_order_3d():
+    # c0 U - kappa Lap U = g in the unit cube, U = sin(pi x) sin(pi y) sin(pi z)
+    c0, kap = 2.0, 1.0
+    errs = []
+    for n in (8, 16):
+        vol = 1.0 / n ** 3
+        A = np.zeros((n ** 3, 4, 4))
+        A[:, 0, 0] = c0 * vol
+        A[:, 1, 1] = A[:, 2, 2] = A[:, 3, 3] = kap * vol
+        x = np.arange(n + 1) / n
+        I = (np.cos(np.pi * x[:-1]) - np.cos(np.pi * x[1:])) / np.pi
+        blk = np.einsum("i,j,k->ijk", I, I, I).reshape(-1)  # block j1 + n (j2 + n j3): I[j3] I[j2] I[j1]
+        b = ((3 * np.pi ** 2 * kap + c0) * blk)[:, None]
+        U, _ = macro.solve(A, b, n, 1, 3)
+        s = np.sin(np.pi * x)
+        exact = np.einsum("i,j,k->ijk", s, s, s).reshape(-1)
+        errs.append(np.abs(U[:, 0] - exact).max())
+    assert errs[1] < 1e-2
+    assert 3.5 < errs[0] / errs[1] < 4.5, errs
