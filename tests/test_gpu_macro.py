@@ -175,3 +175,51 @@ def test_macro_3d_oracle_inputs_and_end_to_end():
     assert eb <= 1e-9, eb
     U, Ub, _, _ = _gpu_macro(plan, _dev(A), bd)
     _check("macro t3d (GPU chain)", cfg, U, Ub, Aref, bref, False)
+
+
+def _macro_blocks_gpu(name):
+    import torch
+
+    from gpu_util import gpu_forward
+
+    cfg = W.PRESETS[name]
+    k, l = W.medium(name)
+    plan, A, _, _, _, (kd, ld) = gpu_forward(cfg, k, l)
+    bd = torch.empty(plan.P * cfg.n_cont, dtype=torch.float64, device=kd.device)
+    plan.macro_load(_dev(W.source_from_labels(l)), bd)
+    return _gpu_macro(plan, _dev(A), bd)[1]
+
+
+@pytest.mark.parametrize("hier,flat,with_oracle", [("t3", None, True), ("c2", "c2flat", False)])
+def test_type1_type2_errors_against_the_fine_solution(hier, flat, with_oracle):
+    # Types 1 and 2 of the paper: the flat (MH) and hierarchical (HMH) block
+    # averages against the continuum averages of the global fine solution
+    from oracle import reference
+
+    cfg = W.PRESETS[hier]
+    k, l = W.medium(hier)
+    u = reference.fine_solution(k, W.source_from_labels(l))
+    Uh = reference.continuum_block_averages(u, l, cfg.n_macro, cfg.n_cont)
+    flat_name = flat or hier
+    U_mh = _macro_blocks_gpu(flat_name) if flat else None
+    if flat is None:
+        import paper_2503_01276_amd.workloads as WW
+        WW.PRESETS["_flat_tmp"] = cfg.replace(levels=1)
+        WW.PRESET_SEEDS["_flat_tmp"] = WW.PRESET_SEEDS[hier]
+        try:
+            U_mh = _macro_blocks_gpu("_flat_tmp")
+        finally:
+            del WW.PRESETS["_flat_tmp"], WW.PRESET_SEEDS["_flat_tmp"]
+    U_hmh = _macro_blocks_gpu(hier)
+    t1, t2 = reference.e2(Uh, U_mh), reference.e2(Uh, U_hmh)
+    say(f"[gpu] {hier}: Type 1 (MH vs fine) {t1}, Type 2 (HMH vs fine) {t2}")
+    assert np.all(np.isfinite(t1)) and np.all(np.isfinite(t2))
+    if with_oracle:
+        f = W.source_from_labels(l)
+        ref = []
+        for L in (1, cfg.levels):
+            c = cfg.replace(levels=L)
+            fwd = oracle.forward(c, k, l, workers=8)
+            ref.append(macro.solve(oracle.stack_A(fwd, c), macro.block_load(c, f, fwd.Phi), c.n_macro, c.n_cont, 2)[1])
+        r1, r2 = reference.e2(Uh, ref[0]), reference.e2(Uh, ref[1])
+        assert np.allclose(t1, r1, rtol=1e-8) and np.allclose(t2, r2, rtol=1e-8), (t1, r1, t2, r2)
