@@ -168,8 +168,9 @@ int mch_macro_load(mch_plan* plan, const double* f, double* b, void* hip_stream)
  * right-hand-side order of the cell problems, discretised by multilinear
  * elements on the coarse blocks (nodes at the block corners of the unit
  * square or cube, U = 0 on its boundary, the block densities integrated exactly),
- * solved by Jacobi-preconditioned CG to the relative tolerance rtol on the
- * preconditioned residual, at most max_iter iterations. A_eff: [P][M][M] and
+ * solved by CG preconditioned with the inverse N x N block of each node (its
+ * continua) to the relative tolerance rtol on the preconditioned residual
+ * (sqrt(r^T M^-1 r) over its initial value), at most max_iter iterations. A_eff: [P][M][M] and
  * b: [P][n_cont] device inputs (any source, e.g. mch_effective_coeffs and
  * mch_macro_load); U: [(n_macro+1)^d][n_cont] nodal values (node
  * k1 + (n_macro+1) (k2 + (n_macro+1) k3)), U_block: [P][n_cont] block

@@ -9,13 +9,16 @@
 // corners of [0, 1]^d and U = 0 on its boundary; the block densities are
 // integrated exactly against the Q1 functions; b_j(p) = int_{K_p} f phi_j.
 // The operator is symmetric positive semi-definite (a sum of Gram forms) and
-// is solved by Jacobi-preconditioned CG.
+// is solved by CG preconditioned with the inverses of the nodal N x N blocks
+// (the continua at one node are strongly coupled through the exchange terms
+// B_ji; point Jacobi ignores that coupling and needs over ten times the
+// iterations on hierarchical tensors).
 //
 // Unknowns: interior node k (1 <= k_a <= n_macro - 1 per axis, axis 1
 // fastest), continuum j at (node index) N + j. Element matrices
 // E_p[(a, j), (b, i)] (index a N + j, corners a in tensor order) are formed
-// once per solve; the CG applies the operator by gathering, per node, the
-// rows of its 2^d blocks. The CG runs in one workgroup: the macro systems of
+// once per solve and summed into nodal block rows over the 3^d neighbours of
+// each node, which the CG applies. The CG runs in one workgroup: the macro systems of
 // the workloads here have a few thousand unknowns, and one workgroup needs no
 // device-wide synchronisation (at 2048^2 it is bound by one CU's bandwidth).
 #include "kernels2d.h"
@@ -133,10 +136,11 @@ MCH_DEV double cg_sum(double v, double* red) {
 }
 
 struct MacroArgs {
-  int nm, N;
-  const double* E;  // [P][2^D N][2^D N]
-  const double* b;  // [P][N]
-  double *x, *r, *z, *p, *q, *dinv;
+  int nm;
+  const double* S;     // nodal stencil rows [3^D N][n]
+  const double* Dinv;  // inverse diagonal blocks [N N][n / N]
+  const double* b;     // [P][N]
+  double *x, *r, *z, *p, *q;
   double rtol;
   int max_iter;
   double* U;   // [(nm+1)^D][N]
@@ -157,6 +161,27 @@ MCH_DEV int interior_index(const int (&k)[3], int ni) {
   return idx;
 }
 
+// Multi-index of interior node nd.
+template <int D>
+MCH_DEV void node_index(int nd, int ni, int (&k)[3]) {
+  k[2] = 1;
+  for (int ax = 0; ax < D; ++ax) {
+    k[ax] = 1 + nd % ni;
+    nd /= ni;
+  }
+}
+
+// Neighbour s of node k, 0 <= s < 3^D: offset (s mod 3) - 1 on axis 1, and so
+// on, axis 1 fastest; s = (3^D - 1) / 2 is the node itself.
+template <int D>
+MCH_DEV void neighbour(const int (&k)[3], int s, int (&nb)[3]) {
+  nb[2] = 1;
+  for (int ax = 0; ax < D; ++ax) {
+    nb[ax] = k[ax] + s % 3 - 1;
+    s /= 3;
+  }
+}
+
 // Block index of the block whose corner a node k is, and the block's corner
 // multi-index.
 template <int D>
@@ -170,80 +195,129 @@ MCH_DEV int block_of(const int (&k)[3], int a, int nm, int (&B)[3]) {
   return idx;
 }
 
-// Diagonal entry of unknown (interior node k; continuum j).
+// Assembled operator as nodal block rows: S[(s N + i) n + u] couples row
+// u = (node, j) to unknown (neighbour s of the node, i); it is the sum, over
+// the blocks that hold both nodes, of their element entries, and zero where
+// the neighbour lies on the boundary (U = 0 there). One thread per row;
+// consecutive rows are consecutive addresses for every (s, i).
 template <int D>
-MCH_DEV double macro_diag(const MacroArgs& m, const int (&k)[3], int j) {
-  constexpr int K = 1 << D;
-  const int N = m.N, KN = K * N;
-  double d = 0.0;
-  for (int a = 0; a < K; ++a) {
-    int B[3];
-    const int pb = block_of<D>(k, a, m.nm, B);
-    d += m.E[((size_t)pb * KN + a * N + j) * KN + a * N + j];
-  }
-  return d;
-}
-
-// The row of that unknown applied to v.
-template <int D>
-MCH_DEV double macro_row(const MacroArgs& m, const int (&k)[3], int j, const double* v) {
-  constexpr int K = 1 << D;
-  const int N = m.N, KN = K * N, ni = m.nm - 1;
-  double y = 0.0;
-  for (int a = 0; a < K; ++a) {
-    int B[3];
-    const int pb = block_of<D>(k, a, m.nm, B);
-    const double* Er = m.E + ((size_t)pb * KN + a * N + j) * KN;
-    for (int bb = 0; bb < K; ++bb) {
-      int nb[3] = {0, 0, 0};
-      for (int ax = 0; ax < D; ++ax) nb[ax] = B[ax] + ((bb >> ax) & 1);
-      const int vi = interior_index<D>(nb, ni);
-      if (vi < 0) continue;  // boundary node: U = 0
-      const double* vv = v + (size_t)vi * N;
-      for (int i = 0; i < N; ++i) y += Er[bb * N + i] * vv[i];
+__global__ __launch_bounds__(MT) void k_macro_stencil(const double* E, int nm, int N, int n, double* S) {
+  constexpr int K = 1 << D, NS = D == 2 ? 9 : 27;
+  const int u = blockIdx.x * MT + threadIdx.x;
+  if (u >= n) return;
+  const int KN = K * N, ni = nm - 1, j = u % N;
+  int k[3];
+  node_index<D>(u / N, ni, k);
+  for (int s = 0; s < NS; ++s) {
+    int nb[3];
+    neighbour<D>(k, s, nb);
+    const bool inside = interior_index<D>(nb, ni) >= 0;
+    for (int i = 0; i < N; ++i) {
+      double v = 0.0;
+      for (int a = 0; inside && a < K; ++a) {
+        int B[3];
+        const int pb = block_of<D>(k, a, nm, B);
+        int c = 0;
+        bool shared = true;
+        for (int ax = 0; ax < D; ++ax) {
+          const int o = nb[ax] - B[ax];
+          shared = shared && (o == 0 || o == 1);
+          c |= (o & 1) << ax;
+        }
+        if (shared) v += E[((size_t)pb * KN + a * N + j) * KN + c * N + i];
+      }
+      S[(size_t)(s * N + i) * n + u] = v;
     }
   }
-  return y;
 }
 
-// Jacobi-preconditioned CG in one workgroup; every thread reads the same
-// reduced scalars, so all leave the loop in the same iteration.
-template <int D>
-__global__ __launch_bounds__(CGT) void k_macro_cg(MacroArgs m) {
-  constexpr int K = 1 << D;
-  __shared__ double red[CGW];
-  const int nm = m.nm, N = m.N, ni = nm - 1;
-  int nint = 1;
-  for (int ax = 0; ax < D; ++ax) nint *= ni;
-  const int n = nint * N;
-  const int tid = threadIdx.x;
-  auto node = [&](int u, int (&k)[3], int& j) {
-    j = u % N;
-    int nd = u / N;
-    k[2] = 1;
-    for (int ax = 0; ax < D; ++ax) {
-      k[ax] = 1 + nd % ni;
-      nd /= ni;
+// Inverse of every node's N x N diagonal block (the continua at one node),
+// Dinv[(j N + i) nn + nd]. The block is symmetric positive definite, so
+// Gauss-Jordan elimination without pivoting is stable.
+template <int NB>
+__global__ __launch_bounds__(MT) void k_macro_blockinv(const double* S, int n, int centre, double* Dinv) {
+  const int nn = n / NB, nd = blockIdx.x * MT + threadIdx.x;
+  if (nd >= nn) return;
+  double a[NB][NB], x[NB][NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j)
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      a[j][i] = S[(size_t)(centre * NB + i) * n + nd * NB + j];
+      x[j][i] = i == j ? 1.0 : 0.0;
     }
-  };
-  // x = 0, r = F, z = D^-1 r, p = z
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    const double piv = 1.0 / a[c][c];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      a[c][i] *= piv;
+      x[c][i] *= piv;
+    }
+#pragma unroll
+    for (int r = 0; r < NB; ++r) {
+      if (r == c) continue;
+      const double f = a[r][c];
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        a[r][i] -= f * a[c][i];
+        x[r][i] -= f * x[c][i];
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < NB; ++j)
+#pragma unroll
+    for (int i = 0; i < NB; ++i) Dinv[(size_t)(j * NB + i) * nn + nd] = x[j][i];
+}
+
+// z = Dinv r on node nd (r given for its NB rows); returns r . z there.
+template <int NB>
+MCH_DEV double node_precond(const double* Dinv, int nn, int nd, const double (&r)[NB], double* z) {
   double rz = 0.0;
-  for (int u = tid; u < n; u += CGT) {
-    int k[3], j;
-    node(u, k, j);
-    double F = 0.0;
-    for (int a = 0; a < K; ++a) {
-      int B[3];
-      F += m.b[(size_t)block_of<D>(k, a, nm, B) * N + j] / K;
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    double zj = 0.0;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) zj += Dinv[(size_t)(j * NB + i) * nn + nd] * r[i];
+    z[(size_t)nd * NB + j] = zj;
+    rz += r[j] * zj;
+  }
+  return rz;
+}
+
+// CG preconditioned by the nodal block inverses, in one workgroup; every
+// thread reads the same reduced scalars, so all leave the loop in the same
+// iteration. The product runs one thread per row, the updates and the
+// preconditioner one thread per node.
+template <int D, int NB>
+__global__ __launch_bounds__(CGT) void k_macro_cg(MacroArgs m) {
+  constexpr int K = 1 << D, NS = D == 2 ? 9 : 27;
+  __shared__ double red[CGW];
+  const int nm = m.nm, ni = nm - 1;
+  int nn = 1;
+  for (int ax = 0; ax < D; ++ax) nn *= ni;
+  const int n = nn * NB;
+  const int tid = threadIdx.x;
+  // x = 0, r = F, z = M^-1 r, p = z
+  double rz = 0.0;
+  for (int nd = tid; nd < nn; nd += CGT) {
+    int k[3];
+    node_index<D>(nd, ni, k);
+    double F[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      F[j] = 0.0;
+      for (int a = 0; a < K; ++a) {
+        int B[3];
+        F[j] += m.b[(size_t)block_of<D>(k, a, nm, B) * NB + j] / K;
+      }
+      m.x[(size_t)nd * NB + j] = 0.0;
+      m.r[(size_t)nd * NB + j] = F[j];
     }
-    const double di = 1.0 / macro_diag<D>(m, k, j);
-    m.dinv[u] = di;
-    m.x[u] = 0.0;
-    m.r[u] = F;
-    const double zu = F * di;
-    m.z[u] = zu;
-    m.p[u] = zu;
-    rz += F * zu;
+    rz += node_precond<NB>(m.Dinv, nn, nd, F, m.z);
+#pragma unroll
+    for (int j = 0; j < NB; ++j) m.p[(size_t)nd * NB + j] = m.z[(size_t)nd * NB + j];
   }
   rz = cg_sum(rz, red);  // the barrier also publishes p
   const double rz0 = rz;
@@ -252,22 +326,33 @@ __global__ __launch_bounds__(CGT) void k_macro_cg(MacroArgs m) {
   while (!done) {
     double pq = 0.0;
     for (int u = tid; u < n; u += CGT) {
-      int k[3], j;
-      node(u, k, j);
-      const double qu = macro_row<D>(m, k, j, m.p);
+      int k[3];
+      node_index<D>(u / NB, ni, k);
+      double qu = 0.0;
+      for (int s = 0; s < NS; ++s) {
+        int nb[3];
+        neighbour<D>(k, s, nb);
+        const int vi = interior_index<D>(nb, ni);
+        if (vi < 0) continue;  // boundary node: U = 0
+#pragma unroll
+        for (int i = 0; i < NB; ++i) qu += m.S[(size_t)(s * NB + i) * n + u] * m.p[(size_t)vi * NB + i];
+      }
       m.q[u] = qu;
       pq += m.p[u] * qu;
     }
     pq = cg_sum(pq, red);
     const double al = rz / pq;
     double rzn = 0.0;
-    for (int u = tid; u < n; u += CGT) {
-      m.x[u] += al * m.p[u];
-      const double ru = m.r[u] - al * m.q[u];
-      m.r[u] = ru;
-      const double zu = ru * m.dinv[u];
-      m.z[u] = zu;
-      rzn += ru * zu;
+    for (int nd = tid; nd < nn; nd += CGT) {
+      double rr[NB];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        const size_t u = (size_t)nd * NB + j;
+        m.x[u] += al * m.p[u];
+        rr[j] = m.r[u] - al * m.q[u];
+        m.r[u] = rr[j];
+      }
+      rzn += node_precond<NB>(m.Dinv, nn, nd, rr, m.z);
     }
     rzn = cg_sum(rzn, red);
     ++it;
@@ -281,26 +366,26 @@ __global__ __launch_bounds__(CGT) void k_macro_cg(MacroArgs m) {
     __syncthreads();  // p complete before the next product
   }
   // nodal values (zero on the boundary) and block averages
-  const int nn = nm + 1;
+  const int nnp = nm + 1;
   int nnodes = 1, nblocks = 1;
   for (int ax = 0; ax < D; ++ax) {
-    nnodes *= nn;
+    nnodes *= nnp;
     nblocks *= nm;
   }
-  for (int u = tid; u < nnodes * N; u += CGT) {
-    const int j = u % N;
-    int nd = u / N, k[3] = {0, 0, 1};
+  for (int u = tid; u < nnodes * NB; u += CGT) {
+    const int j = u % NB;
+    int nd = u / NB, k[3] = {0, 0, 1};
     for (int ax = 0; ax < D; ++ax) {
-      k[ax] = nd % nn;
-      nd /= nn;
+      k[ax] = nd % nnp;
+      nd /= nnp;
     }
     const int vi = interior_index<D>(k, ni);
-    m.U[u] = vi >= 0 ? m.x[(size_t)vi * N + j] : 0.0;
+    m.U[u] = vi >= 0 ? m.x[(size_t)vi * NB + j] : 0.0;
   }
   __syncthreads();
-  for (int u = tid; u < nblocks * N; u += CGT) {
-    const int j = u % N;
-    int pb = u / N, B[3] = {0, 0, 0};
+  for (int u = tid; u < nblocks * NB; u += CGT) {
+    const int j = u % NB;
+    int pb = u / NB, B[3] = {0, 0, 0};
     for (int ax = 0; ax < D; ++ax) {
       B[ax] = pb % nm;
       pb /= nm;
@@ -310,9 +395,9 @@ __global__ __launch_bounds__(CGT) void k_macro_cg(MacroArgs m) {
       size_t idx = 0, str = 1;
       for (int ax = 0; ax < D; ++ax) {
         idx += (size_t)(B[ax] + ((c >> ax) & 1)) * str;
-        str *= nn;
+        str *= nnp;
       }
-      s += m.U[idx * N + j];
+      s += m.U[idx * NB + j];
     }
     m.Ub[u] = s / K;
   }
@@ -356,30 +441,58 @@ int launch_macro_solve(mch_plan* pl, const double* A, const double* b, double* U
     rc = hip_check(hipGetLastError(), "launch k_macro_elem");
   }
   if (rc) return rc;
-  size_t nint = (size_t)N;
-  for (int ax = 0; ax < D; ++ax) nint *= (size_t)(nm - 1);
+  size_t nn = 1;
+  for (int ax = 0; ax < D; ++ax) nn *= (size_t)(nm - 1);
+  const size_t n = nn * N;
+  const int NS = D == 2 ? 9 : 27, grid = (int)((n + MT - 1) / MT);
+  {
+    ProfScope ps(pl, "macro_stencil", s);
+    if (D == 2)
+      hipLaunchKernelGGL(k_macro_stencil<2>, dim3(grid), dim3(MT), 0, s, pl->d_macroE, nm, N, (int)n, pl->d_macroS);
+    else
+      hipLaunchKernelGGL(k_macro_stencil<3>, dim3(grid), dim3(MT), 0, s, pl->d_macroE, nm, N, (int)n, pl->d_macroS);
+    rc = hip_check(hipGetLastError(), "launch k_macro_stencil");
+  }
+  if (rc) return rc;
   MacroArgs m{};
   m.nm = nm;
-  m.N = N;
-  m.E = pl->d_macroE;
+  m.S = pl->d_macroS;
   m.b = b;
   m.x = pl->d_mvec;
-  m.r = m.x + nint;
-  m.z = m.r + nint;
-  m.p = m.z + nint;
-  m.q = m.p + nint;
-  m.dinv = m.q + nint;
+  m.r = m.x + n;
+  m.z = m.r + n;
+  m.p = m.z + n;
+  m.q = m.p + n;
+  double* dinv = m.q + n;  // [N N][nn]
+  m.Dinv = dinv;
   m.rtol = rtol;
   m.max_iter = max_iter;
   m.U = U;
   m.Ub = Ub;
   m.iters = pl->d_macro_iters;
   m.resid = pl->d_macro_resid;
+  const int ngrid = (int)((nn + MT - 1) / MT), centre = (NS - 1) / 2;
+  {
+    ProfScope ps(pl, "macro_blockinv", s);
+    if (N == 1)
+      hipLaunchKernelGGL(k_macro_blockinv<1>, dim3(ngrid), dim3(MT), 0, s, pl->d_macroS, (int)n, centre, dinv);
+    else if (N == 2)
+      hipLaunchKernelGGL(k_macro_blockinv<2>, dim3(ngrid), dim3(MT), 0, s, pl->d_macroS, (int)n, centre, dinv);
+    else
+      hipLaunchKernelGGL(k_macro_blockinv<3>, dim3(ngrid), dim3(MT), 0, s, pl->d_macroS, (int)n, centre, dinv);
+    rc = hip_check(hipGetLastError(), "launch k_macro_blockinv");
+  }
+  if (rc) return rc;
   ProfScope ps(pl, "macro_cg", s);
-  if (D == 2)
-    hipLaunchKernelGGL(k_macro_cg<2>, dim3(1), dim3(CGT), 0, s, m);
-  else
-    hipLaunchKernelGGL(k_macro_cg<3>, dim3(1), dim3(CGT), 0, s, m);
+  if (D == 2) {
+    if (N == 1) hipLaunchKernelGGL((k_macro_cg<2, 1>), dim3(1), dim3(CGT), 0, s, m);
+    else if (N == 2) hipLaunchKernelGGL((k_macro_cg<2, 2>), dim3(1), dim3(CGT), 0, s, m);
+    else hipLaunchKernelGGL((k_macro_cg<2, 3>), dim3(1), dim3(CGT), 0, s, m);
+  } else {
+    if (N == 1) hipLaunchKernelGGL((k_macro_cg<3, 1>), dim3(1), dim3(CGT), 0, s, m);
+    else if (N == 2) hipLaunchKernelGGL((k_macro_cg<3, 2>), dim3(1), dim3(CGT), 0, s, m);
+    else hipLaunchKernelGGL((k_macro_cg<3, 3>), dim3(1), dim3(CGT), 0, s, m);
+  }
   return hip_check(hipGetLastError(), "launch k_macro_cg");
 }
 

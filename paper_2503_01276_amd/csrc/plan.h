@@ -115,10 +115,12 @@ struct mch_plan {
   int32_t* d_child = nullptr;      // [P - n1] macropoint ids
   double* d_phikp = nullptr;       // 3D: Phi on the K_p nodes [P][M][(H+1)^3]
   // macroscopic system (allocated on first use): element matrices
-  // [P][2^d N][2^d N], CG vectors x, r, z, p, q and D^-1 over the interior
-  // macro nodes [(n_macro-1)^d][N], iterations and final relative residual
+  // [P][2^d N][2^d N], nodal stencil rows [3^d N][n] over the n = (n_macro-1)^d N
+  // interior unknowns, CG vectors x, r, z, p, q [n] and the inverse nodal
+  // blocks [N N][n / N], iterations and final relative residual
   double* d_macroE = nullptr;
-  double* d_mvec = nullptr;        // 6 consecutive vectors
+  double* d_macroS = nullptr;
+  double* d_mvec = nullptr;        // x, r, z, p, q, then the block inverses
   int32_t* d_macro_iters = nullptr;
   double* d_macro_resid = nullptr;
   hipStream_t macro_stream = nullptr;  // stream of the last macroscopic solve (may be the default stream)
