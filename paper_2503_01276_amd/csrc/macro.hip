@@ -28,6 +28,9 @@ namespace mch {
 constexpr int MT = 256;    // load and element kernels
 constexpr int CGT = 1024;  // the CG workgroup
 constexpr int CGW = CGT / 64;
+// LDS for the vectors of the LDS-resident CG (152 KiB of the workgroup's
+// 160 KiB; the reduction buffer takes 128 bytes).
+constexpr size_t kMacroLdsDoubles = 19 * 1024;
 
 // 2D: b[p][j] = int_{K_p} f phi_j, j < N: per fine element of K_p, |e| f_e
 // times the mean of phi_j at its four corners (exact for bilinear phi_j).
@@ -289,16 +292,32 @@ MCH_DEV double node_precond(const double* Dinv, int nn, int nd, const double (&r
 // CG preconditioned by the nodal block inverses, in one workgroup; every
 // thread reads the same reduced scalars, so all leave the loop in the same
 // iteration. The product runs one thread per row, the updates and the
-// preconditioner one thread per node.
-template <int D, int NB>
+// preconditioner one thread per node. With LV the vectors x, r, z, p, q and
+// the block inverses live in LDS (systems of up to kMacroLdsDoubles / (5 + N)
+// unknowns), so that only the stencil rows stream from the caches.
+template <int D, int NB, bool LV>
 __global__ __launch_bounds__(CGT) void k_macro_cg(MacroArgs m) {
   constexpr int K = 1 << D, NS = D == 2 ? 9 : 27;
   __shared__ double red[CGW];
+  extern __shared__ double lds_vec[];
   const int nm = m.nm, ni = nm - 1;
   int nn = 1;
   for (int ax = 0; ax < D; ++ax) nn *= ni;
   const int n = nn * NB;
   const int tid = threadIdx.x;
+  double *vx = m.x, *vr = m.r, *vz = m.z, *vp = m.p, *vq = m.q;
+  const double* dinv = m.Dinv;
+  if constexpr (LV) {
+    vx = lds_vec;
+    vr = vx + n;
+    vz = vr + n;
+    vp = vz + n;
+    vq = vp + n;
+    double* dl = vq + n;
+    for (int k = tid; k < NB * n; k += CGT) dl[k] = m.Dinv[k];
+    dinv = dl;
+    __syncthreads();
+  }
   // x = 0, r = F, z = M^-1 r, p = z
   double rz = 0.0;
   for (int nd = tid; nd < nn; nd += CGT) {
@@ -312,12 +331,12 @@ __global__ __launch_bounds__(CGT) void k_macro_cg(MacroArgs m) {
         int B[3];
         F[j] += m.b[(size_t)block_of<D>(k, a, nm, B) * NB + j] / K;
       }
-      m.x[(size_t)nd * NB + j] = 0.0;
-      m.r[(size_t)nd * NB + j] = F[j];
+      vx[(size_t)nd * NB + j] = 0.0;
+      vr[(size_t)nd * NB + j] = F[j];
     }
-    rz += node_precond<NB>(m.Dinv, nn, nd, F, m.z);
+    rz += node_precond<NB>(dinv, nn, nd, F, vz);
 #pragma unroll
-    for (int j = 0; j < NB; ++j) m.p[(size_t)nd * NB + j] = m.z[(size_t)nd * NB + j];
+    for (int j = 0; j < NB; ++j) vp[(size_t)nd * NB + j] = vz[(size_t)nd * NB + j];
   }
   rz = cg_sum(rz, red);  // the barrier also publishes p
   const double rz0 = rz;
@@ -335,10 +354,10 @@ __global__ __launch_bounds__(CGT) void k_macro_cg(MacroArgs m) {
         const int vi = interior_index<D>(nb, ni);
         if (vi < 0) continue;  // boundary node: U = 0
 #pragma unroll
-        for (int i = 0; i < NB; ++i) qu += m.S[(size_t)(s * NB + i) * n + u] * m.p[(size_t)vi * NB + i];
+        for (int i = 0; i < NB; ++i) qu += m.S[(size_t)(s * NB + i) * n + u] * vp[(size_t)vi * NB + i];
       }
-      m.q[u] = qu;
-      pq += m.p[u] * qu;
+      vq[u] = qu;
+      pq += vp[u] * qu;
     }
     pq = cg_sum(pq, red);
     const double al = rz / pq;
@@ -348,11 +367,11 @@ __global__ __launch_bounds__(CGT) void k_macro_cg(MacroArgs m) {
 #pragma unroll
       for (int j = 0; j < NB; ++j) {
         const size_t u = (size_t)nd * NB + j;
-        m.x[u] += al * m.p[u];
-        rr[j] = m.r[u] - al * m.q[u];
-        m.r[u] = rr[j];
+        vx[u] += al * vp[u];
+        rr[j] = vr[u] - al * vq[u];
+        vr[u] = rr[j];
       }
-      rzn += node_precond<NB>(m.Dinv, nn, nd, rr, m.z);
+      rzn += node_precond<NB>(dinv, nn, nd, rr, vz);
     }
     rzn = cg_sum(rzn, red);
     ++it;
@@ -362,7 +381,7 @@ __global__ __launch_bounds__(CGT) void k_macro_cg(MacroArgs m) {
     }
     const double be = rzn / rz;
     rz = rzn;
-    for (int u = tid; u < n; u += CGT) m.p[u] = m.z[u] + be * m.p[u];
+    for (int u = tid; u < n; u += CGT) vp[u] = vz[u] + be * vp[u];
     __syncthreads();  // p complete before the next product
   }
   // nodal values (zero on the boundary) and block averages
@@ -380,7 +399,7 @@ __global__ __launch_bounds__(CGT) void k_macro_cg(MacroArgs m) {
       nd /= nnp;
     }
     const int vi = interior_index<D>(k, ni);
-    m.U[u] = vi >= 0 ? m.x[(size_t)vi * NB + j] : 0.0;
+    m.U[u] = vi >= 0 ? vx[(size_t)vi * NB + j] : 0.0;
   }
   __syncthreads();
   for (int u = tid; u < nblocks * NB; u += CGT) {
@@ -483,17 +502,28 @@ int launch_macro_solve(mch_plan* pl, const double* A, const double* b, double* U
     rc = hip_check(hipGetLastError(), "launch k_macro_blockinv");
   }
   if (rc) return rc;
-  ProfScope ps(pl, "macro_cg", s);
+  const size_t lds_doubles = (5 + (size_t)N) * n;
+  const bool lv = lds_doubles <= kMacroLdsDoubles;
+  const size_t lds = lv ? lds_doubles * sizeof(double) : 0;
+  auto go = [&](auto kernel) -> int {
+    if (lds > 0) {
+      const int e = hip_check(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
+                              "hipFuncSetAttribute");
+      if (e) return e;
+    }
+    ProfScope ps(pl, "macro_cg", s);
+    hipLaunchKernelGGL(kernel, dim3(1), dim3(CGT), lds, s, m);
+    return hip_check(hipGetLastError(), "launch k_macro_cg");
+  };
   if (D == 2) {
-    if (N == 1) hipLaunchKernelGGL((k_macro_cg<2, 1>), dim3(1), dim3(CGT), 0, s, m);
-    else if (N == 2) hipLaunchKernelGGL((k_macro_cg<2, 2>), dim3(1), dim3(CGT), 0, s, m);
-    else hipLaunchKernelGGL((k_macro_cg<2, 3>), dim3(1), dim3(CGT), 0, s, m);
-  } else {
-    if (N == 1) hipLaunchKernelGGL((k_macro_cg<3, 1>), dim3(1), dim3(CGT), 0, s, m);
-    else if (N == 2) hipLaunchKernelGGL((k_macro_cg<3, 2>), dim3(1), dim3(CGT), 0, s, m);
-    else hipLaunchKernelGGL((k_macro_cg<3, 3>), dim3(1), dim3(CGT), 0, s, m);
+    if (N == 1) return lv ? go(k_macro_cg<2, 1, true>) : go(k_macro_cg<2, 1, false>);
+    if (N == 2) return lv ? go(k_macro_cg<2, 2, true>) : go(k_macro_cg<2, 2, false>);
+    return lv ? go(k_macro_cg<2, 3, true>) : go(k_macro_cg<2, 3, false>);
   }
-  return hip_check(hipGetLastError(), "launch k_macro_cg");
+  if (N == 1) return lv ? go(k_macro_cg<3, 1, true>) : go(k_macro_cg<3, 1, false>);
+  if (N == 2) return lv ? go(k_macro_cg<3, 2, true>) : go(k_macro_cg<3, 2, false>);
+  return lv ? go(k_macro_cg<3, 3, true>) : go(k_macro_cg<3, 3, false>);
 }
 
 }  // namespace mch
