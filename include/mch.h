@@ -175,6 +175,10 @@ int mch_macro_load(mch_plan* plan, const double* f, double* b, void* hip_stream)
  * mch_macro_load); U: [(n_macro+1)^d][n_cont] nodal values (node
  * k1 + (n_macro+1) (k2 + (n_macro+1) k3)), U_block: [P][n_cont] block
  * averages, device outputs.
+ * Systems of up to 19456 / (5 + n_cont) unknowns are solved by one
+ * workgroup with its vectors in LDS; larger ones by one cooperative launch
+ * over the device (at most two workgroups per CU) with a fixed-order
+ * grid-wide reduction, so the result is bitwise reproducible either way.
  * The plan allocates the solve's scratch on the first call (host-synchronous
  * then); otherwise asynchronous. MCH_EINVAL for bad arguments. */
 int mch_macro_solve(mch_plan* plan, const double* A_eff, const double* b, double* U, double* U_block,

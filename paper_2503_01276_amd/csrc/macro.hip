@@ -21,6 +21,11 @@
 // each node, which the CG applies. The CG runs in one workgroup: the macro systems of
 // the workloads here have a few thousand unknowns, and one workgroup needs no
 // device-wide synchronisation (at 2048^2 it is bound by one CU's bandwidth).
+#include <hip/hip_cooperative_groups.h>
+
+#include <algorithm>
+#include <cstdlib>
+
 #include "kernels2d.h"
 
 namespace mch {
@@ -29,8 +34,14 @@ constexpr int MT = 256;    // load and element kernels
 constexpr int CGT = 1024;  // the CG workgroup
 constexpr int CGW = CGT / 64;
 // LDS for the vectors of the LDS-resident CG (152 KiB of the workgroup's
-// 160 KiB; the reduction buffer takes 128 bytes).
+// 160 KiB; the reduction buffers take 256 bytes).
 constexpr size_t kMacroLdsDoubles = 19 * 1024;
+// The grid-wide CG: threads per workgroup, and its default number of
+// workgroups (its grid barriers cost in proportion to the workgroups, its
+// stencil stream wants many threads in flight; measured best near 64 x 1024).
+constexpr int GGT = 1024;
+constexpr int GGW = GGT / 64;
+constexpr int kMacroGridDefault = 64;
 
 // 2D: b[p][j] = int_{K_p} f phi_j, j < N: per fine element of K_p, |e| f_e
 // times the mean of phi_j at its four corners (exact for bilinear phi_j).
@@ -127,15 +138,16 @@ __global__ __launch_bounds__(MT) void k_macro_elem(const double* A, int N, doubl
   }
 }
 
-// Sum over the workgroup in a fixed order; every thread gets the result.
+// Sum over the workgroup in a fixed order; every thread gets the result. The
+// buffer may be written again only after a later barrier (the CG alternates
+// two buffers, and each sum is followed by at least one other barrier before
+// its buffer comes round again).
 MCH_DEV double cg_sum(double v, double* red) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   v = wave_sum(v);
   if (lane == 0) red[wave] = v;
   __syncthreads();
-  const double t = tree_sum<CGW, 1>(red);
-  __syncthreads();  // red is reused by the next sum
-  return t;
+  return tree_sum<CGW, 1>(red);
 }
 
 struct MacroArgs {
@@ -144,6 +156,7 @@ struct MacroArgs {
   const double* Dinv;  // inverse diagonal blocks [N N][n / N]
   const double* b;     // [P][N]
   double *x, *r, *z, *p, *q;
+  double* sv;  // s = A p of the grid-wide CG
   double rtol;
   int max_iter;
   double* U;   // [(nm+1)^D][N]
@@ -292,32 +305,27 @@ MCH_DEV double node_precond(const double* Dinv, int nn, int nd, const double (&r
 // CG preconditioned by the nodal block inverses, in one workgroup; every
 // thread reads the same reduced scalars, so all leave the loop in the same
 // iteration. The product runs one thread per row, the updates and the
-// preconditioner one thread per node. With LV the vectors x, r, z, p, q and
-// the block inverses live in LDS (systems of up to kMacroLdsDoubles / (5 + N)
+// preconditioner one thread per node. The vectors x, r, z, p, q and the block
+// inverses live in LDS (systems of up to kMacroLdsDoubles / (5 + N)
 // unknowns), so that only the stencil rows stream from the caches.
-template <int D, int NB, bool LV>
+template <int D, int NB>
 __global__ __launch_bounds__(CGT) void k_macro_cg(MacroArgs m) {
   constexpr int K = 1 << D, NS = D == 2 ? 9 : 27;
-  __shared__ double red[CGW];
+  __shared__ double red[2][CGW];  // alternating reduction buffers
   extern __shared__ double lds_vec[];
   const int nm = m.nm, ni = nm - 1;
   int nn = 1;
   for (int ax = 0; ax < D; ++ax) nn *= ni;
   const int n = nn * NB;
   const int tid = threadIdx.x;
-  double *vx = m.x, *vr = m.r, *vz = m.z, *vp = m.p, *vq = m.q;
-  const double* dinv = m.Dinv;
-  if constexpr (LV) {
-    vx = lds_vec;
-    vr = vx + n;
-    vz = vr + n;
-    vp = vz + n;
-    vq = vp + n;
-    double* dl = vq + n;
-    for (int k = tid; k < NB * n; k += CGT) dl[k] = m.Dinv[k];
-    dinv = dl;
-    __syncthreads();
-  }
+  double* vx = lds_vec;
+  double* vr = vx + n;
+  double* vz = vr + n;
+  double* vp = vz + n;
+  double* vq = vp + n;
+  double* dinv = vq + n;
+  for (int k = tid; k < NB * n; k += CGT) dinv[k] = m.Dinv[k];
+  __syncthreads();
   // x = 0, r = F, z = M^-1 r, p = z
   double rz = 0.0;
   for (int nd = tid; nd < nn; nd += CGT) {
@@ -338,7 +346,7 @@ __global__ __launch_bounds__(CGT) void k_macro_cg(MacroArgs m) {
 #pragma unroll
     for (int j = 0; j < NB; ++j) vp[(size_t)nd * NB + j] = vz[(size_t)nd * NB + j];
   }
-  rz = cg_sum(rz, red);  // the barrier also publishes p
+  rz = cg_sum(rz, red[0]);  // the barrier also publishes p
   const double rz0 = rz;
   int it = 0;
   bool done = !(rz0 > 0.0);
@@ -359,7 +367,7 @@ __global__ __launch_bounds__(CGT) void k_macro_cg(MacroArgs m) {
       vq[u] = qu;
       pq += vp[u] * qu;
     }
-    pq = cg_sum(pq, red);
+    pq = cg_sum(pq, red[1]);
     const double al = rz / pq;
     double rzn = 0.0;
     for (int nd = tid; nd < nn; nd += CGT) {
@@ -373,7 +381,7 @@ __global__ __launch_bounds__(CGT) void k_macro_cg(MacroArgs m) {
       }
       rzn += node_precond<NB>(dinv, nn, nd, rr, vz);
     }
-    rzn = cg_sum(rzn, red);
+    rzn = cg_sum(rzn, red[0]);
     ++it;
     if (rzn <= m.rtol * m.rtol * rz0 || it >= m.max_iter) {
       rz = rzn;
@@ -423,6 +431,167 @@ __global__ __launch_bounds__(CGT) void k_macro_cg(MacroArgs m) {
   if (tid == 0) {
     *m.iters = it;
     *m.resid = rz0 > 0.0 ? sqrt(fmax(rz, 0.0) / rz0) : 0.0;
+  }
+}
+
+// The CG over the whole grid for systems that do not fit in LDS: one
+// cooperative launch, vectors in global memory, rows and nodes strided over
+// all threads. A grid barrier costs in proportion to the number of
+// workgroups, so the loop is the single-reduction form of preconditioned CG
+// of Chronopoulos and Gear (1989), which carries s = A p alongside p and
+// reduces r.z and (A z).z together: two grid barriers per iteration (z
+// published for the product, the fused sum) against four. In exact
+// arithmetic its iterates are those of the loop above. The fused sum stores
+// each workgroup's two sums in part[2 block + {0, 1}]; after the barrier every
+// wave adds part[] lane-strided and across its lanes in a fixed order, so all
+// waves of all workgroups hold bitwise the same scalars and leave the loop in
+// the same iteration, after the same number of barriers.
+MCH_DEV void grid_sum2(double& a, double& b, double* part, double (*red)[GGW], cooperative_groups::grid_group& grid) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  a = wave_sum(a);
+  b = wave_sum(b);
+  if (lane == 0) {
+    red[0][wave] = a;
+    red[1][wave] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = tree_sum<GGW, 1>(red[0]);
+    part[2 * blockIdx.x + 1] = tree_sum<GGW, 1>(red[1]);
+  }
+  grid.sync();
+  double sa = 0.0, sb = 0.0;
+  for (int k = lane; k < (int)gridDim.x; k += 64) {
+    sa += part[2 * k];
+    sb += part[2 * k + 1];
+  }
+  a = wave_sum(sa);
+  b = wave_sum(sb);
+}
+
+template <int D, int NB>
+__global__ __launch_bounds__(GGT) void k_macro_cg_grid(MacroArgs m, double* part) {
+  constexpr int K = 1 << D, NS = D == 2 ? 9 : 27;
+  __shared__ double red[2][GGW];
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  const int nm = m.nm, ni = nm - 1;
+  int nn = 1;
+  for (int ax = 0; ax < D; ++ax) nn *= ni;
+  const int n = nn * NB;
+  const int g0 = blockIdx.x * GGT + threadIdx.x, gs = gridDim.x * GGT;
+  // w = A z on this thread's rows; returns its share of w.z
+  auto product = [&]() -> double {
+    double wz = 0.0;
+    for (int u = g0; u < n; u += gs) {
+      int k[3];
+      node_index<D>(u / NB, ni, k);
+      double wu = 0.0;
+      for (int s = 0; s < NS; ++s) {
+        int nb[3];
+        neighbour<D>(k, s, nb);
+        const int vi = interior_index<D>(nb, ni);
+        if (vi < 0) continue;  // boundary node: U = 0
+#pragma unroll
+        for (int i = 0; i < NB; ++i) wu += m.S[(size_t)(s * NB + i) * n + u] * m.z[(size_t)vi * NB + i];
+      }
+      m.q[u] = wu;
+      wz += wu * m.z[u];
+    }
+    return wz;
+  };
+  // x = 0, r = F, z = M^-1 r
+  double g = 0.0;
+  for (int nd = g0; nd < nn; nd += gs) {
+    int k[3];
+    node_index<D>(nd, ni, k);
+    double F[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      F[j] = 0.0;
+      for (int a = 0; a < K; ++a) {
+        int B[3];
+        F[j] += m.b[(size_t)block_of<D>(k, a, nm, B) * NB + j] / K;
+      }
+      m.x[(size_t)nd * NB + j] = 0.0;
+      m.r[(size_t)nd * NB + j] = F[j];
+    }
+    g += node_precond<NB>(m.Dinv, nn, nd, F, m.z);
+  }
+  grid.sync();  // z complete before the product
+  double dl = product();
+  grid_sum2(g, dl, part, red, grid);
+  const double g0r = g;
+  double gam = g, al = dl != 0.0 ? g / dl : 0.0, be = 0.0;
+  int it = 0;
+  bool done = !(g0r > 0.0);
+  while (!done) {
+    // p = z + be p, s = w + be s (w in q), x += al p, r -= al s, z = M^-1 r
+    double gn = 0.0;
+    for (int nd = g0; nd < nn; nd += gs) {
+      double rr[NB];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        const size_t u = (size_t)nd * NB + j;
+        const double pu = it == 0 ? m.z[u] : m.z[u] + be * m.p[u];
+        const double su = it == 0 ? m.q[u] : m.q[u] + be * m.sv[u];
+        m.p[u] = pu;
+        m.sv[u] = su;
+        m.x[u] += al * pu;
+        rr[j] = m.r[u] - al * su;
+        m.r[u] = rr[j];
+      }
+      gn += node_precond<NB>(m.Dinv, nn, nd, rr, m.z);
+    }
+    grid.sync();  // z complete before the product
+    double dn = product();
+    grid_sum2(gn, dn, part, red, grid);
+    ++it;
+    if (gn <= m.rtol * m.rtol * g0r || it >= m.max_iter) {
+      gam = gn;
+      break;
+    }
+    be = gn / gam;
+    al = gn / (dn - be * gn / al);
+    gam = gn;
+  }
+  const int nnp = nm + 1;
+  int nnodes = 1, nblocks = 1;
+  for (int ax = 0; ax < D; ++ax) {
+    nnodes *= nnp;
+    nblocks *= nm;
+  }
+  for (int u = g0; u < nnodes * NB; u += gs) {
+    const int j = u % NB;
+    int nd = u / NB, k[3] = {0, 0, 1};
+    for (int ax = 0; ax < D; ++ax) {
+      k[ax] = nd % nnp;
+      nd /= nnp;
+    }
+    const int vi = interior_index<D>(k, ni);
+    m.U[u] = vi >= 0 ? m.x[(size_t)vi * NB + j] : 0.0;
+  }
+  grid.sync();
+  for (int u = g0; u < nblocks * NB; u += gs) {
+    const int j = u % NB;
+    int pb = u / NB, B[3] = {0, 0, 0};
+    for (int ax = 0; ax < D; ++ax) {
+      B[ax] = pb % nm;
+      pb /= nm;
+    }
+    double sum = 0.0;
+    for (int c = 0; c < K; ++c) {
+      size_t idx = 0, str = 1;
+      for (int ax = 0; ax < D; ++ax) {
+        idx += (size_t)(B[ax] + ((c >> ax) & 1)) * str;
+        str *= nnp;
+      }
+      sum += m.U[idx * NB + j];
+    }
+    m.Ub[u] = sum / K;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *m.iters = it;
+    *m.resid = g0r > 0.0 ? sqrt(fmax(gam, 0.0) / g0r) : 0.0;
   }
 }
 
@@ -483,6 +652,7 @@ int launch_macro_solve(mch_plan* pl, const double* A, const double* b, double* U
   m.p = m.z + n;
   m.q = m.p + n;
   double* dinv = m.q + n;  // [N N][nn]
+  m.sv = dinv + (size_t)N * n;
   m.Dinv = dinv;
   m.rtol = rtol;
   m.max_iter = max_iter;
@@ -503,27 +673,55 @@ int launch_macro_solve(mch_plan* pl, const double* A, const double* b, double* U
   }
   if (rc) return rc;
   const size_t lds_doubles = (5 + (size_t)N) * n;
-  const bool lv = lds_doubles <= kMacroLdsDoubles;
-  const size_t lds = lv ? lds_doubles * sizeof(double) : 0;
-  auto go = [&](auto kernel) -> int {
-    if (lds > 0) {
-      const int e = hip_check(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
-                              "hipFuncSetAttribute");
+  if (lds_doubles <= kMacroLdsDoubles) {
+    const size_t lds = lds_doubles * sizeof(double);
+    auto go = [&](auto kernel) -> int {
+      int e = hip_check(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
+                        "hipFuncSetAttribute");
       if (e) return e;
+      ProfScope ps(pl, "macro_cg", s);
+      hipLaunchKernelGGL(kernel, dim3(1), dim3(CGT), lds, s, m);
+      return hip_check(hipGetLastError(), "launch k_macro_cg");
+    };
+    if (D == 2) {
+      if (N == 1) return go(k_macro_cg<2, 1>);
+      if (N == 2) return go(k_macro_cg<2, 2>);
+      return go(k_macro_cg<2, 3>);
     }
+    if (N == 1) return go(k_macro_cg<3, 1>);
+    if (N == 2) return go(k_macro_cg<3, 2>);
+    return go(k_macro_cg<3, 3>);
+  }
+  // grid-wide: kMacroGridDefault workgroups of GGT threads (fewer if the rows
+  // need fewer), all co-resident
+  int cus = 0;
+  rc = hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, pl->device), "hipDeviceGetAttribute");
+  if (rc) return rc;
+  auto go_grid = [&](auto kernel) -> int {
+    const void* fn = reinterpret_cast<const void*>(kernel);
+    int per_cu = 0;
+    int e = hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, GGT, 0), "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+    if (e) return e;
+    if (per_cu < 1) return set_error(MCH_EINVAL, "the grid-wide macroscopic CG cannot be resident");
+    size_t want = (n + GGT - 1) / GGT;
+    if (const char* v = std::getenv("MCH_MACRO_GRID")) want = std::max(1, std::atoi(v));  // tuning override
+    else want = std::min<size_t>(want, kMacroGridDefault);
+    const int grid = (int)std::min<size_t>(want, (size_t)cus * per_cu);
+    if (grid > kMacroGridMax) return set_error(MCH_EINVAL, "grid-wide macroscopic CG: too many workgroups");
+    double* part = pl->d_mpart;
+    void* args[] = {&m, &part};
     ProfScope ps(pl, "macro_cg", s);
-    hipLaunchKernelGGL(kernel, dim3(1), dim3(CGT), lds, s, m);
-    return hip_check(hipGetLastError(), "launch k_macro_cg");
+    return hip_check(hipLaunchCooperativeKernel(fn, dim3(grid), dim3(GGT), args, 0, s), "hipLaunchCooperativeKernel");
   };
   if (D == 2) {
-    if (N == 1) return lv ? go(k_macro_cg<2, 1, true>) : go(k_macro_cg<2, 1, false>);
-    if (N == 2) return lv ? go(k_macro_cg<2, 2, true>) : go(k_macro_cg<2, 2, false>);
-    return lv ? go(k_macro_cg<2, 3, true>) : go(k_macro_cg<2, 3, false>);
+    if (N == 1) return go_grid(k_macro_cg_grid<2, 1>);
+    if (N == 2) return go_grid(k_macro_cg_grid<2, 2>);
+    return go_grid(k_macro_cg_grid<2, 3>);
   }
-  if (N == 1) return lv ? go(k_macro_cg<3, 1, true>) : go(k_macro_cg<3, 1, false>);
-  if (N == 2) return lv ? go(k_macro_cg<3, 2, true>) : go(k_macro_cg<3, 2, false>);
-  return lv ? go(k_macro_cg<3, 3, true>) : go(k_macro_cg<3, 3, false>);
+  if (N == 1) return go_grid(k_macro_cg_grid<3, 1>);
+  if (N == 2) return go_grid(k_macro_cg_grid<3, 2>);
+  return go_grid(k_macro_cg_grid<3, 3>);
 }
 
 }  // namespace mch

@@ -615,7 +615,8 @@ int mch::ensure_macro_scratch(mch_plan* p) {
   const size_t nint = (size_t)ipow(p->nm - 1, p->dim) * p->cfg.n_cont;
   int rc = dev_alloc(p, &p->d_macroE, (size_t)p->P * KN * KN);
   if (!rc) rc = dev_alloc(p, &p->d_macroS, (size_t)ipow(3, p->dim) * p->cfg.n_cont * nint);
-  if (!rc) rc = dev_alloc(p, &p->d_mvec, (5 + (size_t)p->cfg.n_cont) * nint);
+  if (!rc) rc = dev_alloc(p, &p->d_mvec, (6 + (size_t)p->cfg.n_cont) * nint);
+  if (!rc) rc = dev_alloc(p, &p->d_mpart, 2 * (size_t)kMacroGridMax);
   if (!rc) rc = dev_alloc(p, &p->d_macro_iters, 1);
   if (!rc) rc = dev_alloc(p, &p->d_macro_resid, 1);
   return rc;

@@ -11,6 +11,9 @@
 namespace mch {
 
 constexpr int MAX_LEVELS = 8;
+// Most workgroups of the grid-wide macroscopic CG (each of its two
+// partial-sum buffers holds one value per workgroup).
+constexpr int kMacroGridMax = 4096;
 
 // Kernel shape chosen for one level's cells.
 struct KernelShape {
@@ -116,11 +119,13 @@ struct mch_plan {
   double* d_phikp = nullptr;       // 3D: Phi on the K_p nodes [P][M][(H+1)^3]
   // macroscopic system (allocated on first use): element matrices
   // [P][2^d N][2^d N], nodal stencil rows [3^d N][n] over the n = (n_macro-1)^d N
-  // interior unknowns, CG vectors x, r, z, p, q [n] and the inverse nodal
-  // blocks [N N][n / N], iterations and final relative residual
+  // interior unknowns, CG vectors x, r, z, p, q [n], the inverse nodal
+  // blocks [N N][n / N] and s [n] (the grid-wide CG), iterations and final
+  // relative residual
   double* d_macroE = nullptr;
   double* d_macroS = nullptr;
-  double* d_mvec = nullptr;        // x, r, z, p, q, then the block inverses
+  double* d_mvec = nullptr;        // x, r, z, p, q, the block inverses, s
+  double* d_mpart = nullptr;       // 2 x kMacroGridMax partial sums (grid-wide CG)
   int32_t* d_macro_iters = nullptr;
   double* d_macro_resid = nullptr;
   hipStream_t macro_stream = nullptr;  // stream of the last macroscopic solve (may be the default stream)

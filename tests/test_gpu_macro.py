@@ -227,9 +227,10 @@ def test_type1_type2_errors_against_the_fine_solution(hier, flat, with_oracle):
 
 @pytest.mark.parametrize("dim,n_fine,n_macro,n_cell", [(2, 1024, 64, 32), (3, 64, 16, 16)])
 def test_macro_solve_large_macrogrid(dim, n_fine, n_macro, n_cell):
-    # more unknowns than the LDS-resident CG holds (7938 in 2D, 6750 in 3D),
-    # so the solve keeps its vectors in global memory; seeded SPD tensors
-    # A_p = R R^T + I/2 stand in for A_eff (the system is SPD for any SPD A_p)
+    # more unknowns than the one-workgroup CG holds in LDS (7938 in 2D, 6750
+    # in 3D), so the solve runs grid-wide with its vectors in global memory;
+    # seeded SPD tensors A_p = R R^T + I/2 stand in for A_eff (the system is
+    # SPD for any SPD A_p)
     from paper_2503_01276_amd import mch
 
     cfg = W.Config(dim=dim, n_fine=n_fine, n_macro=n_macro, n_cell=n_cell, n_sub=2, n_cont=2, levels=1)
@@ -240,4 +241,4 @@ def test_macro_solve_large_macrogrid(dim, n_fine, n_macro, n_cell):
     b = rng.standard_normal((P, cfg.n_cont))
     U, Ub, it, rs = _gpu_macro(mch.Plan(cfg), _dev(A), _dev(b))
     say(f"[gpu] macro {dim}D {n_macro}^{dim} blocks: {it} CG iterations, relative residual {rs:.2e}")
-    _check(f"macro {dim}D {n_macro}^{dim} (global-memory vectors)", cfg, U, Ub, A, b, True)
+    _check(f"macro {dim}D {n_macro}^{dim} (grid-wide CG)", cfg, U, Ub, A, b, True)
