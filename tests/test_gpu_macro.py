@@ -225,20 +225,34 @@ def test_type1_type2_errors_against_the_fine_solution(hier, flat, with_oracle):
         assert np.allclose(t1, r1, rtol=1e-8) and np.allclose(t2, r2, rtol=1e-8), (t1, r1, t2, r2)
 
 
-@pytest.mark.parametrize("dim,n_fine,n_macro,n_cell", [(2, 1024, 64, 32), (3, 64, 16, 16)])
-def test_macro_solve_large_macrogrid(dim, n_fine, n_macro, n_cell):
-    # more unknowns than the one-workgroup CG holds in LDS (7938 in 2D, 6750
-    # in 3D), so the solve runs grid-wide with its vectors in global memory;
-    # seeded SPD tensors A_p = R R^T + I/2 stand in for A_eff (the system is
-    # SPD for any SPD A_p)
+_MACRO_CASES = {
+    # one-workgroup CG with LDS vectors
+    "2d_N1": dict(dim=2, n_fine=64, n_macro=8, n_cell=16, n_cont=1),
+    "2d_N3": dict(dim=2, n_fine=128, n_macro=16, n_cell=64, n_cont=3),
+    "2d_one_node": dict(dim=2, n_fine=16, n_macro=2, n_cell=16, n_cont=2),
+    "3d_N1": dict(dim=3, n_fine=32, n_macro=4, n_cell=16, n_cont=1),
+    "3d_N3": dict(dim=3, n_fine=32, n_macro=4, n_cell=16, n_cont=3),
+    # more unknowns than the one-workgroup CG holds in LDS (7938, 6750 and
+    # 2883 with N = 3): the grid-wide CG with its vectors in global memory
+    "2d_grid": dict(dim=2, n_fine=1024, n_macro=64, n_cell=32, n_cont=2),
+    "3d_grid": dict(dim=3, n_fine=64, n_macro=16, n_cell=16, n_cont=2),
+    "2d_grid_N3": dict(dim=2, n_fine=256, n_macro=32, n_cell=64, n_cont=3),
+}
+
+
+@pytest.mark.parametrize("case", list(_MACRO_CASES))
+def test_macro_solve_shapes(case):
+    # seeded SPD tensors A_p = R R^T + I/2 stand in for A_eff (the assembled
+    # system is SPD for any SPD A_p); GPU against the oracle's direct solve
     from paper_2503_01276_amd import mch
 
-    cfg = W.Config(dim=dim, n_fine=n_fine, n_macro=n_macro, n_cell=n_cell, n_sub=2, n_cont=2, levels=1)
-    P, M = cfg.n_points, cfg.n_cont * (1 + dim)
-    rng = np.random.default_rng(31 + dim)
+    cfg = W.Config(n_sub=2, levels=1, **_MACRO_CASES[case])
+    P, M = cfg.n_points, cfg.n_cont * (1 + cfg.dim)
+    rng = np.random.default_rng(31 + cfg.dim + 10 * cfg.n_cont + cfg.n_macro)
     R = rng.standard_normal((P, M, M))
     A = R @ R.transpose(0, 2, 1) + 0.5 * np.eye(M)
     b = rng.standard_normal((P, cfg.n_cont))
     U, Ub, it, rs = _gpu_macro(mch.Plan(cfg), _dev(A), _dev(b))
-    say(f"[gpu] macro {dim}D {n_macro}^{dim} blocks: {it} CG iterations, relative residual {rs:.2e}")
-    _check(f"macro {dim}D {n_macro}^{dim} (grid-wide CG)", cfg, U, Ub, A, b, True)
+    say(f"[gpu] macro {case}: {it} CG iterations, relative residual {rs:.2e}")
+    _check(f"macro {case}", cfg, U, Ub, A, b, True)
+    assert np.all(U.reshape((cfg.n_macro + 1,) * cfg.dim + (cfg.n_cont,))[(0,) * cfg.dim] == 0.0)
