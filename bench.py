@@ -134,7 +134,7 @@ def cpu_baseline(name: str, workers: int):
         solves = len(pts) * cfg.n_rhs
         return {"value": solves / (t1 - t0), "unit": "cell-solves/s", "cores": workers, "kind": "oracle",
                 "sample": f"{len(pts)} cells of {len(groups)} whole level-1 group(s) of {name} ({solves} solves), "
-                          f"SciPy SuperLU forward only, {t1 - t0:.2f} s, one process per core"}
+                          f"SciPy SuperLU forward only, {t1 - t0:.2f} s, one process per core"}, None
     kt, _ = W.medium(name, channel_factor=W.target_factor(4))
     T = oracle.stack_A(oracle.forward(cfg, kt, l, workers=workers), cfg)
     t0 = time.perf_counter()
@@ -142,7 +142,7 @@ def cpu_baseline(name: str, workers: int):
     A = oracle.stack_A(fwd, cfg)
     t1 = time.perf_counter()
     gA = {p: 2.0 * (A[p] - T[p]) for p in range(cfg.n_points)}
-    oracle.backward(cfg, k, l, fwd, gA, workers=workers)
+    g = oracle.backward(cfg, k, l, fwd, gA, workers=workers)
     t2 = time.perf_counter()
     solves = cfg.n_points * cfg.n_rhs
     return {
@@ -152,7 +152,7 @@ def cpu_baseline(name: str, workers: int):
         "kind": "oracle",
         "sample": f"full {name} workload ({solves} solves): SciPy SuperLU forward {t1 - t0:.2f} s + "
                   f"adjoint {t2 - t1:.2f} s, one process per core",
-    }
+    }, {"A": A, "g": g}
 
 
 class Runner:
@@ -329,10 +329,10 @@ def main():
         copy_probe(args.copy_probe)
         return
 
-    cpu = None
+    cpu, oracle_ref = None, None
     if not args.no_cpu_baseline:
         workers = args.cpu_workers or min(16, os.cpu_count() or 1)
-        cpu = cpu_baseline(args.workload, workers)
+        cpu, oracle_ref = cpu_baseline(args.workload, workers)
         print(f"[bench] cpu baseline: {cpu['value']:.1f} solves/s on {workers} cores", file=sys.stderr, flush=True)
 
     run = Runner(args.workload)
@@ -398,6 +398,20 @@ def main():
                       "dof_ratio": sum(int((lev == n + 1).sum()) * free_dof(n) for n in range(cfg.levels)) /
                                    (plan.P * free_dof(0))},
     }
+    if oracle_ref is not None:
+        # the timed run's own outputs (same inputs every step) against the
+        # oracle's on the full workload: per-point relative Frobenius error of
+        # A_eff (worst point) and relative 2-norm error of dLoss/dlog kappa
+        P, M = plan.P, plan.M
+        Ag = run.A.cpu().numpy().reshape(P, M, M)
+        gg = run.g.cpu().numpy()
+        Ar = oracle_ref["A"]
+        eA = float(max(np.linalg.norm(Ag[p] - Ar[p]) / np.linalg.norm(Ar[p]) for p in range(P)))
+        gr = np.asarray(oracle_ref["g"]).reshape(-1)  # x1 fastest, as the device field
+        eg = float(np.linalg.norm(gg - gr) / np.linalg.norm(gr))
+        detail["rel_err_vs_oracle"] = {"A_eff_worst_point": eA, "grad_log_kappa": eg}
+        print(f"[bench] relative error against the oracle: A_eff {eA:.2e} (worst point), gradient {eg:.2e}",
+              file=sys.stderr, flush=True)
     flat = args.flat or {"c2": "c2flat", "c2ml": "c2flat", "c3": "c3flat"}.get(args.workload)
     if flat == "none":
         flat = None
