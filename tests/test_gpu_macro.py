@@ -256,3 +256,31 @@ def test_macro_solve_shapes(case):
     say(f"[gpu] macro {case}: {it} CG iterations, relative residual {rs:.2e}")
     _check(f"macro {case}", cfg, U, Ub, A, b, True)
     assert np.all(U.reshape((cfg.n_macro + 1,) * cfg.dim + (cfg.n_cont,))[(0,) * cfg.dim] == 0.0)
+
+
+@pytest.mark.parametrize("case", ["2d_N3", "2d_grid"])
+def test_macro_solve_reports_no_convergence(case):
+    # a host-forced stop: max_iter = 3 ends both CG variants after three
+    # iterations (every thread leaves together) and the diagnostics call
+    # reports MCH_ENOCONV; the next solve with a normal budget converges
+    import torch
+
+    from paper_2503_01276_amd import mch
+
+    cfg = W.Config(n_sub=2, levels=1, **_MACRO_CASES[case])
+    P, M, N = cfg.n_points, cfg.n_cont * (1 + cfg.dim), cfg.n_cont
+    rng = np.random.default_rng(77)
+    R = rng.standard_normal((P, M, M))
+    A = _dev(R @ R.transpose(0, 2, 1) + 0.5 * np.eye(M))
+    b = _dev(rng.standard_normal((P, N)))
+    dev = torch.device("cuda:0")
+    U = torch.empty((cfg.n_macro + 1) ** cfg.dim * N, dtype=torch.float64, device=dev)
+    Ub = torch.empty(P * N, dtype=torch.float64, device=dev)
+    plan = mch.Plan(cfg)
+    plan.macro_solve(A, b, U, Ub, rtol=1e-13, max_iter=3)
+    with pytest.raises(mch.MchError) as e:
+        plan.macro_diagnostics()
+    assert "ENOCONV" in str(e.value)
+    U, Ub, it, rs = _gpu_macro(plan, A, b)
+    say(f"[gpu] macro {case}: stopped at 3 iterations as asked, then {it} iterations to {rs:.2e}")
+    assert it > 3 and rs <= 1e-13
