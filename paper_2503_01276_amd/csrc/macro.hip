@@ -18,9 +18,10 @@
 // fastest), continuum j at (node index) N + j. Element matrices
 // E_p[(a, j), (b, i)] (index a N + j, corners a in tensor order) are formed
 // once per solve and summed into nodal block rows over the 3^d neighbours of
-// each node, which the CG applies. The CG runs in one workgroup: the macro systems of
-// the workloads here have a few thousand unknowns, and one workgroup needs no
-// device-wide synchronisation (at 2048^2 it is bound by one CU's bandwidth).
+// each node, which the CG applies. Systems whose vectors fit in LDS (a few
+// thousand unknowns, as on the 512^2 and 128^3 grids) are solved by one
+// workgroup, which needs no device-wide synchronisation; larger ones by one
+// cooperative launch over the device with grid barriers.
 #include <hip/hip_cooperative_groups.h>
 
 #include <algorithm>
