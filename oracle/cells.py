@@ -14,6 +14,11 @@ fine stiffness with kappa of this cell, B_h the fine constraint rows, g the
 constraint right-hand sides, and I the inherited fine solution (the type-2
 right-hand side uses phi^m_{i,t}; the paper's printed phi_{i,t} there is a typo).
 
+Boundary conditions on the cell: homogeneous Dirichlet (bc = 0, the
+configured workloads) or natural Neumann conditions (bc = 1, every node free;
+K_n is then singular on constants, and the KKT matrix stays regular because
+the constraint rows do not vanish on constants).
+
 The KKT matrix is factored with SciPy's SuperLU and every solve takes one step
 of iterative refinement. The effective tensor (Eq. Bs_defi, with R_p = K_p so
 |K_p|/|R_p| = 1) is A_{ab} = Phi_a^T K_h^{K_p} Phi_b, the K_p-restricted
@@ -62,12 +67,12 @@ def assemble_cell(cfg, kappa, label, p: int, level: int) -> CellSystem:
     lc = fem.window(label, org, nc)
     K = fem.assemble_stiffness(kc, h)
     B, g, _ = fem.constraints(lc, cfg.n_sub, cfg.n_cont, cfg.H_el, h)
-    free = fem.free_nodes(nc, dim)
+    free = fem.free_nodes(nc, dim, cfg.bc)
     Kf = K[free][:, free].tocsr()
     Bf = B[:, free]
     r = cfg.eta ** (level - 1)
     Pfull = fem.prolongation(nc, r, dim)
-    cfree = fem.free_nodes(nc // r, dim)
+    cfree = fem.free_nodes(nc // r, dim, cfg.bc)
     P = Pfull[free][:, cfree].tocsr()
     Kn = (P.T @ Kf @ P).tocsr()
     Bn = np.asarray(Bf @ P)  # dense [m, n_coarse_free]

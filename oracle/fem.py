@@ -71,9 +71,12 @@ def element_coords(nc: int, dim: int) -> np.ndarray:
     return np.stack([g.reshape(-1) for g in reversed(grids)], axis=1)
 
 
-def free_nodes(nc: int, dim: int) -> np.ndarray:
-    """Interior nodes (homogeneous Dirichlet on the cell boundary)."""
+def free_nodes(nc: int, dim: int, bc: int = 0) -> np.ndarray:
+    """Free nodes: the interior ones for homogeneous Dirichlet data on the cell
+    boundary (bc = 0), every node for natural (Neumann) conditions (bc = 1)."""
     nn = nc + 1
+    if bc == 1:
+        return np.arange(nn ** dim)
     grids = np.meshgrid(*([np.arange(nn)] * dim), indexing="ij")
     b = [g.reshape(-1) for g in reversed(grids)]
     mask = np.ones(nn ** dim, bool)
