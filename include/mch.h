@@ -121,7 +121,9 @@ int mch_build_interp(const mch_config* cfg, int32_t* nbr, double* weight);
  * info[0] = P (macropoints), info[1] = M (right-hand sides per macropoint),
  * info[2] = m (constraint rows per cell, including inactive ones),
  * info[3] = L, info[4..4+L) = number of macropoints of each level,
- * info[4+L..] unused. info must hold at least 16 entries. */
+ * info[4+L..4+2L) = node rows per thread of each level's 2D solve kernel (the
+ * size-class shape: the workgroup has NC^2 / rows threads; 0 in 3D), the
+ * rest zero. info must hold at least 20 entries (4 + 2 * 8 levels). */
 int mch_plan_info(const mch_plan* plan, int64_t* info);
 
 /* Level (1..L) and the level-1 macropoint of its group (-1 for level 1) of

@@ -661,12 +661,15 @@ extern "C" int mch_build_interp(const mch_config* cfg, int32_t* nbr, double* wei
 
 extern "C" int mch_plan_info(const mch_plan* p, int64_t* info) {
   if (!p || !info) return set_error(MCH_EINVAL, "null argument");
-  for (int k = 0; k < 16; ++k) info[k] = 0;
+  for (int k = 0; k < 4 + 2 * MAX_LEVELS; ++k) info[k] = 0;
   info[0] = p->P;
   info[1] = p->M;
   info[2] = p->m;
   info[3] = p->L;
-  for (int l = 0; l < p->L && 4 + l < 16; ++l) info[4 + l] = p->lev[l].count;
+  for (int l = 0; l < p->L; ++l) {
+    info[4 + l] = p->lev[l].count;
+    info[4 + p->L + l] = p->lev[l].shape.rpt;
+  }
   return MCH_OK;
 }
 
