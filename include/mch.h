@@ -133,25 +133,30 @@ int mch_hierarchy(const mch_plan* plan, int32_t* level, int32_t* parent);
 
 /* Algorithm 1 steps 3-5 (Sec. 3.3): solve every cell problem, level by level,
  * in the hierarchical form (inherited solution plus correction in V_n).
- * kappa: [n_fine^d] f64 > 0, finite; label: [n_fine^d] u8 < n_cont.
- * Values are not validated on the device. Asynchronous on hip_stream.
- * Returns MCH_ENOCONV only from mch_diagnostics; here errors are launch errors. */
+ * kappa: [n_fine^d] f64 > 0, finite; label: [n_fine^d] u8 < n_cont. A
+ * device-side check of both runs first in the same launch sequence; a
+ * violation is reported as MCH_EINVAL by mch_diagnostics (the call itself
+ * stays asynchronous). Asynchronous on hip_stream. Returns MCH_ENOCONV only
+ * from mch_diagnostics; here errors are argument and launch errors. */
 int mch_solve_cells(mch_plan* plan, const double* kappa, const uint8_t* label, void* hip_stream);
 
 /* Effective tensors (Eq. Bs_defi with R_p = K_p): A_eff[p][a][b] =
  * sum over fine elements e of K_p of kappa_e Phi_a|_e^T K_ref Phi_b|_e for the
  * M local solutions of macropoint p. kappa must be the array passed to the
- * last mch_solve_cells. A_eff: [P][M][M] f64 device array. Asynchronous.
- * MCH_ESTALE if no forward solve has been issued on this plan. */
+ * last mch_solve_cells (MCH_EINVAL otherwise). A_eff: [P][M][M] f64 device
+ * array. Asynchronous. MCH_ESTALE if no forward solve has been issued on
+ * this plan. */
 int mch_effective_coeffs(mch_plan* plan, const double* kappa, double* A_eff, void* hip_stream);
 
 /* Adjoint of mch_effective_coeffs o mch_solve_cells: given gA[p][a][b] =
  * dLoss/dA_eff[p][a][b], writes glogk[e] = dLoss/dlog(kappa_e) for every
  * fine element (the gradient flows through the local solutions, through the
  * inherited solutions of the lower levels, and through the explicit kappa in
- * the tensors). Uses the state of the most recent forward on this plan; kappa
- * must be that forward's array. gA: [P][M][M], glogk: [n_fine^d] f64 device.
- * Asynchronous. MCH_ESTALE if no forward solve has been issued. */
+ * the tensors). Uses the state of the most recent forward on this plan,
+ * including its kappa and label arrays, which must still hold the forward's
+ * values; kappa must be that forward's array (MCH_EINVAL otherwise).
+ * gA: [P][M][M], glogk: [n_fine^d] f64 device. Asynchronous. MCH_ESTALE if
+ * no forward solve has been issued. */
 int mch_effective_coeffs_backward(mch_plan* plan, const double* kappa, const double* gA,
                                   double* glogk, void* hip_stream);
 
@@ -200,8 +205,21 @@ int mch_local_solutions(mch_plan* plan, const int64_t* cells, int64_t n, double*
 /* Per (macropoint, right-hand side) Krylov iteration count and final relative
  * projected residual of the most recent forward solve, into host arrays of
  * length P*M. Synchronous (waits for the plan's last stream). Returns
- * MCH_ENOCONV when any solve stopped at max_iter. */
+ * MCH_EINVAL when the forward's kappa was not positive and finite or a label
+ * was >= n_cont on some fine element (the message names the first one; the
+ * forward checks its inputs on the device before the cell kernels, and its
+ * results are then meaningless); otherwise the verdict of
+ * mch_classify_solves on the records (MCH_ESINGULAR, MCH_ENOCONV or MCH_OK). */
 int mch_diagnostics(const mch_plan* plan, int32_t* iters, double* resid);
+
+/* Host-only rule by which mch_diagnostics and mch_adjoint_diagnostics judge
+ * their per-solve records: MCH_ESINGULAR if any iteration count is negative
+ * (a singular constraint Schur matrix), else MCH_ENOCONV if any residual is
+ * not finite (NaN: the recurrence left the finite numbers) or a solve stopped
+ * at max_iter with a residual above rtol, else MCH_OK. iters and resid are
+ * host arrays of n entries owned by the caller. Synchronous; MCH_EINVAL for
+ * null arrays with n > 0 or n < 0. */
+int mch_classify_solves(const int32_t* iters, const double* resid, int64_t n, int32_t max_iter, double rtol);
 
 /* Measurement hook. mode 1 turns profiling on, 0 off; either clears the
  * records. While on, every kernel launch of the plan is bracketed by HIP

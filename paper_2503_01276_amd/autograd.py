@@ -26,12 +26,14 @@ class HierHomog(torch.autograd.Function):
         ctx.plan = plan
         ctx.generation = plan.generation
         ctx.shape = log_kappa.shape
-        ctx.save_for_backward(kappa)
+        # the adjoint kernels read the forward's kappa and labels: keep both
+        # arrays alive (and at the addresses the forward used) until backward
+        ctx.save_for_backward(kappa, lab)
         return A.view(plan.P, plan.M, plan.M)
 
     @staticmethod
     def backward(ctx, gA: torch.Tensor):
-        (kappa,) = ctx.saved_tensors
+        kappa, _lab = ctx.saved_tensors
         plan = ctx.plan
         if plan.generation != ctx.generation:
             raise mch.MchError(mch.MCH_ESTALE, "backward after a newer forward on the same plan")

@@ -10,11 +10,13 @@ using namespace mch;
 // match the captured ones; otherwise captures `issue` afresh. The legacy
 // default stream cannot be captured, so calls on it (and profiled calls)
 // run eagerly.
+// The key holds every device pointer the captured kernels read or write,
+// including those a call takes from the plan (the forward's label array).
 template <typename F>
-static int run_graph(mch_plan* p, mch_plan::Graph& g, const void* k0, const void* k1, const void* k2, hipStream_t s,
-                     F issue) {
+static int run_graph(mch_plan* p, mch_plan::Graph& g, const void* k0, const void* k1, const void* k2,
+                     const void* k3, hipStream_t s, F issue) {
   if (!p->use_graphs || p->profiling || s == nullptr) return issue();
-  if (g.exec && g.stream == s && g.key[0] == k0 && g.key[1] == k1 && g.key[2] == k2)
+  if (g.exec && g.stream == s && g.key[0] == k0 && g.key[1] == k1 && g.key[2] == k2 && g.key[3] == k3)
     return hip_check(hipGraphLaunch(g.exec, s), "hipGraphLaunch");
   if (g.exec) (void)hipGraphExecDestroy(g.exec);
   if (g.graph) (void)hipGraphDestroy(g.graph);
@@ -39,6 +41,7 @@ static int run_graph(mch_plan* p, mch_plan::Graph& g, const void* k0, const void
   g.key[0] = k0;
   g.key[1] = k1;
   g.key[2] = k2;
+  g.key[3] = k3;
   return hip_check(hipGraphLaunch(g.exec, s), "hipGraphLaunch");
 }
 
@@ -55,7 +58,11 @@ extern "C" int mch_solve_cells(mch_plan* p, const double* kappa, const uint8_t* 
   int rc = enter(p, stream, &s);
   if (rc) return rc;
   if (!kappa || !label) return set_error(MCH_EINVAL, "null kappa or label");
-  rc = run_graph(p, p->g_fwd, kappa, label, nullptr, s, [&] { return p->dim == 3 ? launch_forward_3d(p, kappa, label, s) : launch_forward_2d(p, kappa, label, s); });
+  rc = run_graph(p, p->g_fwd, kappa, label, nullptr, nullptr, s, [&] {
+    int r = launch_validate(p, kappa, label, s);
+    if (r) return r;
+    return p->dim == 3 ? launch_forward_3d(p, kappa, label, s) : launch_forward_2d(p, kappa, label, s);
+  });
   if (rc) return rc;
   p->forward_done = 1;
   p->fwd_kappa = kappa;
@@ -70,7 +77,9 @@ extern "C" int mch_effective_coeffs(mch_plan* p, const double* kappa, double* A,
   if (rc) return rc;
   if (!kappa || !A) return set_error(MCH_EINVAL, "null kappa or A_eff");
   if (!p->forward_done) return set_error(MCH_ESTALE, "no forward solve has been issued on this plan");
-  rc = run_graph(p, p->g_eff, kappa, A, p->fwd_label, s, [&] { return p->dim == 3 ? launch_eff_3d(p, kappa, A, s) : launch_eff_2d(p, kappa, A, s); });
+  if (kappa != p->fwd_kappa)
+    return set_error(MCH_EINVAL, "kappa is not the array of the most recent forward solve on this plan");
+  rc = run_graph(p, p->g_eff, kappa, A, p->fwd_label, nullptr, s, [&] { return p->dim == 3 ? launch_eff_3d(p, kappa, A, s) : launch_eff_2d(p, kappa, A, s); });
   if (!rc) p->last_stream = s;
   return rc;
 }
@@ -82,7 +91,10 @@ extern "C" int mch_effective_coeffs_backward(mch_plan* p, const double* kappa, c
   if (rc) return rc;
   if (!kappa || !gA || !glogk) return set_error(MCH_EINVAL, "null argument");
   if (!p->forward_done) return set_error(MCH_ESTALE, "no forward solve has been issued on this plan");
-  rc = run_graph(p, p->g_bwd, kappa, gA, glogk, s, [&] {
+  // the adjoint reads the forward's local solutions, labels and kappa
+  if (kappa != p->fwd_kappa)
+    return set_error(MCH_EINVAL, "kappa is not the array of the most recent forward solve on this plan");
+  rc = run_graph(p, p->g_bwd, kappa, gA, glogk, p->fwd_label, s, [&] {
     return p->dim == 3 ? launch_backward_3d(p, kappa, gA, glogk, s) : launch_backward_2d(p, kappa, gA, glogk, s);
   });
   if (!rc) p->last_stream = s;

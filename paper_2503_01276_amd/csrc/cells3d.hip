@@ -1100,7 +1100,7 @@ __global__ __launch_bounds__((nt3<NC, GAL>())) void k_solve3d(CellArgs a) {
   }
   if (tid == 0) {
     a.iters[(size_t)p * M + alpha] = (rz0 == rz0) ? it : -1;
-    a.resid[(size_t)p * M + alpha] = (rz0 > 0.0) ? sqrt(fmax(rz, 0.0) / rz0) : 0.0;
+    a.resid[(size_t)p * M + alpha] = rel_resid(rz, rz0);
   }
 }
 

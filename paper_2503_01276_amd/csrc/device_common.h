@@ -105,6 +105,14 @@ MCH_DEV double tree_sum(const double* x) {
   }
 }
 
+// Relative residual sqrt(rz / rz0) of a preconditioned recurrence. NaN when
+// either value is NaN, so that a solve whose recurrence turned non-finite is
+// never reported as converged; 0 for a zero right-hand side (rz0 = 0).
+MCH_DEV double rel_resid(double rz, double rz0) {
+  if (rz != rz || rz0 != rz0) return __builtin_nan("");
+  return rz0 > 0.0 ? sqrt(fmax(rz, 0.0) / rz0) : 0.0;
+}
+
 // Value held by lane+1 (0 for the last lane of a group of `width` lanes).
 MCH_DEV double from_right(double v, int c, int width) {
   const double t = dpp_f64<DPP_WAVE_SHL1>(v);

@@ -431,7 +431,7 @@ __global__ __launch_bounds__(CGT) void k_macro_cg(MacroArgs m) {
   }
   if (tid == 0) {
     *m.iters = it;
-    *m.resid = rz0 > 0.0 ? sqrt(fmax(rz, 0.0) / rz0) : 0.0;
+    *m.resid = rel_resid(rz, rz0);
   }
 }
 
@@ -592,7 +592,7 @@ __global__ __launch_bounds__(GGT) void k_macro_cg_grid(MacroArgs m, double* part
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     *m.iters = it;
-    *m.resid = g0r > 0.0 ? sqrt(fmax(gam, 0.0) / g0r) : 0.0;
+    *m.resid = rel_resid(gam, g0r);
   }
 }
 

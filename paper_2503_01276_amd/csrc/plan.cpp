@@ -311,6 +311,8 @@ extern "C" const char* mch_last_error(void) { return g_last_error.c_str(); }
 
 extern "C" void mch_destroy(mch_plan* plan) {
   if (!plan) return;
+  // the plan's streams, graphs and memory belong to its device
+  (void)hipSetDevice(plan->device);
   (void)hipDeviceSynchronize();
   for (auto* g : {&plan->g_fwd, &plan->g_eff, &plan->g_bwd}) {
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
@@ -387,6 +389,25 @@ extern "C" int mch_build_levels(const mch_config* cfg, mch_plan** out) {
     return set_error(MCH_ESINGULAR, "over-constrained: " + std::to_string(c.n_cont * ipow(c.n_sub, d)) +
                                         " constraint rows but " + std::to_string(free_coarsest) +
                                         " free unknowns at the coarsest level");
+  }
+  // kernel shapes per level, checked before any device work so that a
+  // configuration without a kernel fails the same way with or without a GPU
+  for (int l = 0; l < p->L; ++l) {
+    const int r = ipow(c.eta, l), NCl = nc / r, sbw = nc / c.n_sub / r;
+    if (d == 3) {
+      if (!shape_supported_3d(NCl, c.n_sub, c.n_cont)) {
+        delete p;
+        return set_error(MCH_ENOTIMPL, "no 3D kernel instantiated for level cell width " + std::to_string(NCl) +
+                                           " n_sub=" + std::to_string(c.n_sub) + " N=" + std::to_string(c.n_cont));
+      }
+      continue;
+    }
+    const int rpt = default_rpt(NCl, sbw);
+    if (rpt == 0 || !shape_supported_2d(NCl, rpt, c.n_cont, r > 1, c.n_sub)) {
+      delete p;
+      return set_error(MCH_ENOTIMPL, "no kernel instantiated for level cell width " + std::to_string(NCl) +
+                                         " rows/thread " + std::to_string(rpt) + " N=" + std::to_string(c.n_cont));
+    }
   }
   if (const char* v = std::getenv("MCH_GRAPHS")) p->use_graphs = std::atoi(v) != 0;
   if (const char* v = std::getenv("MCH_SERIAL")) p->serial = std::atoi(v) != 0;
@@ -522,6 +543,7 @@ extern "C" int mch_build_levels(const mch_config* cfg, mch_plan** out) {
   if (!rc) rc = dev_alloc(p, &p->d_mu, P * M * m);
   if (!rc) rc = dev_alloc(p, &p->d_iters, P * M);
   if (!rc) rc = dev_alloc(p, &p->d_resid, P * M);
+  if (!rc) rc = dev_alloc(p, &p->d_bad, (size_t)kValidateBlocks);
   if (!rc) rc = upload(p, &p->d_slot, p->slot);
   if (!rc) rc = dev_alloc(p, &p->d_seed_kp, P * M * (size_t)ipow(H + 1, d));
   if (!rc) rc = dev_alloc(p, &p->d_seed_par, n1 * M * (size_t)p->nn);
@@ -630,7 +652,7 @@ extern "C" int mch_macro_diagnostics(const mch_plan* p, int32_t* iters, double* 
   if (!rc) rc = hip_check(hipMemcpy(iters, p->d_macro_iters, sizeof(int32_t), hipMemcpyDeviceToHost), "hipMemcpy");
   if (!rc) rc = hip_check(hipMemcpy(resid, p->d_macro_resid, sizeof(double), hipMemcpyDeviceToHost), "hipMemcpy");
   if (rc) return rc;
-  if (*iters >= p->macro_max_iter && !(*resid <= p->macro_rtol))
+  if (!std::isfinite(*resid) || (*iters >= p->macro_max_iter && !(*resid <= p->macro_rtol)))
     return set_error(MCH_ENOCONV, "the macroscopic solve reached max_iter before rtol");
   return MCH_OK;
 }
@@ -687,6 +709,15 @@ static int diagnostics_impl(const mch_plan* p, int32_t* iters, double* resid, bo
   if (rc) return rc;
   rc = hip_check(hipStreamSynchronize(p->last_stream), "hipStreamSynchronize");
   if (rc) return rc;
+  long long bad[kValidateBlocks];
+  rc = hip_check(hipMemcpy(bad, p->d_bad, sizeof(bad), hipMemcpyDeviceToHost), "hipMemcpy");
+  if (rc) return rc;
+  long long first = -1;
+  for (long long b : bad)
+    if (b >= 0 && (first < 0 || b < first)) first = b;
+  if (first >= 0)
+    return set_error(MCH_EINVAL, "kappa must be positive and finite and labels below n_cont; first offending "
+                                 "fine element " + std::to_string(first));
   size_t cnt = (size_t)p->P * p->M;
   rc = hip_check(hipMemcpy(iters, adjoint ? p->d_iters_adj : p->d_iters, cnt * sizeof(int32_t), hipMemcpyDeviceToHost),
                  "hipMemcpy");
@@ -694,12 +725,21 @@ static int diagnostics_impl(const mch_plan* p, int32_t* iters, double* resid, bo
   rc = hip_check(hipMemcpy(resid, adjoint ? p->d_resid_adj : p->d_resid, cnt * sizeof(double), hipMemcpyDeviceToHost),
                  "hipMemcpy");
   if (rc) return rc;
-  for (size_t k = 0; k < cnt; ++k) {
-    if (iters[k] < 0) return set_error(MCH_ESINGULAR, "singular constraint Schur matrix in a cell");
+  return mch_classify_solves(iters, resid, (int64_t)cnt, p->cfg.max_iter, p->cfg.rtol);
+}
+
+extern "C" int mch_classify_solves(const int32_t* iters, const double* resid, int64_t n, int32_t max_iter,
+                                   double rtol) {
+  if (n < 0 || (n > 0 && (!iters || !resid))) return set_error(MCH_EINVAL, "bad solve record arrays");
+  for (int64_t k = 0; k < n; ++k) {
+    if (iters[k] < 0)
+      return set_error(MCH_ESINGULAR, "singular constraint Schur matrix in a cell (solve " + std::to_string(k) + ")");
   }
-  for (size_t k = 0; k < cnt; ++k) {
-    if (iters[k] >= p->cfg.max_iter && !(resid[k] <= p->cfg.rtol))
-      return set_error(MCH_ENOCONV, "a cell solve reached max_iter before rtol");
+  for (int64_t k = 0; k < n; ++k) {
+    // a solve whose recurrence turned non-finite reports resid NaN
+    if (!std::isfinite(resid[k]) || (iters[k] >= max_iter && !(resid[k] <= rtol)))
+      return set_error(MCH_ENOCONV, "a cell solve reached max_iter before rtol or its residual is not finite "
+                                    "(solve " + std::to_string(k) + ")");
   }
   return MCH_OK;
 }

@@ -14,6 +14,8 @@ constexpr int MAX_LEVELS = 8;
 // Most workgroups of the grid-wide macroscopic CG (each of its two
 // partial-sum buffers holds one value per workgroup).
 constexpr int kMacroGridMax = 4096;
+// Workgroups of the input check (one result slot each).
+constexpr int kValidateBlocks = 256;
 
 // Kernel shape chosen for one level's cells.
 struct KernelShape {
@@ -105,6 +107,9 @@ struct mch_plan {
   int32_t* d_iters = nullptr;
   double* d_resid = nullptr;
   int32_t* d_slot = nullptr;
+  // input check of the last forward: per workgroup the first fine element
+  // with kappa not positive and finite or a label >= n_cont, or -1
+  long long* d_bad = nullptr;
   // adjoint scratch
   double* d_seed_kp = nullptr;   // [P][M][(H+1)^d]
   double* d_seed_par = nullptr;  // [n1][M][nn]
@@ -203,6 +208,8 @@ inline hipStream_t level_stream2(const mch_plan* p, int l, hipStream_t s) { retu
 int hip_check(hipError_t e, const char* what);
 
 // Launchers implemented in the .hip translation units.
+// Input check of kappa and labels (results read by mch_diagnostics).
+int launch_validate(mch_plan* p, const double* kappa, const uint8_t* label, hipStream_t s);
 int launch_forward_2d(mch_plan* p, const double* kappa, const uint8_t* label, hipStream_t s);
 int launch_eff_2d(mch_plan* p, const double* kappa, double* A, hipStream_t s);
 int launch_backward_2d(mch_plan* p, const double* kappa, const double* gA, double* glogk, hipStream_t s);

@@ -7,8 +7,11 @@ import of this module fails loudly: there is no CPU fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import sys
+import weakref
 
 import numpy as np
 
@@ -21,7 +24,7 @@ CODE_NAMES = {MCH_EINVAL: "MCH_EINVAL", MCH_ESINGULAR: "MCH_ESINGULAR", MCH_ENOC
 
 EXPORTS = ["mch_build_levels", "mch_build_hierarchy", "mch_build_interp", "mch_plan_info", "mch_hierarchy", "mch_solve_cells", "mch_effective_coeffs",
            "mch_effective_coeffs_backward", "mch_local_solutions", "mch_diagnostics", "mch_adjoint_diagnostics", "mch_profile",
-           "mch_profile_read", "mch_macro_load", "mch_macro_solve", "mch_macro_diagnostics", "mch_destroy",
+           "mch_profile_read", "mch_classify_solves", "mch_macro_load", "mch_macro_solve", "mch_macro_diagnostics", "mch_destroy",
            "mch_last_error"]
 
 
@@ -73,6 +76,7 @@ def _load():
     lib.mch_adjoint_diagnostics.argtypes = [vp, i32p, dp]
     lib.mch_profile.argtypes = [vp, ctypes.c_int32]
     lib.mch_profile_read.argtypes = [vp, ctypes.c_int32, ctypes.c_char_p, ctypes.c_int32, dp]
+    lib.mch_classify_solves.argtypes = [i32p, dp, ctypes.c_int64, ctypes.c_int32, ctypes.c_double]
     lib.mch_macro_load.argtypes = [vp, vp, vp, vp]
     lib.mch_macro_solve.argtypes = [vp, vp, vp, vp, vp, ctypes.c_double, ctypes.c_int32, vp]
     lib.mch_macro_diagnostics.argtypes = [vp, i32p, dp]
@@ -86,6 +90,22 @@ def _load():
 
 
 LIB = _load()
+
+# Plans still open when the interpreter exits are released by an exit hook,
+# which runs while torch's runtime is still up (hooks run in reverse order of
+# registration, and torch is imported before this one is registered).
+_LIVE = weakref.WeakSet()
+
+
+def _close_all():
+    for plan in list(_LIVE):
+        try:
+            plan.close()
+        except Exception:
+            pass
+
+
+atexit.register(_close_all)
 
 
 def check(rc: int):
@@ -128,6 +148,15 @@ def build_interp(cfg):
     return nbr, w
 
 
+def classify_solves(iters, resid, max_iter: int, rtol: float) -> int:
+    """Status code the library's diagnostics give to per-solve records (host only)."""
+    it = np.ascontiguousarray(iters, dtype=np.int32).reshape(-1)
+    rs = np.ascontiguousarray(resid, dtype=np.float64).reshape(-1)
+    return LIB.mch_classify_solves(it.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                   rs.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), it.size, int(max_iter),
+                                   float(rtol))
+
+
 def _ptr(t) -> ctypes.c_void_p:
     return ctypes.c_void_p(t.data_ptr())
 
@@ -158,14 +187,28 @@ class Plan:
         # node rows per thread of each level's 2D solve kernel (0 in 3D)
         self.rows_per_thread = [int(info[4 + self.levels + k]) for k in range(self.levels)]
         self.generation = 0  # bumped by every forward solve
+        _LIVE.add(self)
 
     def close(self):
+        """Release the plan (mch_destroy). Call it before the interpreter exits."""
         if getattr(self, "_h", None):
             if getattr(self, "_pid", None) == os.getpid():
                 LIB.mch_destroy(self._h)
             self._h = None
 
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
     def __del__(self):
+        # During interpreter shutdown the HIP runtime and torch's streams may
+        # already be torn down: make no HIP call then (the process exit
+        # releases the device memory).
+        if sys.is_finalizing():
+            self._h = None
+            return
         try:
             self.close()
         except Exception:

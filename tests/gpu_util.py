@@ -55,6 +55,48 @@ def A_rel_err(gpu: np.ndarray, ref: np.ndarray) -> np.ndarray:
 PHI_TOL = 1e-8
 A_TOL = 1e-9
 GRAD_TOL = 1e-8
+# Element-wise gradient bar: |g_e - gref_e| <= GRAD_TOL * max(|gref_e|, GRAD_FLOOR * max|gref|).
+# An element's error comes from the solver's error in the local solutions,
+# whose size follows the field's scale, not the element's own value (inside
+# a high-conductivity channel the solutions are nearly constant and g_e is
+# small while the error of its gradient terms is not); below the floor the
+# bar is absolute.
+GRAD_FLOOR = 1e-3
+
+
+def grad_errors(g: np.ndarray, gref: np.ndarray, label: np.ndarray | None = None, floor: float = GRAD_FLOOR):
+    """Gradient parity measures: relative 2-norm over the field, the worst
+    element-wise ratio |g - gref| / max(|gref|, floor * max|gref|) (<= 1 means
+    within 1e-8 of the bar above when divided by GRAD_TOL), the same ratio at
+    other floors for the record, and relative 2-norms per continuum."""
+    g = np.asarray(g, np.float64).reshape(-1)
+    gref = np.asarray(gref, np.float64).reshape(-1)
+    d = np.abs(g - gref)
+    scale = np.abs(gref).max()
+    out = {"rel2": float(np.linalg.norm(g - gref) / np.linalg.norm(gref)),
+           "elem": float((d / np.maximum(np.abs(gref), floor * scale)).max()),
+           "elem_by_floor": {f: float((d / np.maximum(np.abs(gref), f * scale)).max())
+                             for f in (1e-9, 1e-6, 1e-5, 1e-4, 1e-3)},
+           "max_abs_over_max": float(d.max() / scale)}
+    if label is not None:
+        lab = np.asarray(label).reshape(-1)
+        out["per_continuum"] = {int(j): float(np.linalg.norm((g - gref)[lab == j]) /
+                                              max(np.linalg.norm(gref[lab == j]), 1e-300))
+                                for j in np.unique(lab)}
+    return out
+
+
+def assert_grad(name: str, g, gref, label=None):
+    e = grad_errors(g, gref, label)
+    say(f"[gpu] {name}: grad rel err {e['rel2']:.3e}, worst element-wise {e['elem']:.3e} "
+        f"(floor {GRAD_FLOOR:g}; by floor {', '.join(f'{f:g}: {v:.2e}' for f, v in e['elem_by_floor'].items())}), "
+        f"max|dg|/max|g| {e['max_abs_over_max']:.2e}, per continuum "
+        f"{ {j: f'{v:.2e}' for j, v in e.get('per_continuum', {}).items()} }")
+    assert e["rel2"] <= GRAD_TOL, e
+    assert e["elem"] <= GRAD_TOL, e
+    for j, v in e.get("per_continuum", {}).items():
+        assert v <= GRAD_TOL, (j, e)
+    return e
 
 
 def check_forward(name, cfg, k, l, phi_cells, a_points=None, workers=None):
@@ -119,7 +161,6 @@ def grad_case(name, cfg, seed, workers=1):
     plan.effective_coeffs_backward(kd, gAd, gd)
     torch.cuda.synchronize()
     g = gd.cpu().numpy()
-    err = np.linalg.norm(g - gref) / np.linalg.norm(gref)
-    say(f"[gpu] {name}: grad rel err {err:.3e} (|g| = {np.linalg.norm(gref):.3e})")
-    assert err <= GRAD_TOL, err
+    plan.close()
+    assert_grad(name, g, gref, l)
     return g, gref

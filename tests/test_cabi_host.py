@@ -76,6 +76,29 @@ def test_invalid_configurations():
     _expect(good.replace(rtol=0.0), mch.MCH_EINVAL)
     # over-constrained coarsest level: 2 x 2 sub-blocks x 2 continua = 8 rows, 1 free node
     _expect(W.Config(dim=2, n_fine=64, n_macro=8, n_cell=8, n_sub=2, n_cont=2, levels=3), mch.MCH_ESINGULAR)
+    # level widths without a solve kernel (checked before any device work):
+    # 16/8/4 (no workgroup of whole waves for a 4^2 cell) and 48/24/12
+    _expect(W.Config(dim=2, n_fine=64, n_macro=8, n_cell=16, n_sub=2, n_cont=2, levels=3), mch.MCH_ENOTIMPL)
+    _expect(W.Config(dim=2, n_fine=192, n_macro=12, n_cell=48, n_sub=2, n_cont=2, levels=3), mch.MCH_ENOTIMPL)
+    _expect(W.Config(dim=3, n_fine=64, n_macro=8, n_cell=24, n_sub=2, n_cont=2, levels=1), mch.MCH_ENOTIMPL)
+
+
+def test_classify_solves_rule():
+    # the verdict of mch_diagnostics on synthetic per-solve records
+    cs = mch.classify_solves
+    ok_it, ok_rs = np.array([5, 17, 3]), np.array([1e-13, 5e-13, 0.0])
+    assert cs(ok_it, ok_rs, 100, 1e-12) == mch.MCH_OK
+    assert cs(np.array([5, -1, 3]), ok_rs, 100, 1e-12) == mch.MCH_ESINGULAR
+    # stopped at max_iter above rtol; at max_iter but converged is fine
+    assert cs(np.array([5, 100, 3]), np.array([1e-13, 2e-12, 0.0]), 100, 1e-12) == mch.MCH_ENOCONV
+    assert cs(np.array([5, 100, 3]), np.array([1e-13, 1e-12, 0.0]), 100, 1e-12) == mch.MCH_OK
+    # a non-finite residual is never converged, whatever the iteration count
+    assert cs(ok_it, np.array([1e-13, np.nan, 0.0]), 100, 1e-12) == mch.MCH_ENOCONV
+    assert cs(ok_it, np.array([np.inf, 0.0, 0.0]), 100, 1e-12) == mch.MCH_ENOCONV
+    # a singular record outranks a non-converged one
+    assert cs(np.array([100, -1]), np.array([np.nan, 0.0]), 100, 1e-12) == mch.MCH_ESINGULAR
+    assert cs(np.zeros(0), np.zeros(0), 100, 1e-12) == mch.MCH_OK
+    assert mch.LIB.mch_classify_solves(None, None, 3, 100, 1e-12) == mch.MCH_EINVAL
 
 
 def test_null_handles():

@@ -39,29 +39,34 @@ def c4():
 
     from paper_2503_01276_amd import autograd, mch
 
+    import oracle
+
     cfg = W.PRESETS["c2"]
     k, l = W.medium("c2")
     kt, _ = W.medium("c2", channel_factor=W.target_factor(4))
     dev = torch.device("cuda:0")
+    # the target tensors come from the oracle, as for the stored sample
+    say("[gpu] c4: oracle forward of the target medium")
+    Tref = oracle.stack_A(oracle.forward(cfg, kt, l, workers=16), cfg)
+    T = torch.from_numpy(Tref).to(dev)
     plan = mch.Plan(cfg)
     lab = torch.from_numpy(l.reshape(-1).copy()).to(dev)
-    with torch.no_grad():
-        T = autograd.effective_tensors(torch.from_numpy(np.log(kt).reshape(-1)).to(dev), lab, plan).clone()
     logk = torch.from_numpy(np.log(k).reshape(-1)).to(dev).requires_grad_(True)
     A = autograd.effective_tensors(logk, lab, plan)
     loss = ((A - T) ** 2).sum()
     loss.backward()
     torch.cuda.synchronize()
-    return dict(cfg=cfg, k=k, l=l, plan=plan, lab=lab, T=T, logk=logk, grad=logk.grad.detach().clone(),
-                loss=float(loss))
+    yield dict(cfg=cfg, k=k, l=l, plan=plan, lab=lab, T=T, logk=logk, grad=logk.grad.detach().clone(),
+               loss=float(loss))
+    plan.close()
 
 
 def test_c4_gradient_matches_oracle_sample(c4):
+    from gpu_util import assert_grad
+
     idx, ref = _golden()
     g = c4["grad"].cpu().numpy()[idx]
-    err = np.linalg.norm(g - ref) / np.linalg.norm(ref)
-    say(f"[gpu] c4: gradient rel err on {len(idx)} sampled elements {err:.3e}")
-    assert err <= 1e-8, err
+    assert_grad(f"c4 ({len(idx)} sampled elements)", g, ref, c4["l"].reshape(-1)[idx])
 
 
 def test_c4_finite_differences(c4):
@@ -95,13 +100,24 @@ def test_autograd_equals_c_abi_and_stale_raises(c4):
     from paper_2503_01276_amd import autograd, mch
 
     plan, lab, T = c4["plan"], c4["lab"], c4["T"]
+    # the C ABI directly: forward, tensors and backward on one kappa array
+    kappa = torch.exp(c4["logk"].detach()).contiguous()
+    plan.solve_cells(kappa, lab)
+    A_direct = torch.empty(plan.P * plan.M * plan.M, dtype=torch.float64, device=kappa.device)
+    plan.effective_coeffs(kappa, A_direct)
+    g_direct = torch.empty_like(kappa)
+    plan.effective_coeffs_backward(kappa, (2.0 * (A_direct.view(plan.P, plan.M, plan.M) - T)).contiguous().view(-1),
+                                   g_direct)
+    # a backward with another kappa array than the forward's is refused
+    with pytest.raises(mch.MchError) as ei:
+        plan.effective_coeffs_backward(kappa.clone(), torch.zeros_like(A_direct), torch.empty_like(kappa))
+    assert ei.value.code == mch.MCH_EINVAL
+    torch.cuda.synchronize()
     logk = c4["logk"].detach().clone().requires_grad_(True)
     A = autograd.effective_tensors(logk, lab, plan)
-    gA = 2.0 * (A.detach() - T)
-    g_direct = torch.empty_like(logk)
-    plan.effective_coeffs_backward(torch.exp(logk.detach()), gA.contiguous().view(-1), g_direct)
     ((A - T) ** 2).sum().backward()
     torch.cuda.synchronize()
+    assert torch.equal(A.detach().reshape(-1), A_direct)
     assert torch.equal(logk.grad, g_direct)
     # a newer forward on the plan invalidates the first graph's backward
     logk2 = c4["logk"].detach().clone().requires_grad_(True)

@@ -147,3 +147,89 @@ def test_one_and_eight_subblocks_2d():
     c8 = W2.Config(dim=2, n_fine=256, n_macro=8, n_cell=64, n_sub=8, n_cont=1, levels=2)
     k8, l8 = W2.medium_for(c8, seed=23)
     check_forward("s=8 N=1", c8, k8, l8, phi_cells=[0, 1, 9, 63], workers=8)
+
+
+def test_invalid_kappa_and_labels_reported_as_einval():
+    # kappa must be positive and finite and labels below n_cont; the forward's
+    # input check reports the first offending element through mch_diagnostics
+    import torch
+
+    from paper_2503_01276_amd import mch
+
+    cfg = W.PRESETS["t2"].replace(max_iter=200)
+    k, l = W.medium("t2")
+    dev = torch.device("cuda:0")
+    ld = torch.from_numpy(l.reshape(-1).copy()).to(dev)
+    with mch.Plan(cfg) as plan:
+        for what, e, val in (("nan", 123, float("nan")), ("zero", 7, 0.0), ("negative", 4000, -1.0),
+                             ("inf", 999, float("inf"))):
+            bad = k.reshape(-1).copy()
+            bad[e] = val
+            kd = torch.from_numpy(bad).to(dev)
+            say(f"[gpu] edge: kappa {what} at element {e}")
+            plan.solve_cells(kd, ld)
+            torch.cuda.synchronize()
+            with pytest.raises(mch.MchError) as ei:
+                plan.diagnostics()
+            assert ei.value.code == mch.MCH_EINVAL, (what, ei.value)
+            assert f"fine element {e}" in str(ei.value), str(ei.value)
+        lb = l.reshape(-1).copy()
+        lb[321] = cfg.n_cont
+        kd = torch.from_numpy(k.reshape(-1).copy()).to(dev)
+        say("[gpu] edge: label n_cont at element 321")
+        plan.solve_cells(kd, torch.from_numpy(lb).to(dev))
+        torch.cuda.synchronize()
+        with pytest.raises(mch.MchError) as ei:
+            plan.diagnostics()
+        assert ei.value.code == mch.MCH_EINVAL and "fine element 321" in str(ei.value)
+        # a valid forward on the same plan clears the report
+        plan.solve_cells(kd, ld)
+        torch.cuda.synchronize()
+        it, rs = plan.diagnostics()
+        assert it.min() >= 1 and rs.max() <= cfg.rtol
+
+
+def test_label_buffer_swap_replays_match_eager():
+    # two label arrays kept alive and swapped between forwards on one plan:
+    # every captured sequence (forward, tensors, backward) is keyed on the
+    # labels it reads, so each replay equals the eager run of its own labels
+    import torch
+
+    from paper_2503_01276_amd import mch
+
+    cfg = W.PRESETS["t3"]
+    k, l1 = W.medium("t3")
+    _, l2 = W.medium_for(cfg, 31)
+    assert (l1 != l2).any()
+    dev = torch.device("cuda:0")
+    kd = torch.from_numpy(k.reshape(-1).copy()).to(dev)
+    lds = [torch.from_numpy(x.reshape(-1).copy()).to(dev) for x in (l1, l2)]
+    rng = np.random.default_rng(77)
+    with mch.Plan(cfg) as plan:
+        n = plan.P * plan.M * plan.M
+        gA = torch.from_numpy(rng.standard_normal(n)).to(dev)
+        ref = []
+        for ld in lds:  # eager, default stream
+            A = torch.empty(n, dtype=torch.float64, device=dev)
+            g = torch.empty_like(kd)
+            plan.solve_cells(kd, ld)
+            plan.effective_coeffs(kd, A)
+            plan.effective_coeffs_backward(kd, gA, g)
+            torch.cuda.synchronize()
+            ref.append((A, g))
+        assert not torch.equal(ref[0][1], ref[1][1])
+        st = torch.cuda.Stream()
+        A = torch.empty(n, dtype=torch.float64, device=dev)
+        g = torch.empty_like(kd)
+        with torch.cuda.stream(st):
+            for rep in range(6):
+                which = rep % 2
+                plan.solve_cells(kd, lds[which])
+                plan.effective_coeffs(kd, A)
+                plan.effective_coeffs_backward(kd, gA, g)
+                st.synchronize()
+                assert torch.equal(A, ref[which][0]), rep
+                assert torch.equal(g, ref[which][1]), rep
+                A.zero_()
+                g.zero_()
+    say("[gpu] edge: 6 replays alternating two label arrays equal their eager runs")

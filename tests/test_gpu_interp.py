@@ -92,8 +92,9 @@ def test_c2_multilinear_finite_differences():
     plan = mch.Plan(cfg)
     ld = torch.from_numpy(l.reshape(-1).copy()).to(dev)
     T = torch.empty(plan.P * plan.M * plan.M, dtype=torch.float64, device=dev)
-    plan.solve_cells(torch.from_numpy(kt.reshape(-1).copy()).to(dev), ld)
-    plan.effective_coeffs(torch.from_numpy(kt.reshape(-1).copy()).to(dev), T)
+    ktd = torch.from_numpy(kt.reshape(-1).copy()).to(dev)
+    plan.solve_cells(ktd, ld)
+    plan.effective_coeffs(ktd, T)
     base = torch.from_numpy(k.reshape(-1).copy()).to(dev)
     _, g = _loss_and_grad(plan, base, ld, T, True)
     d = 1e-3
