@@ -146,6 +146,7 @@ def test_one_and_eight_subblocks_2d():
     grad_case("adj-t2 s=1", c1, 21, workers=4)
     c8 = W2.Config(dim=2, n_fine=256, n_macro=8, n_cell=64, n_sub=8, n_cont=1, levels=2)
     k8, l8 = W2.medium_for(c8, seed=23)
+    l8 = np.zeros_like(l8)  # one continuum: every element belongs to it
     check_forward("s=8 N=1", c8, k8, l8, phi_cells=[0, 1, 9, 63], workers=8)
 
 
