@@ -48,7 +48,12 @@ def test_L4_three_continua_multilinear_full():
 
 
 def test_L4_three_continua_multilinear_adjoint():
-    grad_case("adj-t4 ml N=3", _t4_three_continua(), 12, workers=8)
+    # Contrast 1e8: at the default tolerance 1e-12 the gradient meets the
+    # relative 2-norm bar (3.6e-10) but its largest element errors are
+    # 2e-10 of the field's maximum, above the element-wise bar; they come
+    # from the Krylov tolerance (1.3e-11 at 1e-13, 7.7e-13 at 1e-14), so the
+    # element-wise check runs at rtol = 1e-14.
+    grad_case("adj-t4 ml N=3", _t4_three_continua().replace(rtol=1e-14), 12, workers=8)
 
 
 def test_c2_multilinear_all_tensors_sampled_phi():
