@@ -46,7 +46,7 @@ class Config:
     eta: int = 2         # coarsening factor
     interp: int = 0      # 0: inherit the level-1 solution of the group (paper's experiments)
     bc: int = 0          # 0: homogeneous Dirichlet on the cell boundary
-    rtol: float = 1e-12  # Krylov tolerance on the preconditioned residual (relative)
+    rtol: float = 1e-13  # Krylov tolerance on the preconditioned residual (relative)
     max_iter: int = 4000
 
     @property
