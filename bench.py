@@ -154,13 +154,15 @@ def cpu_baseline(name: str, workers: int):
         "kind": "oracle",
         "sample": f"full {name} workload ({solves} solves): SciPy SuperLU forward {t1 - t0:.2f} s + "
                   f"adjoint {t2 - t1:.2f} s, one process per core",
-    }, {"A": A, "g": g}
+    }, {"A": A, "g": g, "T": T}
 
 
 class Runner:
     instances = []
 
-    def __init__(self, name: str):
+    def __init__(self, name: str, target=None):
+        """target: A_target [P, M, M] of the loss (host array), or None to form it
+        with the GPU path on the target medium (outside the timed region)."""
         import torch
 
         from paper_2503_01276_amd import mch
@@ -179,11 +181,15 @@ class Runner:
         self.A = torch.empty(P * M * M, dtype=torch.float64, device=dev)
         self.gA = torch.empty_like(self.A)
         self.g = torch.empty_like(self.k)
-        # target tensors: same path on the perturbed medium (an input of the loss, outside timing)
-        kt_d = torch.from_numpy(kt.reshape(-1).copy()).to(dev)
-        self.plan.solve_cells(kt_d, self.l)
-        self.T = torch.empty_like(self.A)
-        self.plan.effective_coeffs(kt_d, self.T)
+        if target is not None:
+            # the oracle's target tensors (an input of the loss)
+            self.T = torch.from_numpy(np.ascontiguousarray(target).reshape(-1)).to(dev)
+        else:
+            # target tensors: same path on the perturbed medium (outside timing)
+            kt_d = torch.from_numpy(kt.reshape(-1).copy()).to(dev)
+            self.plan.solve_cells(kt_d, self.l)
+            self.T = torch.empty_like(self.A)
+            self.plan.effective_coeffs(kt_d, self.T)
         torch.cuda.synchronize()
 
     def step(self, ev=None):
@@ -345,7 +351,7 @@ def main():
         cpu["affinity_cpus"] = avail
         print(f"[bench] cpu baseline: {cpu['value']:.1f} solves/s on {workers} cores", file=sys.stderr, flush=True)
 
-    run = Runner(args.workload)
+    run = Runner(args.workload, target=None if oracle_ref is None else oracle_ref["T"])
     try:
         out = measure(args, run, cpu, oracle_ref)
     finally:
