@@ -191,6 +191,26 @@ int mch_macro_load(mch_plan* plan, const double* f, double* b, void* hip_stream)
 int mch_macro_solve(mch_plan* plan, const double* A_eff, const double* b, double* U, double* U_block,
                     double rtol, int32_t max_iter, void* hip_stream);
 
+/* For callers that cannot allocate device memory when they call (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * mch_macro_solve with every intermediate array in one fixed device buffer of
+ * the library instead of the plan's scratch, which mch_macro_solve allocates
+ * on its first call. The buffer holds 16 MiB on each device the library runs
+ * on, until the process ends; systems whose element matrices, stencil rows
+ * and vectors need more ((P (2^d N)^2 + 3^d N n + (6 + N) n + 8192) doubles,
+ * n = (n_macro - 1)^d N unknowns: the 512^2 and 128^3 workloads need about
+ * 1 MiB) are refused with MCH_EINVAL. Same arguments and results as
+ * mch_macro_solve; additionally iters [1] (int32) and resid [1] (f64) are
+ * device outputs receiving the iteration count and the final relative
+ * residual (mch_macro_diagnostics does not see this call). Makes no
+ * hipMalloc, hipFree or other allocation and does not modify the plan.
+ * Every call on one device shares the buffer: calls that overlap on one
+ * device (two streams, two threads) race on it and must not be issued.
+ * Asynchronous on hip_stream. MCH_EINVAL for bad arguments. */
+int mch_macro_solve_noalloc(const mch_plan* plan, const double* A_eff, const double* b, double* U,
+                            double* U_block, double rtol, int32_t max_iter, int32_t* iters, double* resid,
+                            void* hip_stream);
+
 /* Iterations and final relative residual of the most recent mch_macro_solve
  * (host, synchronous). MCH_ENOCONV if it stopped at max_iter above rtol,
  * MCH_ESTALE if none has been issued. */

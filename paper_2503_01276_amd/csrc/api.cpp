@@ -137,3 +137,15 @@ extern "C" int mch_macro_solve(mch_plan* p, const double* A, const double* b, do
   p->macro_rtol = rtol;
   return MCH_OK;
 }
+
+extern "C" int mch_macro_solve_noalloc(const mch_plan* p, const double* A, const double* b, double* U,
+                                       double* U_block, double rtol, int32_t max_iter, int32_t* iters, double* resid,
+                                       void* stream) {
+  if (!p) return set_error(MCH_EINVAL, "null plan");
+  int rc = hip_check(hipSetDevice(p->device), "hipSetDevice");
+  if (rc) return rc;
+  if (!A || !b || !U || !U_block || !iters || !resid) return set_error(MCH_EINVAL, "null argument");
+  if (!(rtol > 0.0) || max_iter < 1) return set_error(MCH_EINVAL, "rtol must be > 0 and max_iter >= 1");
+  return launch_macro_solve_noalloc(p, A, b, U, U_block, rtol, max_iter, iters, resid,
+                                    reinterpret_cast<hipStream_t>(stream));
+}

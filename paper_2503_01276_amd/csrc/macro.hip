@@ -26,6 +26,8 @@
 
 #include <algorithm>
 #include <cstdlib>
+#include <mutex>
+#include <string>
 
 #include "kernels2d.h"
 
@@ -615,18 +617,40 @@ int launch_macro_load(mch_plan* pl, const double* f, double* b, hipStream_t s) {
   return MCH_OK;
 }
 
-int launch_macro_solve(mch_plan* pl, const double* A, const double* b, double* U, double* Ub, double rtol,
-                       int max_iter, hipStream_t s) {
+// Device arrays of one macroscopic solve: element matrices [P][KN][KN],
+// nodal stencil rows [3^D N][n], vectors x, r, z, p, q [n], block inverses
+// [N N][n / N], s [n], the grid-wide partial sums [2 kMacroGridMax], and the
+// iteration count and final residual.
+struct MacroScratch {
+  double* E;
+  double* S;
+  double* vec;
+  double* part;
+  int32_t* iters;
+  double* resid;
+};
+
+// Doubles of the arrays above for a plan (the two counts are not included).
+static size_t macro_scratch_doubles(const mch_plan* pl) {
+  const int N = pl->cfg.n_cont, D = pl->dim, nm = pl->nm;
+  size_t nn = 1;
+  for (int ax = 0; ax < D; ++ax) nn *= (size_t)(nm - 1);
+  const size_t n = nn * N, KN = (size_t)(1 << D) * N, NS = D == 2 ? 9 : 27;
+  return (size_t)pl->P * KN * KN + NS * N * n + (6 + (size_t)N) * n + 2 * (size_t)kMacroGridMax;
+}
+
+// The launch sequence of a macroscopic solve on the given scratch. prof is
+// the plan whose profiling brackets the launches, or nullptr (no events).
+static int macro_solve_on(const mch_plan* pl, mch_plan* prof, const MacroScratch& sc, const double* A,
+                          const double* b, double* U, double* Ub, double rtol, int max_iter, hipStream_t s) {
   const int N = pl->cfg.n_cont, nm = pl->nm, D = pl->dim;
-  if (nm < 2) return set_error(MCH_EINVAL, "the macroscopic system needs at least 2 blocks per axis");
-  int rc = ensure_macro_scratch(pl);
-  if (rc) return rc;
+  int rc = MCH_OK;
   {
-    ProfScope ps(pl, "macro_elem", s);
+    ProfScope ps(prof, "macro_elem", s);
     if (D == 2)
-      hipLaunchKernelGGL(k_macro_elem<2>, dim3(pl->P), dim3(MT), 0, s, A, N, 1.0 / nm, pl->d_macroE);
+      hipLaunchKernelGGL(k_macro_elem<2>, dim3(pl->P), dim3(MT), 0, s, A, N, 1.0 / nm, sc.E);
     else
-      hipLaunchKernelGGL(k_macro_elem<3>, dim3(pl->P), dim3(MT), 0, s, A, N, 1.0 / nm, pl->d_macroE);
+      hipLaunchKernelGGL(k_macro_elem<3>, dim3(pl->P), dim3(MT), 0, s, A, N, 1.0 / nm, sc.E);
     rc = hip_check(hipGetLastError(), "launch k_macro_elem");
   }
   if (rc) return rc;
@@ -635,19 +659,19 @@ int launch_macro_solve(mch_plan* pl, const double* A, const double* b, double* U
   const size_t n = nn * N;
   const int NS = D == 2 ? 9 : 27, grid = (int)((n + MT - 1) / MT);
   {
-    ProfScope ps(pl, "macro_stencil", s);
+    ProfScope ps(prof, "macro_stencil", s);
     if (D == 2)
-      hipLaunchKernelGGL(k_macro_stencil<2>, dim3(grid), dim3(MT), 0, s, pl->d_macroE, nm, N, (int)n, pl->d_macroS);
+      hipLaunchKernelGGL(k_macro_stencil<2>, dim3(grid), dim3(MT), 0, s, sc.E, nm, N, (int)n, sc.S);
     else
-      hipLaunchKernelGGL(k_macro_stencil<3>, dim3(grid), dim3(MT), 0, s, pl->d_macroE, nm, N, (int)n, pl->d_macroS);
+      hipLaunchKernelGGL(k_macro_stencil<3>, dim3(grid), dim3(MT), 0, s, sc.E, nm, N, (int)n, sc.S);
     rc = hip_check(hipGetLastError(), "launch k_macro_stencil");
   }
   if (rc) return rc;
   MacroArgs m{};
   m.nm = nm;
-  m.S = pl->d_macroS;
+  m.S = sc.S;
   m.b = b;
-  m.x = pl->d_mvec;
+  m.x = sc.vec;
   m.r = m.x + n;
   m.z = m.r + n;
   m.p = m.z + n;
@@ -659,17 +683,17 @@ int launch_macro_solve(mch_plan* pl, const double* A, const double* b, double* U
   m.max_iter = max_iter;
   m.U = U;
   m.Ub = Ub;
-  m.iters = pl->d_macro_iters;
-  m.resid = pl->d_macro_resid;
+  m.iters = sc.iters;
+  m.resid = sc.resid;
   const int ngrid = (int)((nn + MT - 1) / MT), centre = (NS - 1) / 2;
   {
-    ProfScope ps(pl, "macro_blockinv", s);
+    ProfScope ps(prof, "macro_blockinv", s);
     if (N == 1)
-      hipLaunchKernelGGL(k_macro_blockinv<1>, dim3(ngrid), dim3(MT), 0, s, pl->d_macroS, (int)n, centre, dinv);
+      hipLaunchKernelGGL(k_macro_blockinv<1>, dim3(ngrid), dim3(MT), 0, s, sc.S, (int)n, centre, dinv);
     else if (N == 2)
-      hipLaunchKernelGGL(k_macro_blockinv<2>, dim3(ngrid), dim3(MT), 0, s, pl->d_macroS, (int)n, centre, dinv);
+      hipLaunchKernelGGL(k_macro_blockinv<2>, dim3(ngrid), dim3(MT), 0, s, sc.S, (int)n, centre, dinv);
     else
-      hipLaunchKernelGGL(k_macro_blockinv<3>, dim3(ngrid), dim3(MT), 0, s, pl->d_macroS, (int)n, centre, dinv);
+      hipLaunchKernelGGL(k_macro_blockinv<3>, dim3(ngrid), dim3(MT), 0, s, sc.S, (int)n, centre, dinv);
     rc = hip_check(hipGetLastError(), "launch k_macro_blockinv");
   }
   if (rc) return rc;
@@ -681,7 +705,7 @@ int launch_macro_solve(mch_plan* pl, const double* A, const double* b, double* U
                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
                         "hipFuncSetAttribute");
       if (e) return e;
-      ProfScope ps(pl, "macro_cg", s);
+      ProfScope ps(prof, "macro_cg", s);
       hipLaunchKernelGGL(kernel, dim3(1), dim3(CGT), lds, s, m);
       return hip_check(hipGetLastError(), "launch k_macro_cg");
     };
@@ -710,9 +734,9 @@ int launch_macro_solve(mch_plan* pl, const double* A, const double* b, double* U
     else want = std::min<size_t>(want, kMacroGridDefault);
     const int grid = (int)std::min<size_t>(want, (size_t)cus * per_cu);
     if (grid > kMacroGridMax) return set_error(MCH_EINVAL, "grid-wide macroscopic CG: too many workgroups");
-    double* part = pl->d_mpart;
+    double* part = sc.part;
     void* args[] = {&m, &part};
-    ProfScope ps(pl, "macro_cg", s);
+    ProfScope ps(prof, "macro_cg", s);
     return hip_check(hipLaunchCooperativeKernel(fn, dim3(grid), dim3(GGT), args, 0, s), "hipLaunchCooperativeKernel");
   };
   if (D == 2) {
@@ -723,6 +747,67 @@ int launch_macro_solve(mch_plan* pl, const double* A, const double* b, double* U
   if (N == 1) return go_grid(k_macro_cg_grid<3, 1>);
   if (N == 2) return go_grid(k_macro_cg_grid<3, 2>);
   return go_grid(k_macro_cg_grid<3, 3>);
+}
+
+int launch_macro_solve(mch_plan* pl, const double* A, const double* b, double* U, double* Ub, double rtol,
+                       int max_iter, hipStream_t s) {
+  if (pl->nm < 2) return set_error(MCH_EINVAL, "the macroscopic system needs at least 2 blocks per axis");
+  int rc = ensure_macro_scratch(pl);
+  if (rc) return rc;
+  const MacroScratch sc{pl->d_macroE, pl->d_macroS, pl->d_mvec, pl->d_mpart, pl->d_macro_iters, pl->d_macro_resid};
+  return macro_solve_on(pl, pl, sc, A, b, U, Ub, rtol, max_iter, s);
+}
+
+// ---- the solve without allocation ------------------------------------------
+// One fixed buffer per device for the arrays of macro_solve_on, for callers
+// that cannot allocate. In host code `scratch` names a host-side stand-in, not
+// device memory: its device address comes from hipGetSymbolAddress, once per
+// device with that device current, and only that address is handed to
+// kernels. Every call on a device shares the buffer and leaves its contents
+// behind; the kernels write every array before they read it, so nothing needs
+// clearing. Calls that overlap on one device race on it.
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[kMaxDevices] = {};
+
+static int noalloc_scratch(int device, double** out) {
+  if (device < 0 || device >= kMaxDevices) return set_error(MCH_EINVAL, "device ordinal out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    int rc = hip_check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress");
+    if (rc) return rc;
+    g_scratch_ptr[device] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_ptr[device];
+  return MCH_OK;
+}
+
+int launch_macro_solve_noalloc(const mch_plan* pl, const double* A, const double* b, double* U, double* Ub,
+                               double rtol, int max_iter, int32_t* iters, double* resid, hipStream_t s) {
+  if (pl->nm < 2) return set_error(MCH_EINVAL, "the macroscopic system needs at least 2 blocks per axis");
+  const size_t need = macro_scratch_doubles(pl);
+  if (need > kNoAllocScratchDoubles)
+    return set_error(MCH_EINVAL, "macroscopic system too large for the fixed scratch buffer: needs " +
+                                     std::to_string(need * sizeof(double)) + " bytes, the buffer holds " +
+                                     std::to_string(kNoAllocScratchDoubles * sizeof(double)));
+  double* base = nullptr;
+  int rc = noalloc_scratch(pl->device, &base);
+  if (rc) return rc;
+  const int N = pl->cfg.n_cont, D = pl->dim;
+  size_t nn = 1;
+  for (int ax = 0; ax < D; ++ax) nn *= (size_t)(pl->nm - 1);
+  const size_t n = nn * N, KN = (size_t)(1 << D) * N, NS = D == 2 ? 9 : 27;
+  MacroScratch sc{};
+  sc.E = base;
+  sc.S = sc.E + (size_t)pl->P * KN * KN;
+  sc.vec = sc.S + NS * N * n;
+  sc.part = sc.vec + (6 + (size_t)N) * n;
+  sc.iters = iters;
+  sc.resid = resid;
+  return macro_solve_on(pl, nullptr, sc, A, b, U, Ub, rtol, max_iter, s);
 }
 
 }  // namespace mch

@@ -16,6 +16,9 @@ constexpr int MAX_LEVELS = 8;
 constexpr int kMacroGridMax = 4096;
 // Workgroups of the input check (one result slot each).
 constexpr int kValidateBlocks = 256;
+// Fixed device buffer of the macroscopic solve without allocation (per
+// device, in doubles): 16 MiB.
+constexpr size_t kNoAllocScratchDoubles = (size_t)2 << 20;
 
 // Kernel shape chosen for one level's cells.
 struct KernelShape {
@@ -221,6 +224,10 @@ int launch_macro_solve(mch_plan* p, const double* A, const double* b, double* U,
                        int max_iter, hipStream_t s);
 // Device scratch of the macroscopic solve (host-synchronous on first use).
 int ensure_macro_scratch(mch_plan* p);
+// The same solve on the library's fixed per-device buffer: no allocation;
+// iteration count and residual into the caller's device scalars.
+int launch_macro_solve_noalloc(const mch_plan* p, const double* A, const double* b, double* U, double* Ub,
+                               double rtol, int max_iter, int32_t* iters, double* resid, hipStream_t s);
 bool shape_supported_2d(int NC, int rpt, int N, bool galerkin, int n_sub);
 int launch_forward_3d(mch_plan* p, const double* kappa, const uint8_t* label, hipStream_t s);
 int launch_eff_3d(mch_plan* p, const double* kappa, double* A, hipStream_t s);

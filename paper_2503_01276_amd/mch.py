@@ -24,7 +24,7 @@ CODE_NAMES = {MCH_EINVAL: "MCH_EINVAL", MCH_ESINGULAR: "MCH_ESINGULAR", MCH_ENOC
 
 EXPORTS = ["mch_build_levels", "mch_build_hierarchy", "mch_build_interp", "mch_plan_info", "mch_hierarchy", "mch_solve_cells", "mch_effective_coeffs",
            "mch_effective_coeffs_backward", "mch_local_solutions", "mch_diagnostics", "mch_adjoint_diagnostics", "mch_profile",
-           "mch_profile_read", "mch_classify_solves", "mch_macro_load", "mch_macro_solve", "mch_macro_diagnostics", "mch_destroy",
+           "mch_profile_read", "mch_classify_solves", "mch_macro_load", "mch_macro_solve", "mch_macro_solve_noalloc", "mch_macro_diagnostics", "mch_destroy",
            "mch_last_error"]
 
 
@@ -79,6 +79,7 @@ def _load():
     lib.mch_classify_solves.argtypes = [i32p, dp, ctypes.c_int64, ctypes.c_int32, ctypes.c_double]
     lib.mch_macro_load.argtypes = [vp, vp, vp, vp]
     lib.mch_macro_solve.argtypes = [vp, vp, vp, vp, vp, ctypes.c_double, ctypes.c_int32, vp]
+    lib.mch_macro_solve_noalloc.argtypes = [vp, vp, vp, vp, vp, ctypes.c_double, ctypes.c_int32, vp, vp, vp]
     lib.mch_macro_diagnostics.argtypes = [vp, i32p, dp]
     lib.mch_destroy.argtypes = [vp]
     lib.mch_destroy.restype = None
@@ -260,6 +261,20 @@ class Plan:
         _require(U_block, "float64", self.P * N)
         check(LIB.mch_macro_solve(self._h, _ptr(A_eff), _ptr(b), _ptr(U), _ptr(U_block), float(rtol), int(max_iter),
                                   _stream(stream)))
+
+    def macro_solve_noalloc(self, A_eff, b, U, U_block, iters, resid, rtol=1e-12, max_iter=20000, stream=None):
+        """macro_solve on the library's fixed device buffer (no allocation);
+        iteration count and residual into the device tensors iters (int32 [1])
+        and resid (float64 [1])."""
+        N, nm = self.cfg.n_cont, self.cfg.n_macro
+        _require(A_eff, "float64", self.P * self.M * self.M)
+        _require(b, "float64", self.P * N)
+        _require(U, "float64", (nm + 1) ** self.cfg.dim * N)
+        _require(U_block, "float64", self.P * N)
+        _require(iters, "int32", 1)
+        _require(resid, "float64", 1)
+        check(LIB.mch_macro_solve_noalloc(self._h, _ptr(A_eff), _ptr(b), _ptr(U), _ptr(U_block), float(rtol),
+                                          int(max_iter), _ptr(iters), _ptr(resid), _stream(stream)))
 
     def macro_diagnostics(self):
         it = np.zeros(1, np.int32)
