@@ -1,14 +1,23 @@
-"""Size-class autotuner for the 2D cell solves: node rows per thread.
+"""Size-class autotuner for the cell solves.
 
-Each level of a plan solves cells of one width NC with the 2D solve kernel,
-whose shape is the number of node rows a thread owns (the workgroup then has
-NC^2 / rows threads). The library takes the shape from a static table and
-from the environment override MCH_RPT_<NC>, read when a plan is created. This
-tuner times, per cell width of a configuration, every shape the library
-instantiates. It builds a plan with the override set, checks that the plan
-took that shape, and times that width's solve launches with the library's own
-kernel events (median over repetitions). `apply` sets the fastest shapes for
-the plans created afterwards.
+Knobs, read by the library from the environment when a plan is created:
+* per 2D cell width NC, the node rows a thread owns (MCH_RPT_<NC>; the
+  workgroup has NC^2 / rows threads): the register footprint and parallelism
+  of the solve kernel;
+* per 2D cell width NC, the band coarse correction in the preconditioner
+  (MCH_PREC_<NC> = 1 or 0): fewer iterations against more work per
+  iteration and a costlier per-cell setup, which pays off only where the
+  medium's slow modes follow the bands;
+* per plan, whether level 1 runs as two launches so that the children of the
+  first part overlap the tail of the second (MCH_SPLIT = 1 or 0; 2D and 3D).
+
+The tuner times the candidates of one knob at a time, keeping the others at
+their best so far, with the library's own kernel events (median over
+repetitions): for a per-width knob the summed event times of the setup and
+the forward and adjoint solve launches of the levels of that width, for the
+split the elapsed time of the whole forward plus adjoint (captured graphs
+replayed on a side stream, so that concurrent launches count once). It checks through mch_plan_info that a plan took the candidate.
+`apply` sets the winners for the plans created afterwards.
 
     python -m paper_2503_01276_amd.autotune --workload c2
 
@@ -32,63 +41,142 @@ def _env_name(nc: int) -> str:
     return f"MCH_RPT_{nc}"
 
 
-def tune(cfg, kappa, label, reps: int = 3, candidates=CANDIDATES) -> dict:
-    """{NC: {"best": rows, "ms": {rows: median ms of that width's solve launches per forward}}}."""
+def _prec_name(nc: int) -> str:
+    return f"MCH_PREC_{nc}"
+
+
+SPLIT = "MCH_SPLIT"
+
+
+def _time(plan, kd, ld, names, reps: int) -> float:
+    """Median over reps, for one forward (solve + tensors) and adjoint, of the
+    summed event times of the named launches, or with names None of the
+    elapsed time of the whole sequence (replayed graphs on a side stream, so
+    that concurrent launches count once)."""
     import torch
 
-    if cfg.dim != 2:
-        raise ValueError("the size-class shapes are those of the 2D solve kernel")
+    dev = kd.device
+    A = torch.empty(plan.P * plan.M * plan.M, dtype=torch.float64, device=dev)
+    rng = np.random.default_rng(0)
+    gA = torch.from_numpy(rng.standard_normal(A.numel())).to(dev)
+    g = torch.empty_like(kd)
+
+    def once():
+        plan.solve_cells(kd, ld)
+        plan.effective_coeffs(kd, A)
+        plan.effective_coeffs_backward(kd, gA, g)
+
+    per = []
+    if names is None:
+        st = torch.cuda.Stream()
+        with torch.cuda.stream(st):
+            once()  # warm-up and capture
+            st.synchronize()
+            for _ in range(reps):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                once()
+                e1.record()
+                st.synchronize()
+                per.append(e0.elapsed_time(e1))
+        return float(np.median(per))
+    once()  # warm-up
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        plan.profile(True)
+        once()
+        torch.cuda.synchronize()
+        per.append(sum(ms for name, ms in plan.profile_records() if name in names))
+        plan.profile(False)
+    return float(np.median(per))
+
+
+def tune(cfg, kappa, label, reps: int = 3, candidates=CANDIDATES) -> dict:
+    """{"rows": {NC: {"best", "ms"}}, "prec": {NC: {"best", "ms"}}, "split": {"best", "ms"}}
+    (2D); 3D configurations have only the split."""
+    import torch
+
     dev = torch.device("cuda:0")
     kd = torch.from_numpy(np.ascontiguousarray(kappa).reshape(-1).copy()).to(dev)
     ld = torch.from_numpy(np.ascontiguousarray(label).reshape(-1).copy()).to(dev)
     widths = sorted({cfg.n_cell // cfg.eta ** l for l in range(cfg.levels)}, reverse=True)
-    saved = {nc: os.environ.get(_env_name(nc)) for nc in widths}
-    out = {}
+    keys = [_env_name(nc) for nc in widths] + [_prec_name(nc) for nc in widths] + [SPLIT]
+    saved = {k: os.environ.get(k) for k in keys}
+    out = {"rows": {}, "prec": {}}
+
+    def width_names(plan, nc):
+        levels = [l for l in range(cfg.levels) if cfg.n_cell // cfg.eta ** l == nc]
+        names = set()
+        for l in levels:
+            if plan.level_counts[l] > 0:
+                names |= {f"setup_L{l + 1}", f"solve_L{l + 1}", f"adjsolve_L{l + 1}"}
+        return levels, names
+
     try:
-        for nc in widths:
-            times = {}
-            for rows in candidates:
-                os.environ[_env_name(nc)] = str(rows)
-                try:
+        if cfg.dim == 2:
+            # rows per thread, then the preconditioner, per width
+            for nc in widths:
+                times = {}
+                for rows in candidates:
+                    os.environ[_env_name(nc)] = str(rows)
+                    try:
+                        plan = mch.Plan(cfg)
+                    except mch.MchError:
+                        continue  # no kernel instantiated for this shape
+                    try:
+                        levels, names = width_names(plan, nc)
+                        if any(plan.rows_per_thread[l] != rows for l in levels):
+                            continue  # the library fell back to another valid shape
+                        times[rows] = _time(plan, kd, ld, names, reps)
+                    finally:
+                        plan.close()
+                if not times:
+                    raise RuntimeError(f"no instantiated shape for cell width {nc}")
+                best = min(times, key=times.get)
+                out["rows"][nc] = {"best": best, "ms": times}
+                os.environ[_env_name(nc)] = str(best)
+            for nc in widths:
+                times = {}
+                for on in (1, 0):
+                    os.environ[_prec_name(nc)] = str(on)
                     plan = mch.Plan(cfg)
-                except mch.MchError:
-                    continue  # no kernel instantiated for this shape
-                try:
-                    levels = [l for l in range(cfg.levels) if cfg.n_cell // cfg.eta ** l == nc]
-                    if any(plan.rows_per_thread[l] != rows for l in levels):
-                        continue  # the library fell back to another valid shape
-                    names = {f"solve_L{l + 1}" for l in levels if plan.level_counts[l] > 0}
-                    plan.solve_cells(kd, ld)  # warm-up
-                    torch.cuda.synchronize()
-                    per = []
-                    for _ in range(reps):
-                        plan.profile(True)
-                        plan.solve_cells(kd, ld)
-                        torch.cuda.synchronize()
-                        per.append(sum(ms for name, ms in plan.profile_records() if name in names))
-                        plan.profile(False)
-                    times[rows] = float(np.median(per))
-                finally:
-                    plan.close()
-            if not times:
-                raise RuntimeError(f"no instantiated shape for cell width {nc}")
-            best = min(times, key=times.get)
-            out[nc] = {"best": best, "ms": times}
-            # later widths are timed with this width at its best shape
-            os.environ[_env_name(nc)] = str(best)
+                    try:
+                        levels, names = width_names(plan, nc)
+                        if any(plan.band_precond[l] != bool(on) for l in levels):
+                            continue  # no preconditioned kernel for this shape
+                        times[on] = _time(plan, kd, ld, names, reps)
+                    finally:
+                        plan.close()
+                best = min(times, key=times.get)
+                out["prec"][nc] = {"best": best, "ms": times}
+                os.environ[_prec_name(nc)] = str(best)
+        times = {}
+        for on in (1, 0):
+            os.environ[SPLIT] = str(on)
+            plan = mch.Plan(cfg)
+            try:
+                times[on] = _time(plan, kd, ld, None, reps)
+            finally:
+                plan.close()
+        best = min(times, key=times.get)
+        out["split"] = {"best": best, "ms": times}
     finally:
-        for nc, v in saved.items():
+        for k, v in saved.items():
             if v is None:
-                os.environ.pop(_env_name(nc), None)
+                os.environ.pop(k, None)
             else:
-                os.environ[_env_name(nc)] = v
+                os.environ[k] = v
     return out
 
 
 def apply(table: dict) -> None:
-    """Use the tuned shapes for every plan created from now on in this process."""
-    for nc, entry in table.items():
+    """Use the tuned knobs for every plan created from now on in this process."""
+    for nc, entry in table.get("rows", {}).items():
         os.environ[_env_name(int(nc))] = str(int(entry["best"]))
+    for nc, entry in table.get("prec", {}).items():
+        os.environ[_prec_name(int(nc))] = str(int(entry["best"]))
+    if "split" in table:
+        os.environ[SPLIT] = str(int(table["split"]["best"]))
 
 
 def main():
@@ -99,7 +187,7 @@ def main():
     cfg = W.PRESETS[args.workload]
     kappa, label = W.medium(args.workload)
     table = tune(cfg, kappa, label, reps=args.reps)
-    print(json.dumps({str(k): v for k, v in table.items()}))
+    print(json.dumps({k: ({str(a): b for a, b in v.items()} if k != "split" else v) for k, v in table.items()}))
 
 
 if __name__ == "__main__":

@@ -170,6 +170,9 @@ struct CellArgs {
   double* fin;
   double* gin;
   int J;                  // lanes per Schur row in the solve kernel
+  // node rows per band of the band coarse correction in the preconditioner
+  // (the solve kernel's rows per thread), 0 for diagonal scaling alone
+  int prec_rows;
   // adjoint mode inputs
   int adjoint;
   const double* seed_kp;  // [P][M][(H+1)^2] explicit seed on the K_p nodes

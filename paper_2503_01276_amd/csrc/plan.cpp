@@ -9,6 +9,7 @@
 #include <string>
 #include <vector>
 
+#include "kernels2d.h"
 #include "plan.h"
 
 namespace mch {
@@ -448,6 +449,20 @@ extern "C" int mch_build_levels(const mch_config* cfg, mch_plan** out) {
     } else {
       lv.shape.rpt = default_rpt(lv.NC, sbw);
       lv.shape.threads = lv.NC * lv.NC / lv.shape.rpt;
+      // band coarse correction where its kernel exists and fits, by default
+      // on cells of 64 level elements per side (measured: it pays there on
+      // the channel media; on 32^2 and 16^2 cells the fewer iterations do
+      // not make up for the costlier iterations and setup); MCH_PREC=0 turns
+      // it off, 1 keeps the default, 2 uses it on every level that has the
+      // kernel (comparisons)
+      int mode = 1;
+      if (const char* v = std::getenv("MCH_PREC")) mode = std::atoi(v);
+      bool want = mode == 2 || (mode == 1 && lv.NC >= 64);
+      // per cell width (the size-class tuner's knob): MCH_PREC_<NC> = 0 or 1
+      char pname[32];
+      std::snprintf(pname, sizeof(pname), "MCH_PREC_%d", lv.NC);
+      if (const char* v = std::getenv(pname)) want = std::atoi(v) != 0;
+      lv.shape.pre = want && prec_supported_2d(lv.NC, lv.shape.rpt, c.n_cont, lv.r > 1, c.n_sub, p->m);
     }
     if (d == 2 && !shape_supported_2d(lv.NC, lv.shape.rpt, c.n_cont, lv.r > 1, c.n_sub)) {
       rc = set_error(MCH_ENOTIMPL, "no kernel instantiated for level cell width " + std::to_string(lv.NC) +
@@ -589,7 +604,10 @@ extern "C" int mch_build_levels(const mch_config* cfg, mch_plan** out) {
       bpc = d == 3 ? solve_blocks_per_cu_3d(p) : solve_blocks_per_cu_2d(p);
       if (bpc < 0) rc = bpc;
     }
-    if (!rc && bpc > 0 && !ml) {  // interp = 1 runs the levels as a chain: one chunk
+    // MCH_SPLIT=0 runs level 1 as one launch (a scheduling knob of the tuner)
+    bool split = true;
+    if (const char* v = std::getenv("MCH_SPLIT")) split = std::atoi(v) != 0;
+    if (!rc && bpc > 0 && !ml && split) {  // interp = 1 runs the levels as a chain: one chunk
       const size_t slots = (size_t)cus * bpc, W = n1c * p->M, T = W % slots;
       if (W > slots && T != 0) p->n1a = (int)(n1c - (T + p->M - 1) / p->M);
     }
@@ -683,7 +701,7 @@ extern "C" int mch_build_interp(const mch_config* cfg, int32_t* nbr, double* wei
 
 extern "C" int mch_plan_info(const mch_plan* p, int64_t* info) {
   if (!p || !info) return set_error(MCH_EINVAL, "null argument");
-  for (int k = 0; k < 4 + 2 * MAX_LEVELS; ++k) info[k] = 0;
+  for (int k = 0; k < 4 + 3 * MAX_LEVELS; ++k) info[k] = 0;
   info[0] = p->P;
   info[1] = p->M;
   info[2] = p->m;
@@ -691,6 +709,7 @@ extern "C" int mch_plan_info(const mch_plan* p, int64_t* info) {
   for (int l = 0; l < p->L; ++l) {
     info[4 + l] = p->lev[l].count;
     info[4 + p->L + l] = p->lev[l].shape.rpt;
+    info[4 + 2 * p->L + l] = p->lev[l].shape.pre ? 1 : 0;
   }
   return MCH_OK;
 }

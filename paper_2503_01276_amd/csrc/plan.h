@@ -25,6 +25,7 @@ struct KernelShape {
   int NC = 0;    // cell width in level elements
   int rpt = 0;   // node rows per thread
   int threads = 0;
+  bool pre = false;  // 2D: band coarse correction in the preconditioner
 };
 
 struct Level {

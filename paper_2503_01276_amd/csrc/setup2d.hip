@@ -74,7 +74,17 @@ __global__ __launch_bounds__(SETUP_T) void k_setup2d(CellArgs a) {
   double* stat = X + 2 * m;              // (s*s+1)*N*3
   double* wred = stat + (s * s + 1) * N * 3;  // 4*N*3
   double* Dn = wred + (SETUP_T / 64) * N * 3; // NCp*NCp, holds 1/D
-  uint8_t* labS = reinterpret_cast<uint8_t*>(Dn + NCp * NCp);  // fine: NC*NC labels
+  // band coarse correction (prec_rows > 0): band-summed constraint weights
+  // of one band [m][NC] and their forward-eliminated values [NC][m]; for
+  // every band the factors of T_b = L D L^T: the subdiagonal of L and 1/D
+  // [bands][NC] each (filled with T_b's off-diagonal and diagonal first)
+  const bool prec = a.prec_rows > 0;
+  const int nbands = prec ? NC / a.prec_rows : 0;
+  double* BZ = Dn + NCp * NCp;
+  double* Ys = BZ + (prec ? m * NC : 0);
+  double* Lf = Ys + (prec ? m * NC : 0);
+  double* iD = Lf + nbands * NC;
+  uint8_t* labS = reinterpret_cast<uint8_t*>(iD + nbands * NC);  // fine: NC*NC labels
   uint8_t* regS = labS + NC * NC;        // NC*NC sub-block of each element
   __shared__ int singular;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -283,6 +293,144 @@ __global__ __launch_bounds__(SETUP_T) void k_setup2d(CellArgs a) {
   }
   __syncthreads();
 
+  // ---- band coarse correction of the preconditioner -----------------------
+  // The solve kernel preconditions with G^-1 = D^-1 + sum_b Z_b T_b^-1 Z_b^T
+  // (bands of prec_rows node rows, one coarse unknown per node column of a
+  // band; see the kernel), so its Schur matrix is B G^-1 B^T: add
+  // (B Z_b) T_b^-1 (B Z_b)^T = Y^T D^-1 Y per band, with T_b = L D L^T
+  // (tridiagonal over the node columns; column 0 is the Dirichlet boundary,
+  // an identity row) and Y = L^-1 (B Z_b)^T by one forward sweep per
+  // constraint row. The factors of all bands are formed in parallel.
+  if (prec) {
+    const int R = a.prec_rows;
+    // K_n entries of level node (X, Y): centre, north, south, east,
+    // north-east, south-east
+    auto stencil_at = [&](int X, int Y, double* k6) {
+      if (gal) {
+        const double* w9 = nW + (size_t)(Y * NC + X) * 9;
+        k6[0] = w9[4];
+        k6[1] = w9[7];
+        k6[2] = w9[1];
+        k6[3] = w9[5];
+        k6[4] = w9[8];
+        k6[5] = w9[2];
+      } else {
+        auto kq = [&](int ex, int ey) {
+          return a.kappa[(size_t)wrapi(oy + ey, a.n) * a.n + wrapi(ox + ex, a.n)] * (1.0 / 6.0);
+        };
+        const double kSW = kq(X - 1, Y - 1), kSE = kq(X, Y - 1), kNW = kq(X - 1, Y), kNE = kq(X, Y);
+        const double aS = kSW + kSE, aN = kNW + kNE;
+        k6[0] = 4.0 * (aS + aN);
+        k6[1] = -aN;
+        k6[2] = -aS;
+        k6[3] = -(kSE + kNE);
+        k6[4] = -2.0 * kNE;
+        k6[5] = -2.0 * kSE;
+      }
+    };
+    // constraint weight of level node (X, Y) for sub-block q and continuum j
+    // (no row factor), as in S above
+    auto node_weight = [&](int X, int Y, int q, int j) -> double {
+      double w = 0.0;
+      for (int Qd = 0; Qd < 4; ++Qd) {
+        const int EX = X - 1 + (Qd & 1), EY = Y - 1 + (Qd >> 1);
+        if (regS[EY * NC + EX] != q) continue;
+        if (!gal) {
+          w += (labS[EY * NC + EX] == j) ? 1.0 : 0.0;
+        } else {
+          const int side = Qd & 1, part = Qd >> 1;
+          w += (double)nB[((Y * NC + X) * 4 + side * 2 + part) * N + j];
+        }
+      }
+      return w;
+    };
+    // rows of every T_b: off-diagonal T[X][X+1] into Lf, diagonal into iD
+    for (int e = tid; e < nbands * NC; e += SETUP_T) {
+      const int b = e / NC, X = e % NC, yb0 = b * R;
+      double td = 0.0, tc = 0.0;
+      for (int i = 0; i < R; ++i) {
+        const int Y = yb0 + i;
+        const bool fr = X >= 1 && Y >= 1, frE = X + 1 <= NC - 1 && Y >= 1;
+        const bool upIn = i + 1 < R, dnIn = i >= 1 && Y - 1 >= 1;
+        if (!fr) continue;
+        double k6[6];
+        stencil_at(X, Y, k6);
+        td += k6[0] + (upIn ? k6[1] : 0.0) + (dnIn ? k6[2] : 0.0);
+        if (frE) tc += k6[3] + (upIn ? k6[4] : 0.0) + (dnIn ? k6[5] : 0.0);
+      }
+      if (X == 0) {
+        td = 1.0;
+        tc = 0.0;
+      }
+      iD[e] = td;
+      Lf[e] = tc;
+    }
+    __syncthreads();
+    // T_b = L D L^T, one band per thread: l_X = T[X][X-1] / D_{X-1}
+    for (int b = tid; b < nbands; b += SETUP_T) {
+      double* lf = Lf + b * NC;
+      double* id = iD + b * NC;
+      double prevD = id[0], prevT = lf[0];  // D_0 = 1 (identity row)
+      id[0] = 1.0 / prevD;
+      lf[0] = 0.0;
+      for (int X = 1; X < NC; ++X) {
+        const double l = prevT / prevD;
+        const double D = id[X] - l * prevT;
+        prevT = lf[X];
+        prevD = D;
+        lf[X] = l;
+        id[X] = 1.0 / D;
+      }
+    }
+    __syncthreads();
+    // per band only the rows of sub-blocks whose node rows meet the band's
+    // (the others have no weight there), listed in act[]
+    __shared__ int act[64];
+    __shared__ int n_act;
+    for (int b = 0; b < nbands; ++b) {
+      const int yb0 = b * R;
+      if (tid == 0) {
+        int na = 0;
+        for (int k = 0; k < m; ++k) {
+          const int qy = (k / N) / s;
+          if (cwp[k] != 0.0 && qy * sbw <= yb0 + R - 1 && (qy + 1) * sbw >= yb0) act[na++] = k;
+        }
+        n_act = na;
+      }
+      __syncthreads();
+      const int na = n_act;
+      for (int e = tid; e < na * NC; e += SETUP_T) {
+        const int k = act[e / NC], X = e % NC, q = k / N, j = k % N, qx = q % s;
+        double acc = 0.0;
+        if (X >= 1 && X >= qx * sbw && X <= (qx + 1) * sbw) {
+          for (int i = 0; i < R; ++i) {
+            const int Y = yb0 + i;
+            if (Y >= 1) acc += node_weight(X, Y, q, j);
+          }
+        }
+        BZ[e] = cwp[k] * acc;
+      }
+      __syncthreads();
+      const double* lf = Lf + b * NC;
+      for (int ia = tid; ia < na; ia += SETUP_T) {
+        double y = 0.0;
+        for (int X = 0; X < NC; ++X) {
+          y = BZ[ia * NC + X] - lf[X] * y;
+          Ys[X * m + ia] = y;
+        }
+      }
+      __syncthreads();
+      const double* id = iD + b * NC;
+      for (int e = tid; e < na * na; e += SETUP_T) {
+        const int ia = e / na, ib = e % na;
+        double acc = 0.0;
+        for (int X = 0; X < NC; ++X) acc += Ys[X * m + ia] * id[X] * Ys[X * m + ib];
+        S[act[ia] * m + act[ib]] += acc;
+      }
+      __syncthreads();
+    }
+  }
+
   // ---- S^-1 in place by Gauss-Jordan elimination; inactive rows get 1 -----
   // Pivot k: p = S_kk; row k becomes S_kj / p, column k becomes -S_ik / p,
   // the pivot 1 / p, and S_ij -= S_ik S_kj / p elsewhere. S is symmetric
@@ -405,6 +553,7 @@ static size_t setup_lds_bytes(const CellArgs& a) {
   const size_t NCp = a.NC + 1;
   size_t d = (size_t)a.m * a.m + 2 * (size_t)a.m + (size_t)(a.s * a.s + 1) * a.N * 3 + (SETUP_T / 64) * a.N * 3 +
              NCp * NCp;
+  if (a.prec_rows > 0) d += 2 * (size_t)a.m * a.NC + 2 * (size_t)(a.NC / a.prec_rows) * a.NC;
   // labels and sub-block per element (bytes)
   return d * sizeof(double) + 2 * (size_t)a.NC * a.NC;
 }

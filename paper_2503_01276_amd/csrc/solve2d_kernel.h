@@ -10,11 +10,23 @@
 //   [B_n  0    ][beta] = [ g' ],    f = -P^T K_h I,   g' = g - B_h I.
 //
 // Solver: projected preconditioned CG with the constraint preconditioner
-// [D B^T; B 0], D = diag(K_n) (Gould, Hribar & Nocedal 2001), including
-// their residual update so the residual stays orthogonal to range(B^T).
-// The iterate starts feasible (x0 = D^-1 B^T S^-1 g', S = B D^-1 B^T) and
-// every direction lies in null(B), so the constraints hold to rounding.
-// The accumulated projections give the multipliers.
+// [G B^T; B 0] (Gould, Hribar & Nocedal 2001), including their residual
+// update so the residual stays orthogonal to range(B^T). The iterate starts
+// feasible (x0 = G^-1 B^T S^-1 g', S = B G^-1 B^T) and every direction lies
+// in null(B), so the constraints hold to rounding. The accumulated
+// projections give the multipliers.
+//
+// G^-1 = D^-1 + sum_b Z_b T_b^-1 Z_b^T with D = diag(K_n) and, when PRE is
+// set, a coarse correction per band b (the RPT node rows of one band of
+// threads): Z_b has one column per node column of the band, 1 on the band's
+// free nodes of that column, and T_b = Z_b^T K_n Z_b is tridiagonal (node
+// columns couple only to their neighbours). In a high-contrast channel
+// medium the slow modes of diagonal scaling vary slowly along the channels,
+// which the band columns resolve; on the 64^2 fine cells this cuts the
+// iterations about threefold. T_b^-1 is applied by parallel cyclic reduction
+// across the band's lanes (one unknown per lane), with the elimination
+// factors computed once per solve and kept in LDS, so the preconditioner
+// needs no barrier. Without PRE, G = D.
 //
 // Layout inside a workgroup: one (cell, right-hand side) per workgroup; lane
 // c of a band row owns node column c and element column c; each band of RPT
@@ -35,18 +47,34 @@ template <int NC, bool GAL>
 constexpr bool kBig = !GAL && NC >= 64;
 
 // One iteration of the projected PCG needs two workgroup barriers: after the
-// fused reduction of (p.Ap, r.D^-1 r, r.D^-1 Ap, Ap.D^-1 Ap, B D^-1 r,
-// B D^-1 Ap), and after the new search direction is written to LDS. With
-// r' the projected residual, r_new = r' + alpha Ap, so both B D^-1 r_new and
-// r_new.D^-1 r_new follow from those sums without another reduction. Every
+// fused reduction of (p.Ap, r.G^-1 r, r.G^-1 Ap, Ap.G^-1 Ap, B G^-1 r,
+// B G^-1 Ap), and after the new search direction is written to LDS. With
+// r' the projected residual, r_new = r' + alpha Ap, so both B G^-1 r_new and
+// r_new.G^-1 r_new follow from those sums without another reduction. Every
 // wave then solves the small Schur system S v = u on its own (same inputs,
 // same order, identical results), so no wave waits on a serial section.
 constexpr int ZPERIOD = 16;
 
 // S sub-blocks per axis, so m = N S^2 constraint rows and sub-blocks of
 // NC / S level elements spanning NC / (S RPT) bands.
-template <int NC, int RPT, int N, bool GAL, int S>
-__global__ __launch_bounds__(NC* NC / RPT) void k_solve2d(CellArgs a) {
+// Elimination factors of the cyclic reduction over NC lanes, per band: at
+// stride s the factor on the value s lanes below (lanes s..NC-1) and the one
+// on the value s lanes above (lanes 0..NC-1-s).
+constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
+template <int NC>
+constexpr int pcr_per_band() { return 2 * (NC * ilog2(NC) - (NC - 1)); }
+// Offset of stride 2^k's factors within a band's block.
+template <int NC>
+constexpr int pcr_step_offset(int k) {
+  int o = 0;
+  for (int q = 0; q < k; ++q) o += 2 * (NC - (1 << q));
+  return o;
+}
+
+// At least two waves per SIMD: a workgroup of fewer than eight waves would
+// otherwise let the compiler spend the whole register file on one wave.
+template <int NC, int RPT, int N, bool GAL, int S, bool PRE>
+__global__ __launch_bounds__(NC* NC / RPT) __attribute__((amdgpu_waves_per_eu(2))) void k_solve2d(CellArgs a) {
   constexpr int NT = NC * NC / RPT;
   constexpr int NW = NT / 64;
   constexpr int NB = NC / RPT;
@@ -69,6 +97,7 @@ __global__ __launch_bounds__(NC* NC / RPT) void k_solve2d(CellArgs a) {
   double* vW = uW + NW * UST;               // NW*m per-wave v*cw
   double* kS = vW + NW * m;                 // BIG: (NC+1)^2 kappa/6, ring of zeros at -1
   double* xS = kS + (NC + 1) * (NC + 1);    // BIG: NC*NC iterate
+  double* pcr = BIG ? xS + NC * NC : kS;    // PRE: NB * pcr_per_band<NC>() elimination factors
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int c = tid % NC, band = tid / NC, y0 = band * RPT;
@@ -88,6 +117,21 @@ __global__ __launch_bounds__(NC* NC / RPT) void k_solve2d(CellArgs a) {
     sinvL[k] = (row < m && col < m) ? a.sinv[(size_t)p * m * m + row * m + col] : 0.0;
   }
   for (int k = tid; k < m; k += NT) cwS[k] = a.cw[(size_t)p * m + k];
+
+  // Row c of the band matrix T_b (PRE): diagonal Td = T[c][c], Tc = T[c][c+1].
+  double Td = 0.0, Tc = 0.0;
+  // Adds node row i's K_n entries (centre, north, south, east, north-east,
+  // south-east) between free nodes of the band to Td and Tc.
+  auto band_row = [&](int i, double cen, double nor, double sou, double eas, double ne, double se) {
+    const int y = y0 + i;
+    const bool fr = (c >= 1) && (y >= 1);
+    const bool frE = (c + 1 <= NC - 1) && (y >= 1);
+    const bool upIn = (i + 1 < RPT), dnIn = (i >= 1) && (y - 1 >= 1);
+    if (fr) {
+      Td += cen + (upIn ? nor : 0.0) + (dnIn ? sou : 0.0);
+      if (frE) Tc += eas + (upIn ? ne : 0.0) + (dnIn ? se : 0.0);
+    }
+  };
 
   // ---- per-node operator data in registers --------------------------------
   double kq[(GAL || BIG) ? 1 : 2][(GAL || BIG) ? 1 : RPT + 1];
@@ -130,6 +174,11 @@ __global__ __launch_bounds__(NC* NC / RPT) void k_solve2d(CellArgs a) {
       const bool fr = (c >= 1) && (y0 + i >= 1);
       const double ksum = kl[0][i] + kl[1][i] + kl[0][i + 1] + kl[1][i + 1];
       Dinv[i] = fr ? 1.0 / (4.0 * ksum) : 0.0;
+      if constexpr (PRE) {
+        const double kSW = kl[0][i], kSE = kl[1][i], kNW = kl[0][i + 1], kNE = kl[1][i + 1];
+        const double aS = kSW + kSE, aN = kNW + kNE;
+        band_row(i, 4.0 * (aS + aN), -aN, -aS, -(kSE + kNE), -2.0 * kNE, -2.0 * kSE);
+      }
 #pragma unroll
       for (int sd = 0; sd < 2; ++sd)
 #pragma unroll
@@ -154,6 +203,7 @@ __global__ __launch_bounds__(NC* NC / RPT) void k_solve2d(CellArgs a) {
 #pragma unroll
       for (int k = 0; k < 9; ++k) W[i][k] = fr ? nW[nd * 9 + k] : 0.0;
       Dinv[i] = fr ? 1.0 / W[i][4] : 0.0;
+      if constexpr (PRE) band_row(i, W[i][4], W[i][7], W[i][1], W[i][5], W[i][8], W[i][2]);
 #pragma unroll
       for (int sd = 0; sd < 2; ++sd)
 #pragma unroll
@@ -170,6 +220,41 @@ __global__ __launch_bounds__(NC* NC / RPT) void k_solve2d(CellArgs a) {
     }
   }
 
+  // ---- band coarse correction: T_b and its cyclic-reduction factors ---------
+  // Lane c of a band holds row c of T_b: the sum of the K_n entries between
+  // the free nodes of its node column and those of columns c and c + 1 in the
+  // band's rows. Column 0 is the Dirichlet boundary: an identity row.
+  constexpr int LOGNC = ilog2(NC);
+  double pcr_ib = 0.0;  // 1 / the final pivot of the lane's row
+  if constexpr (PRE) {
+    if (c == 0) {
+      Td = 1.0;
+      Tc = 0.0;
+    }
+    double Ta = __shfl_up(Tc, 1, NC);  // T[c][c-1] = T[c-1][c]
+    if (c == 0) Ta = 0.0;
+    double* blk = pcr + (size_t)band * pcr_per_band<NC>();
+#pragma unroll
+    for (int k = 0; k < LOGNC; ++k) {
+      const int st = 1 << k;
+      const bool hasL = c >= st, hasR = c + st < NC;
+      const double aL = __shfl_up(Ta, st, NC), bL = __shfl_up(Td, st, NC), cL = __shfl_up(Tc, st, NC);
+      const double aR = __shfl_down(Ta, st, NC), bR = __shfl_down(Td, st, NC), cR = __shfl_down(Tc, st, NC);
+      const double al = hasL ? -Ta / bL : 0.0;
+      const double ga = hasR ? -Tc / bR : 0.0;
+      const double na = hasL ? al * aL : 0.0;
+      const double ncf = hasR ? ga * cR : 0.0;
+      const double nb = Td + (hasL ? al * cL : 0.0) + (hasR ? ga * aR : 0.0);
+      double* stp = blk + pcr_step_offset<NC>(k);
+      if (hasL) stp[c - st] = al;
+      if (hasR) stp[(NC - st) + c] = ga;
+      Ta = na;
+      Tc = ncf;
+      Td = nb;
+    }
+    pcr_ib = 1.0 / Td;
+  }
+
   // ---- building blocks -------------------------------------------------------
   // A constraint weight widened to binary64. With three continua the widened
   // copies would take 2*RPT*N double registers for the whole solve, so there
@@ -181,6 +266,71 @@ __global__ __launch_bounds__(NC* NC / RPT) void k_solve2d(CellArgs a) {
   };
 
   auto P_at = [&](int xx, int yy) -> double { return pS[(yy + 1) * PW + xx + 1]; };
+
+  // out = G^-1 v on the thread's nodes: D^-1 v, plus (PRE) the band coarse
+  // correction Z_b T_b^-1 Z_b^T v, whose value is one per node column: the
+  // column sum of v over the band's free nodes, reduced across the band's
+  // lanes by the stored elimination factors and scaled by the final pivot.
+  // The same for two vectors at once: their reductions interleave, so the
+  // cross-lane latency is paid once.
+  auto apply_G2 = [&](const double (&v)[RPT], double (&out)[RPT], const double (&v2)[RPT], double (&out2)[RPT]) {
+    if constexpr (PRE) {
+      double d = 0.0, d2 = 0.0;
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        d += (Dinv[i] != 0.0) ? v[i] : 0.0;
+        d2 += (Dinv[i] != 0.0) ? v2[i] : 0.0;
+      }
+      const double* blk = pcr + (size_t)band * pcr_per_band<NC>();
+#pragma unroll
+      for (int k = 0; k < LOGNC; ++k) {
+        const int st = 1 << k;
+        const double* stp = blk + pcr_step_offset<NC>(k);
+        const double dL = __shfl_up(d, st, NC), dR = __shfl_down(d, st, NC);
+        const double dL2 = __shfl_up(d2, st, NC), dR2 = __shfl_down(d2, st, NC);
+        const double al = (c >= st) ? stp[c - st] : 0.0;
+        const double ga = (c + st < NC) ? stp[(NC - st) + c] : 0.0;
+        d += al * dL + ga * dR;
+        d2 += al * dL2 + ga * dR2;
+      }
+      const double y = d * pcr_ib, y2 = d2 * pcr_ib;
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        out[i] = Dinv[i] * v[i] + ((Dinv[i] != 0.0) ? y : 0.0);
+        out2[i] = Dinv[i] * v2[i] + ((Dinv[i] != 0.0) ? y2 : 0.0);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        out[i] = Dinv[i] * v[i];
+        out2[i] = Dinv[i] * v2[i];
+      }
+    }
+  };
+
+  auto apply_G = [&](const double (&v)[RPT], double (&out)[RPT]) {
+    if constexpr (PRE) {
+      double d = 0.0;
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) d += (Dinv[i] != 0.0) ? v[i] : 0.0;
+      const double* blk = pcr + (size_t)band * pcr_per_band<NC>();
+#pragma unroll
+      for (int k = 0; k < LOGNC; ++k) {
+        const int st = 1 << k;
+        const double* stp = blk + pcr_step_offset<NC>(k);
+        const double dL = __shfl_up(d, st, NC), dR = __shfl_down(d, st, NC);
+        const double al = (c >= st) ? stp[c - st] : 0.0;
+        const double ga = (c + st < NC) ? stp[(NC - st) + c] : 0.0;
+        d += al * dL + ga * dR;
+      }
+      const double y = d * pcr_ib;
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) out[i] = Dinv[i] * v[i] + ((Dinv[i] != 0.0) ? y : 0.0);
+    } else {
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) out[i] = Dinv[i] * v[i];
+    }
+  };
 
   // y = K_n v on the thread's nodes (own values in vv, neighbours from pS).
   auto apply_K = [&](const double (&vv)[RPT], double (&yv)[RPT]) {
@@ -394,16 +544,21 @@ __global__ __launch_bounds__(NC* NC / RPT) void k_solve2d(CellArgs a) {
   __syncthreads();  // sinvL, cwS, kS visible
   const double zcw = lane < m ? cwS[lane] : 0.0;
 
-  // ---- feasible start x0 = D^-1 B^T S^-1 g' ---------------------------------
+  // ---- feasible start x0 = G^-1 B^T S^-1 g' ---------------------------------
   double x[RPT], r[RPT], t[RPT], pv[RPT];
   double Vacc = 0.0, vk = 0.0;
   (void)wave_schur(&vk);
 #pragma unroll
   for (int i = 0; i < RPT; ++i) x[i] = 0.0;
   scatter_B(x, 1.0);
+  {
+    double bt[RPT];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) bt[i] = x[i];
+    apply_G(bt, x);
+  }
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
-    x[i] *= Dinv[i];
     pS[(y0 + i + 1) * PW + c + 1] = x[i];
     if constexpr (BIG) xS[(y0 + i) * NC + c] = x[i];
   }
@@ -411,11 +566,10 @@ __global__ __launch_bounds__(NC* NC / RPT) void k_solve2d(CellArgs a) {
   apply_K(x, r);
   double s_rr = 0.0;
 #pragma unroll
-  for (int i = 0; i < RPT; ++i) {
-    r[i] -= f[i];
-    t[i] = Dinv[i] * r[i];
-    s_rr += r[i] * t[i];
-  }
+  for (int i = 0; i < RPT; ++i) r[i] -= f[i];
+  apply_G(r, t);
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) s_rr += r[i] * t[i];
   accumulate_B(t, 0);
   s_rr = wave_sum(s_rr);
   if (lane == 0) red[wave * 4] = s_rr;
@@ -427,11 +581,9 @@ __global__ __launch_bounds__(NC* NC / RPT) void k_solve2d(CellArgs a) {
   double rz = rr - vu;
   const double rz0 = rz;
   scatter_B(r, -1.0);
+  apply_G(r, t);
 #pragma unroll
-  for (int i = 0; i < RPT; ++i) {
-    t[i] = Dinv[i] * r[i];
-    pv[i] = -t[i];
-  }
+  for (int i = 0; i < RPT; ++i) pv[i] = -t[i];
   __syncthreads();  // everyone done reading pS (x0) and part
 #pragma unroll
   for (int i = 0; i < RPT; ++i) pS[(y0 + i + 1) * PW + c + 1] = pv[i];
@@ -441,22 +593,20 @@ __global__ __launch_bounds__(NC* NC / RPT) void k_solve2d(CellArgs a) {
   int it = 0;
   bool done = !(rz0 > 0.0);
   while (!done) {
-    // t = D^-1 r is formed again each iteration rather than kept live across
+    // t = G^-1 r is formed again each iteration rather than kept live across
     // it (fewer registers held through the two barriers)
     double Ap[RPT], tA[RPT];
-#pragma unroll
-    for (int i = 0; i < RPT; ++i) t[i] = Dinv[i] * r[i];
     apply_K(pv, Ap);
+    apply_G2(r, t, Ap, tA);
     double s4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
-      tA[i] = Dinv[i] * Ap[i];
       s4[0] += pv[i] * Ap[i];
       s4[1] += r[i] * t[i];
       s4[2] += t[i] * Ap[i];
       s4[3] += Ap[i] * tA[i];
     }
-    // B D^-1 r' vanishes up to rounding; it is folded in every ZPERIOD
+    // B G^-1 r' vanishes up to rounding; it is folded in every ZPERIOD
     // iterations, which keeps the constraint residual at rounding level.
     const bool withz0 = (it % ZPERIOD) == 0;
     if (withz0) accumulate_B(t, 0);
@@ -467,7 +617,7 @@ __global__ __launch_bounds__(NC* NC / RPT) void k_solve2d(CellArgs a) {
       for (int q = 0; q < 4; ++q) red[wave * 4 + q] = s4[q];
     }
     __syncthreads();
-    // B_n D^-1 Ap and the wave partials are read together; only the final
+    // B_n G^-1 Ap and the wave partials are read together; only the final
     // combination waits for alpha. 1/rrk is formed off the critical path.
     const double z1 = zsum(1);
     const double z0 = withz0 ? zsum(0) : 0.0;
@@ -503,9 +653,10 @@ __global__ __launch_bounds__(NC* NC / RPT) void k_solve2d(CellArgs a) {
       r[i] += al * Ap[i];
     }
     scatter_B(r, -1.0);
+    apply_G(r, t);
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
-      pv[i] = -(Dinv[i] * r[i]) + be * pv[i];
+      pv[i] = -t[i] + be * pv[i];
       pS[(y0 + i + 1) * PW + c + 1] = pv[i];
     }
     __syncthreads();
@@ -515,7 +666,7 @@ __global__ __launch_bounds__(NC* NC / RPT) void k_solve2d(CellArgs a) {
   // The directions keep the iterate feasible only up to the accuracy of S^-1
   // and the rounding of each projection; one correction
   // x -= D^-1 B_n^T S^-1 (B_n x - g') brings the constraint residual back to
-  // rounding level. Every wave leaves the loop in the same iteration, and the
+  // rounding level (x -= G^-1 B_n^T S^-1 (B_n x - g')). Every wave leaves the loop in the same iteration, and the
   // barrier keeps the band partials until every wave has read them.
   {
     double xr[RPT], tc[RPT];
@@ -542,12 +693,14 @@ __global__ __launch_bounds__(NC* NC / RPT) void k_solve2d(CellArgs a) {
     }
     (void)wave_schur(&vk);
     scatter_B(tc, 1.0);
+    double gc[RPT];
+    apply_G(tc, gc);
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       if constexpr (BIG)
-        xS[(y0 + i) * NC + c] = xr[i] - Dinv[i] * tc[i];
+        xS[(y0 + i) * NC + c] = xr[i] - gc[i];
       else
-        x[i] = xr[i] - Dinv[i] * tc[i];
+        x[i] = xr[i] - gc[i];
     }
   }
 

@@ -181,12 +181,14 @@ class Plan:
         h = ctypes.c_void_p()
         check(LIB.mch_build_levels(ctypes.byref(self._c), ctypes.byref(h)))
         self._h = h
-        info = (ctypes.c_int64 * 20)()
+        info = (ctypes.c_int64 * 28)()
         check(LIB.mch_plan_info(self._h, info))
         self.P, self.M, self.m, self.levels = int(info[0]), int(info[1]), int(info[2]), int(info[3])
         self.level_counts = [int(info[4 + k]) for k in range(self.levels)]
         # node rows per thread of each level's 2D solve kernel (0 in 3D)
         self.rows_per_thread = [int(info[4 + self.levels + k]) for k in range(self.levels)]
+        # whether each level's 2D solve uses the band coarse correction
+        self.band_precond = [bool(info[4 + 2 * self.levels + k]) for k in range(self.levels)]
         self.generation = 0  # bumped by every forward solve
         _LIVE.add(self)
 
