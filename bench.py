@@ -327,6 +327,8 @@ def main():
     ap.add_argument("--workload", default="c2", choices=sorted(DESCR))
     ap.add_argument("--flat", default=None, help="flat workload for the speedup (default: c2flat for c2)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tuned", action="store_true",
+                    help="use the library's default kernel knobs instead of the stored tuned ones")
     ap.add_argument("--cpu-workers", type=int, default=None)
     ap.add_argument("--copy-probe", type=int, default=None, metavar="MIB",
                     help="only run a plain copy of MIB MiB (counter calibration) and exit")
@@ -351,9 +353,20 @@ def main():
         cpu["affinity_cpus"] = avail
         print(f"[bench] cpu baseline: {cpu['value']:.1f} solves/s on {workers} cores", file=sys.stderr, flush=True)
 
+    tuned = {}
+    if not args.no_tuned:
+        from paper_2503_01276_amd import autotune
+
+        for w in {args.workload, args.flat or {"c2": "c2flat", "c2ml": "c2flat", "c3": "c3flat"}.get(args.workload)}:
+            if w and w != "none" and autotune.load(w):
+                tuned[w] = autotune.load(w)
+    if args.workload in tuned:
+        from paper_2503_01276_amd import autotune
+
+        autotune.apply(tuned[args.workload])
     run = Runner(args.workload, target=None if oracle_ref is None else oracle_ref["T"])
     try:
-        out = measure(args, run, cpu, oracle_ref)
+        out = measure(args, run, cpu, oracle_ref, tuned)
     finally:
         # release every plan before the interpreter (and torch) shut down
         for r in Runner.instances:
@@ -361,7 +374,15 @@ def main():
     print(json.dumps(out))
 
 
-def measure(args, run, cpu, oracle_ref):
+def _knobs(table):
+    if not table:
+        return None
+    return {"rows_per_thread": {k: v["best"] for k, v in table.get("rows", {}).items()},
+            "band_correction": {k: v["best"] for k, v in table.get("prec", {}).items()},
+            "level1_split": table.get("split", {}).get("best")}
+
+
+def measure(args, run, cpu, oracle_ref, tuned):
     cfg, plan = run.cfg, run.plan
     ms, wall, recs, phases = run.time_steps(args.steps, args.warmup, profile=True)
     print(f"[bench] {args.workload}: {ms:.3f} ms/step (eager, per-kernel events)", file=sys.stderr, flush=True)
@@ -450,6 +471,10 @@ def measure(args, run, cpu, oracle_ref):
     if flat == "none":
         flat = None
     if flat:
+        if flat in tuned:
+            from paper_2503_01276_amd import autotune
+
+            autotune.apply(tuned[flat])
         frun = Runner(flat)
         fms, _, _, fph = frun.time_steps(max(3, args.steps // 4), 1, profile=True)
         detail["flat"] = {"workload": flat, "ms_per_step": fms, **fph,
@@ -480,6 +505,8 @@ def measure(args, run, cpu, oracle_ref):
         detail["macro"] = {"hierarchical": mh}
         print(f"[bench] macroscopic system: {mh['ms']:.3f} ms, {mh['cg_iterations']} CG iterations",
               file=sys.stderr, flush=True)
+    detail["tuned_knobs"] = {w: _knobs(t) for w, t in tuned.items()} or None
+    detail["band_correction_per_level"] = list(plan.band_precond)
     out = {
         "metric": "cell-solves/sec & eff-tensor+grad time, hier L=3 vs flat, 1 GPU, rel err <=1e-8",
         "value": solves / (ms * 1e-3),

@@ -169,6 +169,19 @@ def tune(cfg, kappa, label, reps: int = 3, candidates=CANDIDATES) -> dict:
     return out
 
 
+# Tuned knobs per workload, measured on one MI355X with this module (written
+# by `--out` and merged here); bench.py applies the entry of its workload.
+TUNED_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
+
+
+def load(workload: str):
+    """The stored table of a workload, or None."""
+    if not os.path.exists(TUNED_PATH):
+        return None
+    with open(TUNED_PATH) as fh:
+        return json.load(fh).get(workload)
+
+
 def apply(table: dict) -> None:
     """Use the tuned knobs for every plan created from now on in this process."""
     for nc, entry in table.get("rows", {}).items():
@@ -183,11 +196,16 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--workload", default="c2", choices=sorted(W.PRESETS))
     ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--out", default=None, help="also write {workload: table} as JSON to this file")
     args = ap.parse_args()
     cfg = W.PRESETS[args.workload]
     kappa, label = W.medium(args.workload)
     table = tune(cfg, kappa, label, reps=args.reps)
-    print(json.dumps({k: ({str(a): b for a, b in v.items()} if k != "split" else v) for k, v in table.items()}))
+    js = {k: ({str(a): b for a, b in v.items()} if k != "split" else v) for k, v in table.items()}
+    print(json.dumps(js))
+    if args.out:
+        with open(args.out, "w") as fh:
+            json.dump({args.workload: js}, fh, indent=1)
 
 
 if __name__ == "__main__":

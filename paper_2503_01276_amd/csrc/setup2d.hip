@@ -27,6 +27,18 @@
 namespace mch {
 
 constexpr int SETUP_T = 256;
+// Bands whose Schur corrections the setup forms at once.
+constexpr int PREC_GROUP = 4;
+
+// Most constraint rows a band of prec_rows node rows can meet (the rows of
+// every sub-block row whose nodes reach into the band) and the bands formed
+// at once, for the setup's LDS.
+__host__ __device__ inline void prec_group_sizes(const CellArgs& a, int* NA, int* G) {
+  const int R = a.prec_rows, nbands = a.NC / R;
+  const int rows_of_blocks = R / a.sbw + 2;
+  *NA = rows_of_blocks * a.s * a.N < a.m ? rows_of_blocks * a.s * a.N : a.m;
+  *G = nbands < PREC_GROUP ? nbands : PREC_GROUP;
+}
 
 template <int N>
 struct Quad {
@@ -74,15 +86,18 @@ __global__ __launch_bounds__(SETUP_T) void k_setup2d(CellArgs a) {
   double* stat = X + 2 * m;              // (s*s+1)*N*3
   double* wred = stat + (s * s + 1) * N * 3;  // 4*N*3
   double* Dn = wred + (SETUP_T / 64) * N * 3; // NCp*NCp, holds 1/D
-  // band coarse correction (prec_rows > 0): band-summed constraint weights
-  // of one band [m][NC] and their forward-eliminated values [NC][m]; for
-  // every band the factors of T_b = L D L^T: the subdiagonal of L and 1/D
-  // [bands][NC] each (filled with T_b's off-diagonal and diagonal first)
+  // band coarse correction (prec_rows > 0): for a group of G bands the
+  // band-summed weights of the constraint rows active in each [G][NA][NC]
+  // and their forward-eliminated values [G][NC][NA]; for every band the
+  // factors of T_b = L D L^T: the subdiagonal of L and 1/D [bands][NC] each
+  // (filled with T_b's off-diagonal and diagonal first)
   const bool prec = a.prec_rows > 0;
   const int nbands = prec ? NC / a.prec_rows : 0;
+  int pNA = 0, pG = 0;
+  if (prec) prec_group_sizes(a, &pNA, &pG);
   double* BZ = Dn + NCp * NCp;
-  double* Ys = BZ + (prec ? m * NC : 0);
-  double* Lf = Ys + (prec ? m * NC : 0);
+  double* Ys = BZ + pG * pNA * NC;
+  double* Lf = Ys + pG * pNA * NC;
   double* iD = Lf + nbands * NC;
   uint8_t* labS = reinterpret_cast<uint8_t*>(iD + nbands * NC);  // fine: NC*NC labels
   uint8_t* regS = labS + NC * NC;        // NC*NC sub-block of each element
@@ -383,24 +398,37 @@ __global__ __launch_bounds__(SETUP_T) void k_setup2d(CellArgs a) {
       }
     }
     __syncthreads();
-    // per band only the rows of sub-blocks whose node rows meet the band's
-    // (the others have no weight there), listed in act[]
-    __shared__ int act[64];
-    __shared__ int n_act;
-    for (int b = 0; b < nbands; ++b) {
-      const int yb0 = b * R;
-      if (tid == 0) {
+    // Per band only the rows of sub-blocks whose node rows meet the band's
+    // carry weight there (act[], at most NA of them, inv[] the inverse map);
+    // PREC_GROUP bands at a time, each with its own slices of BZ and Ys.
+    int NA, G;
+    prec_group_sizes(a, &NA, &G);
+    __shared__ int act[PREC_GROUP][64];
+    __shared__ int inv[PREC_GROUP][64];
+    __shared__ int n_act[PREC_GROUP];
+    for (int b0 = 0; b0 < nbands; b0 += G) {
+      const int gb = min(G, nbands - b0);
+      if (tid < gb) {
+        const int yb0 = (b0 + tid) * R;
         int na = 0;
         for (int k = 0; k < m; ++k) {
           const int qy = (k / N) / s;
-          if (cwp[k] != 0.0 && qy * sbw <= yb0 + R - 1 && (qy + 1) * sbw >= yb0) act[na++] = k;
+          inv[tid][k] = -1;
+          if (cwp[k] != 0.0 && qy * sbw <= yb0 + R - 1 && (qy + 1) * sbw >= yb0) {
+            inv[tid][k] = na;
+            act[tid][na++] = k;
+          }
         }
-        n_act = na;
+        // the bound NA holds by construction; if it did not, the cell would
+        // be reported singular rather than solved with a truncated correction
+        if (na > NA) singular = 1;
+        n_act[tid] = na < NA ? na : NA;
       }
       __syncthreads();
-      const int na = n_act;
-      for (int e = tid; e < na * NC; e += SETUP_T) {
-        const int k = act[e / NC], X = e % NC, q = k / N, j = k % N, qx = q % s;
+      for (int e = tid; e < gb * NA * NC; e += SETUP_T) {
+        const int g = e / (NA * NC), ia = (e / NC) % NA, X = e % NC;
+        if (ia >= n_act[g]) continue;
+        const int k = act[g][ia], q = k / N, j = k % N, qx = q % s, yb0 = (b0 + g) * R;
         double acc = 0.0;
         if (X >= 1 && X >= qx * sbw && X <= (qx + 1) * sbw) {
           for (int i = 0; i < R; ++i) {
@@ -411,21 +439,30 @@ __global__ __launch_bounds__(SETUP_T) void k_setup2d(CellArgs a) {
         BZ[e] = cwp[k] * acc;
       }
       __syncthreads();
-      const double* lf = Lf + b * NC;
-      for (int ia = tid; ia < na; ia += SETUP_T) {
+      for (int e = tid; e < gb * NA; e += SETUP_T) {
+        const int g = e / NA, ia = e % NA;
+        if (ia >= n_act[g]) continue;
+        const double* lf = Lf + (b0 + g) * NC;
+        const double* bz = BZ + (size_t)(g * NA + ia) * NC;
+        double* ys = Ys + (size_t)g * NC * NA + ia;
         double y = 0.0;
         for (int X = 0; X < NC; ++X) {
-          y = BZ[ia * NC + X] - lf[X] * y;
-          Ys[X * m + ia] = y;
+          y = bz[X] - lf[X] * y;
+          ys[X * NA] = y;
         }
       }
       __syncthreads();
-      const double* id = iD + b * NC;
-      for (int e = tid; e < na * na; e += SETUP_T) {
-        const int ia = e / na, ib = e % na;
+      for (int e = tid; e < m * m; e += SETUP_T) {
+        const int k = e / m, k2 = e % m;
         double acc = 0.0;
-        for (int X = 0; X < NC; ++X) acc += Ys[X * m + ia] * id[X] * Ys[X * m + ib];
-        S[act[ia] * m + act[ib]] += acc;
+        for (int g = 0; g < gb; ++g) {
+          const int ia = inv[g][k], ib = inv[g][k2];
+          if (ia < 0 || ib < 0) continue;
+          const double* ys = Ys + (size_t)g * NC * NA;
+          const double* id = iD + (b0 + g) * NC;
+          for (int X = 0; X < NC; ++X) acc += ys[X * NA + ia] * id[X] * ys[X * NA + ib];
+        }
+        S[e] += acc;
       }
       __syncthreads();
     }
@@ -553,7 +590,11 @@ static size_t setup_lds_bytes(const CellArgs& a) {
   const size_t NCp = a.NC + 1;
   size_t d = (size_t)a.m * a.m + 2 * (size_t)a.m + (size_t)(a.s * a.s + 1) * a.N * 3 + (SETUP_T / 64) * a.N * 3 +
              NCp * NCp;
-  if (a.prec_rows > 0) d += 2 * (size_t)a.m * a.NC + 2 * (size_t)(a.NC / a.prec_rows) * a.NC;
+  if (a.prec_rows > 0) {
+    int NA, G;
+    prec_group_sizes(a, &NA, &G);
+    d += 2 * (size_t)G * NA * a.NC + 2 * (size_t)(a.NC / a.prec_rows) * a.NC;
+  }
   // labels and sub-block per element (bytes)
   return d * sizeof(double) + 2 * (size_t)a.NC * a.NC;
 }
