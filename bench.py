@@ -52,19 +52,26 @@ KERNEL_SOURCES = {
 # rocprofv3 --pmc runs, each scaled by the ratio of a plain copy's known size
 # to what the same counter reads for it. An entry holds only while the kernel
 # sources hash to the recorded value; otherwise traffic is reported as null.
-_SHA_2D = "2b4319c02335be6a43dcd6aee6387c40b92ab6fdbce2bd6624c42b2c7f65a43f"
+_SHA_2D = "cb44a3ade20c7bb47c5397ddbdf1b470a83ab4433bdecf6a3d4c77797fdacdd8"
 _SHA_3D = "20fee8c7fb8143caea8d5f04397339869a096794af9029b054f8cbd62c45dd57"
-_COPY_SCALE = {"fetch": 1048576.0 / 524305.1, "write": 1048576.0 / 1048576.0}  # 1 GiB copy
+_COPY_SCALE = {"fetch": 1048576.0 / 524304.75, "write": 1048576.0 / 1048576.0}  # 1 GiB copy
 TRAFFIC = {
-    # level-1 forward launches (two chunks per step) and the single adjoint launch
-    ("c2", "solve_L1"): {"sha256": _SHA_2D, "fetch_kib": 8680.8, "write_kib": 16287.0,
+    # level-2 (32^2 Galerkin) forward solve: two launches per step (756 and 396
+    # workgroups), counters averaged over both
+    ("c2", "solve_L2"): {"sha256": _SHA_2D, "fetch_kib": 34054.2, "write_kib": 4941.2,
                          "fetch_scale": _COPY_SCALE["fetch"], "write_scale": _COPY_SCALE["write"]},
-    ("c2", "adjsolve_L1"): {"sha256": _SHA_2D, "fetch_kib": 20944.6, "write_kib": 29490.6,
+    ("c2", "adjsolve_L2"): {"sha256": _SHA_2D, "fetch_kib": 64462.1, "write_kib": 9882.4,
+                            "fetch_scale": _COPY_SCALE["fetch"], "write_scale": _COPY_SCALE["write"]},
+    # level-1 (64^2, band coarse correction) forward chunks (252 and 132
+    # workgroups) averaged, and the single adjoint launch (384)
+    ("c2", "solve_L1"): {"sha256": _SHA_2D, "fetch_kib": 4982.8, "write_kib": 6687.0,
+                         "fetch_scale": _COPY_SCALE["fetch"], "write_scale": _COPY_SCALE["write"]},
+    ("c2", "adjsolve_L1"): {"sha256": _SHA_2D, "fetch_kib": 16225.0, "write_kib": 13194.2,
                             "fetch_scale": _COPY_SCALE["fetch"], "write_scale": _COPY_SCALE["write"]},
     # 3D fine level: forward and adjoint launches share kernel and grid; the
     # counters are the mean over both, so either may be the dominant launch
     ("c3", "solve_L1"): {"sha256": _SHA_3D, "fetch_kib": 85402271.5, "write_kib": 99457282.3,
-                         "fetch_scale": _COPY_SCALE["fetch"], "write_scale": _COPY_SCALE["write"]},
+                         "fetch_scale": 1048576.0 / 524305.1, "write_scale": _COPY_SCALE["write"]},
 }
 TRAFFIC[("c3", "adjsolve_L1")] = TRAFFIC[("c3", "solve_L1")]
 
