@@ -489,8 +489,10 @@ constexpr int nt3() {
 template <int V>
 using IC = std::integral_constant<int, V>;
 
+// At least two waves per SIMD (a smaller workgroup would otherwise let the
+// compiler spend the whole register file on one wave).
 template <int NC, int N, bool GAL>
-__global__ __launch_bounds__((nt3<NC, GAL>())) void k_solve3d(CellArgs a) {
+__global__ __launch_bounds__((nt3<NC, GAL>())) __attribute__((amdgpu_waves_per_eu(2))) void k_solve3d(CellArgs a) {
   constexpr int NT = nt3<NC, GAL>();
   constexpr int NW = NT / 64;
   constexpr int NP = NC + 1;
@@ -545,25 +547,28 @@ __global__ __launch_bounds__((nt3<NC, GAL>())) void k_solve3d(CellArgs a) {
   // Planes of this thread: Z = g + G i (plane 0 is the Dirichlet boundary).
   // The lower octants (elements of layer Z-1) of plane Z lie in constraint
   // region m0 = (Z-1)/sbw and the upper ones in m1 = Z/sbw. A sweep visits the
-  // thread's planes in order; consecutive planes with the same (m0, m1) form a
-  // segment (at most three). Per-octant sums are kept by octant (oz) and
-  // mapped to regions only when a segment ends, so the loop body carries no
-  // region logic.
+  // thread's columns one after another and each column's planes in order;
+  // consecutive planes with the same (m0, m1) form a segment (at most three).
+  // Per-octant sums are kept by octant (oz) and mapped to regions only when a
+  // segment ends, so the loop body carries no region logic. Taking the
+  // columns one at a time keeps one column's sums and windows in registers
+  // rather than all of the thread's.
   const int iFirst = (g == 0) ? 1 : 0;
   auto sweep = [&](auto&& seg_begin, auto&& body, auto&& seg_end) {
 #pragma unroll 1
-    for (int i = iFirst; i < SPT; ++i) {
-      const int Z = g + G * i;
-      const int m0 = (Z - 1) / sbw, m1 = Z / sbw;
-      const int Zp = Z - G, Zn = Z + G;
-      if (i == iFirst || (Zp - 1) / sbw != m0 || Zp / sbw != m1) seg_begin(m0, m1);
-#pragma unroll
-      for (int c = 0; c < CPT; ++c)
+    for (int c = 0; c < CPT; ++c) {
+#pragma unroll 1
+      for (int i = iFirst; i < SPT; ++i) {
+        const int Z = g + G * i;
+        const int m0 = (Z - 1) / sbw, m1 = Z / sbw;
+        const int Zp = Z - G, Zn = Z + G;
+        if (i == iFirst || (Zp - 1) / sbw != m0 || Zp / sbw != m1) seg_begin(c, m0, m1);
         if (colfree(c)) body(c, Z);
-      if (i + 1 == SPT || (Zn - 1) / sbw != m0 || Zn / sbw != m1) seg_end(m0, m1);
+        if (i + 1 == SPT || (Zn - 1) / sbw != m0 || Zn / sbw != m1) seg_end(c, m0, m1);
+      }
     }
   };
-  auto nop2 = [](int, int) {};
+  auto nop3 = [](int, int, int) {};
 
   for (int k = tid; k < MS * 64; k += NT) {
     const int t = k / 64, L = k % 64, row = L / J, col = L % J + J * t;
@@ -631,34 +636,33 @@ __global__ __launch_bounds__((nt3<NC, GAL>())) void k_solve3d(CellArgs a) {
     }
   };
 
-  using Acc = double[CPT][2][2][2][N];
+  // per column: [ox][oy][oz][continuum]
+  using Acc = double[2][2][2][N];
 
-  // acc[c][ox][oy][oz][j] += w * tv over the node's octants.
-  auto accB = [&](Acc& acc, int c, const float (&w)[8][N], double tv) {
+  // acc[ox][oy][oz][j] += w * tv over the node's octants.
+  auto accB = [&](Acc& acc, const float (&w)[8][N], double tv) {
 #pragma unroll
     for (int o = 0; o < 8; ++o)
 #pragma unroll
-      for (int j = 0; j < N; ++j) acc[c][o & 1][(o >> 1) & 1][o >> 2][j] += (double)w[o][j] * tv;
+      for (int j = 0; j < N; ++j) acc[o & 1][(o >> 1) & 1][o >> 2][j] += (double)w[o][j] * tv;
   };
 
   // Element-column combination and segment sums over each region's columns of
   // the octant sums; the leader lane of every region adds them to the per-(g, Y)
   // partials of B_n tv (without cw) in part[vec], regions m0 (oz = 0) and m1.
-  auto flushB = [&](Acc& acc, int vec, int m0, int m1) {
+  auto flushB = [&](Acc& acc, int c, int vec, int m0, int m1) {
 #pragma unroll
-    for (int c = 0; c < CPT; ++c)
+    for (int ey_ = 0; ey_ < 2; ++ey_)
 #pragma unroll
-      for (int ey_ = 0; ey_ < 2; ++ey_)
+      for (int oz = 0; oz < 2; ++oz)
 #pragma unroll
-        for (int oz = 0; oz < 2; ++oz)
-#pragma unroll
-          for (int j = 0; j < N; ++j) {
-            double v = acc[c][1][ey_][oz][j] + from_right(acc[c][0][ey_][oz][j], X, NC);
-            v = seg_sum(v, sbw);
-            const int qz = oz ? m1 : m0;
-            if (X % sbw == 0)
-              part[vec * PARTV + ((((g * NC + Yc(c)) * 2 + ey_) * S + X / sbw) * S + qz) * N + j] += v;
-          }
+        for (int j = 0; j < N; ++j) {
+          double v = acc[1][ey_][oz][j] + from_right(acc[0][ey_][oz][j], X, NC);
+          v = seg_sum(v, sbw);
+          const int qz = oz ? m1 : m0;
+          if (X % sbw == 0)
+            part[vec * PARTV + ((((g * NC + Yc(c)) * 2 + ey_) * S + X / sbw) * S + qz) * N + j] += v;
+        }
   };
 
   // Clear the partials owned by this lane (region leaders) before a sweep.
@@ -674,15 +678,13 @@ __global__ __launch_bounds__((nt3<NC, GAL>())) void k_solve3d(CellArgs a) {
 
   auto zero_acc = [&](Acc& acc) {
 #pragma unroll
-    for (int c = 0; c < CPT; ++c)
+    for (int ex_ = 0; ex_ < 2; ++ex_)
 #pragma unroll
-      for (int ex_ = 0; ex_ < 2; ++ex_)
+      for (int ey_ = 0; ey_ < 2; ++ey_)
 #pragma unroll
-        for (int ey_ = 0; ey_ < 2; ++ey_)
+        for (int oz = 0; oz < 2; ++oz)
 #pragma unroll
-          for (int oz = 0; oz < 2; ++oz)
-#pragma unroll
-            for (int j = 0; j < N; ++j) acc[c][ex_][ey_][oz][j] = 0.0;
+          for (int j = 0; j < N; ++j) acc[ex_][ey_][oz][j] = 0.0;
   };
 
   // Row k of B_n (vector vec) summed over planes and node rows in fixed order.
@@ -720,34 +722,31 @@ __global__ __launch_bounds__((nt3<NC, GAL>())) void k_solve3d(CellArgs a) {
     return wave_sum(vu);
   };
 
-  // cw*v of the octant regions of the thread's columns for a segment.
-  auto load_vs = [&](Acc& vs, int m0, int m1) {
+  // cw*v of the octant regions of column c for a segment.
+  auto load_vs = [&](Acc& vs, int c, int m0, int m1) {
     const double* vv = vW + wave * m;
+    const int Y = Yc(c);
+    const int qy0 = (Y >= 1 ? Y - 1 : 0) / sbw, qy1 = Y / sbw;
 #pragma unroll
-    for (int c = 0; c < CPT; ++c) {
-      const int Y = Yc(c);
-      const int qy0 = (Y >= 1 ? Y - 1 : 0) / sbw, qy1 = Y / sbw;
+    for (int ex_ = 0; ex_ < 2; ++ex_)
 #pragma unroll
-      for (int ex_ = 0; ex_ < 2; ++ex_)
+      for (int ey_ = 0; ey_ < 2; ++ey_)
 #pragma unroll
-        for (int ey_ = 0; ey_ < 2; ++ey_)
+        for (int oz = 0; oz < 2; ++oz)
 #pragma unroll
-          for (int oz = 0; oz < 2; ++oz)
-#pragma unroll
-            for (int j = 0; j < N; ++j) {
-              const int qx = ex_ ? qx1 : qx0, qy = ey_ ? qy1 : qy0, qz = oz ? m1 : m0;
-              vs[c][ex_][ey_][oz][j] = vv[((qz * S + qy) * S + qx) * N + j];
-            }
-    }
+          for (int j = 0; j < N; ++j) {
+            const int qx = ex_ ? qx1 : qx0, qy = ey_ ? qy1 : qy0, qz = oz ? m1 : m0;
+            vs[ex_][ey_][oz][j] = vv[((qz * S + qy) * S + qx) * N + j];
+          }
   };
 
-  // (B_n^T cw v) at a node of column c.
-  auto scatB = [&](const Acc& vs, int c, const float (&w)[8][N]) -> double {
+  // (B_n^T cw v) at a node.
+  auto scatB = [&](const Acc& vs, const float (&w)[8][N]) -> double {
     double t = 0.0;
 #pragma unroll
     for (int o = 0; o < 8; ++o)
 #pragma unroll
-      for (int j = 0; j < N; ++j) t += (double)w[o][j] * vs[c][o & 1][(o >> 1) & 1][o >> 2][j];
+      for (int j = 0; j < N; ++j) t += (double)w[o][j] * vs[o & 1][(o >> 1) & 1][o >> 2][j];
     return t;
   };
 
@@ -797,8 +796,6 @@ __global__ __launch_bounds__((nt3<NC, GAL>())) void k_solve3d(CellArgs a) {
   constexpr bool ZM = G == 1;
   auto phaseA_zmarch = [&](double (&s4)[4]) {
     if constexpr (ZM) {
-      Acc accA;
-      zero_acc(accA);
       clear_part(1);
       auto ld_p = [&](int Yr, int Z) -> double {
         return (Yr >= 0 && Yr <= NC) ? pv[nidx3(X, Yr, Z, NP)] : 0.0;
@@ -807,57 +804,45 @@ __global__ __launch_bounds__((nt3<NC, GAL>())) void k_solve3d(CellArgs a) {
         return (Ye >= 0 && Ye <= NC - 1) ? kwc[X + NC * (Ye + NC * layer)] : 0.0;
       };
       constexpr int KW = GAL ? 1 : 2;  // element windows only on the fine level
-      double wp[CPT][3][3];     // [column][plane Z-1, Z, Z+1][row Y-1, Y, Y+1]
-      double kr[CPT][KW][KW];   // [column][layer Z-1, Z][oy]: elements (X, Y-1+oy)
-      double kl[CPT][KW][KW];   // the same for the elements (X-1, Y-1+oy)
-#pragma unroll
+#pragma unroll 1
       for (int c = 0; c < CPT; ++c) {
         const int Y = Yc(c);
+        Acc accA;
+        zero_acc(accA);
+        double wp[3][3];    // [plane Z-1, Z, Z+1][row Y-1, Y, Y+1]
+        double kr[KW][KW];  // [layer Z-1, Z][oy]: elements (X, Y-1+oy); (X-1, .) by DPP
 #pragma unroll
         for (int row = 0; row < 3; ++row) {
-          wp[c][0][row] = 0.0;
-          wp[c][1][row] = ld_p(Y - 1 + row, 1);
+          wp[0][row] = 0.0;
+          wp[1][row] = ld_p(Y - 1 + row, 1);
         }
         if constexpr (!GAL) {
 #pragma unroll
-          for (int oy = 0; oy < 2; ++oy) {
-            kr[c][0][oy] = ld_k(Y - 1 + oy, 0);
-            kl[c][0][oy] = from_left(kr[c][0][oy], X);
-          }
+          for (int oy = 0; oy < 2; ++oy) kr[0][oy] = ld_k(Y - 1 + oy, 0);
         }
-      }
 #pragma unroll 1
-      for (int Z = 1; Z <= NC - 1; ++Z) {
-        const int m0 = (Z - 1) / sbw, m1 = Z / sbw;
+        for (int Z = 1; Z <= NC - 1; ++Z) {
+          const int m0 = (Z - 1) / sbw, m1 = Z / sbw;
 #pragma unroll
-        for (int c = 0; c < CPT; ++c) {
-          const int Y = Yc(c);
-#pragma unroll
-          for (int row = 0; row < 3; ++row) wp[c][2][row] = (Z + 1 <= NC - 1) ? ld_p(Y - 1 + row, Z + 1) : 0.0;
+          for (int row = 0; row < 3; ++row) wp[2][row] = (Z + 1 <= NC - 1) ? ld_p(Y - 1 + row, Z + 1) : 0.0;
           if constexpr (!GAL) {
 #pragma unroll
-            for (int oy = 0; oy < 2; ++oy) kr[c][1][oy] = ld_k(Y - 1 + oy, Z);
+            for (int oy = 0; oy < 2; ++oy) kr[1][oy] = ld_k(Y - 1 + oy, Z);
           }
-        }
-#pragma unroll
-        for (int c = 0; c < CPT; ++c) {
-          const int Y = Yc(c);
           // neighbour (dx, dy, dz) of the node from the window
           auto nb = [&](int dx, int dy, int dz) -> double {
-            const double v = wp[c][dz + 1][dy + 1];
+            const double v = wp[dz + 1][dy + 1];
             return dx == 0 ? v : (dx < 0 ? from_left(v, X) : from_right(v, X, NC));
           };
           double Ap;
           if constexpr (!GAL) {
-#pragma unroll
-            for (int oy = 0; oy < 2; ++oy) kl[c][1][oy] = from_left(kr[c][1][oy], X);
             double k8[8];
 #pragma unroll
             for (int oz = 0; oz < 2; ++oz)
 #pragma unroll
               for (int oy = 0; oy < 2; ++oy) {
-                k8[2 * oy + 4 * oz] = kl[c][oz][oy];
-                k8[1 + 2 * oy + 4 * oz] = kr[c][oz][oy];
+                k8[2 * oy + 4 * oz] = from_left(kr[oz][oy], X);
+                k8[1 + 2 * oy + 4 * oz] = kr[oz][oy];
               }
             double t = 0.0;
 #pragma unroll
@@ -871,7 +856,7 @@ __global__ __launch_bounds__((nt3<NC, GAL>())) void k_solve3d(CellArgs a) {
               t += k4[0] * nb(-1, -1, sz) + k4[1] * nb(1, -1, sz) + k4[2] * nb(-1, 1, sz) + k4[3] * nb(1, 1, sz);
             }
             const double D = 4.0 * (((k8[0] + k8[1]) + (k8[2] + k8[3])) + ((k8[4] + k8[5]) + (k8[6] + k8[7])));
-            Ap = D * wp[c][1][1] - t;
+            Ap = D * wp[1][1] - t;
           } else {
             // Galerkin level: the node's 27 stored weights (row of K_n)
             const double* w = nW + node_of(Y, Z) * 27;
@@ -883,7 +868,7 @@ __global__ __launch_bounds__((nt3<NC, GAL>())) void k_solve3d(CellArgs a) {
           if (colfree(c)) {
             const size_t q = nidx3(X, Y, Z, NP);
             av[q] = Ap;
-            const double rn = rv[q], pn = wp[c][1][1];
+            const double rn = rv[q], pn = wp[1][1];
             const double di = dinv[node_of(Y, Z)];
             const double tr = di * rn, tA = di * Ap;
             s4[0] += pn * Ap;
@@ -892,25 +877,22 @@ __global__ __launch_bounds__((nt3<NC, GAL>())) void k_solve3d(CellArgs a) {
             s4[3] += Ap * tA;
             float w[8][N];
             node_weights(Y, Z, w);
-            accB(accA, c, w, tA);
+            accB(accA, w, tA);
           }
 #pragma unroll
           for (int row = 0; row < 3; ++row) {
-            wp[c][0][row] = wp[c][1][row];
-            wp[c][1][row] = wp[c][2][row];
+            wp[0][row] = wp[1][row];
+            wp[1][row] = wp[2][row];
           }
           if constexpr (!GAL) {
 #pragma unroll
-            for (int oy = 0; oy < 2; ++oy) {
-              kr[c][0][oy] = kr[c][1][oy];
-              kl[c][0][oy] = kl[c][1][oy];
-            }
+            for (int oy = 0; oy < 2; ++oy) kr[0][oy] = kr[1][oy];
           }
-        }
-        const int Zn = Z + 1;
-        if (Z == NC - 1 || (Zn - 1) / sbw != m0 || Zn / sbw != m1) {
-          flushB(accA, 1, m0, m1);
-          zero_acc(accA);
+          const int Zn = Z + 1;
+          if (Z == NC - 1 || (Zn - 1) / sbw != m0 || Zn / sbw != m1) {
+            flushB(accA, c, 1, m0, m1);
+            zero_acc(accA);
+          }
         }
       }
     }
@@ -931,17 +913,17 @@ __global__ __launch_bounds__((nt3<NC, GAL>())) void k_solve3d(CellArgs a) {
   (void)wave_schur(&vk);
   {
     Acc vs;
-    sweep([&](int m0, int m1) { load_vs(vs, m0, m1); },
+    sweep([&](int c, int m0, int m1) { load_vs(vs, c, m0, m1); },
           [&](int c, int Z) {
             const int Y = Yc(c);
             float w[8][N];
             node_weights(Y, Z, w);
-            const double x0 = dinv[node_of(Y, Z)] * scatB(vs, c, w);
+            const double x0 = dinv[node_of(Y, Z)] * scatB(vs, w);
             const size_t q = nidx3(X, Y, Z, NP);
             pv[q] = x0;
             xv[q] = x0;
           },
-          nop2);
+          nop3);
   }
   __syncthreads();
   // r0 = K x0 - f, t0 = D^-1 r0, r0.t0 and B t0
@@ -950,7 +932,7 @@ __global__ __launch_bounds__((nt3<NC, GAL>())) void k_solve3d(CellArgs a) {
     zero_acc(acc);
     clear_part(0);
     double s_rr = 0.0;
-    sweep(nop2,
+    sweep(nop3,
           [&](int c, int Z) {
             const int Y = Yc(c);
             float w[8][N];
@@ -959,11 +941,11 @@ __global__ __launch_bounds__((nt3<NC, GAL>())) void k_solve3d(CellArgs a) {
             const double rr0 = applyK(pv, Y, Z) - rhs(Y, Z);
             const double t = dinv[node_of(Y, Z)] * rr0;
             s_rr += rr0 * t;
-            accB(acc, c, w, t);
+            accB(acc, w, t);
             rv[q] = rr0;
           },
-          [&](int m0, int m1) {
-            flushB(acc, 0, m0, m1);
+          [&](int c, int m0, int m1) {
+            flushB(acc, c, 0, m0, m1);
             zero_acc(acc);
           });
     s_rr = wave_sum(s_rr);
@@ -978,17 +960,17 @@ __global__ __launch_bounds__((nt3<NC, GAL>())) void k_solve3d(CellArgs a) {
   const double rz0 = rz;
   {
     Acc vs;
-    sweep([&](int m0, int m1) { load_vs(vs, m0, m1); },
+    sweep([&](int c, int m0, int m1) { load_vs(vs, c, m0, m1); },
           [&](int c, int Z) {
             const int Y = Yc(c);
             float w[8][N];
             node_weights(Y, Z, w);
             const size_t q = nidx3(X, Y, Z, NP);
-            const double rp = rv[q] - scatB(vs, c, w);
+            const double rp = rv[q] - scatB(vs, w);
             rv[q] = rp;
             pv[q] = -dinv[node_of(Y, Z)] * rp;
           },
-          nop2);
+          nop3);
   }
   __syncthreads();
 
@@ -1005,7 +987,7 @@ __global__ __launch_bounds__((nt3<NC, GAL>())) void k_solve3d(CellArgs a) {
       Acc accA;
       zero_acc(accA);
       clear_part(1);
-      sweep(nop2,
+      sweep(nop3,
             [&](int c, int Z) {
               const int Y = Yc(c);
               const size_t q = nidx3(X, Y, Z, NP);
@@ -1020,10 +1002,10 @@ __global__ __launch_bounds__((nt3<NC, GAL>())) void k_solve3d(CellArgs a) {
               s4[3] += Ap * tA;
               float w[8][N];
               node_weights(Y, Z, w);
-              accB(accA, c, w, tA);
+              accB(accA, w, tA);
             },
-            [&](int m0, int m1) {
-              flushB(accA, 1, m0, m1);
+            [&](int c, int m0, int m1) {
+              flushB(accA, c, 1, m0, m1);
               zero_acc(accA);
             });
     }
@@ -1032,15 +1014,15 @@ __global__ __launch_bounds__((nt3<NC, GAL>())) void k_solve3d(CellArgs a) {
       Acc accT;
       zero_acc(accT);
       clear_part(0);
-      sweep(nop2,
+      sweep(nop3,
             [&](int c, int Z) {
               const int Y = Yc(c);
               float w[8][N];
               node_weights(Y, Z, w);
-              accB(accT, c, w, dinv[node_of(Y, Z)] * rv[nidx3(X, Y, Z, NP)]);
+              accB(accT, w, dinv[node_of(Y, Z)] * rv[nidx3(X, Y, Z, NP)]);
             },
-            [&](int m0, int m1) {
-              flushB(accT, 0, m0, m1);
+            [&](int c, int m0, int m1) {
+              flushB(accT, c, 0, m0, m1);
               zero_acc(accT);
             });
     }
@@ -1063,12 +1045,12 @@ __global__ __launch_bounds__((nt3<NC, GAL>())) void k_solve3d(CellArgs a) {
     const double rzn = rDr - vu;
     ++it;
     if (rzn <= tol2 || it >= a.max_iter) {
-      sweep(nop2,
+      sweep(nop3,
             [&](int c, int Z) {
               const size_t q = nidx3(X, Yc(c), Z, NP);
               xv[q] += al * pv[q];
             },
-            nop2);
+            nop3);
       rz = rzn;
       break;
     }
@@ -1077,7 +1059,7 @@ __global__ __launch_bounds__((nt3<NC, GAL>())) void k_solve3d(CellArgs a) {
     // phase B: x, projected residual and the new direction
     {
       Acc vs;
-      sweep([&](int m0, int m1) { load_vs(vs, m0, m1); },
+      sweep([&](int c, int m0, int m1) { load_vs(vs, c, m0, m1); },
             [&](int c, int Z) {
               const int Y = Yc(c);
               float w[8][N];
@@ -1085,11 +1067,11 @@ __global__ __launch_bounds__((nt3<NC, GAL>())) void k_solve3d(CellArgs a) {
               const size_t q = nidx3(X, Y, Z, NP);
               const double pn = pv[q];
               xv[q] += al * pn;
-              const double rn = rv[q] + al * av[q] - scatB(vs, c, w);
+              const double rn = rv[q] + al * av[q] - scatB(vs, w);
               rv[q] = rn;
               pv[q] = -dinv[node_of(Y, Z)] * rn + be * pn;
             },
-            nop2);
+            nop3);
     }
     __syncthreads();
   }
