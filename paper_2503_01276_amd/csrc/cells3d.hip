@@ -29,7 +29,6 @@ namespace mch {
 
 constexpr int T3 = 256;   // threads of the set-up and auxiliary kernels
 constexpr int S3D = 2;    // constraint sub-blocks per axis handled by the 3D solve
-constexpr int kXcds = 8;  // accelerator complex dies; workgroups are dealt to them round robin
 
 MCH_DEV size_t nidx3(int X, int Y, int Z, int NP) {
   return (size_t)X + (size_t)NP * ((size_t)Y + (size_t)NP * (size_t)Z);
@@ -197,6 +196,19 @@ __global__ __launch_bounds__(T3) void k_setup3d(CellArgs a) {
       lbc[e] = a.label[ge];
     }
     __syncthreads();
+    // labels of every node's eight octant elements, 2 bits each (3 = none)
+    uint16_t* octc = a.octw + (size_t)ci * nodes;
+    for (int nd = tid; nd < (int)nodes; nd += T3) {
+      const int X = nd % NC, Y = (nd / NC) % NC, Z = nd / (NC * NC);
+      unsigned code = 0;
+      if (X >= 1 && Y >= 1 && Z >= 1) {
+        for (int o = 0; o < 8; ++o) {
+          const int lab = lbc[(X - 1 + (o & 1)) + NC * ((Y - 1 + ((o >> 1) & 1)) + NC * (Z - 1 + (o >> 2)))];
+          code |= (unsigned)(lab < 3 ? lab : 3) << (2 * o);
+        }
+      }
+      octc[nd] = (uint16_t)code;
+    }
     for (int nd = tid; nd < (int)nodes; nd += T3) {
       const int X = nd % NC, Y = (nd / NC) % NC, Z = nd / (NC * NC);
       if (X >= 1 && Y >= 1 && Z >= 1) {
@@ -537,7 +549,7 @@ __global__ __launch_bounds__((nt3<NC, GAL>())) __attribute__((amdgpu_waves_per_e
   double* __restrict__ av = a.vap + vbase;
   const double* __restrict__ dinv = a.dinv + (size_t)ci * NODES;
   const double* __restrict__ kwc = GAL ? nullptr : a.kw + (size_t)ci * NODES;
-  const uint8_t* __restrict__ lbc = GAL ? nullptr : a.labw + (size_t)ci * NODES;
+  const uint16_t* __restrict__ octc = GAL ? nullptr : a.octw + (size_t)ci * NODES;
   const double* __restrict__ nW = GAL ? a.nodeW + (size_t)ci * NODES * 27 : nullptr;
   const float* __restrict__ nB = GAL ? a.nodeB + (size_t)ci * NODES * 8 * N : nullptr;
   const int qx0 = (X >= 1 ? X - 1 : 0) / sbw, qx1 = X / sbw;
@@ -621,11 +633,13 @@ __global__ __launch_bounds__((nt3<NC, GAL>())) __attribute__((amdgpu_waves_per_e
   // Constraint weights of node (X, Y, Z) per octant element and continuum.
   auto node_weights = [&](int Y, int Z, float (&w)[8][N]) {
     if constexpr (!GAL) {
+      // one 16-bit load: the labels of the eight octant elements
+      const unsigned code = octc[node_of(Y, Z)];
 #pragma unroll
       for (int o = 0; o < 8; ++o) {
-        const int lab = lbc[(X - 1 + (o & 1)) + NC * ((Y - 1 + ((o >> 1) & 1)) + NC * (Z - 1 + (o >> 2)))];
+        const unsigned lab = (code >> (2 * o)) & 3u;
 #pragma unroll
-        for (int j = 0; j < N; ++j) w[o][j] = (lab == j) ? 1.0f : 0.0f;
+        for (int j = 0; j < N; ++j) w[o][j] = (lab == (unsigned)j) ? 1.0f : 0.0f;
       }
     } else {
       const float* b = nB + node_of(Y, Z) * 8 * N;

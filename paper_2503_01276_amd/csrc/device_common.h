@@ -9,6 +9,9 @@
 namespace mch {
 
 constexpr int WAVE = 64;
+// Accelerator complex dies; a launch's workgroups are dealt to them round
+// robin (workgroup b runs on die b mod kXcds), each die with its own L2.
+constexpr int kXcds = 8;
 
 MCH_DEV int wrapi(int i, int n) {
   int r = i % n;
@@ -184,6 +187,7 @@ struct CellArgs {
   // and Phi on the K_p nodes of every point
   double* kw;             // fine level: [count][NC^3] kappa*h/12
   uint8_t* labw;          // fine level: [count][NC^3] labels
+  uint16_t* octw;         // fine level: [count][NC^3] labels of the 8 octant elements of each node, 2 bits each (3 = none)
   double* dinv;           // [count][NC^3]
   double* vr;             // [count][M][(NC+1)^3]
   double* vp;

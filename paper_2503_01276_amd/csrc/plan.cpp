@@ -541,6 +541,7 @@ extern "C" int mch_build_levels(const mch_config* cfg, mch_plan** out) {
       if (lv.r == 1) {
         if ((rc = dev_alloc(p, &lv.d_kw, (size_t)lv.count * nodes))) break;
         if ((rc = dev_alloc(p, &lv.d_labw, (size_t)lv.count * nodes))) break;
+        if ((rc = dev_alloc(p, &lv.d_octw, (size_t)lv.count * nodes))) break;
       }
       const size_t padded = (size_t)lv.count * p->M * ipow(lv.NC + 1, 3);
       if ((rc = dev_alloc(p, &lv.d_dinv, (size_t)lv.count * nodes))) break;

@@ -49,6 +49,7 @@ struct Level {
   // r, p, K_n p of every (cell, rhs) [count][M][(NC+1)^3] (zero boundary)
   double* d_kw = nullptr;
   uint8_t* d_labw = nullptr;
+  uint16_t* d_octw = nullptr;   // 3D fine level: octant label codes per node [count][NC^3]
   double* d_dinv = nullptr;
   double* d_vr = nullptr;
   double* d_vp = nullptr;

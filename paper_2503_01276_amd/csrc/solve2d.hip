@@ -124,6 +124,7 @@ CellArgs base_args(mch_plan* pl, const double* kappa, const uint8_t* label, int 
   a.max_iter = pl->cfg.max_iter;
   a.kw = lv.d_kw;
   a.labw = lv.d_labw;
+  a.octw = lv.d_octw;
   a.dinv = lv.d_dinv;
   a.vr = lv.d_vr;
   a.vp = lv.d_vp;

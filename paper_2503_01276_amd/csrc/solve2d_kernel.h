@@ -101,7 +101,27 @@ __global__ __launch_bounds__(NC* NC / RPT) __attribute__((amdgpu_waves_per_eu(2)
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int c = tid % NC, band = tid / NC, y0 = band * RPT;
-  const int ci = a.ci0 + blockIdx.x / M, alpha = blockIdx.x % M;
+  // The M right-hand sides of a cell read the same kappa and label window
+  // (or Galerkin stencils). Workgroups are numbered so that they land on one
+  // XCD and share its L2: in a group of kXcds cells (kXcds M workgroups),
+  // workgroup b takes cell b mod kXcds of the group and right-hand side
+  // (b mod kXcds M) / kXcds. The cells after the last whole group (fewer
+  // than kXcds) take their workgroups in plain order, so the grid is exactly
+  // count M workgroups.
+  int cl, alpha;
+  {
+    const int whole = (a.count / kXcds) * kXcds * M;
+    const int b = blockIdx.x;
+    if (b < whole) {
+      const int grp = b / (kXcds * M), rb = b % (kXcds * M);
+      cl = grp * kXcds + rb % kXcds;
+      alpha = rb / kXcds;
+    } else {
+      cl = (a.count / kXcds) * kXcds + (b - whole) / M;
+      alpha = (b - whole) % M;
+    }
+  }
+  const int ci = a.ci0 + cl;
   const int p = a.cells[ci];
   const int jx = p % a.n_macro, jy = p / a.n_macro;
   const int ox = a.H * jx + a.H / 2 - a.nc / 2, oy = a.H * jy + a.H / 2 - a.nc / 2;
