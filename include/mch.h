@@ -85,7 +85,9 @@ typedef struct {
   int32_t eta;          /* coarsening factor >= 1; n_macro divisible by eta^(L-1) */
   int32_t interp;       /* 0: inherit the level-1 solution of the group (the paper's experiments);
                            1: multilinear interpolation from T_(n-1) */
-  int32_t bc;           /* 0: homogeneous Dirichlet on the cell boundary (only mode implemented) */
+  int32_t bc;           /* cell boundary condition (Sec. 2, the artificial conditions on R_p^+):
+                           0: homogeneous Dirichlet; 1: natural Neumann, every cell node free
+                           (2D only, interp = 0; solved by the generic 2D kernel) */
   double rtol;          /* relative tolerance on the projected preconditioned residual norm */
   int32_t max_iter;     /* Krylov iteration cap per solve */
 } mch_config;
@@ -95,6 +97,10 @@ typedef struct mch_plan mch_plan;
 /* Build the macrogrid hierarchy (Algorithm 1 steps 1-2; Sec. 3.1-3.2),
  * validate the configuration, choose kernels per size class, and allocate the
  * plan's device scratch on the current HIP device. Synchronous.
+ * 2D levels run on the register-resident solve kernel where one is
+ * instantiated for the level's shape (widths 8..64, Dirichlet cells), else on
+ * the generic kernel (Krylov vectors in device memory): Neumann cells, cells
+ * up to 128 fine elements wide, any width divisible by n_sub, n_sub <= 8.
  * Returns MCH_EINVAL for inconsistent sizes, MCH_ESINGULAR when the coarsest
  * level has more constraint rows than free unknowns, MCH_ENOTIMPL for a mode
  * outside the implemented ones, MCH_EHIP on allocation failure.
@@ -122,7 +128,8 @@ int mch_build_interp(const mch_config* cfg, int32_t* nbr, double* weight);
  * info[2] = m (constraint rows per cell, including inactive ones),
  * info[3] = L, info[4..4+L) = number of macropoints of each level,
  * info[4+L..4+2L) = node rows per thread of each level's 2D solve kernel (the
- * size-class shape: the workgroup has NC^2 / rows threads; 0 in 3D),
+ * size-class shape: the workgroup has NC^2 / rows threads; 0 in 3D and for
+ * levels on the generic 2D kernel),
  * info[4+2L..4+3L) = 1 where the level's 2D solve preconditions with the band
  * coarse correction, 0 where with the diagonal alone (and in 3D), the rest
  * zero. info must hold at least 28 entries (4 + 3 * 8 levels). */

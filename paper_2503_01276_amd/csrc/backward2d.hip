@@ -160,12 +160,14 @@ struct LevelTab {
 };
 
 // Seeds of level-1 cell t for right-hand side alpha: sum over its inheriting
-// cells c of Ibar_c = Phibar_c - K_h(c) P w_c - B_h(c)^T mu_c on the fine nodes.
-// 1024 threads; a thread owns up to IB_NODES fine nodes and keeps their sums
-// in registers; per child the LDS holds P w, kappa/6, labels and cw*mu (about
-// 70 KB for 64^2 cells).
+// cells c of Ibar_c = Phibar_c - K_h(c) P w_c - B_h(c)^T mu_c on the free fine
+// nodes. 1024 threads; a thread owns up to NODES fine nodes and keeps their
+// sums in registers; per child the LDS holds P w, labels, cw*mu and (KLDS)
+// kappa/6: about 70 KB for 64^2 cells; 128^2 cells read kappa from global
+// memory instead (P w alone is 133 KB there).
 constexpr int IBT = 1024;
-constexpr int IB_NODES = 5;  // ceil(65^2 / 1024): cells up to 64 elements wide
+constexpr int IB_NODES = 5;       // ceil(65^2 / 1024): cells up to 64 elements wide
+constexpr int IB_NODES_BIG = 17;  // ceil(129^2 / 1024): cells up to 128 elements wide
 
 // prolong_at for a power-of-two ratio r = 2^sh (inv = 1 / r): shifts and
 // masks instead of integer division, the same interpolation formula.
@@ -178,22 +180,24 @@ MCH_DEV double prolong_p2(const double* v, int sh, double inv, int NC, int X, in
          (1 - tx) * ty * v[cy1 * NCp + cx] + tx * ty * v[cy1 * NCp + cx1];
 }
 
+template <int NODES, bool KLDS>
 __global__ __launch_bounds__(IBT) void k_ibar2d(CellArgs a, LevelTab lt, const int32_t* level, const int32_t* child_ptr,
                                                 const int32_t* child, const double* mu, double* seed_par,
                                                 int only_level, int accumulate) {
   extern __shared__ double sm[];
   const int nc = a.nc, nn1 = nc + 1, H = a.H, Hp = H + 1, m = a.m, N = a.N, s = a.s;
   const int nn = nn1 * nn1;
-  double* pwS = sm;                  // [nn1^2]
-  double* kS = pwS + nn;             // [nc^2] kappa/6
-  double* cmS = kS + nc * nc;        // [m] cw * mu
+  const int flo = a.bc ? 0 : 1, fhi = a.bc ? nc : nc - 1;  // free fine nodes
+  double* pwS = sm;                       // [nn1^2]
+  double* kS = pwS + nn;                  // KLDS: [nc^2] kappa/6
+  double* cmS = KLDS ? kS + nc * nc : kS; // [m] cw * mu
   uint8_t* labS = reinterpret_cast<uint8_t*>(cmS + m);  // [nc^2]
   const int tid = threadIdx.x;
   const int t = a.ci0 + blockIdx.x / a.M, al = blockIdx.x % a.M;
   const int k0 = (nc - H) / 2, sb = nc / s;
-  double acc[IB_NODES];
+  double acc[NODES];
 #pragma unroll
-  for (int i = 0; i < IB_NODES; ++i) acc[i] = 0.0;
+  for (int i = 0; i < NODES; ++i) acc[i] = 0.0;
   for (int ch = child_ptr[t]; ch < child_ptr[t + 1]; ++ch) {
     const int p = child[ch];
     const int l = level[p] - 1;
@@ -205,7 +209,7 @@ __global__ __launch_bounds__(IBT) void k_ibar2d(CellArgs a, LevelTab lt, const i
     for (int e = tid; e < nc * nc; e += IBT) {
       const int ex = e % nc, ey = e / nc;
       const size_t ge = (size_t)wrapi(oy + ey, a.n) * a.n + wrapi(ox + ex, a.n);
-      kS[e] = a.kappa[ge] * (1.0 / 6.0);
+      if constexpr (KLDS) kS[e] = a.kappa[ge] * (1.0 / 6.0);
       labS[e] = a.label[ge];
     }
     for (int k = tid; k < m; k += IBT) cmS[k] = a.cw[(size_t)p * m + k] * mu[((size_t)p * a.M + al) * m + k];
@@ -221,11 +225,11 @@ __global__ __launch_bounds__(IBT) void k_ibar2d(CellArgs a, LevelTab lt, const i
     __syncthreads();
     const double* skp = a.seed_kp + ((size_t)p * a.M + al) * Hp * Hp;
 #pragma unroll
-    for (int i = 0; i < IB_NODES; ++i) {
+    for (int i = 0; i < NODES; ++i) {
       const int nd = tid + i * IBT;
       if (nd >= nn) break;
       const int X = nd % nn1, Y = nd / nn1;
-      if (X < 1 || Y < 1 || X >= nc || Y >= nc) continue;
+      if (X < flo || Y < flo || X > fhi || Y > fhi) continue;
       double v[3][3];
 #pragma unroll
       for (int dy = 0; dy < 3; ++dy)
@@ -236,11 +240,17 @@ __global__ __launch_bounds__(IBT) void k_ibar2d(CellArgs a, LevelTab lt, const i
       for (int q = 0; q < 4; ++q) {
         const int qx = q & 1, qy = q >> 1;
         const int ex = X - 1 + qx, ey = Y - 1 + qy;
+        if (ex < 0 || ey < 0 || ex >= nc || ey >= nc) continue;  // outside the cell (Neumann boundary)
         const int e = ey * nc + ex;
         const double c[4] = {v[qy][qx], v[qy][qx + 1], v[qy + 1][qx], v[qy + 1][qx + 1]};
         // the node is corner cn of the element: row cn of 6 K_ref only
         const int cn = (1 - qx) + 2 * (1 - qy);
-        kpw += kS[e] * (4.0 * c[cn] - 2.0 * c[cn ^ 3] - c[cn ^ 1] - c[cn ^ 2]);
+        double ke;
+        if constexpr (KLDS)
+          ke = kS[e];
+        else
+          ke = a.kappa[(size_t)wrapi(oy + ey, a.n) * a.n + wrapi(ox + ex, a.n)] * (1.0 / 6.0);
+        kpw += ke * (4.0 * c[cn] - 2.0 * c[cn ^ 3] - c[cn ^ 1] - c[cn ^ 2]);
         const int lab = labS[e];
         if (lab < N) btmu += cmS[((ey / sb) * s + ex / sb) * N + lab];
       }
@@ -251,10 +261,27 @@ __global__ __launch_bounds__(IBT) void k_ibar2d(CellArgs a, LevelTab lt, const i
   }
   double* dst = seed_par + ((size_t)t * a.M + al) * nn;
 #pragma unroll
-  for (int i = 0; i < IB_NODES; ++i) {
+  for (int i = 0; i < NODES; ++i) {
     const int nd = tid + i * IBT;
     if (nd < nn) dst[nd] = accumulate ? dst[nd] + acc[i] : acc[i];
   }
+}
+
+using IbarFn = void (*)(CellArgs, LevelTab, const int32_t*, const int32_t*, const int32_t*, const double*, double*,
+                       int, int);
+// The parent-seed kernel for cells nc elements wide and its LDS bytes (nullptr
+// beyond 128 elements).
+static IbarFn ibar_kernel(int nc, int m, size_t* lds) {
+  const size_t nn = (size_t)(nc + 1) * (nc + 1), e = (size_t)nc * nc;
+  if (nc <= 64) {
+    *lds = (nn + e + m) * sizeof(double) + e;
+    return k_ibar2d<IB_NODES, true>;
+  }
+  if (nc <= 128) {
+    *lds = (nn + m) * sizeof(double) + e;
+    return k_ibar2d<IB_NODES_BIG, false>;
+  }
+  return nullptr;
 }
 
 // dst[i] += b_1[i] + ... in the order given (the per-level parent seeds)
@@ -329,9 +356,10 @@ static int launch_backward_2d_chain(mch_plan* pl, const double* kappa, const dou
     case 9: seed = k_seed2d<9>; break;
     default: return set_error(MCH_ENOTIMPL, "M");
   }
-  if (nc > 64) return set_error(MCH_ENOTIMPL, "2D cells wider than 64 elements");
-  const size_t lds_ibar = ((size_t)nn1 * nn1 + (size_t)nc * nc + pl->m) * sizeof(double) + (size_t)nc * nc;
-  int rc = set_lds(k_ibar2d, lds_ibar);
+  size_t lds_ibar = 0;
+  const IbarFn ibar = ibar_kernel(nc, pl->m, &lds_ibar);
+  if (!ibar) return set_error(MCH_ENOTIMPL, "2D cells wider than 128 elements");
+  int rc = set_lds(ibar, lds_ibar);
   if (!rc) rc = ensure_streams(pl);
   if (!rc) rc = launch_zero(pl->d_seedT, (size_t)pl->nT * M * pl->nn, s);
   if (!rc) rc = fork_levels(pl, s);
@@ -379,7 +407,7 @@ static int launch_backward_2d_chain(mch_plan* pl, const double* kappa, const dou
       // cell its own single "child") into d_ibar, row = cell index
       {
         ProfScope ps(pl, "ibar", s);
-        hipLaunchKernelGGL(k_ibar2d, dim3(lv.count * M), dim3(IBT), lds_ibar, s, a1, lt, pl->d_level, pl->d_iptr,
+        hipLaunchKernelGGL(ibar, dim3(lv.count * M), dim3(IBT), lds_ibar, s, a1, lt, pl->d_level, pl->d_iptr,
                            lv.d_cells, pl->d_mu, pl->d_ibar, l, 0);
         rc = hip_check(hipGetLastError(), "launch k_ibar2d");
       }
@@ -448,9 +476,10 @@ int launch_backward_2d(mch_plan* pl, const double* kappa, const double* gA, doub
     lt.NC[l] = pl->lev[l].NC;
     lt.w[l] = pl->lev[l].d_w;
   }
-  if (nc > 64) return set_error(MCH_ENOTIMPL, "2D cells wider than 64 elements");
-  const size_t lds_ibar = ((size_t)nn1 * nn1 + (size_t)nc * nc + pl->m) * sizeof(double) + (size_t)nc * nc;
-  if (inherit && (rc = set_lds(k_ibar2d, lds_ibar))) return rc;
+  size_t lds_ibar = 0;
+  const IbarFn ibar = ibar_kernel(nc, pl->m, &lds_ibar);
+  if (!ibar) return set_error(MCH_ENOTIMPL, "2D cells wider than 128 elements");
+  if (inherit && (rc = set_lds(ibar, lds_ibar))) return rc;
   // Parent seeds from the cells of one inheriting level, on that level's
   // stream once its adjoint solve is done, into a buffer of its own (the
   // deepest level's straight into d_seed_par), so the passes run in parallel;
@@ -464,7 +493,7 @@ int launch_backward_2d(mch_plan* pl, const double* kappa, const double* gA, doub
     int r = MCH_OK;
     {
       ProfScope ps(pl, "ibar", t);
-      hipLaunchKernelGGL(k_ibar2d, dim3(n1 * M), dim3(IBT), lds_ibar, t, a1, lt, pl->d_level, pl->d_child_ptr,
+      hipLaunchKernelGGL(ibar, dim3(n1 * M), dim3(IBT), lds_ibar, t, a1, lt, pl->d_level, pl->d_child_ptr,
                          pl->d_child, pl->d_mu, dst, l, 0);
       r = hip_check(hipGetLastError(), "launch k_ibar2d");
     }

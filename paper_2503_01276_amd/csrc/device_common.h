@@ -163,11 +163,13 @@ struct CellArgs {
   // Galerkin tables for this level: T[r*r][16] (R^T K_ref R), rho[r*r][4]
   const double* tabK;
   const double* tabR;
-  // Galerkin level data written by the setup kernel, per cell of this level:
-  // 9-point stencil per owned node [count][NC*NC][9] and constraint weights per
+  // Galerkin level data written by the setup kernel, per cell of this level
+  // (2D, every level node (X, Y) in [0, NC]^2 at Y (NC+1) + X):
+  // 9-point stencil per node [count][(NC+1)^2][9] and constraint weights per
   // node, side (0: element column X-1, 1: column X), part (0: element row Y-1,
-  // 1: row Y) and continuum [count][NC*NC][4][N]; inherited right-hand sides
-  // f [count][M][NC*NC] and g' [count][M][m] from the inherit kernel.
+  // 1: row Y) and continuum [count][(NC+1)^2][4][N]; inherited right-hand
+  // sides f [count][M][(NC+1)^2] and g' [count][M][m] from the inherit kernel.
+  // (3D: the owned nodes [0, NC)^3.)
   double* nodeW;
   float* nodeB;
   double* fin;
@@ -183,13 +185,19 @@ struct CellArgs {
   const int32_t* slot;    // [P] index of the point within its level
   double rtol;
   int max_iter;
+  // cell boundary condition: 0 homogeneous Dirichlet (free level nodes
+  // [1, NC-1]^d), 1 natural Neumann (every node [0, NC]^d free)
+  int bc;
+  // 2D generic solve kernel: threads per constraint sub-block (0: the
+  // register-resident kernel of the level's shape)
+  int gen_tp;
   // 3D cells (unused in 2D): windows, D^-1 and Krylov vectors of this level,
   // and Phi on the K_p nodes of every point
   double* kw;             // fine level: [count][NC^3] kappa*h/12
   uint8_t* labw;          // fine level: [count][NC^3] labels
   uint16_t* octw;         // fine level: [count][NC^3] labels of the 8 octant elements of each node, 2 bits each (3 = none)
-  double* dinv;           // [count][NC^3]
-  double* vr;             // [count][M][(NC+1)^3]
+  double* dinv;           // 3D: [count][NC^3]; 2D generic kernel: [count][M][(NC+1)^2]
+  double* vr;             // 3D: [count][M][(NC+1)^3]; 2D generic kernel: [count][M][(NC+3)^2] (ring of zeros)
   double* vp;
   double* vap;
   double* phikp;          // [P][M][(H+1)^3]

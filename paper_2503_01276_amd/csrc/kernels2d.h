@@ -9,8 +9,12 @@ namespace mch {
 CellArgs base_args(mch_plan* pl, const double* kappa, const uint8_t* label, int l);
 // The same arguments restricted to cells [start, start + count) of the level.
 CellArgs chunk_args(const CellArgs& a, int start, int count);
-// Launch the constrained Krylov solve of every (cell, right-hand side) of a.
+// Launch the constrained Krylov solve of every (cell, right-hand side) of a
+// (the generic kernel when a.gen_tp > 0).
 int launch_solve(const CellArgs& a, int rpt, hipStream_t s);
+int launch_solve_generic(const CellArgs& a, hipStream_t s);
+// Workgroups of the generic solve kernel that fit on one CU at once.
+int generic_blocks_per_cu(const CellArgs& a);
 
 // Lanes per row of the per-wave Schur solve: the largest power of two J with
 // J m <= 64, so the m rows of S^-1 u fit one wave.

@@ -52,6 +52,23 @@ static int default_rpt(int NC, int sbw) {
   return 0;
 }
 
+// 2D level of width NCl: 0 for the register-resident solve kernel, else the
+// generic kernel's threads per sub-block tile (Neumann cells, widths without
+// an instantiated shape, or MCH_GENERIC=1); -1 if neither kernel takes it.
+static int generic_choice_2d(const mch_config& c, int NCl, int r) {
+  const int sbw = c.n_cell / c.n_sub / r;
+  bool gen = c.bc != 0;
+  if (const char* v = std::getenv("MCH_GENERIC")) gen = gen || std::atoi(v) != 0;
+  if (!gen) {
+    const int rpt = default_rpt(NCl, sbw);
+    if (rpt != 0 && shape_supported_2d(NCl, rpt, c.n_cont, r > 1, c.n_sub)) return 0;
+  }
+  // the per-cell kernels around the solve hold a fine cell's nodes in LDS
+  if (c.n_cell > 128) return -1;
+  const int tp = generic_tile_threads(c.n_sub);
+  return tp > 0 ? tp : -1;
+}
+
 template <typename T>
 static int dev_alloc(mch_plan* p, T** ptr, size_t count) {
   *ptr = nullptr;
@@ -358,7 +375,9 @@ extern "C" int mch_build_levels(const mch_config* cfg, mch_plan** out) {
   if (c.n_cont < 1 || c.n_cont > 3) return set_error(MCH_EINVAL, "n_cont must be 1..3");
   if (c.n_sub < 1) return set_error(MCH_EINVAL, "n_sub must be >= 1");
   if (c.interp != 0 && c.interp != 1) return set_error(MCH_EINVAL, "interp must be 0 or 1");
-  if (c.bc != 0) return set_error(MCH_ENOTIMPL, "only bc = 0 (homogeneous Dirichlet) is implemented");
+  if (c.bc != 0 && c.bc != 1) return set_error(MCH_EINVAL, "bc must be 0 (Dirichlet) or 1 (Neumann)");
+  if (c.bc == 1 && c.dim == 3) return set_error(MCH_ENOTIMPL, "Neumann cells are implemented in 2D only");
+  if (c.bc == 1 && c.interp == 1) return set_error(MCH_ENOTIMPL, "Neumann cells with multilinear inheritance");
   if (!(c.rtol > 0.0) || c.max_iter < 1) return set_error(MCH_EINVAL, "rtol must be > 0 and max_iter >= 1");
   const int nc = c.n_cell;
   const int gL = ipow(c.eta, c.levels - 1);
@@ -380,7 +399,7 @@ extern "C" int mch_build_levels(const mch_config* cfg, mch_plan** out) {
   p->m = c.n_cont * ipow(c.n_sub, d);
   p->nn = ipow(nc + 1, d);
   const int coarsest = nc / gL;
-  const int free_coarsest = ipow(coarsest - 1, d);
+  const int free_coarsest = ipow(c.bc ? coarsest + 1 : coarsest - 1, d);
   if (p->m > 64) {
     delete p;
     return set_error(MCH_ENOTIMPL, "more than 64 constraint rows per cell");
@@ -403,11 +422,12 @@ extern "C" int mch_build_levels(const mch_config* cfg, mch_plan** out) {
       }
       continue;
     }
-    const int rpt = default_rpt(NCl, sbw);
-    if (rpt == 0 || !shape_supported_2d(NCl, rpt, c.n_cont, r > 1, c.n_sub)) {
+    (void)sbw;
+    if (generic_choice_2d(c, NCl, r) < 0) {
       delete p;
-      return set_error(MCH_ENOTIMPL, "no kernel instantiated for level cell width " + std::to_string(NCl) +
-                                         " rows/thread " + std::to_string(rpt) + " N=" + std::to_string(c.n_cont));
+      return set_error(MCH_ENOTIMPL, "no 2D solve kernel for level cell width " + std::to_string(NCl) + " n_sub=" +
+                                         std::to_string(c.n_sub) + " n_cell=" + std::to_string(nc) +
+                                         " (the generic kernel takes n_cell <= 128 and n_sub <= 8)");
     }
   }
   if (const char* v = std::getenv("MCH_GRAPHS")) p->use_graphs = std::atoi(v) != 0;
@@ -446,6 +466,10 @@ extern "C" int mch_build_levels(const mch_config* cfg, mch_plan** out) {
                                          " n_sub=" + std::to_string(c.n_sub) + " N=" + std::to_string(c.n_cont));
         break;
       }
+    } else if ((lv.shape.gen_tp = generic_choice_2d(c, lv.NC, lv.r)) > 0) {
+      lv.shape.rpt = 0;
+      lv.shape.threads = (lv.shape.gen_tp * c.n_sub * c.n_sub + 63) / 64 * 64;
+      lv.shape.pre = false;
     } else {
       lv.shape.rpt = default_rpt(lv.NC, sbw);
       lv.shape.threads = lv.NC * lv.NC / lv.shape.rpt;
@@ -464,7 +488,7 @@ extern "C" int mch_build_levels(const mch_config* cfg, mch_plan** out) {
       if (const char* v = std::getenv(pname)) want = std::atoi(v) != 0;
       lv.shape.pre = want && prec_supported_2d(lv.NC, lv.shape.rpt, c.n_cont, lv.r > 1, c.n_sub, p->m);
     }
-    if (d == 2 && !shape_supported_2d(lv.NC, lv.shape.rpt, c.n_cont, lv.r > 1, c.n_sub)) {
+    if (d == 2 && lv.shape.gen_tp == 0 && !shape_supported_2d(lv.NC, lv.shape.rpt, c.n_cont, lv.r > 1, c.n_sub)) {
       rc = set_error(MCH_ENOTIMPL, "no kernel instantiated for level cell width " + std::to_string(lv.NC) +
                                        " rows/thread " + std::to_string(lv.shape.rpt) + " N=" +
                                        std::to_string(c.n_cont));
@@ -485,7 +509,16 @@ extern "C" int mch_build_levels(const mch_config* cfg, mch_plan** out) {
     const size_t rows = (l == 0 && ml) ? (size_t)p->nT : (size_t)lv.count;
     if ((rc = dev_alloc(p, &lv.d_out, rows * p->M * vec))) break;
     if ((rc = dev_alloc(p, &lv.d_w, (size_t)lv.count * p->M * vec))) break;
-    const size_t nodes = (size_t)ipow(lv.NC, d);
+    // 2D level data cover every level node [0, NC]^2; 3D the owned [0, NC)^3
+    const size_t nodes = (size_t)ipow(d == 2 ? lv.NC + 1 : lv.NC, d);
+    if (d == 2 && lv.shape.gen_tp > 0) {
+      // generic solve: D^-1 and the ring-padded r, p and K_n p per (cell, rhs)
+      const size_t cm = (size_t)lv.count * p->M, padded = cm * ipow(lv.NC + 3, 2);
+      if ((rc = dev_alloc(p, &lv.d_dinv, cm * ipow(lv.NC + 1, 2)))) break;
+      if ((rc = dev_alloc(p, &lv.d_vr, padded))) break;
+      if ((rc = dev_alloc(p, &lv.d_vp, padded))) break;
+      if ((rc = dev_alloc(p, &lv.d_vap, padded))) break;
+    }
     if (lv.r > 1) {
       std::vector<double> tk, tr;
       if (d == 3)

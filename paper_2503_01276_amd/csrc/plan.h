@@ -26,6 +26,7 @@ struct KernelShape {
   int rpt = 0;   // node rows per thread
   int threads = 0;
   bool pre = false;  // 2D: band coarse correction in the preconditioner
+  int gen_tp = 0;    // 2D generic solve kernel: threads per sub-block tile (0: not used)
 };
 
 struct Level {
@@ -231,6 +232,11 @@ int ensure_macro_scratch(mch_plan* p);
 int launch_macro_solve_noalloc(const mch_plan* p, const double* A, const double* b, double* U, double* Ub,
                                double rtol, int max_iter, int32_t* iters, double* resid, hipStream_t s);
 bool shape_supported_2d(int NC, int rpt, int N, bool galerkin, int n_sub);
+// 2D generic solve kernel (any width, either boundary condition): threads per
+// sub-block tile for s sub-blocks per axis (0: too many sub-blocks) and the
+// kernel's LDS bytes.
+int generic_tile_threads(int s);
+size_t generic_lds_bytes(int s, int N, int m, int threads);
 int launch_forward_3d(mch_plan* p, const double* kappa, const uint8_t* label, hipStream_t s);
 int launch_eff_3d(mch_plan* p, const double* kappa, double* A, hipStream_t s);
 int launch_backward_3d(mch_plan* p, const double* kappa, const double* gA, double* glogk, hipStream_t s);

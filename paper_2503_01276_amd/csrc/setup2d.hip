@@ -85,7 +85,6 @@ __global__ __launch_bounds__(SETUP_T) void k_setup2d(CellArgs a) {
   double* X = S + m * m;                 // 2*m: pivot row and column
   double* stat = X + 2 * m;              // (s*s+1)*N*3
   double* wred = stat + (s * s + 1) * N * 3;  // 4*N*3
-  double* Dn = wred + (SETUP_T / 64) * N * 3; // NCp*NCp, holds 1/D
   // band coarse correction (prec_rows > 0): for a group of G bands the
   // band-summed weights of the constraint rows active in each [G][NA][NC]
   // and their forward-eliminated values [G][NC][NA]; for every band the
@@ -95,7 +94,7 @@ __global__ __launch_bounds__(SETUP_T) void k_setup2d(CellArgs a) {
   const int nbands = prec ? NC / a.prec_rows : 0;
   int pNA = 0, pG = 0;
   if (prec) prec_group_sizes(a, &pNA, &pG);
-  double* BZ = Dn + NCp * NCp;
+  double* BZ = wred + (SETUP_T / 64) * N * 3;
   double* Ys = BZ + pG * pNA * NC;
   double* Lf = Ys + pG * pNA * NC;
   double* iD = Lf + nbands * NC;
@@ -178,11 +177,13 @@ __global__ __launch_bounds__(SETUP_T) void k_setup2d(CellArgs a) {
   }
 
   // ---- level operator data ------------------------------------------------
-  double* nW = gal ? a.nodeW + (size_t)ci * NC * NC * 9 : nullptr;
-  float* nB = gal ? a.nodeB + (size_t)ci * NC * NC * 4 * N : nullptr;
+  // Free level nodes: [lo, hi]^2 (Dirichlet: the interior; Neumann: all).
+  const int lo = a.bc ? 0 : 1, hi = a.bc ? NC : NC - 1;
+  double* nW = gal ? a.nodeW + (size_t)ci * NCp * NCp * 9 : nullptr;
+  float* nB = gal ? a.nodeB + (size_t)ci * NCp * NCp * 4 * N : nullptr;
   if (gal) {
-    for (int k = tid; k < NC * NC * 9; k += SETUP_T) nW[k] = 0.0;
-    for (int k = tid; k < NC * NC * 4 * N; k += SETUP_T) nB[k] = 0.0f;
+    for (int k = tid; k < NCp * NCp * 9; k += SETUP_T) nW[k] = 0.0;
+    for (int k = tid; k < NCp * NCp * 4 * N; k += SETUP_T) nB[k] = 0.0f;
     __syncthreads();
     // four colour passes: elements of one colour share no node
     for (int color = 0; color < 4; ++color) {
@@ -195,8 +196,7 @@ __global__ __launch_bounds__(SETUP_T) void k_setup2d(CellArgs a) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           const int Xn = EX + (c & 1), Yn = EY + (c >> 1);
-          if (Xn >= NC || Yn >= NC) continue;
-          const int nd = Yn * NC + Xn;
+          const int nd = Yn * NCp + Xn;
 #pragma unroll
           for (int b = 0; b < 4; ++b) {
             const int dx = (b & 1) - (c & 1), dy = (b >> 1) - (c >> 1);
@@ -210,29 +210,24 @@ __global__ __launch_bounds__(SETUP_T) void k_setup2d(CellArgs a) {
       }
       __syncthreads();
     }
-    for (int k = tid; k < NCp * NCp; k += SETUP_T) {
-      const int Xn = k % NCp, Yn = k / NCp;
-      Dn[k] = (Xn >= 1 && Yn >= 1 && Xn < NC && Yn < NC) ? 1.0 / nW[(Yn * NC + Xn) * 9 + 4] : 1.0;
-    }
   } else {
     for (int e = tid; e < NC * NC; e += SETUP_T) {
       const int EX = e % NC, EY = e / NC;
       labS[e] = a.label[(size_t)wrapi(oy + EY, a.n) * a.n + wrapi(ox + EX, a.n)];
     }
-    // D = 4*(((SW + SE) + NW) + NE) of kappa/6, the solve kernel's order
-    for (int k = tid; k < NCp * NCp; k += SETUP_T) {
-      const int Xn = k % NCp, Yn = k / NCp;
-      if (Xn < 1 || Yn < 1 || Xn >= NC || Yn >= NC) {
-        Dn[k] = 1.0;
-        continue;
-      }
-      auto kq = [&](int ex, int ey) {
-        return a.kappa[(size_t)wrapi(oy + ey, a.n) * a.n + wrapi(ox + ex, a.n)] * (1.0 / 6.0);
-      };
-      const double ks = kq(Xn - 1, Yn - 1) + kq(Xn, Yn - 1) + kq(Xn - 1, Yn) + kq(Xn, Yn);
-      Dn[k] = 1.0 / (4.0 * ks);
-    }
   }
+  // 1/D at free level node (Xn, Yn): the Galerkin diagonal, or on the fine
+  // level D = 4*(((SW + SE) + NW) + NE) of kappa/6 (the solve kernels' order;
+  // elements outside the cell count 0)
+  auto inv_d = [&](int Xn, int Yn) -> double {
+    if (gal) return 1.0 / nW[(Yn * NCp + Xn) * 9 + 4];
+    auto kq = [&](int ex, int ey) {
+      if (ex < 0 || ey < 0 || ex >= NC || ey >= NC) return 0.0;
+      return a.kappa[(size_t)wrapi(oy + ey, a.n) * a.n + wrapi(ox + ex, a.n)] * (1.0 / 6.0);
+    };
+    const double ks = kq(Xn - 1, Yn - 1) + kq(Xn, Yn - 1) + kq(Xn - 1, Yn) + kq(Xn, Yn);
+    return 1.0 / (4.0 * ks);
+  };
   // sub-block of every level element
   for (int e = tid; e < NC * NC; e += SETUP_T) regS[e] = (uint8_t)(((e / NC) / sbw) * s + (e % NC) / sbw);
   __syncthreads();
@@ -253,8 +248,8 @@ __global__ __launch_bounds__(SETUP_T) void k_setup2d(CellArgs a) {
     if (qbx < 0 || qby < 0 || qbx >= s || qby >= s) continue;  // uniform across the wave
     const int qb = qby * s + qbx;
     if (qb < qa) continue;
-    const int X0 = max(max(qax, qbx) * sbw, 1), X1 = min((min(qax, qbx) + 1) * sbw, NC - 1);
-    const int Y0 = max(max(qay, qby) * sbw, 1), Y1 = min((min(qay, qby) + 1) * sbw, NC - 1);
+    const int X0 = max(max(qax, qbx) * sbw, lo), X1 = min((min(qax, qbx) + 1) * sbw, hi);
+    const int Y0 = max(max(qay, qby) * sbw, lo), Y1 = min((min(qay, qby) + 1) * sbw, hi);
     const int wX = X1 - X0 + 1, wY = Y1 - Y0 + 1;
     double acc[N * N];
 #pragma unroll
@@ -268,6 +263,7 @@ __global__ __launch_bounds__(SETUP_T) void k_setup2d(CellArgs a) {
 #pragma unroll
       for (int Qd = 0; Qd < 4; ++Qd) {
         const int EX = Xn - 1 + (Qd & 1), EY = Yn - 1 + (Qd >> 1);
+        if (EX < 0 || EY < 0 || EX >= NC || EY >= NC) continue;  // outside the cell (Neumann boundary)
         const int qE = regS[EY * NC + EX];
         if (!gal) {
           const int lab = labS[EY * NC + EX];
@@ -278,7 +274,7 @@ __global__ __launch_bounds__(SETUP_T) void k_setup2d(CellArgs a) {
           }
         } else {
           const int side = Qd & 1, part = Qd >> 1;
-          const float* w4 = nB + ((Yn * NC + Xn) * 4 + side * 2 + part) * N;
+          const float* w4 = nB + ((Yn * NCp + Xn) * 4 + side * 2 + part) * N;
 #pragma unroll
           for (int j = 0; j < N; ++j) {
             const double wj = (double)w4[j];
@@ -287,7 +283,7 @@ __global__ __launch_bounds__(SETUP_T) void k_setup2d(CellArgs a) {
           }
         }
       }
-      const double id = Dn[Yn * NCp + Xn];
+      const double id = inv_d(Xn, Yn);
 #pragma unroll
       for (int j = 0; j < N; ++j)
 #pragma unroll
@@ -322,7 +318,7 @@ __global__ __launch_bounds__(SETUP_T) void k_setup2d(CellArgs a) {
     // north-east, south-east
     auto stencil_at = [&](int X, int Y, double* k6) {
       if (gal) {
-        const double* w9 = nW + (size_t)(Y * NC + X) * 9;
+        const double* w9 = nW + (size_t)(Y * NCp + X) * 9;
         k6[0] = w9[4];
         k6[1] = w9[7];
         k6[2] = w9[1];
@@ -354,7 +350,7 @@ __global__ __launch_bounds__(SETUP_T) void k_setup2d(CellArgs a) {
           w += (labS[EY * NC + EX] == j) ? 1.0 : 0.0;
         } else {
           const int side = Qd & 1, part = Qd >> 1;
-          w += (double)nB[((Y * NC + X) * 4 + side * 2 + part) * N + j];
+          w += (double)nB[((Y * NCp + X) * 4 + side * 2 + part) * N + j];
         }
       }
       return w;
@@ -523,17 +519,22 @@ __global__ __launch_bounds__(SETUP_T) void k_inherit2d(CellArgs a) {
   const int ox = a.H * jx + a.H / 2 - nc / 2, oy = a.H * jy + a.H / 2 - nc / 2;
   const double* I = a.phi1 + ((size_t)a.pslot[ci] * M + al) * (size_t)nn1 * nn1;
   const double inv_r = 1.0 / r;
-  double* fo = a.fin + ((size_t)ci * M + al) * NC * NC;
+  const int NCp = NC + 1;
+  double* fo = a.fin + ((size_t)ci * M + al) * NCp * NCp;
   double* wred = Rs + nn1 * nn1;
+  // free fine nodes [flo, fhi]^2 and free level nodes [lo, hi]^2
+  const int flo = a.bc ? 0 : 1, fhi = a.bc ? nc : nc - 1;
+  const int lo = a.bc ? 0 : 1, hi = a.bc ? NC : NC - 1;
   // R at fine node (x, y): node (x, y) is corner c of the element, and row c
   // of 6 K_ref is 4 v_c - 2 v_(c^3) - v_(c^1) - v_(c^2)
   for (int nd = tid; nd < nn1 * nn1; nd += SETUP_T) {
     const int x = nd % nn1, y = nd / nn1;
     double t = 0.0;
-    if (x >= 1 && y >= 1 && x < nc && y < nc) {
+    if (x >= flo && y >= flo && x <= fhi && y <= fhi) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int ex = x - 1 + (q & 1), ey = y - 1 + (q >> 1);
+        if (ex < 0 || ey < 0 || ex >= nc || ey >= nc) continue;  // outside the cell (Neumann boundary)
         const int c = (x - ex) + 2 * (y - ey);
         auto Iv = [&](int cc) { return I[(size_t)(ey + (cc >> 1)) * nn1 + ex + (cc & 1)]; };
         const double k6 = a.kappa[(size_t)wrapi(oy + ey, a.n) * a.n + wrapi(ox + ex, a.n)] * (1.0 / 6.0);
@@ -543,14 +544,17 @@ __global__ __launch_bounds__(SETUP_T) void k_inherit2d(CellArgs a) {
     Rs[nd] = t;
   }
   __syncthreads();
-  for (int nd = tid; nd < NC * NC; nd += SETUP_T) {
-    const int Xn = nd % NC, Yn = nd / NC;
+  for (int nd = tid; nd < NCp * NCp; nd += SETUP_T) {
+    const int Xn = nd % NCp, Yn = nd / NCp;
     double acc = 0.0;
-    if (Xn >= 1 && Yn >= 1) {
-      for (int dy = 1 - r; dy <= r - 1; ++dy) {
+    if (Xn >= lo && Yn >= lo && Xn <= hi && Yn <= hi) {
+      // the hat's support, clipped to the cell's fine nodes
+      const int dy0 = max(1 - r, -Yn * r), dy1 = min(r - 1, nc - Yn * r);
+      const int dx0 = max(1 - r, -Xn * r), dx1 = min(r - 1, nc - Xn * r);
+      for (int dy = dy0; dy <= dy1; ++dy) {
         const double* row = Rs + (size_t)(Yn * r + dy) * nn1 + Xn * r;
         double racc = 0.0;
-        for (int dx = 1 - r; dx <= r - 1; ++dx) racc += (1.0 - abs(dx) * inv_r) * row[dx];
+        for (int dx = dx0; dx <= dx1; ++dx) racc += (1.0 - abs(dx) * inv_r) * row[dx];
         acc += (1.0 - abs(dy) * inv_r) * racc;
       }
     }
@@ -587,9 +591,7 @@ __global__ __launch_bounds__(SETUP_T) void k_inherit2d(CellArgs a) {
 }
 
 static size_t setup_lds_bytes(const CellArgs& a) {
-  const size_t NCp = a.NC + 1;
-  size_t d = (size_t)a.m * a.m + 2 * (size_t)a.m + (size_t)(a.s * a.s + 1) * a.N * 3 + (SETUP_T / 64) * a.N * 3 +
-             NCp * NCp;
+  size_t d = (size_t)a.m * a.m + 2 * (size_t)a.m + (size_t)(a.s * a.s + 1) * a.N * 3 + (SETUP_T / 64) * a.N * 3;
   if (a.prec_rows > 0) {
     int NA, G;
     prec_group_sizes(a, &NA, &G);

@@ -116,6 +116,8 @@ CellArgs base_args(mch_plan* pl, const double* kappa, const uint8_t* label, int 
   a.gin = lv.d_gin;
   a.J = 1;
   a.prec_rows = lv.shape.pre ? lv.shape.rpt : 0;
+  a.bc = pl->cfg.bc;
+  a.gen_tp = lv.shape.gen_tp;
   a.adjoint = 0;
   a.seed_kp = pl->d_seed_kp;
   a.seed_par = nullptr;
@@ -173,6 +175,8 @@ bool prec_supported_2d(int NC, int rpt, int N, bool gal, int S, int m) {
 }
 
 int launch_solve(const CellArgs& a_in, int rpt, hipStream_t s) {
+  if (a_in.gen_tp > 0) return launch_solve_generic(a_in, s);
+  if (a_in.bc != 0) return set_error(MCH_EINVAL, "the register-resident solve kernel takes Dirichlet cells only");
   CellArgs a = a_in;
   a.J = schur_lanes(a.m);
   const bool gal = a.r > 1;
@@ -195,6 +199,7 @@ int launch_solve(const CellArgs& a_in, int rpt, hipStream_t s) {
 
 int solve_blocks_per_cu_2d(mch_plan* pl) {
   CellArgs a = base_args(pl, nullptr, nullptr, 0);
+  if (a.gen_tp > 0) return generic_blocks_per_cu(a);
   const int rpt = pl->lev[0].shape.rpt;
   const bool pre = a.prec_rows > 0;
   const size_t lds = solve_lds_bytes(a.NC, rpt, a.s, a.N, a.m, false, pre);

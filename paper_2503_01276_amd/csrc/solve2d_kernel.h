@@ -214,11 +214,11 @@ __global__ __launch_bounds__(NC* NC / RPT) __attribute__((amdgpu_waves_per_eu(2)
         }
     }
   } else {
-    const double* nW = a.nodeW + (size_t)ci * NC * NC * 9;
-    const float* nB = a.nodeB + (size_t)ci * NC * NC * 4 * N;
+    const double* nW = a.nodeW + (size_t)ci * (NC + 1) * (NC + 1) * 9;
+    const float* nB = a.nodeB + (size_t)ci * (NC + 1) * (NC + 1) * 4 * N;
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
-      const int nd = (y0 + i) * NC + c;
+      const int nd = (y0 + i) * (NC + 1) + c;
       const bool fr = (c >= 1) && (y0 + i >= 1);
 #pragma unroll
       for (int k = 0; k < 9; ++k) W[i][k] = fr ? nW[nd * 9 + k] : 0.0;
@@ -520,9 +520,9 @@ __global__ __launch_bounds__(NC* NC / RPT) __attribute__((amdgpu_waves_per_eu(2)
   double* uw = uW + wave * UST;
   if (!a.adjoint) {
     if constexpr (GAL) {
-      const double* fi = a.fin + ((size_t)ci * M + alpha) * NC * NC;
+      const double* fi = a.fin + ((size_t)ci * M + alpha) * (NC + 1) * (NC + 1);
 #pragma unroll
-      for (int i = 0; i < RPT; ++i) f[i] = fi[(y0 + i) * NC + c];
+      for (int i = 0; i < RPT; ++i) f[i] = fi[(y0 + i) * (NC + 1) + c];
       for (int k = lane; k < UST; k += 64) uw[k] = k < m ? a.gin[((size_t)ci * M + alpha) * m + k] : 0.0;
     } else {
       for (int k = lane; k < UST; k += 64) uw[k] = k < m ? a.g[((size_t)p * M + alpha) * m + k] : 0.0;

@@ -185,7 +185,8 @@ class Plan:
         check(LIB.mch_plan_info(self._h, info))
         self.P, self.M, self.m, self.levels = int(info[0]), int(info[1]), int(info[2]), int(info[3])
         self.level_counts = [int(info[4 + k]) for k in range(self.levels)]
-        # node rows per thread of each level's 2D solve kernel (0 in 3D)
+        # node rows per thread of each level's 2D solve kernel (0 in 3D and
+        # on levels solved by the generic 2D kernel)
         self.rows_per_thread = [int(info[4 + self.levels + k]) for k in range(self.levels)]
         # whether each level's 2D solve uses the band coarse correction
         self.band_precond = [bool(info[4 + 2 * self.levels + k]) for k in range(self.levels)]

@@ -84,11 +84,18 @@ PRESETS = {
     "c5": Config(dim=2, n_fine=2048, n_macro=256, n_cell=64, n_sub=2, n_cont=3, levels=4),
     "c5ml": Config(dim=2, n_fine=2048, n_macro=256, n_cell=64, n_sub=2, n_cont=3, levels=4, interp=1),
     # small cases for unit tests (several tiles, fast on the CPU)
+    # larger oversampled cells: 128^2 fine elements (4H, H = 32; level widths
+    # 128, 64, 32), and a block-aligned cell of 3 x 3 coarse blocks centred on
+    # K_p with the constraint regions the blocks themselves (one coarse layer
+    # of oversampling; level widths 96, 48, 24)
+    "c6": Config(dim=2, n_fine=512, n_macro=16, n_cell=128, n_sub=4, n_cont=2, levels=3),
+    "c7": Config(dim=2, n_fine=512, n_macro=16, n_cell=96, n_sub=3, n_cont=2, levels=3),
     "t2": Config(dim=2, n_fine=64, n_macro=8, n_cell=16, n_sub=2, n_cont=2, levels=2),
     "t3": Config(dim=2, n_fine=128, n_macro=16, n_cell=32, n_sub=2, n_cont=2, levels=3),
     "t3d": Config(dim=3, n_fine=32, n_macro=4, n_cell=16, n_sub=2, n_cont=2, levels=2),
 }
-PRESET_SEEDS = {"c1": 1, "c2": 2, "c2flat": 2, "c2ml": 2, "c3": 3, "c3flat": 3, "c5": 5, "c5ml": 5, "t2": 7, "t3": 8, "t3d": 9}
+PRESET_SEEDS = {"c1": 1, "c2": 2, "c2flat": 2, "c2ml": 2, "c3": 3, "c3flat": 3, "c5": 5, "c5ml": 5, "c6": 6, "c7": 10,
+                "t2": 7, "t3": 8, "t3d": 9}
 
 
 def _modulation(n: int, dim: int) -> np.ndarray:

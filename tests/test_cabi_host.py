@@ -72,14 +72,17 @@ def test_invalid_configurations():
     _expect(good.replace(n_cont=4), mch.MCH_EINVAL)
     _expect(good.replace(levels=0), mch.MCH_EINVAL)
     _expect(good.replace(interp=2), mch.MCH_EINVAL)
-    _expect(good.replace(bc=1), mch.MCH_ENOTIMPL)
+    _expect(good.replace(bc=2), mch.MCH_EINVAL)
+    _expect(good.replace(bc=1, interp=1), mch.MCH_ENOTIMPL)
+    _expect(W.PRESETS["t3d"].replace(bc=1), mch.MCH_ENOTIMPL)
     _expect(good.replace(rtol=0.0), mch.MCH_EINVAL)
     # over-constrained coarsest level: 2 x 2 sub-blocks x 2 continua = 8 rows, 1 free node
     _expect(W.Config(dim=2, n_fine=64, n_macro=8, n_cell=8, n_sub=2, n_cont=2, levels=3), mch.MCH_ESINGULAR)
-    # level widths without a solve kernel (checked before any device work):
-    # 16/8/4 (no workgroup of whole waves for a 4^2 cell) and 48/24/12
-    _expect(W.Config(dim=2, n_fine=64, n_macro=8, n_cell=16, n_sub=2, n_cont=2, levels=3), mch.MCH_ENOTIMPL)
-    _expect(W.Config(dim=2, n_fine=192, n_macro=12, n_cell=48, n_sub=2, n_cont=2, levels=3), mch.MCH_ENOTIMPL)
+    # shapes without a solve kernel (checked before any device work): 2D
+    # cells wider than 128 fine elements that the register-resident kernel
+    # does not hold either (the generic kernel takes every other width)
+    _expect(W.Config(dim=2, n_fine=320, n_macro=20, n_cell=160, n_sub=2, n_cont=2, levels=1), mch.MCH_ENOTIMPL)
+    _expect(W.Config(dim=2, n_fine=512, n_macro=16, n_cell=256, n_sub=2, n_cont=2, levels=2), mch.MCH_ENOTIMPL)
     _expect(W.Config(dim=3, n_fine=64, n_macro=8, n_cell=24, n_sub=2, n_cont=2, levels=1), mch.MCH_ENOTIMPL)
 
 
