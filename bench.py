@@ -121,6 +121,10 @@ DESCR = {
     "c3": "hierarchical L=2 eta=2, 3D 128^3 fine grid, 8^3 macropoints, 32^3-element cells "
           "(levels 32^3/16^3), N=2, contrast 1e4",
     "c3flat": "flat L=1, 3D 128^3 fine grid, 8^3 macropoints, 32^3-element cells, N=2, contrast 1e4",
+    "c6": "hierarchical L=3 eta=2, 2D 512^2 fine grid, 16x16 macropoints, 128^2-element cells "
+          "(levels 128^2/64^2/32^2, 4x4 constraint sub-blocks), N=2, contrast 1e4",
+    "c7": "hierarchical L=3 eta=2, 2D 512^2 fine grid, 16x16 macropoints, block-aligned cells of 3x3 coarse "
+          "blocks (96^2 elements; levels 96^2/48^2/24^2; constraint regions = the blocks), N=2, contrast 1e4",
 }
 
 
@@ -297,11 +301,16 @@ def kernel_table(recs, steps):
     return {k: {"avg_ms": v[0] / v[1], "launches_per_step": v[1] / steps} for k, v in tab.items()}
 
 
+def free_nodes(cfg, NC: int) -> int:
+    """Free nodes of a level cell NC elements wide (Dirichlet: interior; Neumann: all)."""
+    return (NC + 1 if cfg.bc else NC - 1) ** cfg.dim
+
+
 def solve_flops(runner, level_idx: int, iters: np.ndarray, levels: np.ndarray, adjoint: bool = False):
     cfg = runner.cfg
     r = cfg.eta ** level_idx
     NC = cfg.n_cell // r
-    nfree = (NC - 1) ** cfg.dim
+    nfree = free_nodes(cfg, NC)
     m = runner.plan.m
     its = iters[levels == level_idx + 1].astype(np.float64)
     per_node = FLOPS_PER_NODE_ITER if cfg.dim == 2 else (FLOPS_PER_NODE_ITER_3D_FINE if r == 1 else FLOPS_PER_NODE_ITER_3D_GAL)
@@ -318,12 +327,22 @@ def solve_flops(runner, level_idx: int, iters: np.ndarray, levels: np.ndarray, a
 BYTES_PER_NODE_ITER_3D = 12 * 8 + 10
 
 
+# The generic 2D solve kernel keeps its Krylov vectors in device memory too:
+# the same 12 FP64 vector values per free node and iteration; on the fine
+# level kappa (8 B) and a label byte in each of the two sweeps, on a Galerkin
+# level the node's 9 stencil weights (72 B) and its 4 N binary32 constraint
+# weights in each sweep.
+def bytes_per_node_iter_2d_generic(galerkin: bool, n_cont: int) -> int:
+    return 12 * 8 + ((9 * 8 + 2 * 16 * n_cont) if galerkin else (8 + 2))
+
+
 def solve_bytes(runner, level_idx: int, iters: np.ndarray, levels: np.ndarray):
     cfg = runner.cfg
     NC = cfg.n_cell // cfg.eta ** level_idx
-    nfree = (NC - 1) ** cfg.dim
+    nfree = free_nodes(cfg, NC)
     its = iters[levels == level_idx + 1].astype(np.float64)
-    return float(its.sum()) * BYTES_PER_NODE_ITER_3D * nfree
+    per = BYTES_PER_NODE_ITER_3D if cfg.dim == 3 else bytes_per_node_iter_2d_generic(level_idx > 0, cfg.n_cont)
+    return float(its.sum()) * per * nfree
 
 
 def main():
@@ -411,8 +430,9 @@ def measure(args, run, cpu, oracle_ref, tuned):
         # a level may run as several launches (chunks); per launch = per step / launches
         nl = ktab[dom]["launches_per_step"]
         its = aiters if dom.startswith("adj") else iters
-        if cfg.dim == 3 and li == 0:
-            # the 3D fine level streams its Krylov vectors: HBM roofline
+        if (cfg.dim == 3 and li == 0) or (cfg.dim == 2 and plan.rows_per_thread[li] == 0):
+            # the 3D fine level and the generic 2D kernel stream their Krylov
+            # vectors through device memory: HBM roofline
             nbytes = solve_bytes(run, li, its, lev_pm) / nl
             achieved = nbytes / (ktab[dom]["avg_ms"] * 1e-3) / 1e9
             roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
@@ -433,7 +453,7 @@ def measure(args, run, cpu, oracle_ref, tuned):
     fwd_ms = phases["solve_ms"]
 
     def free_dof(n):  # free nodes of a level-(n+1) cell
-        return (cfg.n_cell // cfg.eta ** n - 1) ** cfg.dim
+        return free_nodes(cfg, cfg.n_cell // cfg.eta ** n)
     detail = {
         **phases,
         "eff_tensor_time_ms": phases["solve_ms"] + phases["eff_ms"],

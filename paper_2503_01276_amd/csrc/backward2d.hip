@@ -163,8 +163,10 @@ struct LevelTab {
 // cells c of Ibar_c = Phibar_c - K_h(c) P w_c - B_h(c)^T mu_c on the free fine
 // nodes. 1024 threads; a thread owns up to NODES fine nodes and keeps their
 // sums in registers; per child the LDS holds P w, labels, cw*mu and (KLDS)
-// kappa/6: about 70 KB for 64^2 cells; 128^2 cells read kappa from global
-// memory instead (P w alone is 133 KB there).
+// kappa/6: about 70 KB for 64^2 cells. 128^2 cells read kappa from global
+// memory instead (P w alone is 133 KB there) and add each child's term to
+// the output in place (the same thread's nodes in every pass, so no race;
+// 17 sums per thread would not fit the registers of 1024 threads).
 constexpr int IBT = 1024;
 constexpr int IB_NODES = 5;       // ceil(65^2 / 1024): cells up to 64 elements wide
 constexpr int IB_NODES_BIG = 17;  // ceil(129^2 / 1024): cells up to 128 elements wide
@@ -195,9 +197,14 @@ __global__ __launch_bounds__(IBT) void k_ibar2d(CellArgs a, LevelTab lt, const i
   const int tid = threadIdx.x;
   const int t = a.ci0 + blockIdx.x / a.M, al = blockIdx.x % a.M;
   const int k0 = (nc - H) / 2, sb = nc / s;
-  double acc[NODES];
+  double acc[KLDS ? NODES : 1];
 #pragma unroll
-  for (int i = 0; i < NODES; ++i) acc[i] = 0.0;
+  for (int i = 0; i < (KLDS ? NODES : 1); ++i) acc[i] = 0.0;
+  double* dst = seed_par + ((size_t)t * a.M + al) * nn;
+  if constexpr (!KLDS) {
+    if (!accumulate)
+      for (int nd = tid; nd < nn; nd += IBT) dst[nd] = 0.0;
+  }
   for (int ch = child_ptr[t]; ch < child_ptr[t + 1]; ++ch) {
     const int p = child[ch];
     const int l = level[p] - 1;
@@ -224,7 +231,9 @@ __global__ __launch_bounds__(IBT) void k_ibar2d(CellArgs a, LevelTab lt, const i
     }
     __syncthreads();
     const double* skp = a.seed_kp + ((size_t)p * a.M + al) * Hp * Hp;
-#pragma unroll
+    // (unrolled when the sums stay in registers; a runtime loop otherwise,
+    // which keeps the per-node temporaries of one node live at a time)
+#pragma unroll(KLDS ? NODES : 1)
     for (int i = 0; i < NODES; ++i) {
       const int nd = tid + i * IBT;
       if (nd >= nn) break;
@@ -256,14 +265,18 @@ __global__ __launch_bounds__(IBT) void k_ibar2d(CellArgs a, LevelTab lt, const i
       }
       double pb = 0.0;
       if (X >= k0 && Y >= k0 && X <= k0 + H && Y <= k0 + H) pb = skp[(Y - k0) * Hp + (X - k0)];
-      acc[i] += pb - kpw - btmu;
+      if constexpr (KLDS)
+        acc[i] += pb - kpw - btmu;
+      else
+        dst[nd] += pb - kpw - btmu;
     }
   }
-  double* dst = seed_par + ((size_t)t * a.M + al) * nn;
+  if constexpr (KLDS) {
 #pragma unroll
-  for (int i = 0; i < NODES; ++i) {
-    const int nd = tid + i * IBT;
-    if (nd < nn) dst[nd] = accumulate ? dst[nd] + acc[i] : acc[i];
+    for (int i = 0; i < NODES; ++i) {
+      const int nd = tid + i * IBT;
+      if (nd < nn) dst[nd] = accumulate ? dst[nd] + acc[i] : acc[i];
+    }
   }
 }
 

@@ -193,8 +193,8 @@ struct CellArgs {
   int gen_tp;
   // 3D cells (unused in 2D): windows, D^-1 and Krylov vectors of this level,
   // and Phi on the K_p nodes of every point
-  double* kw;             // fine level: [count][NC^3] kappa*h/12
-  uint8_t* labw;          // fine level: [count][NC^3] labels
+  double* kw;             // fine level: 3D [count][NC^3] kappa*h/12; 2D generic kernel [count][NC^2] kappa/6
+  uint8_t* labw;          // fine level: [count][NC^d] labels (3D, 2D generic kernel)
   uint16_t* octw;         // fine level: [count][NC^3] labels of the 8 octant elements of each node, 2 bits each (3 = none)
   double* dinv;           // 3D: [count][NC^3]; 2D generic kernel: [count][M][(NC+1)^2]
   double* vr;             // 3D: [count][M][(NC+1)^3]; 2D generic kernel: [count][M][(NC+3)^2] (ring of zeros)

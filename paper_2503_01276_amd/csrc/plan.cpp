@@ -518,6 +518,11 @@ extern "C" int mch_build_levels(const mch_config* cfg, mch_plan** out) {
       if ((rc = dev_alloc(p, &lv.d_vr, padded))) break;
       if ((rc = dev_alloc(p, &lv.d_vp, padded))) break;
       if ((rc = dev_alloc(p, &lv.d_vap, padded))) break;
+      if (lv.r == 1) {
+        // the fine cell's kappa/6 and label windows, written by the setup
+        if ((rc = dev_alloc(p, &lv.d_kw, (size_t)lv.count * lv.NC * lv.NC))) break;
+        if ((rc = dev_alloc(p, &lv.d_labw, (size_t)lv.count * lv.NC * lv.NC))) break;
+      }
     }
     if (lv.r > 1) {
       std::vector<double> tk, tr;

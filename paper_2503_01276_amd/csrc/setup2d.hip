@@ -211,9 +211,18 @@ __global__ __launch_bounds__(SETUP_T) void k_setup2d(CellArgs a) {
       __syncthreads();
     }
   } else {
+    // fine level on the generic solve kernel: the cell's kappa/6 and label
+    // windows for it (a.kw, a.labw; null otherwise)
+    double* kwc = a.kw ? a.kw + (size_t)ci * NC * NC : nullptr;
+    uint8_t* lwc = a.labw ? a.labw + (size_t)ci * NC * NC : nullptr;
     for (int e = tid; e < NC * NC; e += SETUP_T) {
       const int EX = e % NC, EY = e / NC;
-      labS[e] = a.label[(size_t)wrapi(oy + EY, a.n) * a.n + wrapi(ox + EX, a.n)];
+      const size_t ge = (size_t)wrapi(oy + EY, a.n) * a.n + wrapi(ox + EX, a.n);
+      labS[e] = a.label[ge];
+      if (kwc) {
+        kwc[e] = a.kappa[ge] * (1.0 / 6.0);
+        lwc[e] = a.label[ge];
+      }
     }
   }
   // 1/D at free level node (Xn, Yn): the Galerkin diagonal, or on the fine

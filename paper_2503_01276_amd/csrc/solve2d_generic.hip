@@ -17,7 +17,7 @@
 // node of [0, NC]^2 is free (the extra node row and column do not fit the
 // other kernel's one-lane-per-column layout).
 //
-// Layout: one workgroup per (cell, right-hand side), at most 256 threads.
+// Layout: one workgroup per (cell, right-hand side), at most 512 threads.
 // The threads form one tile of TP lanes per constraint sub-block R_q (TP a
 // power of two); a tile owns the level nodes whose lower-left element lies in
 // R_q (plus node row/column NC in the last tiles) and loops over them. A
@@ -35,7 +35,8 @@
 
 namespace mch {
 
-constexpr int GEN_T = 256;  // most threads of a generic-solve workgroup
+constexpr int GEN_T = 512;  // most threads of a generic-solve workgroup
+constexpr int UN = 2;       // nodes per thread whose loads an iteration sweep issues together
 
 // A thread's partial sums, flat so that one DPP pass reduces them all: four
 // dot products, then B_n partials [vector 2][slot: own, left, lower,
@@ -73,8 +74,6 @@ __global__ __launch_bounds__(GEN_T) __attribute__((amdgpu_waves_per_eu(2))) void
   const int cl = blockIdx.x / M, alpha = blockIdx.x % M;
   const int ci = a.ci0 + cl;
   const int p = a.cells[ci];
-  const int jx = p % a.n_macro, jy = p / a.n_macro;
-  const int ox = a.H * jx + a.H / 2 - a.nc / 2, oy = a.H * jy + a.H / 2 - a.nc / 2;
   const size_t vbase = ((size_t)ci * M + alpha);
   double* vr = a.vr + vbase * PW * PW;
   double* vp = a.vp + vbase * PW * PW;
@@ -89,10 +88,14 @@ __global__ __launch_bounds__(GEN_T) __attribute__((amdgpu_waves_per_eu(2))) void
 
   auto pidx = [&](int X, int Y) { return (size_t)(Y + 1) * PW + (X + 1); };
   auto is_free = [&](int X, int Y) { return X >= lo && Y >= lo && X <= hi && Y <= hi; };
-  // kappa/6 of level element (ex, ey) of the fine cell, 0 outside it
+  // fine level: the cell's kappa/6 and label windows (written by the setup
+  // kernel); kappa/6 of element (ex, ey), 0 outside the cell
+  const double* kwc = GAL ? nullptr : a.kw + (size_t)ci * NC * NC;
+  const uint8_t* lwc = GAL ? nullptr : a.labw + (size_t)ci * NC * NC;
   auto kq = [&](int ex, int ey) -> double {
-    if (ex < 0 || ey < 0 || ex >= NC || ey >= NC) return 0.0;
-    return a.kappa[(size_t)wrapi(oy + ey, a.n) * a.n + wrapi(ox + ex, a.n)] * (1.0 / 6.0);
+    const bool in = ex >= 0 && ey >= 0 && ex < NC && ey < NC;
+    const double v = kwc[(in ? ey : 0) * NC + (in ? ex : 0)];
+    return in ? v : 0.0;
   };
   // constraint weights of node (X, Y) per quadrant (side + 2 part) and
   // continuum; quadrants outside the cell weigh 0. The quadrant's sub-block
@@ -109,7 +112,8 @@ __global__ __launch_bounds__(GEN_T) __attribute__((amdgpu_waves_per_eu(2))) void
 #pragma unroll
         for (int j = 0; j < N; ++j) w[q][j] = inside ? b[j] : 0.0f;
       } else {
-        const int lab = inside ? (int)a.label[(size_t)wrapi(oy + ey, a.n) * a.n + wrapi(ox + ex, a.n)] : 255;
+        const int l0 = lwc[(inside ? ey : 0) * NC + (inside ? ex : 0)];
+        const int lab = inside ? l0 : 255;
 #pragma unroll
         for (int j = 0; j < N; ++j) w[q][j] = (lab == j) ? 1.0f : 0.0f;
       }
@@ -350,23 +354,39 @@ __global__ __launch_bounds__(GEN_T) __attribute__((amdgpu_waves_per_eu(2))) void
     // ZPERIOD iterations; it vanishes up to rounding) and B D^-1 Kp
     const bool withz0 = (it % 16) == 0;
     zero_acc(acc);
-    for (int k = tl; k < tnodes; k += TP) {
-      const int X = X0 + k % wX, Y = Y0 + k / wX;
-      if (!is_free(X, Y)) continue;
-      const size_t id = pidx(X, Y);
-      const double Ap = stencil(vp, X, Y);
-      const double di = dinv[Y * NP + X];
-      const double r = vr[id], pv = vp[id];
-      const double t = di * r, tA = di * Ap;
-      acc[0] += pv * Ap;
-      acc[1] += r * t;
-      acc[2] += t * Ap;
-      acc[3] += Ap * tA;
-      float w[4][N];
-      weights(X, Y, w);
-      add_B(acc, 1, w, X, Y, tA);
-      if (withz0) add_B(acc, 0, w, X, Y, t);
-      vap[id] = Ap;
+    // UN nodes per pass: their loads are issued together (node indices past
+    // the tile's last are clamped to its first node and their results dropped)
+    for (int kb = tl; kb < tnodes; kb += UN * TP) {
+      int Xs[UN], Ys[UN];
+      bool use[UN];
+      double Ap[UN], r[UN], pv[UN], di[UN];
+#pragma unroll
+      for (int u = 0; u < UN; ++u) {
+        const int k = kb + u * TP;
+        const int kk = k < tnodes ? k : kb;
+        Xs[u] = X0 + kk % wX;
+        Ys[u] = Y0 + kk / wX;
+        use[u] = k < tnodes && is_free(Xs[u], Ys[u]);
+        const size_t id = pidx(Xs[u], Ys[u]);
+        Ap[u] = stencil(vp, Xs[u], Ys[u]);
+        r[u] = vr[id];
+        pv[u] = vp[id];
+        di[u] = dinv[Ys[u] * NP + Xs[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < UN; ++u) {
+        if (!use[u]) continue;
+        const double t = di[u] * r[u], tA = di[u] * Ap[u];
+        acc[0] += pv[u] * Ap[u];
+        acc[1] += r[u] * t;
+        acc[2] += t * Ap[u];
+        acc[3] += Ap[u] * tA;
+        float w[4][N];
+        weights(Xs[u], Ys[u], w);
+        add_B(acc, 1, w, Xs[u], Ys[u], tA);
+        if (withz0) add_B(acc, 0, w, Xs[u], Ys[u], t);
+        vap[pidx(Xs[u], Ys[u])] = Ap[u];
+      }
     }
     // vec 0 of part holds B D^-1 r, vec 1 B D^-1 Kp (the partials of vector
     // 1 are moved to set 0 when set 0 is not formed, so one set is reduced)
@@ -390,18 +410,36 @@ __global__ __launch_bounds__(GEN_T) __attribute__((amdgpu_waves_per_eu(2))) void
     const bool last = rzn <= tol2 || it >= a.max_iter;
     const double be = rzn * irr;
     rz = rzn;
-    for (int k = tl; k < tnodes; k += TP) {
-      const int X = X0 + k % wX, Y = Y0 + k / wX;
-      if (!is_free(X, Y)) continue;
-      const size_t id = pidx(X, Y);
-      const double pv = vp[id];
-      xo[Y * NP + X] += al * pv;
-      if (last) continue;
-      float w[4][N];
-      weights(X, Y, w);
-      const double r = vr[id] + al * vap[id] - scatter(w, X, Y);
-      vr[id] = r;
-      vp[id] = -dinv[Y * NP + X] * r + be * pv;
+    for (int kb = tl; kb < tnodes; kb += UN * TP) {
+      int Xs[UN], Ys[UN];
+      bool use[UN];
+      double xv[UN], pv[UN], r[UN], Ap[UN], di[UN];
+#pragma unroll
+      for (int u = 0; u < UN; ++u) {
+        const int k = kb + u * TP;
+        const int kk = k < tnodes ? k : kb;
+        Xs[u] = X0 + kk % wX;
+        Ys[u] = Y0 + kk / wX;
+        use[u] = k < tnodes && is_free(Xs[u], Ys[u]);
+        const size_t id = pidx(Xs[u], Ys[u]);
+        xv[u] = xo[Ys[u] * NP + Xs[u]];
+        pv[u] = vp[id];
+        r[u] = vr[id];
+        Ap[u] = vap[id];
+        di[u] = dinv[Ys[u] * NP + Xs[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < UN; ++u) {
+        if (!use[u]) continue;
+        const size_t id = pidx(Xs[u], Ys[u]);
+        xo[Ys[u] * NP + Xs[u]] = xv[u] + al * pv[u];
+        if (last) continue;
+        float w[4][N];
+        weights(Xs[u], Ys[u], w);
+        const double rn = r[u] + al * Ap[u] - scatter(w, Xs[u], Ys[u]);
+        vr[id] = rn;
+        vp[id] = -di[u] * rn + be * pv[u];
+      }
     }
     __syncthreads();
     if (last) break;
@@ -445,11 +483,11 @@ __global__ __launch_bounds__(GEN_T) __attribute__((amdgpu_waves_per_eu(2))) void
 }
 
 // Threads per sub-block tile for s sub-blocks per axis: the largest power of
-// two TP with TP s^2 <= 256 (at least 4), 0 if s^2 > 64.
+// two TP with TP s^2 <= 512 (at least 8), 0 if s^2 > 64.
 int generic_tile_threads(int s) {
   const int t = s * s;
   if (t > 64) return 0;
-  int tp = 256;
+  int tp = GEN_T;
   while (tp * t > GEN_T) tp /= 2;
   return tp;
 }
