@@ -87,7 +87,7 @@ typedef struct {
                            1: multilinear interpolation from T_(n-1) */
   int32_t bc;           /* cell boundary condition (Sec. 2, the artificial conditions on R_p^+):
                            0: homogeneous Dirichlet; 1: natural Neumann, every cell node free
-                           (2D only, interp = 0; solved by the generic 2D kernel) */
+                           (interp = 0; 3D with n_sub = 2; solved by the generic kernels) */
   double rtol;          /* relative tolerance on the projected preconditioned residual norm */
   int32_t max_iter;     /* Krylov iteration cap per solve */
 } mch_config;
@@ -101,6 +101,8 @@ typedef struct mch_plan mch_plan;
  * instantiated for the level's shape (widths 8..64, Dirichlet cells), else on
  * the generic kernel (Krylov vectors in device memory): Neumann cells, cells
  * up to 128 fine elements wide, any width divisible by n_sub, n_sub <= 8.
+ * 3D levels run on the column-marching kernel (Dirichlet cells, widths 8, 16,
+ * 32, n_sub = 2) or, for Neumann cells, on the generic 3D kernel.
  * Returns MCH_EINVAL for inconsistent sizes, MCH_ESINGULAR when the coarsest
  * level has more constraint rows than free unknowns, MCH_ENOTIMPL for a mode
  * outside the implemented ones, MCH_EHIP on allocation failure.

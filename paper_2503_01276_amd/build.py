@@ -15,7 +15,7 @@ LIB = os.path.join(HERE, "libmch.so")
 # (source, object name, extra flags); the 2D solve kernel is compiled once per
 # number of sub-blocks per axis
 SOURCES = [("plan.cpp", "plan", []), ("api.cpp", "api", []), ("setup2d.hip", "setup2d", []),
-           ("solve2d.hip", "solve2d", []), ("backward2d.hip", "backward2d", []), ("interp.hip", "interp", []), ("macro.hip", "macro", []), ("validate.hip", "validate", []), ("solve2d_generic.hip", "solve2d_generic", []),
+           ("solve2d.hip", "solve2d", []), ("backward2d.hip", "backward2d", []), ("interp.hip", "interp", []), ("macro.hip", "macro", []), ("validate.hip", "validate", []), ("solve2d_generic.hip", "solve2d_generic", []), ("solve3d_generic.hip", "solve3d_generic", []),
            ("cells3d.hip", "cells3d", [])] + \
           [("solve2d_inst.hip", f"solve2d_s{s}", [f"-DMCH_SUB={s}"]) for s in (1, 2, 4, 8)]
 HIP_FLAGS = [

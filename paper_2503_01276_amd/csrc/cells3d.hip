@@ -105,7 +105,7 @@ __global__ __launch_bounds__(T3) void k_setup3d(CellArgs a) {
   double* Xm = S + m * m;                    // m*m
   double* stat = Xm + m * m;                 // (s3+1)*N*4
   double* wred = stat + (s3 + 1) * N * 4;    // (T3/64)*N*4
-  double* partS = wred + (T3 / 64) * N * 4;  // npairs*NC
+  double* partS = wred + (T3 / 64) * N * 4;  // npairs * node planes
   __shared__ int singular;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int ci = a.ci0 + blockIdx.x;
@@ -184,21 +184,36 @@ __global__ __launch_bounds__(T3) void k_setup3d(CellArgs a) {
   }
 
   // ---- level operator data ------------------------------------------------
-  const size_t nodes = (size_t)NC * NC * NC;
+  // Level nodes stored per axis: NC (the owned [0, NC), node NC a zero
+  // boundary) for the column-marching solve, NC + 1 (every node) for the
+  // generic one. Free nodes [lo, hi]^3: the interior (Dirichlet) or all
+  // (Neumann); octant elements outside the cell weigh nothing.
+  const bool gen = a.gen_tp > 0;
+  const int NPn = gen ? NC + 1 : NC;
+  const int lo = a.bc ? 0 : 1, hi = a.bc ? NC : NC - 1;
+  auto is_free = [&](int X, int Y, int Z) {
+    return X >= lo && Y >= lo && Z >= lo && X <= hi && Y <= hi && Z <= hi;
+  };
+  auto el_in = [&](int EX, int EY, int EZ) {
+    return EX >= 0 && EY >= 0 && EZ >= 0 && EX < NC && EY < NC && EZ < NC;
+  };
+  const size_t nodes = (size_t)NPn * NPn * NPn;
+  const size_t elems = (size_t)NC * NC * NC;
   double* dinv = a.dinv + (size_t)ci * nodes;
   const double hk = a.h / 12.0;
   if (!gal) {
-    double* kwc = a.kw + (size_t)ci * nodes;
-    uint8_t* lbc = a.labw + (size_t)ci * nodes;
-    for (int e = tid; e < (int)nodes; e += T3) {
+    double* kwc = a.kw + (size_t)ci * elems;
+    uint8_t* lbc = a.labw + (size_t)ci * elems;
+    for (int e = tid; e < (int)elems; e += T3) {
       const size_t ge = gel3(a, ox, oy, oz, e % NC, (e / NC) % NC, e / (NC * NC));
       kwc[e] = a.kappa[ge] * hk;
       lbc[e] = a.label[ge];
     }
     __syncthreads();
-    // labels of every node's eight octant elements, 2 bits each (3 = none)
-    uint16_t* octc = a.octw + (size_t)ci * nodes;
-    for (int nd = tid; nd < (int)nodes; nd += T3) {
+    // labels of every node's eight octant elements, 2 bits each (3 = none),
+    // for the column-marching solve
+    uint16_t* octc = gen ? nullptr : a.octw + (size_t)ci * nodes;
+    for (int nd = tid; nd < (gen ? 0 : (int)nodes); nd += T3) {
       const int X = nd % NC, Y = (nd / NC) % NC, Z = nd / (NC * NC);
       unsigned code = 0;
       if (X >= 1 && Y >= 1 && Z >= 1) {
@@ -210,12 +225,14 @@ __global__ __launch_bounds__(T3) void k_setup3d(CellArgs a) {
       octc[nd] = (uint16_t)code;
     }
     for (int nd = tid; nd < (int)nodes; nd += T3) {
-      const int X = nd % NC, Y = (nd / NC) % NC, Z = nd / (NC * NC);
-      if (X >= 1 && Y >= 1 && Z >= 1) {
+      const int X = nd % NPn, Y = (nd / NPn) % NPn, Z = nd / (NPn * NPn);
+      if (is_free(X, Y, Z)) {
         double k8[8];
 #pragma unroll
-        for (int o = 0; o < 8; ++o)
-          k8[o] = kwc[(X - 1 + (o & 1)) + NC * ((Y - 1 + ((o >> 1) & 1)) + NC * (Z - 1 + (o >> 2)))];
+        for (int o = 0; o < 8; ++o) {
+          const int EX = X - 1 + (o & 1), EY = Y - 1 + ((o >> 1) & 1), EZ = Z - 1 + (o >> 2);
+          k8[o] = el_in(EX, EY, EZ) ? kwc[EX + NC * (EY + NC * EZ)] : 0.0;
+        }
         // same order as the diagonal of the solve kernel's operator
         dinv[nd] = 1.0 / (4.0 * (((k8[0] + k8[1]) + (k8[2] + k8[3])) + ((k8[4] + k8[5]) + (k8[6] + k8[7]))));
       } else {
@@ -226,8 +243,8 @@ __global__ __launch_bounds__(T3) void k_setup3d(CellArgs a) {
     double* nW = a.nodeW + (size_t)ci * nodes * 27;
     float* nB = a.nodeB + (size_t)ci * nodes * 8 * N;
     for (int nd = tid; nd < (int)nodes; nd += T3) {
-      const int X = nd % NC, Y = (nd / NC) % NC, Z = nd / (NC * NC);
-      const bool fr = X >= 1 && Y >= 1 && Z >= 1;
+      const int X = nd % NPn, Y = (nd / NPn) % NPn, Z = nd / (NPn * NPn);
+      const bool fr = is_free(X, Y, Z);
       double W[27];
       float B8[8][N];
 #pragma unroll
@@ -241,6 +258,7 @@ __global__ __launch_bounds__(T3) void k_setup3d(CellArgs a) {
         for (int o = 0; o < 8; ++o) {
           const int ex_ = o & 1, ey_ = (o >> 1) & 1, ez_ = o >> 2;
           const int EX = X - 1 + ex_, EY = Y - 1 + ey_, EZ = Z - 1 + ez_;
+          if (!el_in(EX, EY, EZ)) continue;
           const int ac = (1 - ex_) + 2 * (1 - ey_) + 4 * (1 - ez_);  // corner of the node in element o
           for (int wz = 0; wz < r; ++wz)
             for (int wy = 0; wy < r; ++wy)
@@ -274,11 +292,11 @@ __global__ __launch_bounds__(T3) void k_setup3d(CellArgs a) {
   __syncthreads();
 
   // ---- S = B_n D^-1 B_n^T: (pair, node plane) partials, fixed-order sums --
-  const uint8_t* lbc = gal ? nullptr : a.labw + (size_t)ci * nodes;
+  const uint8_t* lbc = gal ? nullptr : a.labw + (size_t)ci * elems;
   const float* nB = gal ? a.nodeB + (size_t)ci * nodes * 8 * N : nullptr;
-  for (int item = tid; item < npairs * NC; item += T3) {
-    int pr = item / NC;
-    const int Z = item % NC;
+  for (int item = tid; item < npairs * NPn; item += T3) {
+    int pr = item / NPn;
+    const int Z = item % NPn;
     int ra = 0;
     while (pr >= m - ra) {
       pr -= m - ra;
@@ -291,17 +309,18 @@ __global__ __launch_bounds__(T3) void k_setup3d(CellArgs a) {
     const double cwa = cwp[ra], cwb = cwp[rb];
     double acc = 0.0;
     if (abs(qax - qbx) <= 1 && abs(qay - qby) <= 1 && abs(qaz - qbz) <= 1 && cwa != 0.0 && cwb != 0.0) {
-      const int Z0 = max(max(qaz, qbz) * sbw, 1), Z1 = min((min(qaz, qbz) + 1) * sbw, NC - 1);
+      const int Z0 = max(max(qaz, qbz) * sbw, lo), Z1 = min((min(qaz, qbz) + 1) * sbw, hi);
       if (Z >= Z0 && Z <= Z1) {
-        const int X0 = max(max(qax, qbx) * sbw, 1), X1 = min((min(qax, qbx) + 1) * sbw, NC - 1);
-        const int Y0 = max(max(qay, qby) * sbw, 1), Y1 = min((min(qay, qby) + 1) * sbw, NC - 1);
+        const int X0 = max(max(qax, qbx) * sbw, lo), X1 = min((min(qax, qbx) + 1) * sbw, hi);
+        const int Y0 = max(max(qay, qby) * sbw, lo), Y1 = min((min(qay, qby) + 1) * sbw, hi);
         for (int Y = Y0; Y <= Y1; ++Y)
           for (int X = X0; X <= X1; ++X) {
-            const size_t nd = (size_t)X + NC * ((size_t)Y + NC * (size_t)Z);
+            const size_t nd = (size_t)X + NPn * ((size_t)Y + NPn * (size_t)Z);
             double ba = 0.0, bb = 0.0;
 #pragma unroll
             for (int o = 0; o < 8; ++o) {
               const int EX = X - 1 + (o & 1), EY = Y - 1 + ((o >> 1) & 1), EZ = Z - 1 + (o >> 2);
+              if (!el_in(EX, EY, EZ)) continue;
               const int qE = EX / sbw + s * (EY / sbw + s * (EZ / sbw));
               double wa, wb;
               if (gal) {
@@ -330,7 +349,7 @@ __global__ __launch_bounds__(T3) void k_setup3d(CellArgs a) {
     }
     const int rb = ra + pr;
     double acc = 0.0;
-    for (int zz = 0; zz < NC; ++zz) acc += partS[pr0 * NC + zz];
+    for (int zz = 0; zz < NPn; ++zz) acc += partS[pr0 * NPn + zz];
     S[ra * m + rb] = acc;
     S[rb * m + ra] = acc;
   }
@@ -393,7 +412,10 @@ __global__ __launch_bounds__(T3) void k_inherit3d(CellArgs a) {
   int ox, oy, oz;
   cell_origin3(a, p, ox, oy, oz);
   const double* I = a.phi1 + ((size_t)a.pslot[ci] * M + al) * (size_t)nn1 * nn1 * nn1;
-  const size_t nodes = (size_t)NC * NC * NC;
+  // level nodes stored per axis (see the setup) and the free ones
+  const int NPn = a.gen_tp > 0 ? NC + 1 : NC;
+  const int lo = a.bc ? 0 : 1, hi = a.bc ? NC : NC - 1;
+  const size_t nodes = (size_t)NPn * NPn * NPn;
   double* fo = a.fin + ((size_t)ci * M + al) * nodes;
   const double hk = a.h / 12.0, inv_r = 1.0 / r;
   const bool own = tid < L2;
@@ -403,8 +425,9 @@ __global__ __launch_bounds__(T3) void k_inherit3d(CellArgs a) {
   for (int t = 0; t < 2; ++t)
 #pragma unroll
     for (int j = 0; j < N; ++j) acc[t][j] = 0.0;
-  for (int EZ = 0; EZ < NC; ++EZ) {
-    if (own) {
+  // element layer EZ, then node plane Z = EZ from layers EZ - 1 and EZ
+  for (int EZ = 0; EZ <= NC; ++EZ) {
+    if (own && EZ < NC) {
       double Fe[8];
 #pragma unroll
       for (int c = 0; c < 8; ++c) Fe[c] = 0.0;
@@ -444,19 +467,22 @@ __global__ __launch_bounds__(T3) void k_inherit3d(CellArgs a) {
       for (int c = 0; c < 8; ++c) Fl[c] = Fe[c];
     }
     __syncthreads();
-    if (EZ >= 1 && own) {
-      const int X = EX, Y = EY, Z = EZ;
+    const int Z = EZ;
+    for (int col = tid; Z < NPn && col < NPn * NPn; col += T3) {
+      const int X = col % NPn, Y = col / NPn;
       double t = 0.0;
-      if (X >= 1 && Y >= 1) {
+      if (X >= lo && Y >= lo && Z >= lo && X <= hi && Y <= hi && Z <= hi) {
 #pragma unroll
         for (int o = 0; o < 8; ++o) {
           const int ex_ = o & 1, ey_ = (o >> 1) & 1, ez_ = o >> 2;
-          const int layer = (Z - 1 + ez_) & 1;
+          const int EXo = X - 1 + ex_, EYo = Y - 1 + ey_, EZo = Z - 1 + ez_;
+          if (EXo < 0 || EYo < 0 || EZo < 0 || EXo >= NC || EYo >= NC || EZo >= NC) continue;
+          const int layer = EZo & 1;
           const int c = (1 - ex_) + 2 * (1 - ey_) + 4 * (1 - ez_);
-          t += F[((size_t)layer * L2 + (Y - 1 + ey_) * NC + (X - 1 + ex_)) * 8 + c];
+          t += F[((size_t)layer * L2 + EYo * NC + EXo) * 8 + c];
         }
       }
-      fo[(size_t)X + NC * ((size_t)Y + NC * (size_t)Z)] = -t;
+      fo[(size_t)X + NPn * ((size_t)Y + NPn * (size_t)Z)] = -t;
     }
     __syncthreads();
   }
@@ -1308,7 +1334,7 @@ struct LevelTab3 {
 
 // Seeds of level-1 cell t for right-hand side alpha (one workgroup per
 // (t, alpha)): the sum over its inheriting cells c, in a fixed order, of
-// Ibar_c = Phibar_c - K_h(c) P w_c - B_h(c)^T mu_c on the interior fine nodes.
+// Ibar_c = Phibar_c - K_h(c) P w_c - B_h(c)^T mu_c on the free fine nodes.
 // K_h P w and B^T mu are scattered element by element in 8 colour passes
 // (elements of one colour share no node), so every node's sum has a fixed order.
 __global__ __launch_bounds__(T3) void k_ibar3d(CellArgs a, LevelTab3 lt, const int32_t* level, const int32_t* child_ptr,
@@ -1317,6 +1343,7 @@ __global__ __launch_bounds__(T3) void k_ibar3d(CellArgs a, LevelTab3 lt, const i
   const int tid = threadIdx.x;
   const int t = a.ci0 + blockIdx.x / M, al = blockIdx.x % M;
   const int k0 = (nc - H) / 2, sb = nc / s;
+  const int flo = a.bc ? 0 : 1, fhi = a.bc ? nc : nc - 1;  // free fine nodes
   const size_t nn = (size_t)nn1 * nn1 * nn1;
   double* acc = seed_par + ((size_t)t * M + al) * nn;
   const double hk = a.h / 12.0;
@@ -1363,7 +1390,7 @@ __global__ __launch_bounds__(T3) void k_ibar3d(CellArgs a, LevelTab3 lt, const i
 #pragma unroll
         for (int dl = 0; dl < 8; ++dl) {
           const int X = fx + (dl & 1), Y = fy + ((dl >> 1) & 1), Z = fz + (dl >> 2);
-          if (X < 1 || Y < 1 || Z < 1 || X >= nc || Y >= nc || Z >= nc) continue;
+          if (X < flo || Y < flo || Z < flo || X > fhi || Y > fhi || Z > fhi) continue;
           acc[nidx3(X, Y, Z, nn1)] -= kw * y[dl] + cm;
         }
       }
@@ -1372,7 +1399,7 @@ __global__ __launch_bounds__(T3) void k_ibar3d(CellArgs a, LevelTab3 lt, const i
     const double* skp = a.seed_kp + ((size_t)p * M + al) * (size_t)Hp * Hp * Hp;
     for (int nd = tid; nd < Hp * Hp * Hp; nd += T3) {
       const int X = k0 + nd % Hp, Y = k0 + (nd / Hp) % Hp, Z = k0 + nd / (Hp * Hp);
-      if (X < 1 || Y < 1 || Z < 1 || X >= nc || Y >= nc || Z >= nc) continue;
+      if (X < flo || Y < flo || Z < flo || X > fhi || Y > fhi || Z > fhi) continue;
       acc[nidx3(X, Y, Z, nn1)] += skp[nd];
     }
   }
@@ -1486,6 +1513,7 @@ static int launch_solve3_t(const CellArgs& a, hipStream_t s) {
 
 int solve_blocks_per_cu_3d(mch_plan* pl) {
   CellArgs a = base_args(pl, nullptr, nullptr, 0);
+  if (a.gen_tp > 0) return generic3_blocks_per_cu(a);
   a.J = schur_lanes3(a.m);
   const void* fn = nullptr;
   int threads = 0;
@@ -1511,6 +1539,8 @@ int solve_blocks_per_cu_3d(mch_plan* pl) {
 }
 
 static int launch_solve3(const CellArgs& a_in, hipStream_t s) {
+  if (a_in.gen_tp > 0) return launch_solve3d_generic(a_in, s);
+  if (a_in.bc != 0) return set_error(MCH_EINVAL, "the column-marching 3D solve takes Dirichlet cells only");
   CellArgs a = a_in;
   a.J = schur_lanes3(a.m);
   const bool gal = a.r > 1;
@@ -1524,7 +1554,8 @@ static int launch_solve3(const CellArgs& a_in, hipStream_t s) {
 static int launch_setup3(const CellArgs& a, hipStream_t s) {
   const size_t npairs = (size_t)a.m * (a.m + 1) / 2;
   const size_t s3 = (size_t)a.s * a.s * a.s;
-  const size_t lds = ((size_t)2 * a.m * a.m + (s3 + 1) * a.N * 4 + (T3 / 64) * a.N * 4 + npairs * a.NC) * sizeof(double);
+  const size_t planes = a.gen_tp > 0 ? a.NC + 1 : a.NC;  // node planes of the S partials
+  const size_t lds = ((size_t)2 * a.m * a.m + (s3 + 1) * a.N * 4 + (T3 / 64) * a.N * 4 + npairs * planes) * sizeof(double);
   void (*fn)(CellArgs) = nullptr;
   if (a.N == 1) fn = k_setup3d<1>;
   if (a.N == 2) fn = k_setup3d<2>;

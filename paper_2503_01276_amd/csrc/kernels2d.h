@@ -15,6 +15,9 @@ int launch_solve(const CellArgs& a, int rpt, hipStream_t s);
 int launch_solve_generic(const CellArgs& a, hipStream_t s);
 // Workgroups of the generic solve kernel that fit on one CU at once.
 int generic_blocks_per_cu(const CellArgs& a);
+// The 3D generic solve (cells with a.gen_tp > 0) and its workgroups per CU.
+int launch_solve3d_generic(const CellArgs& a, hipStream_t s);
+int generic3_blocks_per_cu(const CellArgs& a);
 
 // Lanes per row of the per-wave Schur solve: the largest power of two J with
 // J m <= 64, so the m rows of S^-1 u fit one wave.

@@ -69,6 +69,19 @@ static int generic_choice_2d(const mch_config& c, int NCl, int r) {
   return tp > 0 ? tp : -1;
 }
 
+// 3D level of width NCl: 0 for the column-marching solve kernel, else the
+// generic 3D kernel's threads per sub-block tile (Neumann cells, or
+// MCH_GENERIC=1); -1 if neither kernel takes it. Both need 2 sub-blocks per
+// axis (the inherited right-hand sides assume it).
+static int generic_choice_3d(const mch_config& c, int NCl) {
+  bool gen = c.bc != 0;
+  if (const char* v = std::getenv("MCH_GENERIC")) gen = gen || std::atoi(v) != 0;
+  if (!gen) return shape_supported_3d(NCl, c.n_sub, c.n_cont) ? 0 : -1;
+  if (c.n_sub != 2 || NCl > 32) return -1;
+  const int tp = generic3_tile_threads(c.n_sub);
+  return tp > 0 ? tp : -1;
+}
+
 template <typename T>
 static int dev_alloc(mch_plan* p, T** ptr, size_t count) {
   *ptr = nullptr;
@@ -376,7 +389,6 @@ extern "C" int mch_build_levels(const mch_config* cfg, mch_plan** out) {
   if (c.n_sub < 1) return set_error(MCH_EINVAL, "n_sub must be >= 1");
   if (c.interp != 0 && c.interp != 1) return set_error(MCH_EINVAL, "interp must be 0 or 1");
   if (c.bc != 0 && c.bc != 1) return set_error(MCH_EINVAL, "bc must be 0 (Dirichlet) or 1 (Neumann)");
-  if (c.bc == 1 && c.dim == 3) return set_error(MCH_ENOTIMPL, "Neumann cells are implemented in 2D only");
   if (c.bc == 1 && c.interp == 1) return set_error(MCH_ENOTIMPL, "Neumann cells with multilinear inheritance");
   if (!(c.rtol > 0.0) || c.max_iter < 1) return set_error(MCH_EINVAL, "rtol must be > 0 and max_iter >= 1");
   const int nc = c.n_cell;
@@ -415,7 +427,7 @@ extern "C" int mch_build_levels(const mch_config* cfg, mch_plan** out) {
   for (int l = 0; l < p->L; ++l) {
     const int r = ipow(c.eta, l), NCl = nc / r, sbw = nc / c.n_sub / r;
     if (d == 3) {
-      if (!shape_supported_3d(NCl, c.n_sub, c.n_cont)) {
+      if (generic_choice_3d(c, NCl) < 0) {
         delete p;
         return set_error(MCH_ENOTIMPL, "no 3D kernel instantiated for level cell width " + std::to_string(NCl) +
                                            " n_sub=" + std::to_string(c.n_sub) + " N=" + std::to_string(c.n_cont));
@@ -461,7 +473,8 @@ extern "C" int mch_build_levels(const mch_config* cfg, mch_plan** out) {
     if (d == 3) {
       lv.shape.rpt = 0;
       lv.shape.threads = ipow(lv.NC, 3) >= 1024 ? 1024 : ipow(lv.NC, 3);
-      if (!shape_supported_3d(lv.NC, c.n_sub, c.n_cont)) {
+      lv.shape.gen_tp = generic_choice_3d(c, lv.NC);
+      if (lv.shape.gen_tp < 0) {
         rc = set_error(MCH_ENOTIMPL, "no 3D kernel instantiated for level cell width " + std::to_string(lv.NC) +
                                          " n_sub=" + std::to_string(c.n_sub) + " N=" + std::to_string(c.n_cont));
         break;
@@ -509,8 +522,9 @@ extern "C" int mch_build_levels(const mch_config* cfg, mch_plan** out) {
     const size_t rows = (l == 0 && ml) ? (size_t)p->nT : (size_t)lv.count;
     if ((rc = dev_alloc(p, &lv.d_out, rows * p->M * vec))) break;
     if ((rc = dev_alloc(p, &lv.d_w, (size_t)lv.count * p->M * vec))) break;
-    // 2D level data cover every level node [0, NC]^2; 3D the owned [0, NC)^3
-    const size_t nodes = (size_t)ipow(d == 2 ? lv.NC + 1 : lv.NC, d);
+    // 2D level data (and 3D on the generic kernel) cover every level node
+    // [0, NC]^d; the column-marching 3D kernel's the owned [0, NC)^3
+    const size_t nodes = (size_t)ipow((d == 2 || lv.shape.gen_tp > 0) ? lv.NC + 1 : lv.NC, d);
     if (d == 2 && lv.shape.gen_tp > 0) {
       // generic solve: D^-1 and the ring-padded r, p and K_n p per (cell, rhs)
       const size_t cm = (size_t)lv.count * p->M, padded = cm * ipow(lv.NC + 3, 2);
@@ -576,12 +590,15 @@ extern "C" int mch_build_levels(const mch_config* cfg, mch_plan** out) {
       if ((rc = dev_alloc(p, &lv.d_I, (size_t)lv.count * p->M * p->nn))) break;
     }
     if (d == 3) {
+      const size_t elems = (size_t)ipow(lv.NC, 3);
       if (lv.r == 1) {
-        if ((rc = dev_alloc(p, &lv.d_kw, (size_t)lv.count * nodes))) break;
-        if ((rc = dev_alloc(p, &lv.d_labw, (size_t)lv.count * nodes))) break;
-        if ((rc = dev_alloc(p, &lv.d_octw, (size_t)lv.count * nodes))) break;
+        if ((rc = dev_alloc(p, &lv.d_kw, (size_t)lv.count * elems))) break;
+        if ((rc = dev_alloc(p, &lv.d_labw, (size_t)lv.count * elems))) break;
+        if (lv.shape.gen_tp == 0 && (rc = dev_alloc(p, &lv.d_octw, (size_t)lv.count * nodes))) break;
       }
-      const size_t padded = (size_t)lv.count * p->M * ipow(lv.NC + 1, 3);
+      // Krylov vectors: a zero boundary plane at NC (column-marching kernel)
+      // or a ring of zeros around [0, NC]^3 (generic kernel)
+      const size_t padded = (size_t)lv.count * p->M * ipow(lv.NC + (lv.shape.gen_tp > 0 ? 3 : 1), 3);
       if ((rc = dev_alloc(p, &lv.d_dinv, (size_t)lv.count * nodes))) break;
       if ((rc = dev_alloc(p, &lv.d_vr, padded))) break;
       if ((rc = dev_alloc(p, &lv.d_vp, padded))) break;

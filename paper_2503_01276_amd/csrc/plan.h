@@ -236,6 +236,9 @@ bool shape_supported_2d(int NC, int rpt, int N, bool galerkin, int n_sub);
 // sub-block tile for s sub-blocks per axis (0: too many sub-blocks) and the
 // kernel's LDS bytes.
 int generic_tile_threads(int s);
+// 3D generic solve kernel (Neumann cells): threads per sub-block tile for s
+// sub-blocks per axis (0: too many).
+int generic3_tile_threads(int s);
 size_t generic_lds_bytes(int s, int N, int m, int threads);
 int launch_forward_3d(mch_plan* p, const double* kappa, const uint8_t* label, hipStream_t s);
 int launch_eff_3d(mch_plan* p, const double* kappa, double* A, hipStream_t s);

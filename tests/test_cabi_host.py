@@ -74,7 +74,7 @@ def test_invalid_configurations():
     _expect(good.replace(interp=2), mch.MCH_EINVAL)
     _expect(good.replace(bc=2), mch.MCH_EINVAL)
     _expect(good.replace(bc=1, interp=1), mch.MCH_ENOTIMPL)
-    _expect(W.PRESETS["t3d"].replace(bc=1), mch.MCH_ENOTIMPL)
+    _expect(W.PRESETS["t3d"].replace(bc=1, n_sub=1), mch.MCH_ENOTIMPL)  # 3D Neumann cells need 2 sub-blocks per axis
     _expect(good.replace(rtol=0.0), mch.MCH_EINVAL)
     # over-constrained coarsest level: 2 x 2 sub-blocks x 2 continua = 8 rows, 1 free node
     _expect(W.Config(dim=2, n_fine=64, n_macro=8, n_cell=8, n_sub=2, n_cont=2, levels=3), mch.MCH_ESINGULAR)

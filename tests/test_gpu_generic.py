@@ -100,3 +100,36 @@ def test_wide_and_block_aligned_cells(name):
 ])
 def test_wide_cells_gradient(cfg, seed):
     grad_case(f"n_cell={cfg.n_cell} n_sub={cfg.n_sub}", cfg, seed, workers=8)
+
+
+# ---- 3D: the generic 3D kernel (Neumann cells; MCH_GENERIC=1 for Dirichlet) ----
+
+def test_neumann_3d_forward_full():
+    cfg = _neumann("t3d")
+    k, l = W.medium("t3d")
+    plan, _ = check_forward("t3d Neumann", cfg, k, l, phi_cells=list(range(cfg.n_points)), workers=4)
+    plan.close()
+
+
+def test_neumann_3d_partition_of_unity():
+    cfg = _neumann("t3d")
+    k, l = W.medium("t3d")
+    cells = list(range(cfg.n_points))
+    plan, _, Phi, it, rs, _ = gpu_forward(cfg, k, l, cells=cells)
+    worst = max(np.abs(Phi[p][:, : cfg.n_cont].sum(axis=1) - 1.0).max() for p in cells)
+    say(f"[gpu] t3d Neumann: max |sum_i phi_i - 1| = {worst:.2e} over {len(cells)} cells")
+    plan.close()
+    assert worst <= PU_TOL, worst
+
+
+def test_neumann_3d_gradient():
+    grad_case("t3d Neumann", _neumann("t3d"), 24, workers=4)
+
+
+def test_generic_3d_kernel_dirichlet(monkeypatch):
+    monkeypatch.setenv("MCH_GENERIC", "1")
+    cfg = W.PRESETS["t3d"]
+    k, l = W.medium("t3d")
+    plan, _ = check_forward("t3d generic", cfg, k, l, phi_cells=list(range(cfg.n_points)), workers=4)
+    plan.close()
+    grad_case("t3d generic", cfg, 25, workers=4)
