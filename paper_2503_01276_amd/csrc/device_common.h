@@ -191,6 +191,9 @@ struct CellArgs {
   // 2D generic solve kernel: threads per constraint sub-block (0: the
   // register-resident kernel of the level's shape)
   int gen_tp;
+  // 2D register-resident solve: workgroups numbered so that a cell's
+  // right-hand sides run on one XCD (1), or in plain order (0)
+  int xcd_groups;
   // 3D cells (unused in 2D): windows, D^-1 and Krylov vectors of this level,
   // and Phi on the K_p nodes of every point
   double* kw;             // fine level: 3D [count][NC^3] kappa*h/12; 2D generic kernel [count][NC^2] kappa/6

@@ -444,6 +444,7 @@ extern "C" int mch_build_levels(const mch_config* cfg, mch_plan** out) {
   }
   if (const char* v = std::getenv("MCH_GRAPHS")) p->use_graphs = std::atoi(v) != 0;
   if (const char* v = std::getenv("MCH_SERIAL")) p->serial = std::atoi(v) != 0;
+  if (const char* v = std::getenv("MCH_XCD")) p->xcd_groups = std::atoi(v) != 0;
   if (hipGetDevice(&p->device) != hipSuccess) {
     delete p;
     return set_error(MCH_EHIP, "no HIP device");

@@ -179,6 +179,7 @@ struct mch_plan {
   } g_fwd, g_eff, g_bwd;
   int use_graphs = 1;
   int serial = 0;  // run every level on the caller's stream (kernel-by-kernel timing)
+  int xcd_groups = 1;  // 2D solve: a cell's right-hand sides on one XCD (MCH_XCD=0: plain order)
   // profiling (off by default)
   int profiling = 0;
   std::vector<mch::ProfRec> prof;

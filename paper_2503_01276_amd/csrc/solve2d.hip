@@ -118,6 +118,7 @@ CellArgs base_args(mch_plan* pl, const double* kappa, const uint8_t* label, int 
   a.prec_rows = lv.shape.pre ? lv.shape.rpt : 0;
   a.bc = pl->cfg.bc;
   a.gen_tp = lv.shape.gen_tp;
+  a.xcd_groups = pl->xcd_groups;
   a.adjoint = 0;
   a.seed_kp = pl->d_seed_kp;
   a.seed_par = nullptr;

@@ -110,14 +110,16 @@ __global__ __launch_bounds__(NC* NC / RPT) __attribute__((amdgpu_waves_per_eu(2)
   // count M workgroups.
   int cl, alpha;
   {
-    const int whole = (a.count / kXcds) * kXcds * M;
+    // cells in whole XCD groups (none when the numbering is off)
+    const int grouped = a.xcd_groups ? (a.count / kXcds) * kXcds : 0;
+    const int whole = grouped * M;
     const int b = blockIdx.x;
     if (b < whole) {
       const int grp = b / (kXcds * M), rb = b % (kXcds * M);
       cl = grp * kXcds + rb % kXcds;
       alpha = rb / kXcds;
     } else {
-      cl = (a.count / kXcds) * kXcds + (b - whole) / M;
+      cl = grouped + (b - whole) / M;
       alpha = (b - whole) % M;
     }
   }

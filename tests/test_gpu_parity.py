@@ -65,6 +65,19 @@ def test_determinism_bitwise():
     assert np.array_equal(A1, A2)
 
 
+def test_workgroup_numbering_is_bitwise_neutral(monkeypatch):
+    # the 2D solve's XCD-grouped workgroup order (default) and plain order
+    # (MCH_XCD=0) solve the same (cell, rhs) pairs with the same arithmetic;
+    # 49 level-1 cells (six whole groups of 8 and a tail of 1) and 147
+    # level-2 cells (18 groups and a tail of 3)
+    cfg = W.Config(dim=2, n_fine=168, n_macro=14, n_cell=32, n_sub=2, n_cont=2, levels=2)
+    k, l = W.medium_for(cfg, 41)
+    _, A1, _, _, _, _ = gpu_forward(cfg, k, l)
+    monkeypatch.setenv("MCH_XCD", "0")
+    _, A2, _, _, _, _ = gpu_forward(cfg, k, l)
+    assert np.array_equal(A1, A2)
+
+
 def test_L1_plan_equals_flat_bitwise():
     # a hierarchical configuration with L = 1 runs the flat path exactly
     cfg = W.PRESETS["t2"].replace(levels=1)
