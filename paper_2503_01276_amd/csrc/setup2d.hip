@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
+#include <cstdlib>
 
 #include "kernels2d.h"
 
@@ -76,8 +77,8 @@ MCH_DEV void coarse_element(const CellArgs& a, int ox, int oy, int EX, int EY, Q
   }
 }
 
-template <int N>
-__global__ __launch_bounds__(SETUP_T) void k_setup2d(CellArgs a) {
+template <int N, int T>
+__global__ __launch_bounds__(T) void k_setup2d(CellArgs a) {
   extern __shared__ double sm[];
   const int m = a.m, s = a.s, nc = a.nc, NC = a.NC, NCp = NC + 1, sbw = a.sbw;
   const bool gal = a.r > 1;
@@ -94,7 +95,7 @@ __global__ __launch_bounds__(SETUP_T) void k_setup2d(CellArgs a) {
   const int nbands = prec ? NC / a.prec_rows : 0;
   int pNA = 0, pG = 0;
   if (prec) prec_group_sizes(a, &pNA, &pG);
-  double* BZ = wred + (SETUP_T / 64) * N * 3;
+  double* BZ = wred + (T / 64) * N * 3;
   double* Ys = BZ + pG * pNA * NC;
   double* Lf = Ys + pG * pNA * NC;
   double* iD = Lf + nbands * NC;
@@ -124,7 +125,7 @@ __global__ __launch_bounds__(SETUP_T) void k_setup2d(CellArgs a) {
     double acc[N][3];
 #pragma unroll
     for (int j = 0; j < N; ++j) acc[j][0] = acc[j][1] = acc[j][2] = 0.0;
-    for (int k = tid; k < w * w; k += SETUP_T) {
+    for (int k = tid; k < w * w; k += T) {
       const int ex = x0 + k % w, ey = y0 + k / w;
       const int lab = a.label[(size_t)wrapi(oy + ey, a.n) * a.n + wrapi(ox + ex, a.n)];
 #pragma unroll
@@ -146,7 +147,7 @@ __global__ __launch_bounds__(SETUP_T) void k_setup2d(CellArgs a) {
     __syncthreads();
     if (tid < N * 3) {
       double v = 0.0;
-      for (int w2 = 0; w2 < SETUP_T / 64; ++w2) v += wred[w2 * N * 3 + tid];
+      for (int w2 = 0; w2 < T / 64; ++w2) v += wred[w2 * N * 3 + tid];
       stat[reg * N * 3 + tid] = v;
     }
     __syncthreads();
@@ -182,14 +183,14 @@ __global__ __launch_bounds__(SETUP_T) void k_setup2d(CellArgs a) {
   double* nW = gal ? a.nodeW + (size_t)ci * NCp * NCp * 9 : nullptr;
   float* nB = gal ? a.nodeB + (size_t)ci * NCp * NCp * 4 * N : nullptr;
   if (gal) {
-    for (int k = tid; k < NCp * NCp * 9; k += SETUP_T) nW[k] = 0.0;
-    for (int k = tid; k < NCp * NCp * 4 * N; k += SETUP_T) nB[k] = 0.0f;
+    for (int k = tid; k < NCp * NCp * 9; k += T) nW[k] = 0.0;
+    for (int k = tid; k < NCp * NCp * 4 * N; k += T) nB[k] = 0.0f;
     __syncthreads();
     // four colour passes: elements of one colour share no node
     for (int color = 0; color < 4; ++color) {
       const int cx = color & 1, cy = color >> 1;
       const int hx = (NC - cx + 1) / 2, hy = (NC - cy + 1) / 2;
-      for (int k = tid; k < hx * hy; k += SETUP_T) {
+      for (int k = tid; k < hx * hy; k += T) {
         const int EX = cx + 2 * (k % hx), EY = cy + 2 * (k / hx);
         Quad<N> qd;
         coarse_element<N>(a, ox, oy, EX, EY, qd);
@@ -215,7 +216,7 @@ __global__ __launch_bounds__(SETUP_T) void k_setup2d(CellArgs a) {
     // windows for it (a.kw, a.labw; null otherwise)
     double* kwc = a.kw ? a.kw + (size_t)ci * NC * NC : nullptr;
     uint8_t* lwc = a.labw ? a.labw + (size_t)ci * NC * NC : nullptr;
-    for (int e = tid; e < NC * NC; e += SETUP_T) {
+    for (int e = tid; e < NC * NC; e += T) {
       const int EX = e % NC, EY = e / NC;
       const size_t ge = (size_t)wrapi(oy + EY, a.n) * a.n + wrapi(ox + EX, a.n);
       labS[e] = a.label[ge];
@@ -238,7 +239,7 @@ __global__ __launch_bounds__(SETUP_T) void k_setup2d(CellArgs a) {
     return 1.0 / (4.0 * ks);
   };
   // sub-block of every level element
-  for (int e = tid; e < NC * NC; e += SETUP_T) regS[e] = (uint8_t)(((e / NC) / sbw) * s + (e % NC) / sbw);
+  for (int e = tid; e < NC * NC; e += T) regS[e] = (uint8_t)(((e / NC) / sbw) * s + (e % NC) / sbw);
   __syncthreads();
 
   // ---- S = B_n D^-1 B_n^T --------------------------------------------------
@@ -248,9 +249,9 @@ __global__ __launch_bounds__(SETUP_T) void k_setup2d(CellArgs a) {
   // node's elements in qa and in qb (element counts, or the Galerkin weights),
   // and accumulate all N x N products times 1/D; a wave sum in fixed order
   // gives the block, scaled by the row weights.
-  for (int k = tid; k < m * m; k += SETUP_T) S[k] = 0.0;
+  for (int k = tid; k < m * m; k += T) S[k] = 0.0;
   __syncthreads();
-  for (int t = wave; t < s * s * 9; t += SETUP_T / 64) {
+  for (int t = wave; t < s * s * 9; t += T / 64) {
     const int qa = t / 9, d9 = t % 9;
     const int qax = qa % s, qay = qa / s;
     const int qbx = qax + d9 % 3 - 1, qby = qay + d9 / 3 - 1;
@@ -365,7 +366,7 @@ __global__ __launch_bounds__(SETUP_T) void k_setup2d(CellArgs a) {
       return w;
     };
     // rows of every T_b: off-diagonal T[X][X+1] into Lf, diagonal into iD
-    for (int e = tid; e < nbands * NC; e += SETUP_T) {
+    for (int e = tid; e < nbands * NC; e += T) {
       const int b = e / NC, X = e % NC, yb0 = b * R;
       double td = 0.0, tc = 0.0;
       for (int i = 0; i < R; ++i) {
@@ -387,7 +388,7 @@ __global__ __launch_bounds__(SETUP_T) void k_setup2d(CellArgs a) {
     }
     __syncthreads();
     // T_b = L D L^T, one band per thread: l_X = T[X][X-1] / D_{X-1}
-    for (int b = tid; b < nbands; b += SETUP_T) {
+    for (int b = tid; b < nbands; b += T) {
       double* lf = Lf + b * NC;
       double* id = iD + b * NC;
       double prevD = id[0], prevT = lf[0];  // D_0 = 1 (identity row)
@@ -430,7 +431,7 @@ __global__ __launch_bounds__(SETUP_T) void k_setup2d(CellArgs a) {
         n_act[tid] = na < NA ? na : NA;
       }
       __syncthreads();
-      for (int e = tid; e < gb * NA * NC; e += SETUP_T) {
+      for (int e = tid; e < gb * NA * NC; e += T) {
         const int g = e / (NA * NC), ia = (e / NC) % NA, X = e % NC;
         if (ia >= n_act[g]) continue;
         const int k = act[g][ia], q = k / N, j = k % N, qx = q % s, yb0 = (b0 + g) * R;
@@ -444,7 +445,7 @@ __global__ __launch_bounds__(SETUP_T) void k_setup2d(CellArgs a) {
         BZ[e] = cwp[k] * acc;
       }
       __syncthreads();
-      for (int e = tid; e < gb * NA; e += SETUP_T) {
+      for (int e = tid; e < gb * NA; e += T) {
         const int g = e / NA, ia = e % NA;
         if (ia >= n_act[g]) continue;
         const double* lf = Lf + (b0 + g) * NC;
@@ -457,7 +458,7 @@ __global__ __launch_bounds__(SETUP_T) void k_setup2d(CellArgs a) {
         }
       }
       __syncthreads();
-      for (int e = tid; e < m * m; e += SETUP_T) {
+      for (int e = tid; e < m * m; e += T) {
         const int k = e / m, k2 = e % m;
         double acc = 0.0;
         for (int g = 0; g < gb; ++g) {
@@ -477,7 +478,7 @@ __global__ __launch_bounds__(SETUP_T) void k_setup2d(CellArgs a) {
   // Pivot k: p = S_kk; row k becomes S_kj / p, column k becomes -S_ik / p,
   // the pivot 1 / p, and S_ij -= S_ik S_kj / p elsewhere. S is symmetric
   // positive definite, so every pivot is positive without row exchanges.
-  for (int k = tid; k < m; k += SETUP_T)
+  for (int k = tid; k < m; k += T)
     if (cwp[k] == 0.0) S[k * m + k] = 1.0;
   double* rowk = X;       // S_kj / p
   double* colk = X + m;   // S_ik
@@ -486,12 +487,12 @@ __global__ __launch_bounds__(SETUP_T) void k_setup2d(CellArgs a) {
     const double piv = S[k * m + k];
     if (!(piv > 0.0) && tid == 0) singular = 1;
     const double ip = piv > 0.0 ? 1.0 / piv : 1.0;
-    for (int j = tid; j < m; j += SETUP_T) {
+    for (int j = tid; j < m; j += T) {
       rowk[j] = S[k * m + j] * ip;
       colk[j] = S[j * m + k];
     }
     __syncthreads();
-    for (int e = tid; e < m * m; e += SETUP_T) {
+    for (int e = tid; e < m * m; e += T) {
       const int i = e / m, j = e % m;
       double v;
       if (i == k)
@@ -505,7 +506,7 @@ __global__ __launch_bounds__(SETUP_T) void k_setup2d(CellArgs a) {
   }
   __syncthreads();
   const bool bad = singular != 0;
-  for (int k = tid; k < m * m; k += SETUP_T) a.sinv[(size_t)p * m * m + k] = bad ? __builtin_nan("") : S[k];
+  for (int k = tid; k < m * m; k += T) a.sinv[(size_t)p * m * m + k] = bad ? __builtin_nan("") : S[k];
 }
 
 // Inherited right-hand sides of a level >= 2 cell, one workgroup per
@@ -599,8 +600,8 @@ __global__ __launch_bounds__(SETUP_T) void k_inherit2d(CellArgs a) {
   }
 }
 
-static size_t setup_lds_bytes(const CellArgs& a) {
-  size_t d = (size_t)a.m * a.m + 2 * (size_t)a.m + (size_t)(a.s * a.s + 1) * a.N * 3 + (SETUP_T / 64) * a.N * 3;
+static size_t setup_lds_bytes(const CellArgs& a, int threads) {
+  size_t d = (size_t)a.m * a.m + 2 * (size_t)a.m + (size_t)(a.s * a.s + 1) * a.N * 3 + (threads / 64) * a.N * 3;
   if (a.prec_rows > 0) {
     int NA, G;
     prec_group_sizes(a, &NA, &G);
@@ -620,16 +621,29 @@ static int lds_attr(F fn, size_t lds) {
   return MCH_OK;
 }
 
+// Threads of the set-up workgroup: a level of few cells (the fine level of a
+// small macrogrid, whose set-up precedes its solve on the critical path) gets
+// 1024 so that the workgroups still fill much of the GPU.
+static int setup_threads(const CellArgs& a) {
+  static const int wide = [] {
+    const char* v = std::getenv("MCH_SETUP_WIDE");
+    return v ? std::atoi(v) : 1;
+  }();
+  return (wide && a.count <= 128) ? 1024 : SETUP_T;
+}
+
 int launch_setup(const CellArgs& a, hipStream_t s) {
-  const size_t lds = setup_lds_bytes(a);
+  const int threads = setup_threads(a);
+  const size_t lds = setup_lds_bytes(a, threads);
   void (*fn)(CellArgs) = nullptr;
-  if (a.N == 1) fn = k_setup2d<1>;
-  if (a.N == 2) fn = k_setup2d<2>;
-  if (a.N == 3) fn = k_setup2d<3>;
+#define MCH_SETUP(n_)                                              \
+  if (a.N == n_) fn = threads == 1024 ? k_setup2d<n_, 1024> : k_setup2d<n_, SETUP_T>;
+  MCH_SETUP(1) MCH_SETUP(2) MCH_SETUP(3)
+#undef MCH_SETUP
   if (!fn) return set_error(MCH_ENOTIMPL, "n_cont");
   int rc = lds_attr(fn, lds);
   if (rc) return rc;
-  hipLaunchKernelGGL(fn, dim3(a.count), dim3(SETUP_T), lds, s, a);
+  hipLaunchKernelGGL(fn, dim3(a.count), dim3(threads), lds, s, a);
   return hip_check(hipGetLastError(), "launch k_setup2d");
 }
 
