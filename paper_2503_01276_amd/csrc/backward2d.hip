@@ -215,7 +215,7 @@ __global__ __launch_bounds__(IBT) void k_ibar2d(CellArgs a, LevelTab lt, const i
     __syncthreads();  // previous child's data fully consumed
     for (int e = tid; e < nc * nc; e += IBT) {
       const int ex = e % nc, ey = e / nc;
-      const size_t ge = (size_t)wrapi(oy + ey, a.n) * a.n + wrapi(ox + ex, a.n);
+      const size_t ge = (size_t)wrap1(oy + ey, a.n) * a.n + wrap1(ox + ex, a.n);
       if constexpr (KLDS) kS[e] = a.kappa[ge] * (1.0 / 6.0);
       labS[e] = a.label[ge];
     }
@@ -258,7 +258,7 @@ __global__ __launch_bounds__(IBT) void k_ibar2d(CellArgs a, LevelTab lt, const i
         if constexpr (KLDS)
           ke = kS[e];
         else
-          ke = a.kappa[(size_t)wrapi(oy + ey, a.n) * a.n + wrapi(ox + ex, a.n)] * (1.0 / 6.0);
+          ke = a.kappa[(size_t)wrap1(oy + ey, a.n) * a.n + wrap1(ox + ex, a.n)] * (1.0 / 6.0);
         kpw += ke * (4.0 * c[cn] - 2.0 * c[cn ^ 3] - c[cn ^ 1] - c[cn ^ 2]);
         const int lab = labS[e];
         if (lab < N) btmu += cmS[((ey / sb) * s + ex / sb) * N + lab];

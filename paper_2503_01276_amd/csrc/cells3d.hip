@@ -45,7 +45,7 @@ MCH_DEV void cell_origin3(const CellArgs& a, int p, int& ox, int& oy, int& oz) {
 // Global element index of cell-local element (ex, ey, ez), periodic wrap.
 MCH_DEV size_t gel3(const CellArgs& a, int ox, int oy, int oz, int ex, int ey, int ez) {
   const int n = a.n;
-  return ((size_t)wrapi(oz + ez, n) * n + (size_t)wrapi(oy + ey, n)) * n + (size_t)wrapi(ox + ex, n);
+  return ((size_t)wrap1(oz + ez, n) * n + (size_t)wrap1(oy + ey, n)) * n + (size_t)wrap1(ox + ex, n);
 }
 
 // y = (12/h) K_ref v for one hexahedron.

@@ -13,6 +13,14 @@ constexpr int WAVE = 64;
 // robin (workgroup b runs on die b mod kXcds), each die with its own L2.
 constexpr int kXcds = 8;
 
+// i mod n for a coordinate within one period of the grid, -n <= i < 2n (a
+// cell-window coordinate: the window starts at most n/2 before the grid and
+// is at most n wide): a compare and an add instead of an integer division.
+MCH_DEV int wrap1(int i, int n) {
+  i = i < 0 ? i + n : i;
+  return i >= n ? i - n : i;
+}
+
 MCH_DEV int wrapi(int i, int n) {
   int r = i % n;
   return r < 0 ? r + n : r;

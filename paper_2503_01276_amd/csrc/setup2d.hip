@@ -58,9 +58,9 @@ MCH_DEV void coarse_element(const CellArgs& a, int ox, int oy, int EX, int EY, Q
     for (int j = 0; j < N; ++j) q.b[c][j] = 0.0;
   const int r = a.r;
   for (int v = 0; v < r; ++v) {
-    const int gy = wrapi(oy + EY * r + v, a.n);
+    const int gy = wrap1(oy + EY * r + v, a.n);
     for (int u = 0; u < r; ++u) {
-      const int gx = wrapi(ox + EX * r + u, a.n);
+      const int gx = wrap1(ox + EX * r + u, a.n);
       const size_t e = (size_t)gy * a.n + gx;
       const double kap = a.kappa[e];
       const int lab = a.label[e];
@@ -127,7 +127,7 @@ __global__ __launch_bounds__(T) void k_setup2d(CellArgs a) {
     for (int j = 0; j < N; ++j) acc[j][0] = acc[j][1] = acc[j][2] = 0.0;
     for (int k = tid; k < w * w; k += T) {
       const int ex = x0 + k % w, ey = y0 + k / w;
-      const int lab = a.label[(size_t)wrapi(oy + ey, a.n) * a.n + wrapi(ox + ex, a.n)];
+      const int lab = a.label[(size_t)wrap1(oy + ey, a.n) * a.n + wrap1(ox + ex, a.n)];
 #pragma unroll
       for (int j = 0; j < N; ++j) {
         if (lab == j) {
@@ -218,7 +218,7 @@ __global__ __launch_bounds__(T) void k_setup2d(CellArgs a) {
     uint8_t* lwc = a.labw ? a.labw + (size_t)ci * NC * NC : nullptr;
     for (int e = tid; e < NC * NC; e += T) {
       const int EX = e % NC, EY = e / NC;
-      const size_t ge = (size_t)wrapi(oy + EY, a.n) * a.n + wrapi(ox + EX, a.n);
+      const size_t ge = (size_t)wrap1(oy + EY, a.n) * a.n + wrap1(ox + EX, a.n);
       labS[e] = a.label[ge];
       if (kwc) {
         kwc[e] = a.kappa[ge] * (1.0 / 6.0);
@@ -233,7 +233,7 @@ __global__ __launch_bounds__(T) void k_setup2d(CellArgs a) {
     if (gal) return 1.0 / nW[(Yn * NCp + Xn) * 9 + 4];
     auto kq = [&](int ex, int ey) {
       if (ex < 0 || ey < 0 || ex >= NC || ey >= NC) return 0.0;
-      return a.kappa[(size_t)wrapi(oy + ey, a.n) * a.n + wrapi(ox + ex, a.n)] * (1.0 / 6.0);
+      return a.kappa[(size_t)wrap1(oy + ey, a.n) * a.n + wrap1(ox + ex, a.n)] * (1.0 / 6.0);
     };
     const double ks = kq(Xn - 1, Yn - 1) + kq(Xn, Yn - 1) + kq(Xn - 1, Yn) + kq(Xn, Yn);
     return 1.0 / (4.0 * ks);
@@ -337,7 +337,7 @@ __global__ __launch_bounds__(T) void k_setup2d(CellArgs a) {
         k6[5] = w9[2];
       } else {
         auto kq = [&](int ex, int ey) {
-          return a.kappa[(size_t)wrapi(oy + ey, a.n) * a.n + wrapi(ox + ex, a.n)] * (1.0 / 6.0);
+          return a.kappa[(size_t)wrap1(oy + ey, a.n) * a.n + wrap1(ox + ex, a.n)] * (1.0 / 6.0);
         };
         const double kSW = kq(X - 1, Y - 1), kSE = kq(X, Y - 1), kNW = kq(X - 1, Y), kNE = kq(X, Y);
         const double aS = kSW + kSE, aN = kNW + kNE;
@@ -547,7 +547,7 @@ __global__ __launch_bounds__(SETUP_T) void k_inherit2d(CellArgs a) {
         if (ex < 0 || ey < 0 || ex >= nc || ey >= nc) continue;  // outside the cell (Neumann boundary)
         const int c = (x - ex) + 2 * (y - ey);
         auto Iv = [&](int cc) { return I[(size_t)(ey + (cc >> 1)) * nn1 + ex + (cc & 1)]; };
-        const double k6 = a.kappa[(size_t)wrapi(oy + ey, a.n) * a.n + wrapi(ox + ex, a.n)] * (1.0 / 6.0);
+        const double k6 = a.kappa[(size_t)wrap1(oy + ey, a.n) * a.n + wrap1(ox + ex, a.n)] * (1.0 / 6.0);
         t += k6 * (4.0 * Iv(c) - 2.0 * Iv(c ^ 3) - Iv(c ^ 1) - Iv(c ^ 2));
       }
     }
@@ -579,7 +579,7 @@ __global__ __launch_bounds__(SETUP_T) void k_inherit2d(CellArgs a) {
     for (int j = 0; j < N; ++j) acc[j] = 0.0;
     for (int k = tid; k < sb * sb; k += SETUP_T) {
       const int ex = x0 + k % sb, ey = y0 + k / sb;
-      const int lab = a.label[(size_t)wrapi(oy + ey, a.n) * a.n + wrapi(ox + ex, a.n)];
+      const int lab = a.label[(size_t)wrap1(oy + ey, a.n) * a.n + wrap1(ox + ex, a.n)];
       const double es = (I[(size_t)ey * nn1 + ex] + I[(size_t)ey * nn1 + ex + 1]) +
                         (I[(size_t)(ey + 1) * nn1 + ex] + I[(size_t)(ey + 1) * nn1 + ex + 1]);
 #pragma unroll

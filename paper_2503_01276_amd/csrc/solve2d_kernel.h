@@ -179,7 +179,7 @@ __global__ __launch_bounds__(NC* NC / RPT) __attribute__((amdgpu_waves_per_eu(2)
       for (int i = 0; i <= RPT; ++i) {
         const int ex = c - 1 + sd, ey = y0 - 1 + i;
         const bool ok = ex >= 0 && ey >= 0;
-        const size_t e = (size_t)wrapi(oy + ey, a.n) * a.n + wrapi(ox + ex, a.n);
+        const size_t e = (size_t)wrap1(oy + ey, a.n) * a.n + wrap1(ox + ex, a.n);
         kl[sd][i] = ok ? a.kappa[e] * (1.0 / 6.0) : 0.0;
         lab[sd][i] = ok ? (int)a.label[e] : 255;
         if constexpr (!BIG) kq[sd][i] = kl[sd][i];
@@ -187,7 +187,7 @@ __global__ __launch_bounds__(NC* NC / RPT) __attribute__((amdgpu_waves_per_eu(2)
     if constexpr (BIG) {
       for (int k = tid; k < (NC + 1) * (NC + 1); k += NT) {
         const int ex = k % (NC + 1) - 1, ey = k / (NC + 1) - 1;
-        const size_t e = (size_t)wrapi(oy + ey, a.n) * a.n + wrapi(ox + ex, a.n);
+        const size_t e = (size_t)wrap1(oy + ey, a.n) * a.n + wrap1(ox + ex, a.n);
         kS[k] = (ex >= 0 && ey >= 0) ? a.kappa[e] * (1.0 / 6.0) : 0.0;
       }
     }
