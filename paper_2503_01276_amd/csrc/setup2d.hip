@@ -511,15 +511,18 @@ __global__ __launch_bounds__(T) void k_setup2d(CellArgs a) {
 
 // Inherited right-hand sides of a level >= 2 cell, one workgroup per
 // (cell, alpha): f = -P^T K_h I on the level nodes and g' = g - B_h I, with I
-// the inherited level-1 solution. First R = K_h I at every interior fine node
-// (each node from its four fine elements, kappa and I straight from global
-// memory) into LDS; then f at a level node is minus the hat-weighted sum of R
-// over the node's support. B_h I is summed sub-block by sub-block, each wave
-// keeping its partial per sub-block and continuum; one barrier, then the
-// waves' partials in a fixed order.
+// the inherited level-1 solution. f is formed element by element: a fine
+// element's K_e I_e (its four corner values) goes to the four corners of the
+// level element containing it with the bilinear weights of its corners, so
+// each fine element is visited once (kappa and I straight from global
+// memory). The level elements are split over groups of lanes, whose partial
+// corner sums are reduced with DPP into LDS; a level node then adds the
+// corners of its (up to four) level elements in a fixed order. B_h I is
+// summed sub-block by sub-block, each wave keeping its partial per sub-block
+// and continuum; one barrier, then the waves' partials in a fixed order.
 template <int N>
 __global__ __launch_bounds__(SETUP_T) void k_inherit2d(CellArgs a) {
-  extern __shared__ double Rs[];  // [(nc+1)^2] R = K_h I, then [s*s][NW][N] partials
+  extern __shared__ double Fc[];  // [NC^2][4] corner sums of f per level element, then [s*s][NW][N] partials
   constexpr int NW = SETUP_T / 64;
   const int nc = a.nc, nn1 = nc + 1, NC = a.NC, r = a.r, m = a.m, s = a.s, M = a.M;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -529,43 +532,57 @@ __global__ __launch_bounds__(SETUP_T) void k_inherit2d(CellArgs a) {
   const int ox = a.H * jx + a.H / 2 - nc / 2, oy = a.H * jy + a.H / 2 - nc / 2;
   const double* I = a.phi1 + ((size_t)a.pslot[ci] * M + al) * (size_t)nn1 * nn1;
   const double inv_r = 1.0 / r;
-  const int NCp = NC + 1;
+  const int NCp = NC + 1, L2e = NC * NC;
   double* fo = a.fin + ((size_t)ci * M + al) * NCp * NCp;
-  double* wred = Rs + nn1 * nn1;
-  // free fine nodes [flo, fhi]^2 and free level nodes [lo, hi]^2
-  const int flo = a.bc ? 0 : 1, fhi = a.bc ? nc : nc - 1;
+  double* wred = Fc + (size_t)L2e * 4;
+  // free level nodes [lo, hi]^2
   const int lo = a.bc ? 0 : 1, hi = a.bc ? NC : NC - 1;
-  // R at fine node (x, y): node (x, y) is corner c of the element, and row c
-  // of 6 K_ref is 4 v_c - 2 v_(c^3) - v_(c^1) - v_(c^2)
-  for (int nd = tid; nd < nn1 * nn1; nd += SETUP_T) {
-    const int x = nd % nn1, y = nd / nn1;
-    double t = 0.0;
-    if (x >= flo && y >= flo && x <= fhi && y <= fhi) {
+  // lanes per level element: the largest power of two with L2e groups fitting
+  // the workgroup (1 when there are more level elements than lanes)
+  int tpe = 1;
+  while (tpe * 2 * L2e <= SETUP_T && tpe < 64) tpe *= 2;
+  const int groups = SETUP_T / tpe;
+  for (int E0 = tid / tpe; E0 - tid / tpe < L2e; E0 += groups) {
+    // every lane of a group runs the same trip; groups past the last level
+    // element contribute nothing
+    const bool live = E0 < L2e;
+    const int EX = live ? E0 % NC : 0, EY = live ? E0 / NC : 0;
+    double fc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = tid % tpe; live && k < r * r; k += tpe) {
+      const int u = k % r, v = k / r;
+      const int ex = EX * r + u, ey = EY * r + v;
+      const double k6 = a.kappa[(size_t)wrap1(oy + ey, a.n) * a.n + wrap1(ox + ex, a.n)] * (1.0 / 6.0);
+      double Iv[4], y[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int ex = x - 1 + (q & 1), ey = y - 1 + (q >> 1);
-        if (ex < 0 || ey < 0 || ex >= nc || ey >= nc) continue;  // outside the cell (Neumann boundary)
-        const int c = (x - ex) + 2 * (y - ey);
-        auto Iv = [&](int cc) { return I[(size_t)(ey + (cc >> 1)) * nn1 + ex + (cc & 1)]; };
-        const double k6 = a.kappa[(size_t)wrap1(oy + ey, a.n) * a.n + wrap1(ox + ex, a.n)] * (1.0 / 6.0);
-        t += k6 * (4.0 * Iv(c) - 2.0 * Iv(c ^ 3) - Iv(c ^ 1) - Iv(c ^ 2));
+      for (int d = 0; d < 4; ++d) Iv[d] = I[(size_t)(ey + (d >> 1)) * nn1 + ex + (d & 1)];
+      kref6_apply(Iv, y);
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        const double tx = (u + (d & 1)) * inv_r, ty = (v + (d >> 1)) * inv_r;
+        const double yd = k6 * y[d];
+        fc[0] += (1.0 - tx) * (1.0 - ty) * yd;
+        fc[1] += tx * (1.0 - ty) * yd;
+        fc[2] += (1.0 - tx) * ty * yd;
+        fc[3] += tx * ty * yd;
       }
     }
-    Rs[nd] = t;
+    if (tpe > 1) seg_sum_n<4>(fc, tpe);
+    if (live && tid % tpe == 0) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) Fc[(size_t)E0 * 4 + c] = fc[c];
+    }
   }
   __syncthreads();
   for (int nd = tid; nd < NCp * NCp; nd += SETUP_T) {
     const int Xn = nd % NCp, Yn = nd / NCp;
     double acc = 0.0;
     if (Xn >= lo && Yn >= lo && Xn <= hi && Yn <= hi) {
-      // the hat's support, clipped to the cell's fine nodes
-      const int dy0 = max(1 - r, -Yn * r), dy1 = min(r - 1, nc - Yn * r);
-      const int dx0 = max(1 - r, -Xn * r), dx1 = min(r - 1, nc - Xn * r);
-      for (int dy = dy0; dy <= dy1; ++dy) {
-        const double* row = Rs + (size_t)(Yn * r + dy) * nn1 + Xn * r;
-        double racc = 0.0;
-        for (int dx = dx0; dx <= dx1; ++dx) racc += (1.0 - abs(dx) * inv_r) * row[dx];
-        acc += (1.0 - abs(dy) * inv_r) * racc;
+      // node (Xn, Yn) is corner c of level element (Xn - cx, Yn - cy)
+#pragma unroll
+      for (int c = 3; c >= 0; --c) {
+        const int EX = Xn - (c & 1), EY = Yn - (c >> 1);
+        if (EX < 0 || EY < 0 || EX >= NC || EY >= NC) continue;
+        acc += Fc[((size_t)EY * NC + EX) * 4 + c];
       }
     }
     fo[nd] = -acc;
@@ -654,7 +671,7 @@ int launch_inherit(const CellArgs& a, hipStream_t s) {
   if (a.N == 2) fn = k_inherit2d<2>;
   if (a.N == 3) fn = k_inherit2d<3>;
   if (!fn) return set_error(MCH_ENOTIMPL, "n_cont");
-  const size_t lds = ((size_t)(a.nc + 1) * (a.nc + 1) + (size_t)a.s * a.s * (SETUP_T / 64) * a.N) * sizeof(double);
+  const size_t lds = ((size_t)a.NC * a.NC * 4 + (size_t)a.s * a.s * (SETUP_T / 64) * a.N) * sizeof(double);
   int rc = lds_attr(fn, lds);
   if (rc) return rc;
   hipLaunchKernelGGL(fn, dim3(a.count * a.M), dim3(SETUP_T), lds, s, a);
