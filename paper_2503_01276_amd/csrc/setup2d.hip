@@ -41,39 +41,33 @@ __host__ __device__ inline void prec_group_sizes(const CellArgs& a, int* NA, int
   *G = nbands < PREC_GROUP ? nbands : PREC_GROUP;
 }
 
+// Coarse element data, flat so that one DPP pass sums it over lanes: the
+// element stiffness [16] (corners in tensor order), then the constraint
+// weights per corner and continuum [4][N] (no 1/(4 n_qj)).
 template <int N>
-struct Quad {
-  double K[16];   // coarse element stiffness, corners in tensor order
-  double b[4][N]; // constraint weights per corner and continuum (no 1/(4 n_qj))
-};
+constexpr int quad_len() { return 16 + 4 * N; }
 
-// Coarse element (EX, EY) of the level-r cell from its r^2 fine elements.
+// The part of coarse element (EX, EY) of the level-r cell from its fine
+// elements first, first + stride, ... (of the r^2, x fastest).
 template <int N>
-MCH_DEV void coarse_element(const CellArgs& a, int ox, int oy, int EX, int EY, Quad<N>& q) {
+MCH_DEV void coarse_element_part(const CellArgs& a, int ox, int oy, int EX, int EY, int first, int stride,
+                                 double (&q)[quad_len<N>()]) {
 #pragma unroll
-  for (int k = 0; k < 16; ++k) q.K[k] = 0.0;
-#pragma unroll
-  for (int c = 0; c < 4; ++c)
-#pragma unroll
-    for (int j = 0; j < N; ++j) q.b[c][j] = 0.0;
+  for (int k = 0; k < quad_len<N>(); ++k) q[k] = 0.0;
   const int r = a.r;
-  for (int v = 0; v < r; ++v) {
-    const int gy = wrap1(oy + EY * r + v, a.n);
-    for (int u = 0; u < r; ++u) {
-      const int gx = wrap1(ox + EX * r + u, a.n);
-      const size_t e = (size_t)gy * a.n + gx;
-      const double kap = a.kappa[e];
-      const int lab = a.label[e];
-      const int pos = u + r * v;
-      const double* tk = a.tabK + pos * 16;
-      const double* tr = a.tabR + pos * 4;
+  for (int pos = first; pos < r * r; pos += stride) {
+    const int u = pos % r, v = pos / r;
+    const size_t e = (size_t)wrap1(oy + EY * r + v, a.n) * a.n + wrap1(ox + EX * r + u, a.n);
+    const double kap = a.kappa[e];
+    const int lab = a.label[e];
+    const double* tk = a.tabK + pos * 16;
+    const double* tr = a.tabR + pos * 4;
 #pragma unroll
-      for (int k = 0; k < 16; ++k) q.K[k] += kap * tk[k];
+    for (int k = 0; k < 16; ++k) q[k] += kap * tk[k];
 #pragma unroll
-      for (int c = 0; c < 4; ++c)
+    for (int c = 0; c < 4; ++c)
 #pragma unroll
-        for (int j = 0; j < N; ++j) q.b[c][j] += (lab == j) ? tr[c] : 0.0;
-    }
+      for (int j = 0; j < N; ++j) q[16 + c * N + j] += (lab == j) ? tr[c] : 0.0;
   }
 }
 
@@ -186,14 +180,35 @@ __global__ __launch_bounds__(T) void k_setup2d(CellArgs a) {
     for (int k = tid; k < NCp * NCp * 9; k += T) nW[k] = 0.0;
     for (int k = tid; k < NCp * NCp * 4 * N; k += T) nB[k] = 0.0f;
     __syncthreads();
-    // four colour passes: elements of one colour share no node
+    // four colour passes: elements of one colour share no node. When a pass
+    // has fewer elements than lanes, a group of tpe lanes (a power of two)
+    // shares an element's fine elements and sums its data with DPP; every
+    // lane of a group runs the same trips.
     for (int color = 0; color < 4; ++color) {
       const int cx = color & 1, cy = color >> 1;
-      const int hx = (NC - cx + 1) / 2, hy = (NC - cy + 1) / 2;
-      for (int k = tid; k < hx * hy; k += T) {
-        const int EX = cx + 2 * (k % hx), EY = cy + 2 * (k / hx);
-        Quad<N> qd;
-        coarse_element<N>(a, ox, oy, EX, EY, qd);
+      const int hx = (NC - cx + 1) / 2, hy = (NC - cy + 1) / 2, ne = hx * hy;
+      int tpe = 1;
+      while (tpe * 2 * ne <= T && tpe < 64) tpe *= 2;
+      const int g0 = tid / tpe, groups = T / tpe;
+      for (int k = g0; k - g0 < ne; k += groups) {
+        const bool live = k < ne;
+        const int EX = live ? cx + 2 * (k % hx) : 0, EY = live ? cy + 2 * (k / hx) : 0;
+        constexpr int QL = quad_len<N>();
+        double qv[QL];
+        coarse_element_part<N>(a, ox, oy, EX, EY, live ? tid % tpe : a.r * a.r, tpe, qv);
+        if (tpe > 1) {
+#pragma unroll
+          for (int c0 = 0; c0 < QL; c0 += 4) {
+            double v4[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) v4[t] = c0 + t < QL ? qv[c0 + t] : 0.0;
+            seg_sum_n<4>(v4, tpe);
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+              if (c0 + t < QL) qv[c0 + t] = v4[t];
+          }
+        }
+        if (!live || tid % tpe != 0) continue;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           const int Xn = EX + (c & 1), Yn = EY + (c >> 1);
@@ -201,12 +216,12 @@ __global__ __launch_bounds__(T) void k_setup2d(CellArgs a) {
 #pragma unroll
           for (int b = 0; b < 4; ++b) {
             const int dx = (b & 1) - (c & 1), dy = (b >> 1) - (c >> 1);
-            nW[nd * 9 + (dy + 1) * 3 + dx + 1] += qd.K[c * 4 + b];
+            nW[nd * 9 + (dy + 1) * 3 + dx + 1] += qv[c * 4 + b];
           }
           const int side = (c & 1) ? 0 : 1;   // element left of the node -> side 0
           const int part = (c >> 1) ? 0 : 1;  // element below the node -> part 0
 #pragma unroll
-          for (int j = 0; j < N; ++j) nB[((nd * 4) + side * 2 + part) * N + j] += (float)qd.b[c][j];
+          for (int j = 0; j < N; ++j) nB[((nd * 4) + side * 2 + part) * N + j] += (float)qv[16 + c * N + j];
         }
       }
       __syncthreads();
