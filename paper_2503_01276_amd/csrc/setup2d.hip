@@ -524,6 +524,12 @@ __global__ __launch_bounds__(T) void k_setup2d(CellArgs a) {
   for (int k = tid; k < m * m; k += T) a.sinv[(size_t)p * m * m + k] = bad ? __builtin_nan("") : S[k];
 }
 
+// Whether the inherit kernel sums B_h I in its element pass: its per-element
+// sums (NC^2 N values) and the corner sums of f (4 NC^2) fit the LDS.
+__host__ __device__ inline bool inherit_fused(int NC, int N) {
+  return (size_t)NC * NC * (4 + N) * sizeof(double) <= 160 * 1024;
+}
+
 // Inherited right-hand sides of a level >= 2 cell, one workgroup per
 // (cell, alpha): f = -P^T K_h I on the level nodes and g' = g - B_h I, with I
 // the inherited level-1 solution. f is formed element by element: a fine
@@ -532,15 +538,20 @@ __global__ __launch_bounds__(T) void k_setup2d(CellArgs a) {
 // each fine element is visited once (kappa and I straight from global
 // memory). The level elements are split over groups of lanes, whose partial
 // corner sums are reduced with DPP into LDS; a level node then adds the
-// corners of its (up to four) level elements in a fixed order. B_h I is
-// summed sub-block by sub-block, each wave keeping its partial per sub-block
-// and continuum; one barrier, then the waves' partials in a fixed order.
+// corners of its (up to four) level elements in a fixed order. The same pass
+// sums I over each fine element per continuum (B_h I): a level element lies
+// in one sub-block, so its per-continuum sums go to LDS too and each
+// constraint row adds those of its sub-block's level elements in order.
 template <int N>
 __global__ __launch_bounds__(SETUP_T) void k_inherit2d(CellArgs a) {
-  extern __shared__ double Fc[];  // [NC^2][4] corner sums of f per level element, then [s*s][NW][N] partials
+  extern __shared__ double Fc[];  // [NC^2][4] corner sums of f, then (fused) [NC^2][N] element sums of I
+                                  // per continuum, or [s*s][NW][N] wave partials of B_h I
   constexpr int NW = SETUP_T / 64;
   const int nc = a.nc, nn1 = nc + 1, NC = a.NC, r = a.r, m = a.m, s = a.s, M = a.M;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // B_h I in the element pass unless the per-element sums would not fit the
+  // LDS (level cells of 64^2 elements); then in a pass of its own
+  const bool fused = inherit_fused(NC, N);
   const int ci = a.ci0 + blockIdx.x / M, al = blockIdx.x % M;
   const int p = a.cells[ci];
   const int jx = p % a.n_macro, jy = p / a.n_macro;
@@ -549,7 +560,8 @@ __global__ __launch_bounds__(SETUP_T) void k_inherit2d(CellArgs a) {
   const double inv_r = 1.0 / r;
   const int NCp = NC + 1, L2e = NC * NC;
   double* fo = a.fin + ((size_t)ci * M + al) * NCp * NCp;
-  double* wred = Fc + (size_t)L2e * 4;
+  double* Eb = Fc + (size_t)L2e * 4;
+  double* wred = Eb;
   // free level nodes [lo, hi]^2
   const int lo = a.bc ? 0 : 1, hi = a.bc ? NC : NC - 1;
   // lanes per level element: the largest power of two with L2e groups fitting
@@ -562,14 +574,22 @@ __global__ __launch_bounds__(SETUP_T) void k_inherit2d(CellArgs a) {
     // element contribute nothing
     const bool live = E0 < L2e;
     const int EX = live ? E0 % NC : 0, EY = live ? E0 / NC : 0;
-    double fc[4] = {0.0, 0.0, 0.0, 0.0};
+    // corner sums of f (4), then element sums of I per continuum (N)
+    double fc[4 + N];
+#pragma unroll
+    for (int t = 0; t < 4 + N; ++t) fc[t] = 0.0;
     for (int k = tid % tpe; live && k < r * r; k += tpe) {
       const int u = k % r, v = k / r;
       const int ex = EX * r + u, ey = EY * r + v;
-      const double k6 = a.kappa[(size_t)wrap1(oy + ey, a.n) * a.n + wrap1(ox + ex, a.n)] * (1.0 / 6.0);
+      const size_t ge = (size_t)wrap1(oy + ey, a.n) * a.n + wrap1(ox + ex, a.n);
+      const double k6 = a.kappa[ge] * (1.0 / 6.0);
+      const int lab = a.label[ge];
       double Iv[4], y[4];
 #pragma unroll
       for (int d = 0; d < 4; ++d) Iv[d] = I[(size_t)(ey + (d >> 1)) * nn1 + ex + (d & 1)];
+      const double es = (Iv[0] + Iv[1]) + (Iv[2] + Iv[3]);
+#pragma unroll
+      for (int j = 0; j < N; ++j) fc[4 + j] += (lab == j) ? es : 0.0;
       kref6_apply(Iv, y);
 #pragma unroll
       for (int d = 0; d < 4; ++d) {
@@ -581,10 +601,14 @@ __global__ __launch_bounds__(SETUP_T) void k_inherit2d(CellArgs a) {
         fc[3] += tx * ty * yd;
       }
     }
-    if (tpe > 1) seg_sum_n<4>(fc, tpe);
+    if (tpe > 1) seg_sum_n<4 + N>(fc, tpe);
     if (live && tid % tpe == 0) {
 #pragma unroll
       for (int c = 0; c < 4; ++c) Fc[(size_t)E0 * 4 + c] = fc[c];
+      if (fused) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) Eb[(size_t)E0 * N + j] = fc[4 + j];
+      }
     }
   }
   __syncthreads();
@@ -602,33 +626,51 @@ __global__ __launch_bounds__(SETUP_T) void k_inherit2d(CellArgs a) {
     }
     fo[nd] = -acc;
   }
-  // B_h I: element sums of I per sub-block and continuum
-  const int sb = nc / s;
-  for (int reg = 0; reg < s * s; ++reg) {
-    const int x0 = (reg % s) * sb, y0 = (reg / s) * sb;
-    double acc[N];
+  if (!fused) {
+    // B_h I: element sums of I per sub-block and continuum, wave partials
+    const int sb = nc / s;
+    for (int reg = 0; reg < s * s; ++reg) {
+      const int x0 = (reg % s) * sb, y0 = (reg / s) * sb;
+      double acc[N];
 #pragma unroll
-    for (int j = 0; j < N; ++j) acc[j] = 0.0;
-    for (int k = tid; k < sb * sb; k += SETUP_T) {
-      const int ex = x0 + k % sb, ey = y0 + k / sb;
-      const int lab = a.label[(size_t)wrap1(oy + ey, a.n) * a.n + wrap1(ox + ex, a.n)];
-      const double es = (I[(size_t)ey * nn1 + ex] + I[(size_t)ey * nn1 + ex + 1]) +
-                        (I[(size_t)(ey + 1) * nn1 + ex] + I[(size_t)(ey + 1) * nn1 + ex + 1]);
+      for (int j = 0; j < N; ++j) acc[j] = 0.0;
+      for (int k = tid; k < sb * sb; k += SETUP_T) {
+        const int ex = x0 + k % sb, ey = y0 + k / sb;
+        const int lab = a.label[(size_t)wrap1(oy + ey, a.n) * a.n + wrap1(ox + ex, a.n)];
+        const double es = (I[(size_t)ey * nn1 + ex] + I[(size_t)ey * nn1 + ex + 1]) +
+                          (I[(size_t)(ey + 1) * nn1 + ex] + I[(size_t)(ey + 1) * nn1 + ex + 1]);
 #pragma unroll
-      for (int j = 0; j < N; ++j) acc[j] += (lab == j) ? es : 0.0;
+        for (int j = 0; j < N; ++j) acc[j] += (lab == j) ? es : 0.0;
+      }
+      wave_sum_n<N>(acc);
+      if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) wred[(reg * NW + wave) * N + j] = acc[j];
+      }
     }
-    wave_sum_n<N>(acc);
-    if (lane == 0) {
-#pragma unroll
-      for (int j = 0; j < N; ++j) wred[(reg * NW + wave) * N + j] = acc[j];
-    }
+    __syncthreads();
   }
-  __syncthreads();
-  for (int k = tid; k < m; k += SETUP_T) {
-    const int q = k / N, j = k % N;
-    double bI = 0.0;
-    for (int w2 = 0; w2 < NW; ++w2) bI += wred[(q * NW + w2) * N + j];
-    a.gin[((size_t)ci * M + al) * m + k] = a.g[((size_t)p * M + al) * m + k] - a.cw[(size_t)p * m + k] * bI;
+  // B_h I per constraint row: (fused) the sums of the sub-block's level
+  // elements, one wave per row with a fixed-order wave sum, or the waves'
+  // partials in order
+  const int sbw = a.sbw;
+  if (fused) {
+    for (int k = wave; k < m; k += NW) {
+      const int q = k / N, j = k % N, qx = q % s, qy = q / s;
+      double bI = 0.0;
+      for (int e = lane; e < sbw * sbw; e += 64)
+        bI += Eb[((size_t)(qy * sbw + e / sbw) * NC + qx * sbw + e % sbw) * N + j];
+      bI = wave_sum(bI);
+      if (lane == 0)
+        a.gin[((size_t)ci * M + al) * m + k] = a.g[((size_t)p * M + al) * m + k] - a.cw[(size_t)p * m + k] * bI;
+    }
+  } else {
+    for (int k = tid; k < m; k += SETUP_T) {
+      const int q = k / N, j = k % N;
+      double bI = 0.0;
+      for (int w2 = 0; w2 < NW; ++w2) bI += wred[(q * NW + w2) * N + j];
+      a.gin[((size_t)ci * M + al) * m + k] = a.g[((size_t)p * M + al) * m + k] - a.cw[(size_t)p * m + k] * bI;
+    }
   }
 }
 
@@ -686,7 +728,9 @@ int launch_inherit(const CellArgs& a, hipStream_t s) {
   if (a.N == 2) fn = k_inherit2d<2>;
   if (a.N == 3) fn = k_inherit2d<3>;
   if (!fn) return set_error(MCH_ENOTIMPL, "n_cont");
-  const size_t lds = ((size_t)a.NC * a.NC * 4 + (size_t)a.s * a.s * (SETUP_T / 64) * a.N) * sizeof(double);
+  const size_t L2e = (size_t)a.NC * a.NC;
+  const size_t lds = (L2e * 4 + (inherit_fused(a.NC, a.N) ? L2e * a.N : (size_t)a.s * a.s * (SETUP_T / 64) * a.N)) *
+                     sizeof(double);
   int rc = lds_attr(fn, lds);
   if (rc) return rc;
   hipLaunchKernelGGL(fn, dim3(a.count * a.M), dim3(SETUP_T), lds, s, a);
