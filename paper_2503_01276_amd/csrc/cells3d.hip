@@ -800,11 +800,14 @@ __global__ __launch_bounds__((nt3<NC, GAL>())) __attribute__((amdgpu_waves_per_e
     const int r = a.r, H = a.H, Hp = H + 1, k0 = (a.nc - H) / 2;
     const double* skp = a.seed_kp + ((size_t)p * M + alpha) * (size_t)Hp * Hp * Hp;
     double t = 0.0;
-    for (int dw = -(r - 1); dw <= r - 1; ++dw)
-      for (int dv = -(r - 1); dv <= r - 1; ++dv)
-        for (int du = -(r - 1); du <= r - 1; ++du) {
+    // the hat's support clipped to the K_p nodes (often empty)
+    const int du0 = max(-(r - 1), k0 - X * r), du1 = min(r - 1, k0 + H - X * r);
+    const int dv0 = max(-(r - 1), k0 - Y * r), dv1 = min(r - 1, k0 + H - Y * r);
+    const int dw0 = max(-(r - 1), k0 - Z * r), dw1 = min(r - 1, k0 + H - Z * r);
+    for (int dw = dw0; dw <= dw1; ++dw)
+      for (int dv = dv0; dv <= dv1; ++dv)
+        for (int du = du0; du <= du1; ++du) {
           const int fx = X * r + du - k0, fy = Y * r + dv - k0, fz = Z * r + dw - k0;
-          if (fx < 0 || fy < 0 || fz < 0 || fx > H || fy > H || fz > H) continue;
           const double wgt = (1.0 - fabs((double)du) / r) * (1.0 - fabs((double)dv) / r) * (1.0 - fabs((double)dw) / r);
           t += wgt * skp[nidx3(fx, fy, fz, Hp)];
         }

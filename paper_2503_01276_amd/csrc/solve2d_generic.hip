@@ -263,10 +263,12 @@ __global__ __launch_bounds__(GEN_T) __attribute__((amdgpu_waves_per_eu(2))) void
         // seeds from the cells that inherit from this one (all fine nodes)
         const double* skp = a.seed_kp + ((size_t)p * M + alpha) * (size_t)((a.H + 1) * (a.H + 1));
         const int rr = a.r;
-        for (int dv = -(rr - 1); dv <= rr - 1; ++dv)
-          for (int du = -(rr - 1); du <= rr - 1; ++du) {
+        // the hat's support clipped to the K_p nodes (often empty)
+        const int du0 = max(-(rr - 1), k0 - X * rr), du1 = min(rr - 1, k0 + a.H - X * rr);
+        const int dv0 = max(-(rr - 1), k0 - Y * rr), dv1 = min(rr - 1, k0 + a.H - Y * rr);
+        for (int dv = dv0; dv <= dv1; ++dv)
+          for (int du = du0; du <= du1; ++du) {
             const int fx = X * rr + du - k0, fy = Y * rr + dv - k0;
-            if (fx < 0 || fy < 0 || fx > a.H || fy > a.H) continue;
             const double wgt = (1.0 - fabs((double)du) / rr) * (1.0 - fabs((double)dv) / rr);
             f += wgt * skp[fy * (a.H + 1) + fx];
           }
