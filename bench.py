@@ -533,7 +533,7 @@ def measure(args, run, cpu, oracle_ref, tuned):
         print(f"[bench] macroscopic system: {mh['ms']:.3f} ms, {mh['cg_iterations']} CG iterations",
               file=sys.stderr, flush=True)
     detail["tuned_knobs"] = {w: _knobs(t) for w, t in tuned.items()} or None
-    detail["band_correction_per_level"] = list(plan.band_precond)
+    detail["band_subbands_per_level"] = list(plan.band_subbands)
     out = {
         "metric": "cell-solves/sec & eff-tensor+grad time, hier L=3 vs flat, 1 GPU, rel err <=1e-8",
         "value": solves / (ms * 1e-3),

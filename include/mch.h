@@ -132,9 +132,10 @@ int mch_build_interp(const mch_config* cfg, int32_t* nbr, double* weight);
  * info[4+L..4+2L) = node rows per thread of each level's 2D solve kernel (the
  * size-class shape: the workgroup has NC^2 / rows threads; 0 in 3D and for
  * levels on the generic 2D kernel),
- * info[4+2L..4+3L) = 1 where the level's 2D solve preconditions with the band
- * coarse correction, 0 where with the diagonal alone (and in 3D), the rest
- * zero. info must hold at least 28 entries (4 + 3 * 8 levels). */
+ * info[4+2L..4+3L) = the sub-bands per thread's node rows (1 or 2) where the
+ * level's 2D solve preconditions with the band coarse correction, 0 where
+ * with the diagonal alone (and in 3D), the rest zero. info must hold at
+ * least 28 entries (4 + 3 * 8 levels). */
 int mch_plan_info(const mch_plan* plan, int64_t* info);
 
 /* Level (1..L) and the level-1 macropoint of its group (-1 for level 1) of

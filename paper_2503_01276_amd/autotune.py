@@ -5,9 +5,10 @@ Knobs, read by the library from the environment when a plan is created:
   workgroup has NC^2 / rows threads): the register footprint and parallelism
   of the solve kernel;
 * per 2D cell width NC, the band coarse correction in the preconditioner
-  (MCH_PREC_<NC> = 1 or 0): fewer iterations against more work per
-  iteration and a costlier per-cell setup, which pays off only where the
-  medium's slow modes follow the bands;
+  (MCH_PREC_<NC> = 1: one band per thread's node rows, 2: two sub-bands of
+  half as many rows, 0: the diagonal alone): fewer iterations against more
+  work per iteration and a costlier per-cell setup, which pays off only where
+  the medium's slow modes follow the bands;
 * per plan, whether level 1 runs as two launches so that the children of the
   first part overlap the tail of the second (MCH_SPLIT = 1 or 0; 2D and 3D).
 
@@ -137,13 +138,13 @@ def tune(cfg, kappa, label, reps: int = 3, candidates=CANDIDATES) -> dict:
                 os.environ[_env_name(nc)] = str(best)
             for nc in widths:
                 times = {}
-                for on in (1, 0):
+                for on in (2, 1, 0):
                     os.environ[_prec_name(nc)] = str(on)
                     plan = mch.Plan(cfg)
                     try:
                         levels, names = width_names(plan, nc)
-                        if any(plan.band_precond[l] != bool(on) for l in levels):
-                            continue  # no preconditioned kernel for this shape
+                        if any(plan.band_subbands[l] != on for l in levels):
+                            continue  # no kernel with this preconditioner for the shape
                         times[on] = _time(plan, kd, ld, names, reps)
                     finally:
                         plan.close()

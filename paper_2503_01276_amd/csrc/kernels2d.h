@@ -29,21 +29,21 @@ constexpr int schur_lanes(int m) {
 
 // Solve kernel for cells of S sub-blocks per axis (S = 1, 2, 4, 8; one
 // translation unit each): the kernel of a (cell width, node rows per thread,
-// continua, Galerkin, band coarse correction) shape and its block size, or
-// nullptr if that shape is not instantiated.
+// continua, Galerkin, band coarse correction, sub-bands per thread) shape and
+// its block size, or nullptr if that shape is not instantiated.
 template <int S>
-const void* solve_kernel_sub(int NC, int rpt, int N, bool gal, bool pre, int* threads);
+const void* solve_kernel_sub(int NC, int rpt, int N, bool gal, bool pre, int sb, int* threads);
 template <>
-const void* solve_kernel_sub<1>(int, int, int, bool, bool, int*);
+const void* solve_kernel_sub<1>(int, int, int, bool, bool, int, int*);
 template <>
-const void* solve_kernel_sub<2>(int, int, int, bool, bool, int*);
+const void* solve_kernel_sub<2>(int, int, int, bool, bool, int, int*);
 template <>
-const void* solve_kernel_sub<4>(int, int, int, bool, bool, int*);
+const void* solve_kernel_sub<4>(int, int, int, bool, bool, int, int*);
 template <>
-const void* solve_kernel_sub<8>(int, int, int, bool, bool, int*);
-// Whether a level can use the band coarse correction (kernel instantiated
-// and its LDS within the budget).
-bool prec_supported_2d(int NC, int rpt, int N, bool gal, int S, int m);
+const void* solve_kernel_sub<8>(int, int, int, bool, bool, int, int*);
+// Whether a level can use the band coarse correction with sb sub-bands per
+// thread's rows (kernel instantiated and its LDS within the budget).
+bool prec_supported_2d(int NC, int rpt, int N, bool gal, int S, int m, int sb);
 // Per-cell setup (constraint rows, right-hand sides, Galerkin data, S^-1).
 int launch_setup(const CellArgs& a, hipStream_t s);
 // Inherited right-hand sides of a level >= 2 (needs the level-1 solutions).

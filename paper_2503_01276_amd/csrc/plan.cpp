@@ -496,11 +496,19 @@ extern "C" int mch_build_levels(const mch_config* cfg, mch_plan** out) {
       int mode = 1;
       if (const char* v = std::getenv("MCH_PREC")) mode = std::atoi(v);
       bool want = mode == 2 || (mode == 1 && lv.NC >= 64);
-      // per cell width (the size-class tuner's knob): MCH_PREC_<NC> = 0 or 1
+      // per cell width (the size-class tuner's knob): MCH_PREC_<NC> = 0 (off),
+      // 1 (bands of a thread's node rows) or 2 (two sub-bands per thread's
+      // rows, where that kernel exists and fits)
+      int sb = 1;
       char pname[32];
       std::snprintf(pname, sizeof(pname), "MCH_PREC_%d", lv.NC);
-      if (const char* v = std::getenv(pname)) want = std::atoi(v) != 0;
-      lv.shape.pre = want && prec_supported_2d(lv.NC, lv.shape.rpt, c.n_cont, lv.r > 1, c.n_sub, p->m);
+      if (const char* v = std::getenv(pname)) {
+        const int k = std::atoi(v);
+        want = k != 0;
+        sb = k >= 2 ? 2 : 1;
+      }
+      lv.shape.pre = want && prec_supported_2d(lv.NC, lv.shape.rpt, c.n_cont, lv.r > 1, c.n_sub, p->m, sb);
+      lv.shape.sb = lv.shape.pre ? sb : 1;
     }
     if (d == 2 && lv.shape.gen_tp == 0 && !shape_supported_2d(lv.NC, lv.shape.rpt, c.n_cont, lv.r > 1, c.n_sub)) {
       rc = set_error(MCH_ENOTIMPL, "no kernel instantiated for level cell width " + std::to_string(lv.NC) +
@@ -766,7 +774,7 @@ extern "C" int mch_plan_info(const mch_plan* p, int64_t* info) {
   for (int l = 0; l < p->L; ++l) {
     info[4 + l] = p->lev[l].count;
     info[4 + p->L + l] = p->lev[l].shape.rpt;
-    info[4 + 2 * p->L + l] = p->lev[l].shape.pre ? 1 : 0;
+    info[4 + 2 * p->L + l] = p->lev[l].shape.pre ? p->lev[l].shape.sb : 0;
   }
   return MCH_OK;
 }

@@ -26,6 +26,7 @@ struct KernelShape {
   int rpt = 0;   // node rows per thread
   int threads = 0;
   bool pre = false;  // 2D: band coarse correction in the preconditioner
+  int sb = 1;        // 2D: sub-bands of the correction per thread's node rows
   int gen_tp = 0;    // 2D generic solve kernel: threads per sub-block tile (0: not used)
 };
 

@@ -115,7 +115,7 @@ CellArgs base_args(mch_plan* pl, const double* kappa, const uint8_t* label, int 
   a.fin = lv.d_fin;
   a.gin = lv.d_gin;
   a.J = 1;
-  a.prec_rows = lv.shape.pre ? lv.shape.rpt : 0;
+  a.prec_rows = lv.shape.pre ? lv.shape.rpt / lv.shape.sb : 0;
   a.bc = pl->cfg.bc;
   a.gen_tp = lv.shape.gen_tp;
   a.xcd_groups = pl->xcd_groups;
@@ -142,37 +142,38 @@ static int ilog2i(int v) {
   return k;
 }
 
-static size_t solve_lds_bytes(int NC, int rpt, int s, int N, int m, bool gal, bool pre) {
+static size_t solve_lds_bytes(int NC, int rpt, int s, int N, int m, bool gal, bool pre, int sb) {
   const int NT = NC * NC / rpt, NW = NT / 64, NB = NC / rpt, PW = NC + 2;
   const int J = schur_lanes(m), MS = (m + J - 1) / J, UST = MS * J;
   size_t d = (size_t)PW * PW + 4 * NW + (size_t)NB * 4 * s * N + (size_t)MS * 64 + (size_t)m + (size_t)NW * UST +
              (size_t)NW * m;
-  if (!gal && NC >= 64) d += (size_t)(NC + 1) * (NC + 1) + (size_t)NC * NC;
+  // 64^2 fine cells: kappa/6 and (one band per thread) the iterate
+  if (!gal && NC >= 64) d += (size_t)(NC + 1) * (NC + 1) + (sb > 1 ? 0 : (size_t)NC * NC);
   // elimination factors of the band coarse correction (see the kernel)
-  if (pre) d += (size_t)NB * 2 * ((size_t)NC * ilog2i(NC) - (NC - 1));
+  if (pre) d += (size_t)NB * sb * 2 * ((size_t)NC * ilog2i(NC) - (NC - 1));
   return d * sizeof(double);
 }
 
 // Solve kernel of a shape (nullptr if not instantiated) and its block size.
-static const void* solve_kernel(int NC, int rpt, int N, bool gal, bool pre, int S, int* threads) {
+static const void* solve_kernel(int NC, int rpt, int N, bool gal, bool pre, int sb, int S, int* threads) {
   switch (S) {
-    case 1: return solve_kernel_sub<1>(NC, rpt, N, gal, pre, threads);
-    case 2: return solve_kernel_sub<2>(NC, rpt, N, gal, pre, threads);
-    case 4: return solve_kernel_sub<4>(NC, rpt, N, gal, pre, threads);
-    case 8: return solve_kernel_sub<8>(NC, rpt, N, gal, pre, threads);
+    case 1: return solve_kernel_sub<1>(NC, rpt, N, gal, pre, sb, threads);
+    case 2: return solve_kernel_sub<2>(NC, rpt, N, gal, pre, sb, threads);
+    case 4: return solve_kernel_sub<4>(NC, rpt, N, gal, pre, sb, threads);
+    case 8: return solve_kernel_sub<8>(NC, rpt, N, gal, pre, sb, threads);
     default: return nullptr;
   }
 }
 
 bool shape_supported_2d(int NC, int rpt, int N, bool gal, int S) {
   int threads = 0;
-  return solve_kernel(NC, rpt, N, gal, false, S, &threads) != nullptr;
+  return solve_kernel(NC, rpt, N, gal, false, 1, S, &threads) != nullptr;
 }
 
-bool prec_supported_2d(int NC, int rpt, int N, bool gal, int S, int m) {
+bool prec_supported_2d(int NC, int rpt, int N, bool gal, int S, int m, int sb) {
   int threads = 0;
-  return solve_kernel(NC, rpt, N, gal, true, S, &threads) != nullptr &&
-         solve_lds_bytes(NC, rpt, S, N, m, gal, true) <= 160 * 1024;
+  return solve_kernel(NC, rpt, N, gal, true, sb, S, &threads) != nullptr &&
+         solve_lds_bytes(NC, rpt, S, N, m, gal, true, sb) <= 160 * 1024;
 }
 
 int launch_solve(const CellArgs& a_in, int rpt, hipStream_t s) {
@@ -182,11 +183,13 @@ int launch_solve(const CellArgs& a_in, int rpt, hipStream_t s) {
   a.J = schur_lanes(a.m);
   const bool gal = a.r > 1;
   const bool pre = a.prec_rows > 0;
-  if (pre && a.prec_rows != rpt) return set_error(MCH_EINVAL, "band coarse correction rows differ from the kernel's");
-  const size_t lds = solve_lds_bytes(a.NC, rpt, a.s, a.N, a.m, gal, pre);
+  // sub-bands per thread's rows: the correction's band height divides them
+  const int sb = pre ? rpt / a.prec_rows : 1;
+  if (pre && a.prec_rows * sb != rpt) return set_error(MCH_EINVAL, "band coarse correction rows do not divide the kernel's");
+  const size_t lds = solve_lds_bytes(a.NC, rpt, a.s, a.N, a.m, gal, pre, sb);
   if (lds > 160 * 1024) return set_error(MCH_EINVAL, "cell solve exceeds the LDS budget");
   int threads = 0;
-  const void* fn = solve_kernel(a.NC, rpt, a.N, gal, pre, a.s, &threads);
+  const void* fn = solve_kernel(a.NC, rpt, a.N, gal, pre, sb, a.s, &threads);
   if (!fn) return set_error(MCH_ENOTIMPL, "no kernel for this cell shape");
   if (lds > 64 * 1024) {
     int rc = hip_check(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
@@ -203,9 +206,10 @@ int solve_blocks_per_cu_2d(mch_plan* pl) {
   if (a.gen_tp > 0) return generic_blocks_per_cu(a);
   const int rpt = pl->lev[0].shape.rpt;
   const bool pre = a.prec_rows > 0;
-  const size_t lds = solve_lds_bytes(a.NC, rpt, a.s, a.N, a.m, false, pre);
+  const int sb = pre ? rpt / a.prec_rows : 1;
+  const size_t lds = solve_lds_bytes(a.NC, rpt, a.s, a.N, a.m, false, pre, sb);
   int threads = 0;
-  const void* fn = solve_kernel(a.NC, rpt, a.N, false, pre, a.s, &threads);
+  const void* fn = solve_kernel(a.NC, rpt, a.N, false, pre, sb, a.s, &threads);
   if (!fn) return set_error(MCH_ENOTIMPL, "no kernel for this cell shape");
   if (lds > 64 * 1024) {
     int rc = hip_check(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),

@@ -25,18 +25,22 @@ constexpr bool kValid = NC % MCH_SUB == 0 && (NC / MCH_SUB) % RPT == 0 && N * MC
 }  // namespace
 
 template <>
-const void* solve_kernel_sub<MCH_SUB>(int NC, int rpt, int N, bool gal, bool pre, int* threads) {
-  // the band coarse correction needs bands of at least two node rows
-#define X(nc_, r_, n_, g_)                                                                        \
-  if constexpr (kValid<nc_, r_, n_>) {                                                            \
-    if (NC == nc_ && rpt == r_ && N == n_ && gal == g_) {                                         \
-      *threads = nc_ * nc_ / r_;                                                                  \
-      if constexpr (r_ >= 2) {                                                                    \
-        if (pre) return reinterpret_cast<const void*>(k_solve2d<nc_, r_, n_, g_, MCH_SUB, true>); \
-      }                                                                                           \
-      if (pre) return nullptr;                                                                    \
-      return reinterpret_cast<const void*>(k_solve2d<nc_, r_, n_, g_, MCH_SUB, false>);           \
-    }                                                                                             \
+const void* solve_kernel_sub<MCH_SUB>(int NC, int rpt, int N, bool gal, bool pre, int sb, int* threads) {
+  // the band coarse correction needs bands of at least two node rows; two
+  // sub-bands per thread exist for the 64^2 fine cells (8 rows per thread)
+#define X(nc_, r_, n_, g_)                                                                           \
+  if constexpr (kValid<nc_, r_, n_>) {                                                               \
+    if (NC == nc_ && rpt == r_ && N == n_ && gal == g_) {                                            \
+      *threads = nc_ * nc_ / r_;                                                                     \
+      if constexpr (r_ >= 2) {                                                                       \
+        if (pre && sb == 1) return reinterpret_cast<const void*>(k_solve2d<nc_, r_, n_, g_, MCH_SUB, true, 1>); \
+      }                                                                                              \
+      if constexpr (nc_ == 64 && r_ == 8 && !g_) {                                                   \
+        if (pre && sb == 2) return reinterpret_cast<const void*>(k_solve2d<nc_, r_, n_, g_, MCH_SUB, true, 2>); \
+      }                                                                                              \
+      if (pre) return nullptr;                                                                       \
+      return reinterpret_cast<const void*>(k_solve2d<nc_, r_, n_, g_, MCH_SUB, false, 1>);           \
+    }                                                                                                \
   }
   MCH_SHAPES(X)
 #undef X

@@ -26,7 +26,12 @@
 // iterations about threefold. T_b^-1 is applied by parallel cyclic reduction
 // across the band's lanes (one unknown per lane), with the elimination
 // factors computed once per solve and kept in LDS, so the preconditioner
-// needs no barrier. Without PRE, G = D.
+// needs no barrier. Without PRE, G = D. With SB = 2 the correction uses
+// sub-bands of RPT / 2 node rows (two coarse unknowns per node column and
+// band of threads, two tridiagonal systems per band): on the 64^2 cells of
+// the three-continuum medium with inclusions this halves the iterations
+// against bands of RPT rows. The factors of both then fill the LDS that the
+// 64^2 iterate took, so the iterate is kept in the output array instead.
 //
 // Layout inside a workgroup: one (cell, right-hand side) per workgroup; lane
 // c of a band row owns node column c and element column c; each band of RPT
@@ -53,7 +58,19 @@ constexpr bool kBig = !GAL && NC >= 64;
 // r_new.G^-1 r_new follow from those sums without another reduction. Every
 // wave then solves the small Schur system S v = u on its own (same inputs,
 // same order, identical results), so no wave waits on a serial section.
+//
+// B G^-1 r' vanishes only as far as the Schur matrix of the set-up equals
+// B G^-1 B^T for the G^-1 the iteration applies. With D alone that holds to
+// rounding, and the remainder is folded in every ZPERIOD iterations. With
+// the band correction the set-up forms S from an LDL^T factorisation of T_b
+// while the iteration applies T_b^-1 by cyclic reduction; the two agree only
+// to about cond(T_b) times the unit roundoff (T_b inherits the contrast of
+// the medium), and a remainder left for several iterations slows the
+// convergence and costs digits in the solution (and more in the next
+// level's Galerkin operators built from it). It is folded in every
+// ZPERIOD_BAND iterations there.
 constexpr int ZPERIOD = 16;
+constexpr int ZPERIOD_BAND = 1;
 
 // S sub-blocks per axis, so m = N S^2 constraint rows and sub-blocks of
 // NC / S level elements spanning NC / (S RPT) bands.
@@ -73,13 +90,16 @@ constexpr int pcr_step_offset(int k) {
 
 // At least two waves per SIMD: a workgroup of fewer than eight waves would
 // otherwise let the compiler spend the whole register file on one wave.
-template <int NC, int RPT, int N, bool GAL, int S, bool PRE>
+template <int NC, int RPT, int N, bool GAL, int S, bool PRE, int SB>
 __global__ __launch_bounds__(NC* NC / RPT) __attribute__((amdgpu_waves_per_eu(2))) void k_solve2d(CellArgs a) {
   constexpr int NT = NC * NC / RPT;
   constexpr int NW = NT / 64;
   constexpr int NB = NC / RPT;
   constexpr int PW = NC + 2;
   constexpr bool BIG = kBig<NC, GAL>;
+  constexpr int HB = RPT / SB;                 // node rows per sub-band of the correction
+  constexpr bool XG = BIG && SB > 1;           // iterate in the output array, not LDS
+  static_assert(SB == 1 || (PRE && RPT % SB == 0), "sub-bands need the band correction");
   constexpr int m = N * S * S, s = S, sbw = NC / S, NBS = NB / S;
   static_assert(NC % S == 0 && sbw % RPT == 0 && m <= 64, "unsupported cell shape");
   extern __shared__ double smem[];
@@ -96,8 +116,8 @@ __global__ __launch_bounds__(NC* NC / RPT) __attribute__((amdgpu_waves_per_eu(2)
   double* uW = cwS + m;                     // NW*UST per-wave right-hand side
   double* vW = uW + NW * UST;               // NW*m per-wave v*cw
   double* kS = vW + NW * m;                 // BIG: (NC+1)^2 kappa/6, ring of zeros at -1
-  double* xS = kS + (NC + 1) * (NC + 1);    // BIG: NC*NC iterate
-  double* pcr = BIG ? xS + NC * NC : kS;    // PRE: NB * pcr_per_band<NC>() elimination factors
+  double* xS = kS + (NC + 1) * (NC + 1);    // BIG (not XG): NC*NC iterate
+  double* pcr = BIG ? (XG ? xS : xS + NC * NC) : kS;  // PRE: NB SB pcr_per_band<NC>() elimination factors
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int c = tid % NC, band = tid / NC, y0 = band * RPT;
@@ -125,6 +145,15 @@ __global__ __launch_bounds__(NC* NC / RPT) __attribute__((amdgpu_waves_per_eu(2)
   }
   const int ci = a.ci0 + cl;
   const int p = a.cells[ci];
+  // the iterate of node row i of the thread's column: LDS (BIG), or the
+  // output array itself (XG; its row and column NC stay the zero boundary)
+  double* const xg = a.out + ((size_t)ci * M + alpha) * (size_t)(NC + 1) * (NC + 1);
+  auto xat = [&](int i) -> double& {
+    if constexpr (XG)
+      return xg[(size_t)(y0 + i) * (NC + 1) + c];
+    else
+      return xS[(y0 + i) * NC + c];
+  };
   const int jx = p % a.n_macro, jy = p / a.n_macro;
   const int ox = a.H * jx + a.H / 2 - a.nc / 2, oy = a.H * jy + a.H / 2 - a.nc / 2;
   const bool split0 = (y0 > 0) && (y0 % sbw == 0);
@@ -140,18 +169,21 @@ __global__ __launch_bounds__(NC* NC / RPT) __attribute__((amdgpu_waves_per_eu(2)
   }
   for (int k = tid; k < m; k += NT) cwS[k] = a.cw[(size_t)p * m + k];
 
-  // Row c of the band matrix T_b (PRE): diagonal Td = T[c][c], Tc = T[c][c+1].
-  double Td = 0.0, Tc = 0.0;
+  // Row c of the (sub-)band matrices T_b (PRE): diagonal Td = T[c][c],
+  // Tc = T[c][c+1], one pair per sub-band.
+  double Td[SB], Tc[SB];
+#pragma unroll
+  for (int b = 0; b < SB; ++b) Td[b] = Tc[b] = 0.0;
   // Adds node row i's K_n entries (centre, north, south, east, north-east,
-  // south-east) between free nodes of the band to Td and Tc.
+  // south-east) between free nodes of its sub-band to Td and Tc.
   auto band_row = [&](int i, double cen, double nor, double sou, double eas, double ne, double se) {
-    const int y = y0 + i;
+    const int y = y0 + i, ib = i % HB, sb = i / HB;
     const bool fr = (c >= 1) && (y >= 1);
     const bool frE = (c + 1 <= NC - 1) && (y >= 1);
-    const bool upIn = (i + 1 < RPT), dnIn = (i >= 1) && (y - 1 >= 1);
+    const bool upIn = (ib + 1 < HB), dnIn = (ib >= 1) && (y - 1 >= 1);
     if (fr) {
-      Td += cen + (upIn ? nor : 0.0) + (dnIn ? sou : 0.0);
-      if (frE) Tc += eas + (upIn ? ne : 0.0) + (dnIn ? se : 0.0);
+      Td[sb] += cen + (upIn ? nor : 0.0) + (dnIn ? sou : 0.0);
+      if (frE) Tc[sb] += eas + (upIn ? ne : 0.0) + (dnIn ? se : 0.0);
     }
   };
 
@@ -247,34 +279,40 @@ __global__ __launch_bounds__(NC* NC / RPT) __attribute__((amdgpu_waves_per_eu(2)
   // the free nodes of its node column and those of columns c and c + 1 in the
   // band's rows. Column 0 is the Dirichlet boundary: an identity row.
   constexpr int LOGNC = ilog2(NC);
-  double pcr_ib = 0.0;  // 1 / the final pivot of the lane's row
-  if constexpr (PRE) {
-    if (c == 0) {
-      Td = 1.0;
-      Tc = 0.0;
-    }
-    double Ta = __shfl_up(Tc, 1, NC);  // T[c][c-1] = T[c-1][c]
-    if (c == 0) Ta = 0.0;
-    double* blk = pcr + (size_t)band * pcr_per_band<NC>();
+  double pcr_ib[SB];  // 1 / the final pivot of the lane's row, per sub-band
 #pragma unroll
-    for (int k = 0; k < LOGNC; ++k) {
-      const int st = 1 << k;
-      const bool hasL = c >= st, hasR = c + st < NC;
-      const double aL = __shfl_up(Ta, st, NC), bL = __shfl_up(Td, st, NC), cL = __shfl_up(Tc, st, NC);
-      const double aR = __shfl_down(Ta, st, NC), bR = __shfl_down(Td, st, NC), cR = __shfl_down(Tc, st, NC);
-      const double al = hasL ? -Ta / bL : 0.0;
-      const double ga = hasR ? -Tc / bR : 0.0;
-      const double na = hasL ? al * aL : 0.0;
-      const double ncf = hasR ? ga * cR : 0.0;
-      const double nb = Td + (hasL ? al * cL : 0.0) + (hasR ? ga * aR : 0.0);
-      double* stp = blk + pcr_step_offset<NC>(k);
-      if (hasL) stp[c - st] = al;
-      if (hasR) stp[(NC - st) + c] = ga;
-      Ta = na;
-      Tc = ncf;
-      Td = nb;
+  for (int b = 0; b < SB; ++b) pcr_ib[b] = 0.0;
+  if constexpr (PRE) {
+#pragma unroll
+    for (int b = 0; b < SB; ++b) {
+      double td = Td[b], tc = Tc[b];
+      if (c == 0) {
+        td = 1.0;
+        tc = 0.0;
+      }
+      double Ta = __shfl_up(tc, 1, NC);  // T[c][c-1] = T[c-1][c]
+      if (c == 0) Ta = 0.0;
+      double* blk = pcr + (size_t)(band * SB + b) * pcr_per_band<NC>();
+#pragma unroll
+      for (int k = 0; k < LOGNC; ++k) {
+        const int st = 1 << k;
+        const bool hasL = c >= st, hasR = c + st < NC;
+        const double aL = __shfl_up(Ta, st, NC), bL = __shfl_up(td, st, NC), cL = __shfl_up(tc, st, NC);
+        const double aR = __shfl_down(Ta, st, NC), bR = __shfl_down(td, st, NC), cR = __shfl_down(tc, st, NC);
+        const double al = hasL ? -Ta / bL : 0.0;
+        const double ga = hasR ? -tc / bR : 0.0;
+        const double na = hasL ? al * aL : 0.0;
+        const double ncf = hasR ? ga * cR : 0.0;
+        const double nb = td + (hasL ? al * cL : 0.0) + (hasR ? ga * aR : 0.0);
+        double* stp = blk + pcr_step_offset<NC>(k);
+        if (hasL) stp[c - st] = al;
+        if (hasR) stp[(NC - st) + c] = ga;
+        Ta = na;
+        tc = ncf;
+        td = nb;
+      }
+      pcr_ib[b] = 1.0 / td;
     }
-    pcr_ib = 1.0 / Td;
   }
 
   // ---- building blocks -------------------------------------------------------
@@ -297,27 +335,31 @@ __global__ __launch_bounds__(NC* NC / RPT) __attribute__((amdgpu_waves_per_eu(2)
   // cross-lane latency is paid once.
   auto apply_G2 = [&](const double (&v)[RPT], double (&out)[RPT], const double (&v2)[RPT], double (&out2)[RPT]) {
     if constexpr (PRE) {
-      double d = 0.0, d2 = 0.0;
+      double d[SB], d2[SB];
+#pragma unroll
+      for (int b = 0; b < SB; ++b) d[b] = d2[b] = 0.0;
 #pragma unroll
       for (int i = 0; i < RPT; ++i) {
-        d += (Dinv[i] != 0.0) ? v[i] : 0.0;
-        d2 += (Dinv[i] != 0.0) ? v2[i] : 0.0;
+        d[i / HB] += (Dinv[i] != 0.0) ? v[i] : 0.0;
+        d2[i / HB] += (Dinv[i] != 0.0) ? v2[i] : 0.0;
       }
-      const double* blk = pcr + (size_t)band * pcr_per_band<NC>();
 #pragma unroll
       for (int k = 0; k < LOGNC; ++k) {
         const int st = 1 << k;
-        const double* stp = blk + pcr_step_offset<NC>(k);
-        const double dL = __shfl_up(d, st, NC), dR = __shfl_down(d, st, NC);
-        const double dL2 = __shfl_up(d2, st, NC), dR2 = __shfl_down(d2, st, NC);
-        const double al = (c >= st) ? stp[c - st] : 0.0;
-        const double ga = (c + st < NC) ? stp[(NC - st) + c] : 0.0;
-        d += al * dL + ga * dR;
-        d2 += al * dL2 + ga * dR2;
+#pragma unroll
+        for (int b = 0; b < SB; ++b) {
+          const double* stp = pcr + (size_t)(band * SB + b) * pcr_per_band<NC>() + pcr_step_offset<NC>(k);
+          const double dL = __shfl_up(d[b], st, NC), dR = __shfl_down(d[b], st, NC);
+          const double dL2 = __shfl_up(d2[b], st, NC), dR2 = __shfl_down(d2[b], st, NC);
+          const double al = (c >= st) ? stp[c - st] : 0.0;
+          const double ga = (c + st < NC) ? stp[(NC - st) + c] : 0.0;
+          d[b] += al * dL + ga * dR;
+          d2[b] += al * dL2 + ga * dR2;
+        }
       }
-      const double y = d * pcr_ib, y2 = d2 * pcr_ib;
 #pragma unroll
       for (int i = 0; i < RPT; ++i) {
+        const double y = d[i / HB] * pcr_ib[i / HB], y2 = d2[i / HB] * pcr_ib[i / HB];
         out[i] = Dinv[i] * v[i] + ((Dinv[i] != 0.0) ? y : 0.0);
         out2[i] = Dinv[i] * v2[i] + ((Dinv[i] != 0.0) ? y2 : 0.0);
       }
@@ -332,22 +374,25 @@ __global__ __launch_bounds__(NC* NC / RPT) __attribute__((amdgpu_waves_per_eu(2)
 
   auto apply_G = [&](const double (&v)[RPT], double (&out)[RPT]) {
     if constexpr (PRE) {
-      double d = 0.0;
+      double d[SB];
 #pragma unroll
-      for (int i = 0; i < RPT; ++i) d += (Dinv[i] != 0.0) ? v[i] : 0.0;
-      const double* blk = pcr + (size_t)band * pcr_per_band<NC>();
+      for (int b = 0; b < SB; ++b) d[b] = 0.0;
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) d[i / HB] += (Dinv[i] != 0.0) ? v[i] : 0.0;
 #pragma unroll
       for (int k = 0; k < LOGNC; ++k) {
         const int st = 1 << k;
-        const double* stp = blk + pcr_step_offset<NC>(k);
-        const double dL = __shfl_up(d, st, NC), dR = __shfl_down(d, st, NC);
-        const double al = (c >= st) ? stp[c - st] : 0.0;
-        const double ga = (c + st < NC) ? stp[(NC - st) + c] : 0.0;
-        d += al * dL + ga * dR;
-      }
-      const double y = d * pcr_ib;
 #pragma unroll
-      for (int i = 0; i < RPT; ++i) out[i] = Dinv[i] * v[i] + ((Dinv[i] != 0.0) ? y : 0.0);
+        for (int b = 0; b < SB; ++b) {
+          const double* stp = pcr + (size_t)(band * SB + b) * pcr_per_band<NC>() + pcr_step_offset<NC>(k);
+          const double dL = __shfl_up(d[b], st, NC), dR = __shfl_down(d[b], st, NC);
+          const double al = (c >= st) ? stp[c - st] : 0.0;
+          const double ga = (c + st < NC) ? stp[(NC - st) + c] : 0.0;
+          d[b] += al * dL + ga * dR;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) out[i] = Dinv[i] * v[i] + ((Dinv[i] != 0.0) ? d[i / HB] * pcr_ib[i / HB] : 0.0);
     } else {
 #pragma unroll
       for (int i = 0; i < RPT; ++i) out[i] = Dinv[i] * v[i];
@@ -584,7 +629,7 @@ __global__ __launch_bounds__(NC* NC / RPT) __attribute__((amdgpu_waves_per_eu(2)
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
     pS[(y0 + i + 1) * PW + c + 1] = x[i];
-    if constexpr (BIG) xS[(y0 + i) * NC + c] = x[i];
+    if constexpr (BIG) xat(i) = x[i];
   }
   __syncthreads();
   apply_K(x, r);
@@ -630,9 +675,9 @@ __global__ __launch_bounds__(NC* NC / RPT) __attribute__((amdgpu_waves_per_eu(2)
       s4[2] += t[i] * Ap[i];
       s4[3] += Ap[i] * tA[i];
     }
-    // B G^-1 r' vanishes up to rounding; it is folded in every ZPERIOD
-    // iterations, which keeps the constraint residual at rounding level.
-    const bool withz0 = (it % ZPERIOD) == 0;
+    // B G^-1 r' is folded in periodically (see ZPERIOD), which keeps the
+    // constraint residual at rounding level.
+    const bool withz0 = (it % (PRE ? ZPERIOD_BAND : ZPERIOD)) == 0;
     if (withz0) accumulate_B(t, 0);
     accumulate_B(tA, 1);
     wave_sum_n<4>(s4);
@@ -659,7 +704,7 @@ __global__ __launch_bounds__(NC* NC / RPT) __attribute__((amdgpu_waves_per_eu(2)
 #pragma unroll
       for (int i = 0; i < RPT; ++i) {
         if constexpr (BIG)
-          xS[(y0 + i) * NC + c] += al * pv[i];
+          xat(i) += al * pv[i];
         else
           x[i] += al * pv[i];
       }
@@ -671,7 +716,7 @@ __global__ __launch_bounds__(NC* NC / RPT) __attribute__((amdgpu_waves_per_eu(2)
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       if constexpr (BIG)
-        xS[(y0 + i) * NC + c] += al * pv[i];
+        xat(i) += al * pv[i];
       else
         x[i] += al * pv[i];
       r[i] += al * Ap[i];
@@ -697,7 +742,7 @@ __global__ __launch_bounds__(NC* NC / RPT) __attribute__((amdgpu_waves_per_eu(2)
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       if constexpr (BIG)
-        xr[i] = xS[(y0 + i) * NC + c];
+        xr[i] = xat(i);
       else
         xr[i] = x[i];
       tc[i] = 0.0;
@@ -722,7 +767,7 @@ __global__ __launch_bounds__(NC* NC / RPT) __attribute__((amdgpu_waves_per_eu(2)
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       if constexpr (BIG)
-        xS[(y0 + i) * NC + c] = xr[i] - gc[i];
+        xat(i) = xr[i] - gc[i];
       else
         x[i] = xr[i] - gc[i];
     }
@@ -732,7 +777,9 @@ __global__ __launch_bounds__(NC* NC / RPT) __attribute__((amdgpu_waves_per_eu(2)
   const size_t vec = (size_t)(NC + 1) * (NC + 1);
   double* dst = a.out + ((size_t)ci * M + alpha) * vec;
 #pragma unroll
-  for (int i = 0; i < RPT; ++i) dst[(size_t)(y0 + i) * (NC + 1) + c] = BIG ? xS[(y0 + i) * NC + c] : x[i];
+  for (int i = 0; i < RPT; ++i) {
+    if constexpr (!XG) dst[(size_t)(y0 + i) * (NC + 1) + c] = BIG ? xS[(y0 + i) * NC + c] : x[i];
+  }
   if (wave == 0) {
     const int k = lane / J, jj = lane % J;
     if (k < m && jj == 0) a.beta[((size_t)p * M + alpha) * m + k] = -Vacc;

@@ -188,8 +188,10 @@ class Plan:
         # node rows per thread of each level's 2D solve kernel (0 in 3D and
         # on levels solved by the generic 2D kernel)
         self.rows_per_thread = [int(info[4 + self.levels + k]) for k in range(self.levels)]
-        # whether each level's 2D solve uses the band coarse correction
-        self.band_precond = [bool(info[4 + 2 * self.levels + k]) for k in range(self.levels)]
+        # whether each level's 2D solve uses the band coarse correction, and
+        # with how many sub-bands per thread's node rows (0: none)
+        self.band_subbands = [int(info[4 + 2 * self.levels + k]) for k in range(self.levels)]
+        self.band_precond = [b > 0 for b in self.band_subbands]
         self.generation = 0  # bumped by every forward solve
         _LIVE.add(self)
 

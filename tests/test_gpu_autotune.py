@@ -36,7 +36,7 @@ def test_autotune_times_every_knob_and_the_tuned_plan_agrees():
         autotune.apply(table)
         tuned = mch.Plan(cfg)
         assert tuned.rows_per_thread == [table["rows"][nc]["best"] for nc in widths]
-        assert tuned.band_precond == [bool(table["prec"][nc]["best"]) for nc in widths]
+        assert tuned.band_subbands == [table["prec"][nc]["best"] for nc in widths]
         tuned.close()
         _, A1, *_ = gpu_forward(cfg, k, l)
         err = np.abs(A1 - A0).max() / np.abs(A0).max()

@@ -85,3 +85,21 @@ def test_L1_plan_equals_flat_bitwise():
     _, A1, _, _, _, _ = gpu_forward(cfg, k, l)
     _, A2, _, _, _, _ = gpu_forward(cfg.replace(eta=3), k, l)
     assert np.array_equal(A1, A2)
+
+
+def test_band_correction_two_sub_bands(monkeypatch):
+    # 64^2 fine cells over 8 x 8 coarse blocks of 8 elements (the shape of the
+    # 2048^2 batch, where the two sub-bands pay off), three continua with
+    # inclusions, the band correction on two sub-bands of 4 node rows per
+    # thread (MCH_PREC_64=2): forward on every cell and the adjoint gradient
+    # against the oracle
+    from gpu_util import grad_case
+
+    monkeypatch.setenv("MCH_PREC_64", "2")
+    cfg = W.Config(dim=2, n_fine=128, n_macro=16, n_cell=64, n_sub=2, n_cont=3, levels=2)
+    k, l = W.medium_for(cfg, 51)
+    plan, _ = _check("two sub-bands", cfg, k, l, phi_cells=list(range(cfg.n_points)), workers=8)
+    info = (plan.band_subbands[0], plan.rows_per_thread[0])
+    plan.close()
+    assert info == (2, 8), info
+    grad_case("two sub-bands", cfg, 52, workers=8)
