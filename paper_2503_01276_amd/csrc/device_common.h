@@ -136,6 +136,77 @@ MCH_DEV double from_left(double v, int c) {
   return (c == 0) ? 0.0 : t;
 }
 
+// ---- the band matrices of the preconditioner's coarse correction ----------
+// The solve kernel applies T_b^-1 (tridiagonal over a band's node columns)
+// by cyclic reduction, and the set-up builds the Schur matrix B G^-1 B^T with
+// the same factors. Both call the functions below with contraction of
+// multiply-add pairs off or made explicit, so the two compute T_b's entries
+// and its factors to the last bit alike: two factorisations of a band matrix
+// of condition 1e8 that differ in rounding disagree in the eighth digit, and
+// a Schur matrix from one does not project the residual of the other.
+
+// Adds one node row's K_n entries (centre, north, south, east, north-east,
+// south-east) between free nodes of a band to the diagonal td and the
+// super-diagonal tc of its band matrix row: the row's own entries always,
+// its northern neighbour's if that row is in the band (upIn), its southern
+// one's likewise (dnIn); the eastern ones only where the node to the east is
+// free (frE).
+MCH_DEV void band_row_add(double& td, double& tc, bool frE, bool upIn, bool dnIn, double cen, double nor,
+                          double sou, double eas, double ne, double se) {
+#pragma clang fp contract(off)
+  td += cen + (upIn ? nor : 0.0) + (dnIn ? sou : 0.0);
+  if (frE) tc += eas + (upIn ? ne : 0.0) + (dnIn ? se : 0.0);
+}
+
+// The six K_n entries of a fine-level node from the kappa / 6 of its four
+// elements (south-west, south-east, north-west, north-east).
+MCH_DEV void fine_stencil6(double kSW, double kSE, double kNW, double kNE, double (&k6)[6]) {
+#pragma clang fp contract(off)
+  const double aS = kSW + kSE, aN = kNW + kNE;
+  k6[0] = 4.0 * (aS + aN);
+  k6[1] = -aN;
+  k6[2] = -aS;
+  k6[3] = -(kSE + kNE);
+  k6[4] = -2.0 * kNE;
+  k6[5] = -2.0 * kSE;
+}
+
+// Offset of stride 2^k's factors in a band's block; the block holds
+// pcr_offset(nc, log2 nc) values.
+__host__ __device__ constexpr int pcr_offset(int nc, int k) { return 2 * (k * nc - ((1 << k) - 1)); }
+
+// Cyclic reduction of a tridiagonal system held one row per lane in groups
+// of nc lanes (a power of two, at most a wave): lane c holds its row's
+// sub-diagonal a, diagonal b and super-diagonal cc. Step k (stride 2^k)
+// eliminates the couplings at that stride; its factors on the rows 2^k
+// below and above are stored through put(k, hasL, hasR, al, ga). Returns
+// 1 / the final pivot of the lane's row.
+template <typename Put>
+MCH_DEV double pcr_factor(int c, int nc, int logn, double a, double b, double cc, Put&& put) {
+#pragma clang fp contract(off)
+#pragma unroll
+  for (int k = 0; k < logn; ++k) {
+    const int st = 1 << k;
+    const bool hasL = c >= st, hasR = c + st < nc;
+    const double aL = __shfl_up(a, st, nc), bL = __shfl_up(b, st, nc), cL = __shfl_up(cc, st, nc);
+    const double aR = __shfl_down(a, st, nc), bR = __shfl_down(b, st, nc), cR = __shfl_down(cc, st, nc);
+    const double al = hasL ? -a / bL : 0.0;
+    const double ga = hasR ? -cc / bR : 0.0;
+    put(k, hasL, hasR, al, ga);
+    const double na = hasL ? al * aL : 0.0;
+    const double nc2 = hasR ? ga * cR : 0.0;
+    b = __builtin_fma(ga, hasR ? aR : 0.0, __builtin_fma(al, hasL ? cL : 0.0, b));
+    a = na;
+    cc = nc2;
+  }
+  return 1.0 / b;
+}
+
+// One elimination step on a right-hand side: d + al d_below + ga d_above.
+MCH_DEV double pcr_rhs(double d, double al, double dL, double ga, double dR) {
+  return __builtin_fma(ga, dR, __builtin_fma(al, dL, d));
+}
+
 // Arguments shared by the cell kernels. Every pointer is a device pointer;
 // per-point arrays are indexed by the global macropoint index p.
 struct CellArgs {

@@ -28,8 +28,10 @@
 namespace mch {
 
 constexpr int SETUP_T = 256;
-// Bands whose Schur corrections the setup forms at once.
+// Bands whose Schur corrections the setup forms at once (one group of at
+// most 64 lanes each).
 constexpr int PREC_GROUP = 4;
+static_assert(PREC_GROUP * 64 <= SETUP_T, "a set-up workgroup reduces PREC_GROUP band matrices at once");
 
 // Most constraint rows a band of prec_rows node rows can meet (the rows of
 // every sub-block row whose nodes reach into the band) and the bands formed
@@ -80,20 +82,20 @@ __global__ __launch_bounds__(T) void k_setup2d(CellArgs a) {
   double* X = S + m * m;                 // 2*m: pivot row and column
   double* stat = X + 2 * m;              // (s*s+1)*N*3
   double* wred = stat + (s * s + 1) * N * 3;  // 4*N*3
-  // band coarse correction (prec_rows > 0): for a group of G bands the
-  // band-summed weights of the constraint rows active in each [G][NA][NC]
-  // and their forward-eliminated values [G][NC][NA]; for every band the
-  // factors of T_b = L D L^T: the subdiagonal of L and 1/D [bands][NC] each
-  // (filled with T_b's off-diagonal and diagonal first)
+  // band coarse correction (prec_rows > 0), for a group of G bands: the
+  // band-summed weights of the constraint rows active in each [G][NA][NC],
+  // T_b^-1 applied to them [G][NA][NC], the cyclic-reduction factors of each
+  // T_b [G][pcr_offset(NC, log2 NC)] and 1 / its final pivots [G][NC]
   const bool prec = a.prec_rows > 0;
   const int nbands = prec ? NC / a.prec_rows : 0;
   int pNA = 0, pG = 0;
   if (prec) prec_group_sizes(a, &pNA, &pG);
+  const int logNC = 31 - __builtin_clz(NC), pcb = pcr_offset(NC, logNC);
   double* BZ = wred + (T / 64) * N * 3;
   double* Ys = BZ + pG * pNA * NC;
-  double* Lf = Ys + pG * pNA * NC;
-  double* iD = Lf + nbands * NC;
-  uint8_t* labS = reinterpret_cast<uint8_t*>(iD + nbands * NC);  // fine: NC*NC labels
+  double* Fs = Ys + pG * pNA * NC;
+  double* IBs = Fs + pG * pcb;
+  uint8_t* labS = reinterpret_cast<uint8_t*>(IBs + pG * NC);  // fine: NC*NC labels
   uint8_t* regS = labS + NC * NC;        // NC*NC sub-block of each element
   __shared__ int singular;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -333,15 +335,16 @@ __global__ __launch_bounds__(T) void k_setup2d(CellArgs a) {
   // The solve kernel preconditions with G^-1 = D^-1 + sum_b Z_b T_b^-1 Z_b^T
   // (bands of prec_rows node rows, one coarse unknown per node column of a
   // band; see the kernel), so its Schur matrix is B G^-1 B^T: add
-  // (B Z_b) T_b^-1 (B Z_b)^T = Y^T D^-1 Y per band, with T_b = L D L^T
-  // (tridiagonal over the node columns; column 0 is the Dirichlet boundary,
-  // an identity row) and Y = L^-1 (B Z_b)^T by one forward sweep per
-  // constraint row. The factors of all bands are formed in parallel.
+  // (B Z_b) T_b^-1 (B Z_b)^T per band. T_b (tridiagonal over the node
+  // columns; column 0 is the Dirichlet boundary, an identity row) is reduced
+  // as in the kernel, one row per lane in groups of NC lanes, with the same
+  // factors to the last bit, and its inverse applied to each active
+  // constraint row's band sums (B Z_b)^T.
   if (prec) {
     const int R = a.prec_rows;
     // K_n entries of level node (X, Y): centre, north, south, east,
     // north-east, south-east
-    auto stencil_at = [&](int X, int Y, double* k6) {
+    auto stencil_at = [&](int X, int Y, double (&k6)[6]) {
       if (gal) {
         const double* w9 = nW + (size_t)(Y * NCp + X) * 9;
         k6[0] = w9[4];
@@ -354,14 +357,7 @@ __global__ __launch_bounds__(T) void k_setup2d(CellArgs a) {
         auto kq = [&](int ex, int ey) {
           return a.kappa[(size_t)wrap1(oy + ey, a.n) * a.n + wrap1(ox + ex, a.n)] * (1.0 / 6.0);
         };
-        const double kSW = kq(X - 1, Y - 1), kSE = kq(X, Y - 1), kNW = kq(X - 1, Y), kNE = kq(X, Y);
-        const double aS = kSW + kSE, aN = kNW + kNE;
-        k6[0] = 4.0 * (aS + aN);
-        k6[1] = -aN;
-        k6[2] = -aS;
-        k6[3] = -(kSE + kNE);
-        k6[4] = -2.0 * kNE;
-        k6[5] = -2.0 * kSE;
+        fine_stencil6(kq(X - 1, Y - 1), kq(X, Y - 1), kq(X - 1, Y), kq(X, Y), k6);
       }
     };
     // constraint weight of level node (X, Y) for sub-block q and continuum j
@@ -380,48 +376,10 @@ __global__ __launch_bounds__(T) void k_setup2d(CellArgs a) {
       }
       return w;
     };
-    // rows of every T_b: off-diagonal T[X][X+1] into Lf, diagonal into iD
-    for (int e = tid; e < nbands * NC; e += T) {
-      const int b = e / NC, X = e % NC, yb0 = b * R;
-      double td = 0.0, tc = 0.0;
-      for (int i = 0; i < R; ++i) {
-        const int Y = yb0 + i;
-        const bool fr = X >= 1 && Y >= 1, frE = X + 1 <= NC - 1 && Y >= 1;
-        const bool upIn = i + 1 < R, dnIn = i >= 1 && Y - 1 >= 1;
-        if (!fr) continue;
-        double k6[6];
-        stencil_at(X, Y, k6);
-        td += k6[0] + (upIn ? k6[1] : 0.0) + (dnIn ? k6[2] : 0.0);
-        if (frE) tc += k6[3] + (upIn ? k6[4] : 0.0) + (dnIn ? k6[5] : 0.0);
-      }
-      if (X == 0) {
-        td = 1.0;
-        tc = 0.0;
-      }
-      iD[e] = td;
-      Lf[e] = tc;
-    }
-    __syncthreads();
-    // T_b = L D L^T, one band per thread: l_X = T[X][X-1] / D_{X-1}
-    for (int b = tid; b < nbands; b += T) {
-      double* lf = Lf + b * NC;
-      double* id = iD + b * NC;
-      double prevD = id[0], prevT = lf[0];  // D_0 = 1 (identity row)
-      id[0] = 1.0 / prevD;
-      lf[0] = 0.0;
-      for (int X = 1; X < NC; ++X) {
-        const double l = prevT / prevD;
-        const double D = id[X] - l * prevT;
-        prevT = lf[X];
-        prevD = D;
-        lf[X] = l;
-        id[X] = 1.0 / D;
-      }
-    }
-    __syncthreads();
     // Per band only the rows of sub-blocks whose node rows meet the band's
     // carry weight there (act[], at most NA of them, inv[] the inverse map);
-    // PREC_GROUP bands at a time, each with its own slices of BZ and Ys.
+    // PREC_GROUP bands at a time, each with its own slices of BZ, Ys, Fs, IBs
+    // and the NC lanes tid / NC == g.
     int NA, G;
     prec_group_sizes(a, &NA, &G);
     __shared__ int act[PREC_GROUP][64];
@@ -445,6 +403,34 @@ __global__ __launch_bounds__(T) void k_setup2d(CellArgs a) {
         if (na > NA) singular = 1;
         n_act[tid] = na < NA ? na : NA;
       }
+      // row X of T_b, then its cyclic reduction (the lanes of a group are
+      // consecutive threads of one wave, NC <= 64)
+      if (tid < gb * NC) {
+        const int g = tid / NC, X = tid % NC, yb0 = (b0 + g) * R;
+        double td = 0.0, tc = 0.0;
+        for (int i = 0; i < R; ++i) {
+          const int Y = yb0 + i;
+          const bool fr = X >= 1 && Y >= 1, frE = X + 1 <= NC - 1 && Y >= 1;
+          const bool upIn = i + 1 < R, dnIn = i >= 1 && Y - 1 >= 1;
+          if (!fr) continue;
+          double k6[6];
+          stencil_at(X, Y, k6);
+          band_row_add(td, tc, frE, upIn, dnIn, k6[0], k6[1], k6[2], k6[3], k6[4], k6[5]);
+        }
+        if (X == 0) {
+          td = 1.0;
+          tc = 0.0;
+        }
+        double ta = __shfl_up(tc, 1, NC);  // T[X][X-1] = T[X-1][X]
+        if (X == 0) ta = 0.0;
+        double* blk = Fs + g * pcb;
+        IBs[g * NC + X] = pcr_factor(X, NC, logNC, ta, td, tc, [&](int k, bool hasL, bool hasR, double al, double ga) {
+          double* stp = blk + pcr_offset(NC, k);
+          const int st = 1 << k;
+          if (hasL) stp[X - st] = al;
+          if (hasR) stp[(NC - st) + X] = ga;
+        });
+      }
       __syncthreads();
       for (int e = tid; e < gb * NA * NC; e += T) {
         const int g = e / (NA * NC), ia = (e / NC) % NA, X = e % NC;
@@ -460,16 +446,22 @@ __global__ __launch_bounds__(T) void k_setup2d(CellArgs a) {
         BZ[e] = cwp[k] * acc;
       }
       __syncthreads();
-      for (int e = tid; e < gb * NA; e += T) {
-        const int g = e / NA, ia = e % NA;
-        if (ia >= n_act[g]) continue;
-        const double* lf = Lf + (b0 + g) * NC;
-        const double* bz = BZ + (size_t)(g * NA + ia) * NC;
-        double* ys = Ys + (size_t)g * NC * NA + ia;
-        double y = 0.0;
-        for (int X = 0; X < NC; ++X) {
-          y = bz[X] - lf[X] * y;
-          ys[X * NA] = y;
+      // Ys = T_b^-1 BZ, one active row at a time per group of lanes
+      if (tid < gb * NC) {
+        const int g = tid / NC, X = tid % NC;
+        const double* blk = Fs + g * pcb;
+        const double ib = IBs[g * NC + X];
+        for (int ia = 0; ia < n_act[g]; ++ia) {
+          double d = BZ[(g * NA + ia) * NC + X];
+          for (int k = 0; k < logNC; ++k) {
+            const int st = 1 << k;
+            const double* stp = blk + pcr_offset(NC, k);
+            const double dL = __shfl_up(d, st, NC), dR = __shfl_down(d, st, NC);
+            const double al = (X >= st) ? stp[X - st] : 0.0;
+            const double ga = (X + st < NC) ? stp[(NC - st) + X] : 0.0;
+            d = pcr_rhs(d, al, dL, ga, dR);
+          }
+          Ys[(g * NA + ia) * NC + X] = d * ib;
         }
       }
       __syncthreads();
@@ -479,9 +471,9 @@ __global__ __launch_bounds__(T) void k_setup2d(CellArgs a) {
         for (int g = 0; g < gb; ++g) {
           const int ia = inv[g][k], ib = inv[g][k2];
           if (ia < 0 || ib < 0) continue;
-          const double* ys = Ys + (size_t)g * NC * NA;
-          const double* id = iD + (b0 + g) * NC;
-          for (int X = 0; X < NC; ++X) acc += ys[X * NA + ia] * id[X] * ys[X * NA + ib];
+          const double* bz = BZ + (size_t)(g * NA + ia) * NC;
+          const double* ys = Ys + (size_t)(g * NA + ib) * NC;
+          for (int X = 0; X < NC; ++X) acc += bz[X] * ys[X];
         }
         S[e] += acc;
       }
@@ -679,7 +671,9 @@ static size_t setup_lds_bytes(const CellArgs& a, int threads) {
   if (a.prec_rows > 0) {
     int NA, G;
     prec_group_sizes(a, &NA, &G);
-    d += 2 * (size_t)G * NA * a.NC + 2 * (size_t)(a.NC / a.prec_rows) * a.NC;
+    int lg = 0;
+    while ((1 << (lg + 1)) <= a.NC) ++lg;
+    d += 2 * (size_t)G * NA * a.NC + (size_t)G * (pcr_offset(a.NC, lg) + a.NC);
   }
   // labels and sub-block per element (bytes)
   return d * sizeof(double) + 2 * (size_t)a.NC * a.NC;

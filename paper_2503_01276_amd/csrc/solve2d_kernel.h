@@ -59,18 +59,10 @@ constexpr bool kBig = !GAL && NC >= 64;
 // wave then solves the small Schur system S v = u on its own (same inputs,
 // same order, identical results), so no wave waits on a serial section.
 //
-// B G^-1 r' vanishes only as far as the Schur matrix of the set-up equals
-// B G^-1 B^T for the G^-1 the iteration applies. With D alone that holds to
-// rounding, and the remainder is folded in every ZPERIOD iterations. With
-// the band correction the set-up forms S from an LDL^T factorisation of T_b
-// while the iteration applies T_b^-1 by cyclic reduction; the two agree only
-// to about cond(T_b) times the unit roundoff (T_b inherits the contrast of
-// the medium), and a remainder left for several iterations slows the
-// convergence and costs digits in the solution (and more in the next
-// level's Galerkin operators built from it). It is folded in every
-// ZPERIOD_BAND iterations there.
+// B G^-1 r' vanishes up to rounding (the set-up's Schur matrix is formed
+// with the same G^-1, the band factors included, to the last bit); it is
+// folded in every ZPERIOD iterations.
 constexpr int ZPERIOD = 16;
-constexpr int ZPERIOD_BAND = 1;
 
 // S sub-blocks per axis, so m = N S^2 constraint rows and sub-blocks of
 // NC / S level elements spanning NC / (S RPT) bands.
@@ -80,13 +72,18 @@ constexpr int ZPERIOD_BAND = 1;
 constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
 template <int NC>
 constexpr int pcr_per_band() { return 2 * (NC * ilog2(NC) - (NC - 1)); }
-// Offset of stride 2^k's factors within a band's block.
+// Offset of stride 2^k's factors within a band's block (the set-up's
+// pcr_offset, which takes a run-time width; this form leaves the kernel's
+// LDS addressing to fold into immediate offsets).
 template <int NC>
 constexpr int pcr_step_offset(int k) {
   int o = 0;
   for (int q = 0; q < k; ++q) o += 2 * (NC - (1 << q));
   return o;
 }
+static_assert(pcr_step_offset<64>(5) == pcr_offset(64, 5) && pcr_per_band<64>() == pcr_offset(64, 6) &&
+                  pcr_step_offset<16>(3) == pcr_offset(16, 3) && pcr_per_band<16>() == pcr_offset(16, 4),
+              "the kernel's and the set-up's factor layouts agree");
 
 // At least two waves per SIMD: a workgroup of fewer than eight waves would
 // otherwise let the compiler spend the whole register file on one wave.
@@ -181,10 +178,7 @@ __global__ __launch_bounds__(NC* NC / RPT) __attribute__((amdgpu_waves_per_eu(2)
     const bool fr = (c >= 1) && (y >= 1);
     const bool frE = (c + 1 <= NC - 1) && (y >= 1);
     const bool upIn = (ib + 1 < HB), dnIn = (ib >= 1) && (y - 1 >= 1);
-    if (fr) {
-      Td[sb] += cen + (upIn ? nor : 0.0) + (dnIn ? sou : 0.0);
-      if (frE) Tc[sb] += eas + (upIn ? ne : 0.0) + (dnIn ? se : 0.0);
-    }
+    if (fr) band_row_add(Td[sb], Tc[sb], frE, upIn, dnIn, cen, nor, sou, eas, ne, se);
   };
 
   // ---- per-node operator data in registers --------------------------------
@@ -229,9 +223,9 @@ __global__ __launch_bounds__(NC* NC / RPT) __attribute__((amdgpu_waves_per_eu(2)
       const double ksum = kl[0][i] + kl[1][i] + kl[0][i + 1] + kl[1][i + 1];
       Dinv[i] = fr ? 1.0 / (4.0 * ksum) : 0.0;
       if constexpr (PRE) {
-        const double kSW = kl[0][i], kSE = kl[1][i], kNW = kl[0][i + 1], kNE = kl[1][i + 1];
-        const double aS = kSW + kSE, aN = kNW + kNE;
-        band_row(i, 4.0 * (aS + aN), -aN, -aS, -(kSE + kNE), -2.0 * kNE, -2.0 * kSE);
+        double k6[6];
+        fine_stencil6(kl[0][i], kl[1][i], kl[0][i + 1], kl[1][i + 1], k6);
+        band_row(i, k6[0], k6[1], k6[2], k6[3], k6[4], k6[5]);
       }
 #pragma unroll
       for (int sd = 0; sd < 2; ++sd)
@@ -293,25 +287,12 @@ __global__ __launch_bounds__(NC* NC / RPT) __attribute__((amdgpu_waves_per_eu(2)
       double Ta = __shfl_up(tc, 1, NC);  // T[c][c-1] = T[c-1][c]
       if (c == 0) Ta = 0.0;
       double* blk = pcr + (size_t)(band * SB + b) * pcr_per_band<NC>();
-#pragma unroll
-      for (int k = 0; k < LOGNC; ++k) {
-        const int st = 1 << k;
-        const bool hasL = c >= st, hasR = c + st < NC;
-        const double aL = __shfl_up(Ta, st, NC), bL = __shfl_up(td, st, NC), cL = __shfl_up(tc, st, NC);
-        const double aR = __shfl_down(Ta, st, NC), bR = __shfl_down(td, st, NC), cR = __shfl_down(tc, st, NC);
-        const double al = hasL ? -Ta / bL : 0.0;
-        const double ga = hasR ? -tc / bR : 0.0;
-        const double na = hasL ? al * aL : 0.0;
-        const double ncf = hasR ? ga * cR : 0.0;
-        const double nb = td + (hasL ? al * cL : 0.0) + (hasR ? ga * aR : 0.0);
+      pcr_ib[b] = pcr_factor(c, NC, LOGNC, Ta, td, tc, [&](int k, bool hasL, bool hasR, double al, double ga) {
         double* stp = blk + pcr_step_offset<NC>(k);
+        const int st = 1 << k;
         if (hasL) stp[c - st] = al;
         if (hasR) stp[(NC - st) + c] = ga;
-        Ta = na;
-        tc = ncf;
-        td = nb;
-      }
-      pcr_ib[b] = 1.0 / td;
+      });
     }
   }
 
@@ -353,8 +334,8 @@ __global__ __launch_bounds__(NC* NC / RPT) __attribute__((amdgpu_waves_per_eu(2)
           const double dL2 = __shfl_up(d2[b], st, NC), dR2 = __shfl_down(d2[b], st, NC);
           const double al = (c >= st) ? stp[c - st] : 0.0;
           const double ga = (c + st < NC) ? stp[(NC - st) + c] : 0.0;
-          d[b] += al * dL + ga * dR;
-          d2[b] += al * dL2 + ga * dR2;
+          d[b] = pcr_rhs(d[b], al, dL, ga, dR);
+          d2[b] = pcr_rhs(d2[b], al, dL2, ga, dR2);
         }
       }
 #pragma unroll
@@ -388,7 +369,7 @@ __global__ __launch_bounds__(NC* NC / RPT) __attribute__((amdgpu_waves_per_eu(2)
           const double dL = __shfl_up(d[b], st, NC), dR = __shfl_down(d[b], st, NC);
           const double al = (c >= st) ? stp[c - st] : 0.0;
           const double ga = (c + st < NC) ? stp[(NC - st) + c] : 0.0;
-          d[b] += al * dL + ga * dR;
+          d[b] = pcr_rhs(d[b], al, dL, ga, dR);
         }
       }
 #pragma unroll
@@ -677,7 +658,7 @@ __global__ __launch_bounds__(NC* NC / RPT) __attribute__((amdgpu_waves_per_eu(2)
     }
     // B G^-1 r' is folded in periodically (see ZPERIOD), which keeps the
     // constraint residual at rounding level.
-    const bool withz0 = (it % (PRE ? ZPERIOD_BAND : ZPERIOD)) == 0;
+    const bool withz0 = (it % ZPERIOD) == 0;
     if (withz0) accumulate_B(t, 0);
     accumulate_B(tA, 1);
     wave_sum_n<4>(s4);
