@@ -52,25 +52,25 @@ KERNEL_SOURCES = {
 # rocprofv3 --pmc runs, each scaled by the ratio of a plain copy's known size
 # to what the same counter reads for it. An entry holds only while the kernel
 # sources hash to the recorded value; otherwise traffic is reported as null.
-_SHA_2D = "cb44a3ade20c7bb47c5397ddbdf1b470a83ab4433bdecf6a3d4c77797fdacdd8"
-_SHA_3D = "28c78fcc78abefe7655664cc9445228d1fc74ebe0e7bbefe12bd2fc1b0cf54d6"
-_COPY_SCALE = {"fetch": 1048576.0 / 524304.75, "write": 1048576.0 / 1048576.0}  # 1 GiB copy
+_SHA_2D = "da1372cd04fce063f19b89cbde539016cab35b6e5b16f0cdbdd34a75b9202178"
+_SHA_3D = "ff5b98abba5cd73e6601d39f2242a819b014cb1bd676920895bcfd808bff1f9c"
+_COPY_SCALE = {"fetch": 1048576.0 / 524304.92, "write": 1048576.0 / 1048576.0}  # 1 GiB copy
 TRAFFIC = {
     # level-2 (32^2 Galerkin) forward solve: two launches per step (756 and 396
     # workgroups), counters averaged over both
-    ("c2", "solve_L2"): {"sha256": _SHA_2D, "fetch_kib": 34054.2, "write_kib": 4941.2,
+    ("c2", "solve_L2"): {"sha256": _SHA_2D, "fetch_kib": 9079.0, "write_kib": 4916.1,
                          "fetch_scale": _COPY_SCALE["fetch"], "write_scale": _COPY_SCALE["write"]},
-    ("c2", "adjsolve_L2"): {"sha256": _SHA_2D, "fetch_kib": 64462.1, "write_kib": 9882.4,
+    ("c2", "adjsolve_L2"): {"sha256": _SHA_2D, "fetch_kib": 12168.5, "write_kib": 9830.1,
                             "fetch_scale": _COPY_SCALE["fetch"], "write_scale": _COPY_SCALE["write"]},
     # level-1 (64^2, band coarse correction) forward chunks (252 and 132
     # workgroups) averaged, and the single adjoint launch (384)
-    ("c2", "solve_L1"): {"sha256": _SHA_2D, "fetch_kib": 4982.8, "write_kib": 6687.0,
+    ("c2", "solve_L1"): {"sha256": _SHA_2D, "fetch_kib": 1753.0, "write_kib": 6296.0,
                          "fetch_scale": _COPY_SCALE["fetch"], "write_scale": _COPY_SCALE["write"]},
-    ("c2", "adjsolve_L1"): {"sha256": _SHA_2D, "fetch_kib": 16225.0, "write_kib": 13194.2,
+    ("c2", "adjsolve_L1"): {"sha256": _SHA_2D, "fetch_kib": 8858.1, "write_kib": 12590.1,
                             "fetch_scale": _COPY_SCALE["fetch"], "write_scale": _COPY_SCALE["write"]},
     # 3D fine level: forward and adjoint launches share kernel and grid; the
     # counters are the mean over both, so either may be the dominant launch
-    ("c3", "solve_L1"): {"sha256": _SHA_3D, "fetch_kib": 77048185.5, "write_kib": 81359427.8,
+    ("c3", "solve_L1"): {"sha256": _SHA_3D, "fetch_kib": 74603016.6, "write_kib": 81343140.2,
                          "fetch_scale": _COPY_SCALE["fetch"], "write_scale": _COPY_SCALE["write"]},
 }
 TRAFFIC[("c3", "adjsolve_L1")] = TRAFFIC[("c3", "solve_L1")]
