@@ -981,6 +981,44 @@ __global__ __launch_bounds__((nt3<NC, GAL>())) __attribute__((amdgpu_waves_per_e
     }
   };
 
+  // Phase B (x, the projected residual and the new direction) as a z-march
+  // with the loads one plane ahead: step Z issues the node data of plane Z+1
+  // (p, x, r, K p, D^-1) and updates plane Z from what the previous step
+  // loaded, so a step's stores and arithmetic overlap the next step's loads.
+  auto phaseB_zmarch = [&](double al, double be) {
+#pragma unroll 1
+    for (int c = 0; c < CPT; ++c) {
+      if (!colfree(c)) continue;
+      const int Y = Yc(c);
+      auto q_of = [&](int Z) -> size_t { return nidx3(X, Y, Z, NP); };
+      double pn = pv[q_of(1)], xn = xv[q_of(1)], rn = rv[q_of(1)], an = av[q_of(1)];
+      double di = dinv[node_of(Y, 1)];
+      Acc vs;
+#pragma unroll 1
+      for (int Z = 1; Z <= NC - 1; ++Z) {
+        const int m0 = (Z - 1) / sbw, m1 = Z / sbw;
+        if (Z == 1 || (Z - 2) / sbw != m0 || (Z - 1) / sbw != m1) load_vs(vs, c, m0, m1);
+        // plane Z+1 (the last step reloads its own plane; those values go unused)
+        const int Zn = (Z + 1 <= NC - 1) ? Z + 1 : Z;
+        const size_t qn = q_of(Zn);
+        const double pn2 = pv[qn], xn2 = xv[qn], rn2 = rv[qn], an2 = av[qn];
+        const double di2 = dinv[node_of(Y, Zn)];
+        float w[8][N];
+        node_weights(Y, Z, w);
+        const size_t q = q_of(Z);
+        xv[q] = xn + al * pn;
+        const double r2 = rn + al * an - scatB(vs, w);
+        rv[q] = r2;
+        pv[q] = -di * r2 + be * pn;
+        pn = pn2;
+        xn = xn2;
+        rn = rn2;
+        an = an2;
+        di = di2;
+      }
+    }
+  };
+
   // ---- right-hand side of the constraints -------------------------------------
   double* uw = uW + wave * m;
   if (!a.adjoint) {
@@ -1140,7 +1178,9 @@ __global__ __launch_bounds__((nt3<NC, GAL>())) __attribute__((amdgpu_waves_per_e
     const double be = rzn / rrk;
     rz = rzn;
     // phase B: x, projected residual and the new direction
-    {
+    if constexpr (ZM) {
+      phaseB_zmarch(al, be);
+    } else {
       Acc vs;
       sweep([&](int c, int m0, int m1) { load_vs(vs, c, m0, m1); },
             [&](int c, int Z) {
