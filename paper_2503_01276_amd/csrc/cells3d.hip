@@ -829,21 +829,18 @@ __global__ __launch_bounds__((nt3<NC, GAL>())) __attribute__((amdgpu_waves_per_e
     return t;
   };
 
-  // Phase A on the fine level as a z-march: every thread walks its columns
-  // plane by plane with a register window of p (planes Z-1, Z, Z+1 x rows
-  // Y-1, Y, Y+1 at its own x) and of the element coefficients of its x
-  // column; x-1 / x+1 values come from the neighbouring lanes by DPP (lanes of
-  // a row hold consecutive x). On the Galerkin level (PF) the loads run one
-  // plane ahead: step Z issues plane Z+2 of p and the node data (r, D^-1) of
-  // plane Z+1 and computes plane Z from what the previous step loaded, so a
-  // step's 27-weight row overlaps the next step's loads (level-2 solve of the
-  // 128^3 workload 62.7 -> 58.6 ms, measured against the previous build on
-  // one GPU). On the fine level the same reordering was slower (79.6 -> 84.1
-  // ms: the extra live values push the kernel into scratch), so there a step
-  // loads its own plane. Every lane runs the march (DPP needs them all);
-  // nodes off the free set contribute nothing.
+  // Phase A as a z-march: every thread walks its columns plane by plane with
+  // a register window of p (planes Z-1, Z, Z+1 x rows Y-1, Y, Y+1 at its own
+  // x) and of the element coefficients of its x column; x-1 / x+1 values come
+  // from the neighbouring lanes by DPP (lanes of a row hold consecutive x).
+  // The loads run one plane ahead: step Z issues plane Z+2 of p, element
+  // layer Z+1 and the node data (r, D^-1) of plane Z+1, and computes plane Z
+  // from what the previous step loaded, so a step's arithmetic overlaps the
+  // next step's loads (on the 128^3 workload: Galerkin level 62.7 -> 58.6 ms,
+  // fine level 72.2 -> 68.2 ms once phase B no longer held the registers).
+  // Every lane runs the march (DPP needs them all); nodes off the free set
+  // contribute nothing.
   constexpr bool ZM = G == 1;
-  constexpr bool PF = GAL;
   auto phaseA_zmarch = [&](double (&s4)[4]) {
     if constexpr (ZM) {
       clear_part(1);
@@ -869,41 +866,29 @@ __global__ __launch_bounds__((nt3<NC, GAL>())) __attribute__((amdgpu_waves_per_e
         for (int row = 0; row < 3; ++row) {
           wp[0][row] = 0.0;
           wp[1][row] = ld_p(Y - 1 + row, 1);
-          wp[2][row] = PF ? ld_p(Y - 1 + row, 2) : 0.0;
+          wp[2][row] = ld_p(Y - 1 + row, 2);
         }
         if constexpr (!GAL) {
 #pragma unroll
           for (int oy = 0; oy < 2; ++oy) {
             kr[0][oy] = ld_k(Y - 1 + oy, 0);
-            kr[1][oy] = PF ? ld_k(Y - 1 + oy, 1) : 0.0;
+            kr[1][oy] = ld_k(Y - 1 + oy, 1);
           }
         }
-        double rn = PF ? ld_r(1) : 0.0, di = PF ? ld_d(1) : 0.0;
+        double rn = ld_r(1), di = ld_d(1);
 #pragma unroll 1
         for (int Z = 1; Z <= NC - 1; ++Z) {
           const int m0 = (Z - 1) / sbw, m1 = Z / sbw;
-          // PF: loads of the next step; otherwise this step's plane Z+1 of p
-          // and element layer Z
-          double wpn[3] = {0.0, 0.0, 0.0};
+          // loads of the next step
+          double wpn[3];
           double krn[KW] = {};
-          double rnn = 0.0, dnn = 0.0;
-          if constexpr (PF) {
 #pragma unroll
-            for (int row = 0; row < 3; ++row) wpn[row] = ld_p(Y - 1 + row, Z + 2);
-            if constexpr (!GAL) {
+          for (int row = 0; row < 3; ++row) wpn[row] = ld_p(Y - 1 + row, Z + 2);
+          if constexpr (!GAL) {
 #pragma unroll
-              for (int oy = 0; oy < 2; ++oy) krn[oy] = ld_k(Y - 1 + oy, Z + 1);
-            }
-            rnn = ld_r(Z + 1);
-            dnn = ld_d(Z + 1);
-          } else {
-#pragma unroll
-            for (int row = 0; row < 3; ++row) wp[2][row] = ld_p(Y - 1 + row, Z + 1);
-            if constexpr (!GAL) {
-#pragma unroll
-              for (int oy = 0; oy < 2; ++oy) kr[1][oy] = ld_k(Y - 1 + oy, Z);
-            }
+            for (int oy = 0; oy < 2; ++oy) krn[oy] = ld_k(Y - 1 + oy, Z + 1);
           }
+          const double rnn = ld_r(Z + 1), dnn = ld_d(Z + 1);
           // neighbour (dx, dy, dz) of the node from the window
           auto nb = [&](int dx, int dy, int dz) -> double {
             const double v = wp[dz + 1][dy + 1];
@@ -942,10 +927,6 @@ __global__ __launch_bounds__((nt3<NC, GAL>())) __attribute__((amdgpu_waves_per_e
           }
           if (fr) {
             av[nidx3(X, Y, Z, NP)] = Ap;
-            if constexpr (!PF) {
-              rn = ld_r(Z);
-              di = ld_d(Z);
-            }
             const double pn = wp[1][1];
             const double tr = di * rn, tA = di * Ap;
             s4[0] += pn * Ap;
@@ -966,7 +947,7 @@ __global__ __launch_bounds__((nt3<NC, GAL>())) __attribute__((amdgpu_waves_per_e
 #pragma unroll
             for (int oy = 0; oy < 2; ++oy) {
               kr[0][oy] = kr[1][oy];
-              if constexpr (PF) kr[1][oy] = krn[oy];
+              kr[1][oy] = krn[oy];
             }
           }
           rn = rnn;
@@ -982,39 +963,56 @@ __global__ __launch_bounds__((nt3<NC, GAL>())) __attribute__((amdgpu_waves_per_e
   };
 
   // Phase B (x, the projected residual and the new direction) as a z-march
-  // with the loads one plane ahead: step Z issues the node data of plane Z+1
-  // (p, x, r, K p, D^-1) and updates plane Z from what the previous step
-  // loaded, so a step's stores and arithmetic overlap the next step's loads.
+  // with the loads two planes ahead: step Z issues the node data of plane
+  // Z+2 (p, x, r, K p, D^-1) and updates plane Z from what earlier steps
+  // loaded, so a step's stores and arithmetic overlap the loads of the next
+  // two (fine-level solve of the 128^3 workload: 80.1 ms with the plain
+  // sweep, 72.4 ms one plane ahead, 62.9 ms two planes ahead with phase A's
+  // loads ahead too: 4.1 TB/s of algorithmic traffic).
   auto phaseB_zmarch = [&](double al, double be) {
 #pragma unroll 1
     for (int c = 0; c < CPT; ++c) {
       if (!colfree(c)) continue;
       const int Y = Yc(c);
       auto q_of = [&](int Z) -> size_t { return nidx3(X, Y, Z, NP); };
-      double pn = pv[q_of(1)], xn = xv[q_of(1)], rn = rv[q_of(1)], an = av[q_of(1)];
-      double di = dinv[node_of(Y, 1)];
+      // node data of planes Z (0) and Z+1 (1)
+      double pn[2], xn[2], rn[2], an[2], di[2];
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const int Zk = (1 + k <= NC - 1) ? 1 + k : 1;
+        pn[k] = pv[q_of(Zk)];
+        xn[k] = xv[q_of(Zk)];
+        rn[k] = rv[q_of(Zk)];
+        an[k] = av[q_of(Zk)];
+        di[k] = dinv[node_of(Y, Zk)];
+      }
       Acc vs;
 #pragma unroll 1
       for (int Z = 1; Z <= NC - 1; ++Z) {
         const int m0 = (Z - 1) / sbw, m1 = Z / sbw;
         if (Z == 1 || (Z - 2) / sbw != m0 || (Z - 1) / sbw != m1) load_vs(vs, c, m0, m1);
-        // plane Z+1 (the last step reloads its own plane; those values go unused)
-        const int Zn = (Z + 1 <= NC - 1) ? Z + 1 : Z;
+        // plane Z+2 (the last steps reload plane Z; those values go unused)
+        const int Zn = (Z + 2 <= NC - 1) ? Z + 2 : Z;
         const size_t qn = q_of(Zn);
         const double pn2 = pv[qn], xn2 = xv[qn], rn2 = rv[qn], an2 = av[qn];
         const double di2 = dinv[node_of(Y, Zn)];
         float w[8][N];
         node_weights(Y, Z, w);
         const size_t q = q_of(Z);
-        xv[q] = xn + al * pn;
-        const double r2 = rn + al * an - scatB(vs, w);
+        xv[q] = xn[0] + al * pn[0];
+        const double r2 = rn[0] + al * an[0] - scatB(vs, w);
         rv[q] = r2;
-        pv[q] = -di * r2 + be * pn;
-        pn = pn2;
-        xn = xn2;
-        rn = rn2;
-        an = an2;
-        di = di2;
+        pv[q] = -di[0] * r2 + be * pn[0];
+        pn[0] = pn[1];
+        xn[0] = xn[1];
+        rn[0] = rn[1];
+        an[0] = an[1];
+        di[0] = di[1];
+        pn[1] = pn2;
+        xn[1] = xn2;
+        rn[1] = rn2;
+        an[1] = an2;
+        di[1] = di2;
       }
     }
   };
