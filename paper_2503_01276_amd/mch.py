@@ -208,11 +208,12 @@ class Plan:
     def __exit__(self, *exc):
         self.close()
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # During interpreter shutdown the HIP runtime and torch's streams may
         # already be torn down: make no HIP call then (the process exit
-        # releases the device memory).
-        if sys.is_finalizing():
+        # releases the device memory). The check is bound at definition time,
+        # since module globals such as sys may already be cleared by then.
+        if _finalizing():
             self._h = None
             return
         try:
