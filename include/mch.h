@@ -55,6 +55,37 @@
  * Every int-returning call returns MCH_OK (0) or a negative code; nothing
  * throws across the ABI. mch_last_error() returns a thread-local message
  * describing the most recent failure on the calling thread.
+ *
+ * Tuning knobs
+ * ------------
+ * mch_build_levels reads these environment variables when it creates a
+ * plan; none changes what is computed beyond rounding (the Krylov stopping
+ * test is the same), only how:
+ *   MCH_RPT_<NC>     node rows per thread of the 2D solve kernel for level
+ *                    cell width NC (default 8 for NC >= 64, else 4; a value
+ *                    without an instantiated kernel falls back to the first
+ *                    valid one of 4, 8, 2, 1, 16);
+ *   MCH_PREC         band coarse correction in the 2D preconditioner: 0 off,
+ *                    1 on for widths >= 64 (default), 2 on for every width
+ *                    with a kernel;
+ *   MCH_PREC_<NC>    the same per width: 0 off, 1 bands of a thread's node
+ *                    rows, 2 two sub-bands of half as many rows (each only
+ *                    where its kernel exists and fits the LDS, else off);
+ *   MCH_SPLIT        0 runs level 1 as one launch instead of two (default 1);
+ *   MCH_GENERIC      1 puts every level on the generic solve kernels (the
+ *                    kernels Neumann cells and wide cells always use);
+ *   MCH_XCD          0 numbers the 2D solve's workgroups in plain order
+ *                    instead of grouping a cell's right-hand sides on one XCD
+ *                    (bitwise the same results);
+ *   MCH_SETUP_WIDE   0 keeps 256-thread set-up workgroups on levels of at most
+ *                    128 cells (default 1: 1024 threads there; read once per
+ *                    process);
+ *   MCH_GRAPHS       0 launches every call eagerly instead of replaying
+ *                    captured graphs;
+ *   MCH_SERIAL       1 puts every launch on the caller's stream (isolated
+ *                    per-kernel timings);
+ *   MCH_MACRO_GRID   workgroups of the grid-wide macroscopic CG.
+ * mch_plan_info reports the shape and preconditioner each level took.
  */
 #ifndef MCH_H
 #define MCH_H
