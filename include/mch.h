@@ -59,8 +59,9 @@
  * Tuning knobs
  * ------------
  * mch_build_levels reads these environment variables when it creates a
- * plan; none changes what is computed beyond rounding (the Krylov stopping
- * test is the same), only how:
+ * plan. None changes the problems solved, only how they are solved; results
+ * agree to the Krylov tolerance (the preconditioner knobs move the iterates)
+ * or bitwise where stated:
  *   MCH_RPT_<NC>     node rows per thread of the 2D solve kernel for level
  *                    cell width NC (default 8 for NC >= 64, else 4; a value
  *                    without an instantiated kernel falls back to the first
