@@ -1731,6 +1731,13 @@ int launch_forward_3d(mch_plan* pl, const double* kappa, const uint8_t* label, h
   char name[32];
   int rc = ensure_streams(pl);
   if (!rc) rc = fork_levels(pl, s);
+  // the level-1 set-up first: it heads the critical path
+  const int n1 = pl->lev[0].count, n1a = pl->n1a;
+  const CellArgs a1 = base_args(pl, kappa, label, 0);
+  if (!rc && n1) {
+    ProfScope ps(pl, "setup_L1", s);
+    rc = launch_setup3(a1, s);
+  }
   for (int l = 1; l < pl->L && !rc; ++l) {
     if (pl->lev[l].count == 0) continue;
     CellArgs a = base_args(pl, kappa, label, l);
@@ -1738,13 +1745,8 @@ int launch_forward_3d(mch_plan* pl, const double* kappa, const uint8_t* label, h
     ProfScope ps(pl, name, level_stream(pl, l, s));
     rc = launch_setup3(a, level_stream(pl, l, s));
   }
-  const int n1 = pl->lev[0].count, n1a = pl->n1a;
   if (!rc && n1) {
-    CellArgs a = base_args(pl, kappa, label, 0);
-    {
-      ProfScope ps(pl, "setup_L1", s);
-      rc = launch_setup3(a, s);
-    }
+    const CellArgs& a = a1;
     if (!rc && n1a > 0) {
       ProfScope ps(pl, "solve_L1", s);
       rc = launch_solve3(chunk_args(a, 0, n1a), s);

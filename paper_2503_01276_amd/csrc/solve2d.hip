@@ -285,6 +285,15 @@ int launch_forward_2d(mch_plan* pl, const double* kappa, const uint8_t* label, h
   char name[32];
   int rc = ensure_streams(pl);
   if (!rc) rc = fork_levels(pl, s);
+  // The level-1 set-up is issued first: it heads the critical path, and
+  // issued after the other levels' set-ups its workgroups (1024 threads on
+  // the small fine levels) waited for CUs those had taken.
+  const int n1 = pl->lev[0].count, n1a = pl->n1a;
+  const CellArgs a1 = base_args(pl, kappa, label, 0);
+  if (!rc && n1) {
+    ProfScope ps(pl, "setup_L1", s);
+    rc = launch_setup(a1, s);
+  }
   for (int l = 1; l < pl->L && !rc; ++l) {
     if (pl->lev[l].count == 0) continue;
     CellArgs a = base_args(pl, kappa, label, l);
@@ -295,13 +304,8 @@ int launch_forward_2d(mch_plan* pl, const double* kappa, const uint8_t* label, h
     }
     if (!rc && !pl->serial) rc = hip_check(hipEventRecord(pl->ev_setup[l], pl->side[l]), "hipEventRecord");
   }
-  const int n1 = pl->lev[0].count, n1a = pl->n1a;
   if (!rc && n1) {
-    CellArgs a = base_args(pl, kappa, label, 0);
-    {
-      ProfScope ps(pl, "setup_L1", s);
-      rc = launch_setup(a, s);
-    }
+    const CellArgs& a = a1;
     if (!rc && n1a > 0) {
       ProfScope ps(pl, "solve_L1", s);
       rc = launch_solve(chunk_args(a, 0, n1a), pl->lev[0].shape.rpt, s);
