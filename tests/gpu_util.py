@@ -1,6 +1,8 @@
 """Helpers for the GPU tests: run the HIP path through the C ABI and compare with the oracle."""
 from __future__ import annotations
 
+import contextlib
+import os
 import sys
 
 import numpy as np
@@ -9,6 +11,24 @@ import numpy as np
 def say(msg: str):
     print(msg, flush=True)
     sys.stdout.flush()
+
+
+@contextlib.contextmanager
+def tuned_knobs(workload: str):
+    """The stored tuned knobs of a workload (the launch configuration bench.py
+    times) for the plans created inside the block; the environment is
+    restored afterwards."""
+    from paper_2503_01276_amd import autotune
+
+    saved = dict(os.environ)
+    try:
+        table = autotune.load(workload)
+        if table:
+            autotune.apply(table)
+        yield table
+    finally:
+        os.environ.clear()
+        os.environ.update(saved)
 
 
 def gpu_forward(cfg, kappa, label, cells=None):

@@ -11,7 +11,7 @@ import pytest
 import oracle
 from paper_2503_01276_amd import workloads as W
 
-from gpu_util import A_rel_err, gpu_forward, phi_rel_err, say
+from gpu_util import A_rel_err, gpu_forward, phi_rel_err, say, tuned_knobs
 
 pytestmark = pytest.mark.gpu
 
@@ -27,7 +27,9 @@ def c5():
     pts = sorted(set(groups) | set(int(p) for p in np.flatnonzero(np.isin(par, groups))))
     phi_cells = [groups[0]] + [int(p) for p in pts if lev[p] == 4][:2] + [int(p) for p in pts if lev[p] == 2][:1]
     say(f"[gpu] c5: full forward on the GPU, {len(pts)} sampled cells")
-    plan, A, Phi, it, rs, dev = gpu_forward(cfg, k, l, cells=phi_cells)
+    with tuned_knobs("c5") as table:  # the configuration the bench times
+        plan, A, Phi, it, rs, dev = gpu_forward(cfg, k, l, cells=phi_cells)
+    say(f"[gpu] c5: tuned knobs {'applied' if table else 'absent'}; band sub-bands per level {plan.band_subbands}")
     return dict(cfg=cfg, k=k, l=l, plan=plan, A=A, Phi=Phi, it=it, rs=rs, pts=pts, phi_cells=phi_cells, dev=dev)
 
 
