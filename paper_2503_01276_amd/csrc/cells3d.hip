@@ -94,8 +94,8 @@ MCH_DEV double phi_at3(const CellArgs& a, int ci, int alpha, int X, int Y, int Z
 // and per-octant constraint weights of every level node; D^-1;
 // S = B_n D^-1 B_n^T and S^-1 by Cholesky.
 // ---------------------------------------------------------------------------
-template <int N>
-__global__ __launch_bounds__(T3) void k_setup3d(CellArgs a) {
+template <int N, int TB>
+__global__ __launch_bounds__(TB) void k_setup3d(CellArgs a) {
   extern __shared__ double sm[];
   const int m = a.m, s = a.s, nc = a.nc, NC = a.NC, sbw = a.sbw, r = a.r, H = a.H;
   const bool gal = r > 1;
@@ -104,8 +104,8 @@ __global__ __launch_bounds__(T3) void k_setup3d(CellArgs a) {
   double* S = sm;                            // m*m
   double* Xm = S + m * m;                    // m*m
   double* stat = Xm + m * m;                 // (s3+1)*N*4
-  double* wred = stat + (s3 + 1) * N * 4;    // (T3/64)*N*4
-  double* partS = wred + (T3 / 64) * N * 4;  // npairs * node planes
+  double* wred = stat + (s3 + 1) * N * 4;    // (TB/64)*N*4
+  double* partS = wred + (TB / 64) * N * 4;  // npairs * node planes
   __shared__ int singular;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int ci = a.ci0 + blockIdx.x;
@@ -130,7 +130,7 @@ __global__ __launch_bounds__(T3) void k_setup3d(CellArgs a) {
     double acc[N][4];
 #pragma unroll
     for (int j = 0; j < N; ++j) acc[j][0] = acc[j][1] = acc[j][2] = acc[j][3] = 0.0;
-    for (int k = tid; k < w * w * w; k += T3) {
+    for (int k = tid; k < w * w * w; k += TB) {
       const int ex = x0 + k % w, ey = y0 + (k / w) % w, ez = z0 + k / (w * w);
       const int lab = a.label[gel3(a, ox, oy, oz, ex, ey, ez)];
 #pragma unroll
@@ -153,7 +153,7 @@ __global__ __launch_bounds__(T3) void k_setup3d(CellArgs a) {
     __syncthreads();
     if (tid < N * 4) {
       double v = 0.0;
-      for (int w2 = 0; w2 < T3 / 64; ++w2) v += wred[w2 * N * 4 + tid];
+      for (int w2 = 0; w2 < TB / 64; ++w2) v += wred[w2 * N * 4 + tid];
       stat[reg * N * 4 + tid] = v;
     }
     __syncthreads();
@@ -204,7 +204,7 @@ __global__ __launch_bounds__(T3) void k_setup3d(CellArgs a) {
   if (!gal) {
     double* kwc = a.kw + (size_t)ci * elems;
     uint8_t* lbc = a.labw + (size_t)ci * elems;
-    for (int e = tid; e < (int)elems; e += T3) {
+    for (int e = tid; e < (int)elems; e += TB) {
       const size_t ge = gel3(a, ox, oy, oz, e % NC, (e / NC) % NC, e / (NC * NC));
       kwc[e] = a.kappa[ge] * hk;
       lbc[e] = a.label[ge];
@@ -213,7 +213,7 @@ __global__ __launch_bounds__(T3) void k_setup3d(CellArgs a) {
     // labels of every node's eight octant elements, 2 bits each (3 = none),
     // for the column-marching solve
     uint16_t* octc = gen ? nullptr : a.octw + (size_t)ci * nodes;
-    for (int nd = tid; nd < (gen ? 0 : (int)nodes); nd += T3) {
+    for (int nd = tid; nd < (gen ? 0 : (int)nodes); nd += TB) {
       const int X = nd % NC, Y = (nd / NC) % NC, Z = nd / (NC * NC);
       unsigned code = 0;
       if (X >= 1 && Y >= 1 && Z >= 1) {
@@ -224,7 +224,7 @@ __global__ __launch_bounds__(T3) void k_setup3d(CellArgs a) {
       }
       octc[nd] = (uint16_t)code;
     }
-    for (int nd = tid; nd < (int)nodes; nd += T3) {
+    for (int nd = tid; nd < (int)nodes; nd += TB) {
       const int X = nd % NPn, Y = (nd / NPn) % NPn, Z = nd / (NPn * NPn);
       if (is_free(X, Y, Z)) {
         double k8[8];
@@ -242,7 +242,7 @@ __global__ __launch_bounds__(T3) void k_setup3d(CellArgs a) {
   } else {
     double* nW = a.nodeW + (size_t)ci * nodes * 27;
     float* nB = a.nodeB + (size_t)ci * nodes * 8 * N;
-    for (int nd = tid; nd < (int)nodes; nd += T3) {
+    for (int nd = tid; nd < (int)nodes; nd += TB) {
       const int X = nd % NPn, Y = (nd / NPn) % NPn, Z = nd / (NPn * NPn);
       const bool fr = is_free(X, Y, Z);
       double W[27];
@@ -294,7 +294,7 @@ __global__ __launch_bounds__(T3) void k_setup3d(CellArgs a) {
   // ---- S = B_n D^-1 B_n^T: (pair, node plane) partials, fixed-order sums --
   const uint8_t* lbc = gal ? nullptr : a.labw + (size_t)ci * elems;
   const float* nB = gal ? a.nodeB + (size_t)ci * nodes * 8 * N : nullptr;
-  for (int item = tid; item < npairs * NPn; item += T3) {
+  for (int item = tid; item < npairs * NPn; item += TB) {
     int pr = item / NPn;
     const int Z = item % NPn;
     int ra = 0;
@@ -341,7 +341,7 @@ __global__ __launch_bounds__(T3) void k_setup3d(CellArgs a) {
     partS[item] = acc;
   }
   __syncthreads();
-  for (int pr0 = tid; pr0 < npairs; pr0 += T3) {
+  for (int pr0 = tid; pr0 < npairs; pr0 += TB) {
     int pr = pr0, ra = 0;
     while (pr >= m - ra) {
       pr -= m - ra;
@@ -384,7 +384,7 @@ __global__ __launch_bounds__(T3) void k_setup3d(CellArgs a) {
   }
   __syncthreads();
   const bool bad = singular != 0;
-  for (int k = tid; k < m * m; k += T3) {
+  for (int k = tid; k < m * m; k += TB) {
     const int i = k / m, j = k % m;
     double v = 0.0;
     for (int t = (i > j ? i : j); t < m; ++t) v += Xm[t * m + i] * Xm[t * m + j];
@@ -1633,18 +1633,24 @@ static int launch_solve3(const CellArgs& a_in, hipStream_t s) {
 }
 
 static int launch_setup3(const CellArgs& a, hipStream_t s) {
+  // a level of few cells (the fine level of a small macrogrid, which heads
+  // the critical path) gets 1024 threads per cell so that its workgroups
+  // still use much of the GPU
+  const int tb = a.count <= 128 ? 1024 : T3;
   const size_t npairs = (size_t)a.m * (a.m + 1) / 2;
   const size_t s3 = (size_t)a.s * a.s * a.s;
   const size_t planes = a.gen_tp > 0 ? a.NC + 1 : a.NC;  // node planes of the S partials
-  const size_t lds = ((size_t)2 * a.m * a.m + (s3 + 1) * a.N * 4 + (T3 / 64) * a.N * 4 + npairs * planes) * sizeof(double);
+  const size_t lds = ((size_t)2 * a.m * a.m + (s3 + 1) * a.N * 4 + (size_t)(tb / 64) * a.N * 4 + npairs * planes) *
+                     sizeof(double);
   void (*fn)(CellArgs) = nullptr;
-  if (a.N == 1) fn = k_setup3d<1>;
-  if (a.N == 2) fn = k_setup3d<2>;
-  if (a.N == 3) fn = k_setup3d<3>;
+#define MCH_SETUP3(n_) \
+  if (a.N == n_) fn = tb == 1024 ? k_setup3d<n_, 1024> : k_setup3d<n_, T3>;
+  MCH_SETUP3(1) MCH_SETUP3(2) MCH_SETUP3(3)
+#undef MCH_SETUP3
   if (!fn) return set_error(MCH_ENOTIMPL, "n_cont");
   int rc = lds_attr3(fn, lds);
   if (rc) return rc;
-  hipLaunchKernelGGL(fn, dim3(a.count), dim3(T3), lds, s, a);
+  hipLaunchKernelGGL(fn, dim3(a.count), dim3(tb), lds, s, a);
   return hip_check(hipGetLastError(), "launch k_setup3d");
 }
 
