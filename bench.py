@@ -68,12 +68,17 @@ TRAFFIC = {
                          "fetch_scale": _COPY_SCALE["fetch"], "write_scale": _COPY_SCALE["write"]},
     ("c2", "adjsolve_L1"): {"sha256": _SHA_2D, "fetch_kib": 8858.1, "write_kib": 12590.1,
                             "fetch_scale": _COPY_SCALE["fetch"], "write_scale": _COPY_SCALE["write"]},
+    # 2048^2 batch, level 1 (64^2 cells, two sub-bands): forward and adjoint
+    # launches share kernel and grid; the counters are the mean over both
+    ("c5", "solve_L1"): {"sha256": _SHA_2D, "fetch_kib": 253397.2, "write_kib": 471709.7,
+                         "fetch_scale": _COPY_SCALE["fetch"], "write_scale": _COPY_SCALE["write"]},
     # 3D fine level: forward and adjoint launches share kernel and grid; the
     # counters are the mean over both, so either may be the dominant launch
     ("c3", "solve_L1"): {"sha256": _SHA_3D, "fetch_kib": 76635078.4, "write_kib": 81523225.1,
                          "fetch_scale": _COPY_SCALE["fetch"], "write_scale": _COPY_SCALE["write"]},
 }
 TRAFFIC[("c3", "adjsolve_L1")] = TRAFFIC[("c3", "solve_L1")]
+TRAFFIC[("c5", "adjsolve_L1")] = TRAFFIC[("c5", "solve_L1")]
 
 
 def kernel_sources_sha256(dim: int) -> str:
