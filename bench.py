@@ -52,21 +52,21 @@ KERNEL_SOURCES = {
 # rocprofv3 --pmc runs, each scaled by the ratio of a plain copy's known size
 # to what the same counter reads for it. An entry holds only while the kernel
 # sources hash to the recorded value; otherwise traffic is reported as null.
-_SHA_2D = "da1372cd04fce063f19b89cbde539016cab35b6e5b16f0cdbdd34a75b9202178"
+_SHA_2D = "20e92547a39d54f9f1b450021a59c07bb7c978199c29dd0e41896f18c75ee764"
 _SHA_3D = "3a5c6d28d2e609d6d0cd1faaff50a32235d5b19661ca27678dca3f6d5c42be57"
-_COPY_SCALE = {"fetch": 1048576.0 / 524304.92, "write": 1048576.0 / 1048576.0}  # 1 GiB copy
+_COPY_SCALE = {"fetch": 1048576.0 / 524304.79, "write": 1048576.0 / 1048576.0}  # 1 GiB copy
 TRAFFIC = {
     # level-2 (32^2 Galerkin) forward solve: two launches per step (756 and 396
     # workgroups), counters averaged over both
-    ("c2", "solve_L2"): {"sha256": _SHA_2D, "fetch_kib": 9079.0, "write_kib": 4916.1,
+    ("c2", "solve_L2"): {"sha256": _SHA_2D, "fetch_kib": 9080.5, "write_kib": 4916.1,
                          "fetch_scale": _COPY_SCALE["fetch"], "write_scale": _COPY_SCALE["write"]},
-    ("c2", "adjsolve_L2"): {"sha256": _SHA_2D, "fetch_kib": 12168.5, "write_kib": 9830.1,
+    ("c2", "adjsolve_L2"): {"sha256": _SHA_2D, "fetch_kib": 12170.0, "write_kib": 9830.1,
                             "fetch_scale": _COPY_SCALE["fetch"], "write_scale": _COPY_SCALE["write"]},
     # level-1 (64^2, band coarse correction) forward chunks (252 and 132
     # workgroups) averaged, and the single adjoint launch (384)
-    ("c2", "solve_L1"): {"sha256": _SHA_2D, "fetch_kib": 1753.0, "write_kib": 6296.0,
+    ("c2", "solve_L1"): {"sha256": _SHA_2D, "fetch_kib": 1751.3, "write_kib": 10136.0,
                          "fetch_scale": _COPY_SCALE["fetch"], "write_scale": _COPY_SCALE["write"]},
-    ("c2", "adjsolve_L1"): {"sha256": _SHA_2D, "fetch_kib": 8858.1, "write_kib": 12590.1,
+    ("c2", "adjsolve_L1"): {"sha256": _SHA_2D, "fetch_kib": 8855.5, "write_kib": 18228.1,
                             "fetch_scale": _COPY_SCALE["fetch"], "write_scale": _COPY_SCALE["write"]},
     # 2048^2 batch, level 1 (64^2 cells, two sub-bands): forward and adjoint
     # launches share kernel and grid; the counters are the mean over both

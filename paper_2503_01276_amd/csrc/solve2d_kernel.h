@@ -643,11 +643,17 @@ __global__ __launch_bounds__(NC* NC / RPT) __attribute__((amdgpu_waves_per_eu(2)
   int it = 0;
   bool done = !(rz0 > 0.0);
   while (!done) {
-    // t = G^-1 r is formed again each iteration rather than kept live across
-    // it (fewer registers held through the two barriers)
+    // t = G^-1 r' is kept from the end of the previous iteration where the
+    // band correction makes G^-1 costly (its cyclic reductions outweigh the
+    // registers t holds through the two barriers: level-1 solve 0.572 ->
+    // 0.528 ms on the 512^2 workload, 67.4 -> 63.7 ms on the 2048^2 one);
+    // with D alone it is formed again beside G^-1 Ap, which frees them
     double Ap[RPT], tA[RPT];
     apply_K(pv, Ap);
-    apply_G2(r, t, Ap, tA);
+    if constexpr (PRE)
+      apply_G(Ap, tA);
+    else
+      apply_G2(r, t, Ap, tA);
     double s4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
