@@ -70,7 +70,7 @@ TRAFFIC = {
                             "fetch_scale": _COPY_SCALE["fetch"], "write_scale": _COPY_SCALE["write"]},
     # 2048^2 batch, level 1 (64^2 cells, two sub-bands): forward and adjoint
     # launches share kernel and grid; the counters are the mean over both
-    ("c5", "solve_L1"): {"sha256": _SHA_2D, "fetch_kib": 253397.2, "write_kib": 471709.7,
+    ("c5", "solve_L1"): {"sha256": _SHA_2D, "fetch_kib": 283922.0, "write_kib": 9298468.2,
                          "fetch_scale": _COPY_SCALE["fetch"], "write_scale": _COPY_SCALE["write"]},
     # 3D fine level: forward and adjoint launches share kernel and grid; the
     # counters are the mean over both, so either may be the dominant launch
